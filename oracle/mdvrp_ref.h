@@ -1,0 +1,119 @@
+/*
+ * mdvrp_ref.h -- plain CPU oracle for the MDVRP local-search hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library. The product path (the
+ * HIP library) never links, calls or includes anything from this directory,
+ * and this directory includes nothing from the product.
+ *
+ * What it computes (paper: Lei & Hao, "A GPU-Accelerated Hybrid Method for a
+ * Class of Multi-Depot Vehicle Routing Problems"):
+ *   - the multi-penalty evaluation function F(S) (Section 3.2.1, Eq. 2, and
+ *     its full form Eq. A.1 in the supplementary material), with fixed integer
+ *     penalty weights in place of the dynamic coefficients;
+ *   - time warp and duration by Vidal's sequence concatenation (cited in
+ *     Section 3.2.2 and in Appendix A);
+ *   - the neighbourhood of Relocate, Swap, 2-opt*, 2-opt (Section 3.2.2) and
+ *     the two depot operators Depot-Insert / Depot-Replace (Section 3.2.2,
+ *     Fig. 1), restricted to granular lists (Section 3.2.3, Eq. 3);
+ *   - the leader-follower multi-move selection (Section 3.2.5);
+ *   - the local search loop (Algorithm 2).
+ * Every move is evaluated by rebuilding the changed routes as explicit node
+ * lists and recomputing their cost from scratch.
+ *
+ * All pointers are host pointers. Functions return 0 on success, a negative
+ * code on error (-1 invalid input, -3 output capacity too small: the required
+ * count is written to the count argument).
+ */
+#ifndef MDVRP_REF_H
+#define MDVRP_REF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t n_depots, n_customers;
+  const int32_t *c, *t;            /* N*N row-major */
+  const int32_t *q, *s, *e, *l;    /* length N */
+  int32_t Q, NV, Dmax;             /* Dmax < 0: no duration limit */
+  int32_t open_routes, has_tw, theta;
+  int32_t w_tw, w_load, w_dur, w_depot; /* w_depot < 0: use 2*max c - min c */
+} ref_instance;
+
+/* Move kinds (id = kind<<56 | variant<<48 | a<<24 | b). */
+enum { REF_REL1 = 0, REF_REL2 = 1, REF_SWP11 = 2, REF_SWP21 = 3, REF_SWP12 = 4, REF_SWP22 = 5,
+       REF_X2 = 6, REF_2OPT = 7, REF_DINS = 8, REF_DREP = 9 };
+/* Operator families (bit positions of a family mask). */
+enum { REF_FAM_REL = 0, REF_FAM_SWP = 1, REF_FAM_X2 = 2, REF_FAM_2OPT = 3, REF_FAM_DINS = 4,
+       REF_FAM_DREP = 5 };
+
+typedef struct {
+  int64_t dF, dD, dTW, dLX, dDX, dV4;
+  uint64_t id;
+  int32_t res[3]; /* route index r >= 0, depot d as -2-d, -1 none */
+} ref_move;
+
+/* Instance statistics: out[0] = Theta = 2*max c - min c over u != v,
+ * out[1], out[2] = Gamma = sum c / sum t reduced to num/den,
+ * out[3] = effective depot weight. */
+int ref_instance_stats(const ref_instance* I, int64_t out[4]);
+
+/* Granular lists (Section 3.2.3): nbr[(u - n_depots)*theta + k], nbr_len[u - n_depots]. */
+int ref_neighbours(const ref_instance* I, int32_t* nbr, int32_t* nbr_len);
+
+/* F(S) and its terms: terms[0..5] = D, TW, LX, DX, CL, FX. Returns 0. */
+int ref_cost(const ref_instance* I, int32_t n_routes, const int32_t* nodes, const int32_t* offs,
+             const int32_t* start, const int32_t* end, int64_t* F, int64_t terms[6]);
+
+/* Every evaluated move of the families in fam_mask (dense list). */
+int ref_eval(const ref_instance* I, const int32_t* nbr, const int32_t* nbr_len,
+             int32_t n_routes, const int32_t* nodes, const int32_t* offs,
+             const int32_t* start, const int32_t* end, uint32_t fam_mask,
+             ref_move* out, int64_t cap, int64_t* count);
+
+/* One step: evaluate fam_mask, select (leader + followers), apply.
+ * The new solution is written to the out arrays (capacity: n_customers
+ * nodes, n_customers routes). sel_ids receives the selected ids in
+ * selection order. */
+int ref_step(const ref_instance* I, const int32_t* nbr, const int32_t* nbr_len,
+             int32_t n_routes, const int32_t* nodes, const int32_t* offs,
+             const int32_t* start, const int32_t* end, uint32_t fam_mask, int32_t leader_only,
+             int32_t* o_nroutes, int32_t* o_nodes, int32_t* o_offs, int32_t* o_start,
+             int32_t* o_end, uint64_t* sel_ids, int64_t* sel_dF, int32_t* n_sel,
+             int64_t* n_eval);
+
+/* Apply the (route-disjoint) moves with the given ids; output as in ref_step. */
+int ref_apply_ids(const ref_instance* I, int32_t n_routes, const int32_t* nodes, const int32_t* offs,
+                  const int32_t* start, const int32_t* end, const uint64_t* ids, int32_t n_ids,
+                  int32_t* o_nroutes, int32_t* o_nodes, int32_t* o_offs, int32_t* o_start, int32_t* o_end);
+
+typedef struct {
+  int32_t mode;        /* 0 = passes over a permutation of families, 1 = union */
+  int32_t leader_only; /* 1 = apply the leader alone */
+  int32_t max_passes;  /* 0 = until a local optimum */
+  int32_t pad;
+  uint64_t seed;
+} ref_ls_options;
+
+typedef struct {
+  int64_t passes, steps, moves_applied, evaluated, F;
+} ref_ls_stats;
+
+/* Local search to a local optimum for each of n_sol solutions (OpenMP over
+ * solutions). Input/output in the batch layout: routes of solution k are
+ * sol_offs[k]..sol_offs[k+1]-1. Output capacity: n_sol*n_customers routes. */
+int ref_local_search(const ref_instance* I, const int32_t* nbr, const int32_t* nbr_len,
+                     int32_t n_sol, const int32_t* nodes, const int32_t* offs,
+                     const int32_t* start, const int32_t* end, const int32_t* sol_offs,
+                     const ref_ls_options* opt, int32_t* o_nodes, int32_t* o_offs,
+                     int32_t* o_start, int32_t* o_end, int32_t* o_sol_offs, ref_ls_stats* stats);
+
+/* Family order of pass p: Fisher-Yates driven by SplitMix64 seeded with seed ^ p. */
+int ref_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,382 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+These run without a GPU. Each check ties the oracle to something other than
+itself: hand-computed values, brute force over departure times, whole-solution
+recomputation of F, an independent neighbourhood built with Python lists,
+closed-form move counts, and the properties that define the selection.
+"""
+import numpy as np
+import pytest
+
+import t0_brute as T0
+from oracle import ALL_FAMILIES, Ref, family_order
+from paper_2605_05208_amd import gen
+from paper_2605_05208_amd.gen import Instance, Solution, canonical
+
+
+def _inst(xy, q, Q, nd, scale=10, has_tw=0, e=None, l=None, s=None, w_load=10, Dmax=-1, NV=4,
+          open_routes=0, w_tw=0, w_dur=0, theta=None):
+    xy = np.asarray(xy, np.int64)
+    n = len(xy)
+    d = xy[:, None, :] - xy[None, :, :]
+    c = np.floor(np.sqrt((d * d).sum(-1)) * scale + 0.5).astype(np.int32)
+    z = np.zeros(n, np.int32)
+    return Instance(n_depots=nd, n_customers=n - nd, c=c, t=c, q=np.asarray(q, np.int32),
+                    s=z if s is None else np.asarray(s, np.int32), e=z if e is None else np.asarray(e, np.int32),
+                    l=np.full(n, gen.BIG_HORIZON, np.int32) if l is None else np.asarray(l, np.int32),
+                    Q=Q, NV=NV, Dmax=Dmax, open_routes=open_routes, has_tw=has_tw,
+                    theta=theta or (n - nd - 1), w_tw=w_tw, w_load=w_load, w_dur=w_dur, w_depot=-1)
+
+
+# ----------------------------------------------------------------------------- hand cases
+
+def test_hand_cost_example():
+    """Depot (0,0), customers (3,4) and (6,8), scale 10: arcs 50, 50, 100 -> D = 200.
+    q = 5 and 7 with Q = 10 overloads by 2; w_load = 10 -> F = 220 (Eq. 1, Eq. A.1)."""
+    I = _inst([(0, 0), (3, 4), (6, 8)], [0, 5, 7], 10, 1)
+    F, terms = Ref(I).cost(Solution([(0, [1, 2], 0)]))
+    assert terms.tolist() == [200, 0, 2, 0, 0, 0]
+    assert F == 220
+
+
+def _tw_route_cost(nodes_ew, travel):
+    """One route start -> ... -> end with windows; returns (TW, D) through the oracle.
+
+    The instance is built so that F reads off the route's time warp (w_tw = 1)
+    and duration (w_dur = 1 with Dmax = 0)."""
+    n = len(nodes_ew)
+    c = np.zeros((n, n), np.int32)
+    for k, tk in enumerate(travel):
+        c[k, k + 1] = c[k + 1, k] = tk
+    e = np.array([a for a, _ in nodes_ew], np.int32)
+    l = np.array([b for _, b in nodes_ew], np.int32)
+    # node 0 is the depot; the last node plays an open route's last customer
+    I = Instance(n_depots=1, n_customers=n - 1, c=c, t=c, q=np.zeros(n, np.int32), s=np.zeros(n, np.int32),
+                 e=e, l=l, Q=10, NV=9, Dmax=0, open_routes=1, has_tw=1, theta=1, w_tw=1, w_load=0,
+                 w_dur=0, w_depot=0)
+    _, terms = Ref(I).cost(Solution([(0, list(range(1, n)), -1)]))
+    I2 = Instance(**{**I.__dict__, "w_tw": 0, "w_dur": 1})
+    _, terms2 = Ref(I2).cost(Solution([(0, list(range(1, n)), -1)]))
+    return int(terms[1]), int(terms2[3])
+
+
+@pytest.mark.parametrize("case,expect", [
+    # (W1) a[0,10] -> b[100,200], t = 10: wait 80 -> D = 90, no warp
+    (([(0, 10), (100, 200)], [10]), (0, 90)),
+    # (W2) a[0,10] -> b[0,5], t = 10: arrive 10 > 5 -> warp 5, D = 10
+    (([(0, 10), (0, 5)], [10]), (5, 10)),
+    # (W3) a[0,100] -> b[50,50] -> c[0,55], t = 10, 10: depart 40, arrive c at 60 -> warp 5, D = 20
+    (([(0, 100), (50, 50), (0, 55)], [10, 10]), (5, 20)),
+])
+def test_time_warp_hand_cases(case, expect):
+    assert _tw_route_cost(*case) == expect
+
+
+# ----------------------------------------------------------------------------- time warp vs enumeration
+
+def test_time_warp_fold_equals_departure_enumeration():
+    """Vidal's concatenation folded left must equal the lexicographic minimum of
+    (time warp, duration) over every integer departure time (T0 enumeration)."""
+    rng = np.random.default_rng(7)
+    checked = 0
+    for trial in range(300):
+        I = gen.tiny(10_000 + trial, has_tw=1, open_routes=int(trial % 3 == 0))
+        sol = gen.random_solution(I, trial)
+        ref = Ref(I)
+        for (a, xs, b) in sol.routes:
+            single = Solution([(a, xs, b)])
+            I1 = Instance(**{**I.__dict__, "w_tw": 1, "w_load": 0, "w_dur": 0, "w_depot": 0, "Dmax": 0})
+            _, tr = Ref(I1).cost(single)
+            tw, dur = T0.tw_dur(I, a, xs, -1 if I.open_routes else b)
+            assert int(tr[1]) == tw, (trial, a, xs, b)
+            assert int(tr[3]) == dur, (trial, a, xs, b)
+            checked += 1
+        del ref
+    assert checked > 300
+    del rng
+
+
+def test_concat_associative_on_random_segments():
+    """The concatenation operator is associative (the GPU scans rely on it)."""
+    rng = np.random.default_rng(3)
+
+    def cat(a, t, b):
+        D1, W1, E1, L1 = a
+        D2, W2, E2, L2 = b
+        dl = D1 - W1 + t
+        w = max(E2 - dl - L1, 0)
+        x = max(E1 + dl - L2, 0)
+        return (D1 + D2 + t + w, W1 + W2 + x, max(E2 - dl, E1) - w, min(L2 - dl, L1) + x)
+
+    for _ in range(20000):
+        segs = []
+        for _k in range(3):
+            e = int(rng.integers(0, 300))
+            segs.append((int(rng.integers(0, 50)), int(rng.integers(0, 20)), e, e + int(rng.integers(0, 200))))
+        t1, t2 = int(rng.integers(0, 60)), int(rng.integers(0, 60))
+        a, b, c = segs
+        assert cat(cat(a, t1, b), t2, c) == cat(a, t1, cat(b, t2, c))
+
+
+# ----------------------------------------------------------------------------- instance data
+
+@pytest.mark.parametrize("seed", range(12))
+def test_theta_and_neighbour_lists(seed):
+    I = gen.tiny(20_000 + seed, has_tw=seed % 2, theta=[None, 3, 1][seed % 3])
+    ref = Ref(I)
+    st = ref.stats()
+    assert st["Theta"] == T0.theta_norm(I)
+    nbr, ln = ref.neighbours()
+    py = T0.neighbour_lists(I)
+    for u in range(I.n_depots, I.N):
+        k = u - I.n_depots
+        assert list(nbr[k * I.theta:k * I.theta + ln[k]]) == py[u]
+
+
+def test_neighbour_lists_match_stable_argsort_without_windows():
+    I = gen.config1()
+    nbr, ln = Ref(I).neighbours()
+    cust = np.arange(I.n_depots, I.N)
+    for k, u in enumerate(cust):
+        row = I.c[u, cust].astype(np.int64)
+        order = cust[np.argsort(row, kind="stable")]
+        order = order[order != u][:I.theta]
+        assert list(nbr[k * I.theta:k * I.theta + ln[k]]) == list(order)
+
+
+@pytest.mark.parametrize("which", ["config2", "config4_0", "config4_7"])
+def test_generator_reference_plan_is_feasible(which):
+    """Windows are centred on a reference plan with no time warp and no duration excess,
+    except on single-customer routes whose direct round trip already exceeds Dmax
+    (such a customer is infeasible in every solution; the penalties carry it)."""
+    I = gen.config2() if which == "config2" else gen.config4_instance(int(which.split("_")[1]))
+    routes = gen.reference_plan(I)
+    ref = Ref(I)
+    for r in routes:
+        a, xs, b = r
+        F, terms = ref.cost(Solution([r]))
+        if len(xs) == 1 and int(I.t[a, xs[0]]) + int(I.s[xs[0]]) + int(I.t[xs[0], a]) > I.Dmax:
+            continue
+        assert terms[1] == 0 and terms[3] == 0, r
+    served = sorted(x for _, xs, _ in routes for x in xs)
+    assert served == list(range(I.n_depots, I.N))
+
+
+# ----------------------------------------------------------------------------- move deltas vs brute force
+
+def _cases():
+    out = []
+    for seed in range(40):
+        has_tw = seed % 2
+        open_r = int(seed % 5 == 3)
+        theta = None if seed % 3 else 3
+        Dmax = 40 if (seed % 7 == 1 and not has_tw) else -1
+        out.append((seed, has_tw, open_r, theta, Dmax))
+    return out
+
+
+@pytest.mark.parametrize("seed,has_tw,open_r,theta,Dmax", _cases())
+def test_every_move_delta_equals_recomputed_F(seed, has_tw, open_r, theta, Dmax):
+    """For every evaluated move: the neighbour built by Python list surgery equals the
+    oracle's applied neighbour, and dF (and each term delta) equals the whole-solution
+    recomputation F(m(S)) - F(S) with brute-force time warp."""
+    I = gen.tiny(30_000 + seed, has_tw=has_tw, open_routes=open_r, theta=theta, Dmax=Dmax)
+    ref = Ref(I)
+    nbr, ln = ref.neighbours()
+    nbrs = {u: list(nbr[(u - I.n_depots) * I.theta:(u - I.n_depots) * I.theta + ln[u - I.n_depots]])
+            for u in range(I.n_depots, I.N)}
+    sols = [gen.random_solution(I, seed), gen.start_solution(I, seed)]
+    for sol in sols:
+        routes = [(a, list(xs), -1 if I.open_routes else b) for (a, xs, b) in sol.routes]
+        F0, t0 = T0.F_terms(I, routes)
+        assert ref.cost(sol)[0] == F0
+        moves = ref.eval(sol, ALL_FAMILIES)
+        got = {int(m["id"]): m for m in moves}
+        assert len(got) == len(moves), "duplicate ids"
+        py = T0.all_neighbours(I, routes, ALL_FAMILIES, nbrs)
+        non_drep = {k for k in got if (k >> 56) != 9}
+        assert non_drep == set(py), (sorted(non_drep ^ set(py))[:5])
+        for mid, nb in py.items():
+            m = got[mid]
+            F1, t1 = T0.F_terms(I, nb)
+            assert int(m["dF"]) == F1 - F0, (hex(mid),)
+            assert int(m["dD"]) == t1["D"] - t0["D"]
+            assert int(m["dTW"]) == t1["TW"] - t0["TW"]
+            assert int(m["dLX"]) == t1["LX"] - t0["LX"]
+            assert int(m["dDX"]) == t1["DX"] - t0["DX"]
+            assert int(m["dV4"]) == (t1["CL"] + t1["FX"]) - (t0["CL"] + t0["FX"])
+            assert canonical(nb) != canonical(routes), "no-op move"
+            assert canonical(ref.apply_ids(sol, [mid]).routes) == canonical(nb)
+            kind, a, b = mid >> 56, (mid >> 24) & 0xFFFFFF, mid & 0xFFFFFF
+            if kind <= 7:  # pair moves create the arc a -> b
+                assert any(xs[k] == a and xs[k + 1] == b for (_, xs, _) in nb for k in range(len(xs) - 1))
+        # Depot-Replace: the best of the surviving cases, ties to the lower case
+        cands = T0.drep_candidates(I, routes)
+        drep = {k: m for k, m in got.items() if (k >> 56) == 9}
+        assert len(drep) == len(cands)
+        for (ri, d), cases in cands.items():
+            best = None
+            for cs, nr in cases:
+                nb = T0.apply_change(routes, {ri: nr})
+                key = (T0.F_terms(I, nb)[0] - F0, cs)
+                best = key if best is None or key < best else best
+            a = routes[ri][1][0]
+            hits = [m for k, m in drep.items() if ((k >> 24) & 0xFFFFFF) == a and (k & 0xFFFFFF) == d]
+            assert len(hits) == 1
+            assert int(hits[0]["dF"]) == best[0]
+            assert (int(hits[0]["id"]) >> 48) & 0xFF == best[1]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_closed_form_move_counts(seed):
+    I = gen.tiny(40_000 + seed, has_tw=seed % 2, open_routes=int(seed % 4 == 1))
+    ref = Ref(I)
+    nbr, ln = ref.neighbours()
+    sol = gen.random_solution(I, seed)
+    moves = ref.eval(sol, ALL_FAMILIES)
+    kinds = (moves["id"] >> np.uint64(56)).astype(int)
+    nd = I.n_depots
+    L = [len(xs) for _, xs, _ in sol.routes]
+    assert (kinds == 8).sum() == nd * sum(x - 1 for x in L)
+    if I.open_routes:
+        exp_drep = (nd - 1) * len(L)
+    else:
+        exp_drep = sum(nd - 1 if a == b else nd for (a, _, b) in sol.routes)
+    assert (kinds == 9).sum() == exp_drep
+    loc = {x: (ri, k) for ri, (_, xs, _) in enumerate(sol.routes) for k, x in enumerate(xs)}
+    pairs = [(u, int(v)) for u in range(nd, I.N)
+             for v in nbr[(u - nd) * I.theta:(u - nd) * I.theta + ln[u - nd]]]
+    succ_same = sum(1 for u, v in pairs if loc[u][0] == loc[v][0] and loc[v][1] == loc[u][1] + 1)
+    assert (kinds == 0).sum() == len(pairs) - succ_same
+    assert (kinds == 6).sum() == sum(1 for u, v in pairs if loc[u][0] != loc[v][0])
+    if not I.has_tw:
+        assert (kinds == 7).sum() == sum(1 for u, v in pairs if loc[u][0] == loc[v][0] and loc[u][1] < loc[v][1] - 1)
+    else:
+        assert (kinds == 7).sum() == 0
+
+
+# ----------------------------------------------------------------------------- selection
+
+@pytest.mark.parametrize("seed", range(25))
+def test_selection_is_the_greedy_and_is_maximal(seed):
+    I = gen.tiny(50_000 + seed, has_tw=seed % 2, nc=8)
+    ref = Ref(I)
+    sol = gen.start_solution(I, seed) if seed % 2 else gen.random_solution(I, seed)
+    for fam in [ALL_FAMILIES, 1, 2, 4, 16, 32]:
+        moves = ref.eval(sol, fam)
+        for lo in (0, 1):
+            _, ids, dFs, _ = ref.step(sol, fam, lo)
+            sel = T0.greedy(moves, bool(lo))
+            assert [int(moves[k]["id"]) for k in sel] == [int(x) for x in ids]
+            if lo or not sel:
+                continue
+            used = {}
+            for k in sel:
+                for r in moves[k]["res"]:
+                    if r != -1:
+                        assert r not in used, "selected moves share a resource"
+                        used[int(r)] = k
+            lead = sel[0]
+            for k in range(len(moves)):
+                m = moves[k]
+                elig = m["dD"] < 0 and m["dTW"] == 0 and m["dLX"] == 0 and m["dDX"] == 0 and m["dV4"] == 0
+                if not elig or k in sel:
+                    continue
+                blockers = [used[int(r)] for r in m["res"] if r != -1 and int(r) in used]
+                assert blockers, "an eligible follower was left out without a conflict"
+                keyk = (int(m["dF"]), int(m["id"]))
+                assert any(b == lead or (int(moves[b]["dF"]), int(moves[b]["id"])) < keyk for b in blockers)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_multimove_F_is_additive(seed):
+    """F(S') = F(S) + sum of the selected deltas (Section 3.2.5 conflict rule + depot counts)."""
+    I = gen.tiny(60_000 + seed, has_tw=seed % 2, nc=8)
+    ref = Ref(I)
+    sol = gen.random_solution(I, seed)
+    for fam in [ALL_FAMILIES, 1, 2, 4, 8, 16, 32]:
+        new, ids, dFs, _ = ref.step(sol, fam, 0)
+        routes = [(a, list(xs), -1 if I.open_routes else b) for (a, xs, b) in sol.routes]
+        nroutes = [(a, list(xs), -1 if I.open_routes else b) for (a, xs, b) in new.routes]
+        assert T0.F_terms(I, nroutes)[0] == T0.F_terms(I, routes)[0] + int(dFs.sum())
+
+
+# ----------------------------------------------------------------------------- local search
+
+def test_family_order_is_a_permutation():
+    seen = set()
+    for p in range(50):
+        for has_tw in (0, 1):
+            f = family_order(has_tw, 12345, p)
+            assert sorted(f) == ([0, 1, 2, 4, 5] if has_tw else [0, 1, 2, 3, 4, 5])
+            seen.add(tuple(f))
+    assert len(seen) > 20
+
+
+@pytest.mark.parametrize("seed,mode,leader_only", [(s, m, lo) for s in range(8) for m in (0, 1) for lo in (0, 1)])
+def test_local_search_reaches_certified_optimum(seed, mode, leader_only):
+    """Algorithm 2 stops only when no family has an improving move (full oracle certificate)."""
+    I = gen.tiny(70_000 + seed, has_tw=seed % 2, open_routes=int(seed % 3 == 2))
+    ref = Ref(I)
+    sol = gen.random_solution(I, seed)
+    out, st = ref.local_search([sol], mode=mode, seed=99, leader_only=leader_only)
+    moves = ref.eval(out[0], ALL_FAMILIES)
+    assert len(moves) == 0 or int(moves["dF"].min()) >= 0
+    assert st[0]["F"] == ref.cost(out[0])[0] <= ref.cost(sol)[0]
+    served = sorted(x for _, xs, _ in out[0].routes for x in xs)
+    assert served == list(range(I.n_depots, I.N))
+
+
+def _two_opt_gain(c, tour):
+    """Independent O(n^2) scan over customer-anchored 2-opt moves of a closed tour."""
+    best = 0
+    n = len(tour)
+    for i in range(1, n - 2):
+        for j in range(i + 2, n - 1):
+            a, b, x, y = tour[i], tour[i + 1], tour[j], tour[j + 1]
+            best = min(best, c[a, x] + c[b, y] - c[a, b] - c[x, y])
+    return best
+
+
+def _relocate_gain(c, tour):
+    """Independent scan: move a customer in front of another customer."""
+    best = 0
+    base = sum(int(c[tour[k], tour[k + 1]]) for k in range(len(tour) - 1))
+    for i in range(1, len(tour) - 1):
+        rest = tour[:i] + tour[i + 1:]
+        for p in range(1, len(rest) - 1):
+            if p == i:
+                continue
+            t2 = rest[:p] + [tour[i]] + rest[p:]
+            best = min(best, sum(int(c[t2[k], t2[k + 1]]) for k in range(len(t2) - 1)) - base)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tsp_special_case_is_two_opt_and_relocate_optimal(seed):
+    """One depot, one vehicle, no binding capacity, no windows: the LS optimum is a tour
+    with no improving 2-opt and no improving one-node relocation."""
+    rng = np.random.default_rng(seed)
+    n = 14
+    xy = rng.integers(0, 100, size=(n + 1, 2))
+    I = _inst(xy, [0] + [1] * n, 10 * n, 1, NV=1)
+    tour = [int(x) for x in rng.permutation(np.arange(1, n + 1))]
+    ref = Ref(I)
+    out, _ = ref.local_search([Solution([(0, tour, 0)])], seed=seed)
+    assert len(out[0].routes) == 1
+    a, xs, b = out[0].routes[0]
+    t = [a] + xs + [b]
+    c = I.c.astype(np.int64)
+    assert _two_opt_gain(c, t) == 0
+    assert _relocate_gain(c, t) == 0
+
+
+def test_config1_optimum_has_closed_routes():
+    """With w_depot = Theta and no windows, every route ends at its start depot at the optimum."""
+    I = gen.config1()
+    ref = Ref(I)
+    out, st = ref.local_search([gen.start_solution(I, 101_000)], seed=7)
+    for a, xs, b in out[0].routes:
+        assert a == b
+    F, terms = ref.cost(out[0])
+    assert terms[4] == 0 and terms[5] == 0
