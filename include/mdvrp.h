@@ -1,0 +1,244 @@
+/*
+ * mdvrp.h -- C-ABI of libmdvrp: the data-parallel local-search hot path of a
+ * hybrid method for multi-depot vehicle routing (MDVRP, MDVRPTW, MDOVRP),
+ * after Lei & Hao, "A GPU-Accelerated Hybrid Method for a Class of
+ * Multi-Depot Vehicle Routing Problems".
+ *
+ * Problem (paper Section 1): depots have ids [0, n_depots), customers
+ * [n_depots, N); c and t are N*N travel distances and times; q demand, s
+ * service time, [e, l] time window; Q vehicle capacity, NV vehicles per
+ * depot, Dmax route-duration limit. A solution is a set of routes
+ * S = {R_1..R_M}, each (start depot, customers..., end depot).
+ *
+ * Conventions
+ *  - Every call returns an mdvrp_status; no call throws, prints or aborts.
+ *  - Device memory is owned by the caller. Objects carve their device state
+ *    out of a caller-provided workspace sized by the matching *_query call;
+ *    the library never allocates device memory. Handles are host objects
+ *    owned by the library and released by the *_destroy calls.
+ *  - Calls are ordered on the caller's HIP stream (passed as void*, a
+ *    hipStream_t; NULL = the default stream). Calls that return host values
+ *    synchronise that stream.
+ *  - A handle is not thread-safe.
+ *  - All numbers are int32 fixed point; sums and objective values are int64.
+ *    Every result is bit-exact and deterministic.
+ */
+#ifndef MDVRP_H
+#define MDVRP_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mdvrp_status;
+#define MDVRP_OK 0
+#define MDVRP_EINVAL (-1)  /* invalid argument or input data */
+#define MDVRP_ERANGE (-2)  /* input outside the int32-safe range of the fixed-point arithmetic */
+#define MDVRP_ENOSPC (-3)  /* workspace or output too small (required size written where stated) */
+#define MDVRP_EDEVICE (-4) /* HIP runtime error; text from mdvrp_last_error() */
+#define MDVRP_ESTATE (-5)  /* call out of order, or an internal invariant failed */
+
+/* Operator families (bits of a family mask), paper Section 3.2.2. */
+#define MDVRP_FAM_RELOCATE 0x01u      /* Relocate of 1- and 2-node sequences */
+#define MDVRP_FAM_SWAP 0x02u          /* Swap of 1- and 2-node sequences */
+#define MDVRP_FAM_2OPT_STAR 0x04u     /* 2-opt* between two routes */
+#define MDVRP_FAM_2OPT 0x08u          /* 2-opt inside a route (instances without time windows) */
+#define MDVRP_FAM_DEPOT_INSERT 0x10u  /* Depot-Insert (Fig. 1a) */
+#define MDVRP_FAM_DEPOT_REPLACE 0x20u /* Depot-Replace (Fig. 1b) */
+#define MDVRP_FAM_ALL 0x3Fu
+
+/* Move kinds encoded in a move id: id = kind<<56 | variant<<48 | a<<24 | b. */
+#define MDVRP_KIND_REL1 0
+#define MDVRP_KIND_REL2 1
+#define MDVRP_KIND_SWP11 2
+#define MDVRP_KIND_SWP21 3
+#define MDVRP_KIND_SWP12 4
+#define MDVRP_KIND_SWP22 5
+#define MDVRP_KIND_2OPT_STAR 6
+#define MDVRP_KIND_2OPT 7
+#define MDVRP_KIND_DEPOT_INSERT 8
+#define MDVRP_KIND_DEPOT_REPLACE 9
+
+typedef struct mdvrp_instance mdvrp_instance;
+typedef struct mdvrp_batch mdvrp_batch;
+
+/* Instance description. Array pointers are DEVICE pointers owned by the caller
+ * and must stay valid for the lifetime of the instance handle. */
+typedef struct {
+  int32_t n_depots, n_customers; /* ids: depots [0,n_depots), customers [n_depots,N) */
+  const int32_t *c, *t;          /* N*N row-major, >= 0; t may alias c. Without time
+                                    windows c (and t) must be symmetric. */
+  const int32_t *q, *s, *e, *l;  /* length N; depots: q = s = 0, [e,l] = departure/return window */
+  int32_t Q, NV, Dmax;           /* capacity (> 0), vehicles per depot (>= 0), Dmax < 0: no limit */
+  int32_t open_routes;           /* 1 = MDOVRP: routes have no arrival depot */
+  int32_t has_tw;                /* 1 = time windows (time warp), 2-opt and reversed blocks off */
+  int32_t theta;                 /* granular list size, 1..128 (>= n_customers-1: full) */
+  int32_t w_tw, w_load, w_dur;   /* fixed penalty weights (>= 0) */
+  int32_t w_depot;               /* < 0: 2*max c - min c (the Eq. A.1 normaliser) */
+} mdvrp_instance_desc;
+
+/* ------------------------------------------------------------------------- instance */
+
+/* Validate the scalar fields of desc and the HOST arrays q, s, e, l (desc's
+ * pointers taken as host pointers; c and t are not read). Pure CPU; usable
+ * without a GPU. Checks: n_depots >= 1, n_customers >= 1, N <= 65535,
+ * Q > 0, NV >= 0, 1 <= theta <= 128, weights >= 0, q >= 0, s >= 0, e <= l,
+ * depots q = s = 0. */
+mdvrp_status mdvrp_validate_instance_host(const mdvrp_instance_desc* desc);
+
+/* Device workspace needed by mdvrp_instance_create. */
+mdvrp_status mdvrp_instance_workspace_query(const mdvrp_instance_desc* desc, size_t* bytes);
+
+/* Preprocess an instance (once): matrix statistics, the Theta normaliser and
+ * Gamma of Eq. A.1 / Eq. 3, time-window arc pruning and the theta-nearest
+ * granular lists by eta (Section 3.2.3). Synchronises the stream.
+ * Errors: EINVAL (bad desc or data, asymmetric c/t without time windows,
+ * negative entries), ERANGE (distances too large for the fixed-point keys:
+ * 8*max c >= 2^25), ENOSPC (ws_bytes too small), EDEVICE. */
+mdvrp_status mdvrp_instance_create(const mdvrp_instance_desc* desc, void* ws, size_t ws_bytes, void* stream,
+                                   mdvrp_instance** out);
+
+/* Host copy of instance facts: [0] Theta, [1] Gamma numerator, [2] Gamma
+ * denominator, [3] effective depot weight, [4] max c, [5] min c, [6] max t,
+ * [7] longest route (customers) the int32 segment arithmetic accepts. */
+mdvrp_status mdvrp_instance_info(const mdvrp_instance* inst, int64_t out[8]);
+
+/* Copy the granular lists into DEVICE arrays: nbr[(u - n_depots)*theta + k]
+ * (customer ids ranked by eta, -1 padding; n_customers*theta entries) and
+ * nbr_len[u - n_depots] (n_customers entries). */
+mdvrp_status mdvrp_instance_copy_lists(const mdvrp_instance* inst, int32_t* nbr, int32_t* nbr_len, void* stream);
+
+void mdvrp_instance_destroy(mdvrp_instance* inst);
+
+/* ------------------------------------------------------------------------- batches */
+
+/* A batch is a set of units; unit k holds one solution of instance
+ * insts[unit_inst[k]] (host arrays). All instances of a batch must agree on
+ * has_tw and open_routes. */
+mdvrp_status mdvrp_batch_workspace_query(const mdvrp_instance* const* insts, int32_t n_inst,
+                                         const int32_t* unit_inst, int32_t n_units, size_t* bytes);
+mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, int32_t n_inst, const int32_t* unit_inst,
+                                int32_t n_units, void* ws, size_t ws_bytes, void* stream, mdvrp_batch** out);
+void mdvrp_batch_destroy(mdvrp_batch* batch);
+
+/* Validate solutions given in HOST arrays (layout of mdvrp_solutions_load) for
+ * units whose instances are described by descs[unit_inst[k]] (only the scalar
+ * fields of descs are read). Pure CPU. Checks, per unit: offsets increase;
+ * every customer appears exactly once; routes are non-empty; starts (and
+ * ends unless open) are depots; at most n_customers routes. */
+mdvrp_status mdvrp_validate_solutions_host(const mdvrp_instance_desc* descs, int32_t n_inst, const int32_t* unit_inst,
+                                           int32_t n_units, const int32_t* route_nodes,
+                                           const int32_t* route_offsets, const int32_t* route_start,
+                                           const int32_t* route_end, const int32_t* unit_route_offsets);
+
+/* Load one solution per unit from DEVICE arrays: routes of unit k are
+ * unit_route_offsets[k] .. unit_route_offsets[k+1]-1 (n_units+1 entries);
+ * route r visits route_nodes[route_offsets[r] .. route_offsets[r+1]-1]
+ * between depots route_start[r] and route_end[r] (ignored when open).
+ * The arrays are copied to the host and validated first (EINVAL), then the
+ * route-major segment state is built on the device. Synchronises. */
+mdvrp_status mdvrp_solutions_load(mdvrp_batch* batch, const int32_t* route_nodes, const int32_t* route_offsets,
+                                  const int32_t* route_start, const int32_t* route_end,
+                                  const int32_t* unit_route_offsets, int32_t n_routes_total,
+                                  int32_t n_nodes_total, void* stream);
+
+/* Export the current solutions to DEVICE arrays. Unit k writes its customers to
+ * route_nodes[node_base_k ..] with node_base_k = sum of n_customers of units < k,
+ * and its routes to entries [route_base_k ..] of route_offsets (values index
+ * route_nodes; one extra closing entry), route_start and route_end, with
+ * route_base_k = sum over units < k of (n_customers + 1); route_count[k] = number
+ * of routes. Capacity: sum(n_customers) nodes, sum(n_customers + 1) routes. */
+mdvrp_status mdvrp_solutions_export(const mdvrp_batch* batch, int32_t* route_nodes, int32_t* route_offsets,
+                                    int32_t* route_start, int32_t* route_end, int32_t* route_count, void* stream);
+
+/* F(S) of every unit recomputed from the current routes (Eq. A.1 with fixed
+ * weights): F[k] and terms[k*6 + 0..5] = D, TW, LX, DX, CL, FX (DEVICE arrays,
+ * terms nullable). */
+mdvrp_status mdvrp_batch_cost(mdvrp_batch* batch, int64_t* F, int64_t* terms, void* stream);
+
+/* Host copy of per-unit counters, 8 per unit: running F, evaluated moves,
+ * passes, steps, moves applied, error bits, active flag, moves selected in
+ * the latest step. Synchronises. */
+mdvrp_status mdvrp_batch_state(const mdvrp_batch* batch, int64_t* out_host);
+
+/* ------------------------------------------------------------------------- hot path */
+
+/* One dense record per evaluated move (debug output). */
+typedef struct {
+  int64_t dF, dD, dTW, dLX, dDX, dV4; /* deltas of F, distance, time warp, load excess,
+                                         duration excess, closure + fleet excess */
+  uint64_t id;                        /* kind<<56 | variant<<48 | a<<24 | b */
+  int32_t unit;
+  int32_t res[3];                     /* route slot r, or n_customers + depot, or -1 */
+} mdvrp_dense_rec;
+
+#define MDVRP_EVAL_DENSE 0x1u
+
+/* Evaluate, in parallel, the penalised delta of every move of the families in
+ * family_mask for every active unit (paper Sections 3.2.1-3.2.4: Eq. A.1
+ * deltas over the granular neighbourhood). The result (per-unit leader
+ * candidate and follower candidates) stays in the batch for
+ * mdvrp_select_multimove. With MDVRP_EVAL_DENSE every evaluated move is
+ * also written to dense (DEVICE array of dense_cap records; *dense_count, a
+ * DEVICE counter the caller zeroes, receives the total, which may exceed
+ * dense_cap). Families without moves in an instance (2-opt with time
+ * windows) are ignored. */
+mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* batch, uint32_t family_mask, uint32_t flags,
+                                      mdvrp_dense_rec* dense, int64_t dense_cap,
+                                      unsigned long long* dense_count, void* stream);
+
+/* Leader-follower selection (Section 3.2.5) over the last evaluation: the
+ * leader is the move with the smallest (dF, id) and is taken when dF < 0;
+ * followers (dD < 0 and no change of any penalty term) are taken in ascending
+ * (dF, id) order when they share no route and no depot vehicle count with a
+ * move already taken. leader_only = 1 keeps the leader alone. The selection
+ * is prepared for mdvrp_apply_moves. When sel_ids is non-NULL, unit k's
+ * selected ids and deltas are written to sel_ids / sel_dF [k*sel_cap ..] and
+ * their count to sel_count[k] (DEVICE arrays). */
+mdvrp_status mdvrp_select_multimove(mdvrp_batch* batch, uint32_t family_mask, int32_t leader_only,
+                                    uint64_t* sel_ids, int64_t* sel_dF, int32_t* sel_count, int32_t sel_cap,
+                                    void* stream);
+
+/* Apply the selected moves of every unit (they are route-disjoint, so the
+ * order does not matter), delete emptied routes and rebuild the segment
+ * state of the changed routes. */
+mdvrp_status mdvrp_apply_moves(mdvrp_batch* batch, void* stream);
+
+#define MDVRP_LS_PASSES 0 /* Algorithm 2: per pass, every family in a seeded random order */
+#define MDVRP_LS_UNION 1  /* every step evaluates all families together */
+
+typedef struct {
+  int32_t mode;        /* MDVRP_LS_PASSES or MDVRP_LS_UNION */
+  int32_t leader_only; /* 1 = single-move steps (the paper's ETGA-S) */
+  int32_t max_passes;  /* search depth delta; 0 = until a local optimum */
+  int32_t poll_every;  /* passes between host convergence checks (>= 1) */
+  uint64_t seed;       /* family order of pass p: Fisher-Yates with SplitMix64(seed ^ p) */
+} mdvrp_ls_options;
+
+typedef struct {
+  int64_t passes, steps, moves_applied, evaluated, F;
+  int32_t converged, err;
+} mdvrp_ls_stats;
+
+/* Local search to a local optimum for every unit of the batch (Algorithm 2 with
+ * the multi-move step). A unit stops when a full pass applies nothing. stats
+ * (HOST array of n_units, nullable) receives per-unit results. Synchronises.
+ * Errors: ERANGE when a route grew beyond the int32-safe length, ENOSPC on
+ * internal capacity overflow, EDEVICE. */
+mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* batch, const mdvrp_ls_options* opts,
+                                           mdvrp_ls_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------- misc */
+
+const char* mdvrp_status_string(mdvrp_status s);
+/* Text of the last error raised on the calling thread. */
+const char* mdvrp_last_error(void);
+/* Family order of pass p as the library computes it (host; for checks). */
+int32_t mdvrp_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,684 @@
+// api.hip -- C-ABI entry points of libmdvrp (host side).
+//
+// Validation runs on the host before any launch; device state is carved out of
+// caller-provided workspaces; launches go to the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mdvrp.h"
+#include "kernels.h"
+
+using namespace mdvrp;
+
+namespace {
+
+thread_local std::string g_err;
+
+mdvrp_status fail(mdvrp_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+mdvrp_status fail(mdvrp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(MDVRP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Bump allocator over a caller workspace; with base == nullptr it only measures.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <class T> T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += sizeof(T) * std::max<size_t>(n, 1);
+    return p;
+  }
+};
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+constexpr int kMaxTheta = 128;
+constexpr int kTileItems = 256;
+constexpr int kRebuildMaxTiles = 128;
+
+}  // namespace
+
+struct mdvrp_instance {
+  mdvrp_instance_desc d;
+  int N = 0;
+  int32_t* nbr = nullptr;
+  int32_t* nbr_len = nullptr;
+  int64_t* partial = nullptr;
+  int64_t* stats = nullptr;
+  int nblocks = 0;
+  int64_t Theta = 0, gnum = 1, gden = 1, w_depot = 0, max_c = 0, min_c = 0, max_t = 0;
+  int64_t len_guard = 0;
+  int t_is_c = 0;
+};
+
+struct mdvrp_batch {
+  std::vector<const mdvrp_instance*> inst;
+  std::vector<int> unit_inst;
+  int n_units = 0;
+  int has_tw = 0, open = 0;
+  std::vector<UnitDesc> h_units;
+  UnitDesc* d_units = nullptr;
+  int32_t* d_tile_off[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<int32_t> h_tile_off[4];
+  int32_t* d_active = nullptr;
+  int32_t* d_node_base = nullptr;
+  int32_t* d_route_base = nullptr;
+  int64_t* d_state = nullptr;
+  LaunchCtx ctx(void* stream) const {
+    LaunchCtx L;
+    L.stream = S(stream);
+    L.units = d_units;
+    L.n_units = n_units;
+    L.has_tw = has_tw;
+    L.open = open;
+    for (int k = 0; k < 4; ++k) {
+      L.tile_off[k] = d_tile_off[k];
+      L.tiles[k] = h_tile_off[k].empty() ? 0 : h_tile_off[k].back();
+    }
+    L.active_count = d_active;
+    return L;
+  }
+};
+
+// ============================================================================ misc
+
+extern "C" const char* mdvrp_status_string(mdvrp_status s) {
+  switch (s) {
+    case MDVRP_OK: return "ok";
+    case MDVRP_EINVAL: return "invalid argument";
+    case MDVRP_ERANGE: return "value out of the fixed-point range";
+    case MDVRP_ENOSPC: return "insufficient space";
+    case MDVRP_EDEVICE: return "device error";
+    case MDVRP_ESTATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* mdvrp_last_error(void) { return g_err.c_str(); }
+
+// SplitMix64 (Steele, Lea and Flood, 2014).
+static uint64_t splitmix64_next(uint64_t* st) {
+  uint64_t z = (*st += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Algorithm 2 visits the operator families in a random order each pass.
+extern "C" int32_t mdvrp_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam) {
+  int n = 0;
+  fam[n++] = FAM_REL;
+  fam[n++] = FAM_SWP;
+  fam[n++] = FAM_X2;
+  if (!has_tw) fam[n++] = FAM_2OPT;
+  fam[n++] = FAM_DINS;
+  fam[n++] = FAM_DREP;
+  uint64_t st = seed ^ (uint64_t)pass;
+  for (int i = n - 1; i >= 1; --i) {
+    const int j = (int)(splitmix64_next(&st) % (uint64_t)(i + 1));
+    std::swap(fam[i], fam[j]);
+  }
+  return n;
+}
+
+// ============================================================================ instance
+
+static mdvrp_status check_scalars(const mdvrp_instance_desc* d) {
+  if (!d) return fail(MDVRP_EINVAL, "null descriptor");
+  if (d->n_depots < 1 || d->n_customers < 1) return fail(MDVRP_EINVAL, "need at least one depot and one customer");
+  if ((int64_t)d->n_depots + d->n_customers > 65535) return fail(MDVRP_EINVAL, "N = %d exceeds 65535",
+                                                                  d->n_depots + d->n_customers);
+  if (d->Q <= 0) return fail(MDVRP_EINVAL, "Q must be > 0");
+  if (d->NV < 0) return fail(MDVRP_EINVAL, "NV must be >= 0");
+  if (d->theta < 1 || d->theta > kMaxTheta) return fail(MDVRP_EINVAL, "theta must be in [1, %d]", kMaxTheta);
+  if (d->w_tw < 0 || d->w_load < 0 || d->w_dur < 0) return fail(MDVRP_EINVAL, "penalty weights must be >= 0");
+  if (d->open_routes != 0 && d->open_routes != 1) return fail(MDVRP_EINVAL, "open_routes must be 0 or 1");
+  if (d->has_tw != 0 && d->has_tw != 1) return fail(MDVRP_EINVAL, "has_tw must be 0 or 1");
+  if (!d->c || !d->t || !d->q || !d->s || !d->e || !d->l) return fail(MDVRP_EINVAL, "null array");
+  return MDVRP_OK;
+}
+
+static mdvrp_status check_node_arrays(const mdvrp_instance_desc* d, const int32_t* q, const int32_t* s,
+                                      const int32_t* e, const int32_t* l) {
+  const int n = d->n_depots + d->n_customers;
+  for (int x = 0; x < n; ++x) {
+    if (q[x] < 0 || s[x] < 0) return fail(MDVRP_EINVAL, "node %d: negative demand or service", x);
+    if (e[x] > l[x]) return fail(MDVRP_EINVAL, "node %d: e > l", x);
+    if (x < d->n_depots && (q[x] != 0 || s[x] != 0)) return fail(MDVRP_EINVAL, "depot %d: q and s must be 0", x);
+  }
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_validate_instance_host(const mdvrp_instance_desc* d) {
+  mdvrp_status st = check_scalars(d);
+  if (st) return st;
+  return check_node_arrays(d, d->q, d->s, d->e, d->l);
+}
+
+static void carve_instance(Carve& cv, const mdvrp_instance_desc* d, mdvrp_instance* I) {
+  const int n = d->n_depots + d->n_customers;
+  const int nb = inst_stats_blocks(n);
+  int32_t* nbr = cv.take<int32_t>((size_t)d->n_customers * d->theta);
+  int32_t* nbl = cv.take<int32_t>(d->n_customers);
+  int64_t* part = cv.take<int64_t>((size_t)nb * 8);
+  int64_t* st = cv.take<int64_t>(8);
+  if (I) {
+    I->nbr = nbr;
+    I->nbr_len = nbl;
+    I->partial = part;
+    I->stats = st;
+    I->nblocks = nb;
+  }
+}
+
+extern "C" mdvrp_status mdvrp_instance_workspace_query(const mdvrp_instance_desc* d, size_t* bytes) {
+  mdvrp_status st = check_scalars(d);
+  if (st) return st;
+  if (!bytes) return fail(MDVRP_EINVAL, "null bytes");
+  Carve cv(nullptr);
+  carve_instance(cv, d, nullptr);
+  *bytes = cv.off + 256;
+  return MDVRP_OK;
+}
+
+static int64_t gcd64(int64_t a, int64_t b) {
+  a = a < 0 ? -a : a;
+  b = b < 0 ? -b : b;
+  while (b) { const int64_t r = a % b; a = b; b = r; }
+  return a;
+}
+
+extern "C" mdvrp_status mdvrp_instance_create(const mdvrp_instance_desc* d, void* ws, size_t ws_bytes, void* stream,
+                                              mdvrp_instance** out) {
+  mdvrp_status st = check_scalars(d);
+  if (st) return st;
+  if (!out) return fail(MDVRP_EINVAL, "null out");
+  size_t need = 0;
+  mdvrp_instance_workspace_query(d, &need);
+  if (!ws || ws_bytes < need) return fail(MDVRP_ENOSPC, "instance workspace needs %zu bytes", need);
+  const int n = d->n_depots + d->n_customers;
+  std::vector<int32_t> q(n), s(n), e(n), l(n);
+  HIP_TRY(hipMemcpyAsync(q.data(), d->q, sizeof(int32_t) * n, hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipMemcpyAsync(s.data(), d->s, sizeof(int32_t) * n, hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipMemcpyAsync(e.data(), d->e, sizeof(int32_t) * n, hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipMemcpyAsync(l.data(), d->l, sizeof(int32_t) * n, hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipStreamSynchronize(S(stream)));
+  st = check_node_arrays(d, q.data(), s.data(), e.data(), l.data());
+  if (st) return st;
+
+  mdvrp_instance* I = new mdvrp_instance();
+  I->d = *d;
+  I->N = n;
+  I->t_is_c = d->t == d->c;
+  Carve cv(ws);
+  carve_instance(cv, d, I);
+  launch_inst_stats(S(stream), d->c, d->t, n, I->partial, I->nblocks);
+  launch_inst_stats_final(S(stream), I->partial, I->nblocks, I->stats);
+  int64_t h[8];
+  hipError_t he = hipMemcpyAsync(h, I->stats, sizeof h, hipMemcpyDeviceToHost, S(stream));
+  if (he == hipSuccess) he = hipStreamSynchronize(S(stream));
+  if (he != hipSuccess) {
+    delete I;
+    return fail(MDVRP_EDEVICE, "instance statistics: %s", hipGetErrorString(he));
+  }
+  if (h[5]) { delete I; return fail(MDVRP_EINVAL, "negative entries in c or t"); }
+  if (!d->has_tw && h[4]) { delete I; return fail(MDVRP_EINVAL, "c/t must be symmetric without time windows"); }
+  I->max_c = n > 1 ? h[0] : 0;
+  I->min_c = n > 1 ? h[1] : 0;
+  I->max_t = n > 1 ? h[6] : 0;
+  I->Theta = 2 * I->max_c - I->min_c;
+  const int64_t g = gcd64(h[2], h[3]);
+  I->gnum = (h[3] == 0 || g == 0) ? 1 : h[2] / g;
+  I->gden = (h[3] == 0 || g == 0) ? 1 : h[3] / g;
+  I->w_depot = d->w_depot < 0 ? I->Theta : d->w_depot;
+  // fixed-point guards
+  if (8 * I->max_c >= (1ll << 25)) { delete I; return fail(MDVRP_ERANGE, "8*max c = %lld >= 2^25", (long long)(8 * I->max_c)); }
+  int64_t smax = 0, emin = INT32_MAX, lmax = 0;
+  for (int x = 0; x < n; ++x) {
+    smax = std::max<int64_t>(smax, s[x]);
+    emin = std::min<int64_t>(emin, e[x]);
+    lmax = std::max<int64_t>(lmax, l[x]);
+  }
+  int64_t per_node = std::max<int64_t>(I->max_c, I->max_t + smax);
+  if (d->has_tw) per_node = I->max_c + I->max_t + smax + (lmax - emin);
+  I->len_guard = per_node > 0 ? ((int64_t)INT32_MAX / (2 * per_node)) - 2 : (int64_t)d->n_customers;
+  if (I->len_guard < 2) { delete I; return fail(MDVRP_ERANGE, "values too large for int32 route segments"); }
+  if (d->has_tw) {
+    const __int128 span = (__int128)(lmax - emin) + smax + I->max_t;
+    const __int128 kmax = (__int128)I->max_c * I->gden + (__int128)I->gnum * 11 * span;
+    if (kmax >= ((__int128)1 << 62)) { delete I; return fail(MDVRP_ERANGE, "granular-list keys overflow int64"); }
+  }
+  launch_nbr_lists(S(stream), d->c, d->t, d->s, d->e, d->l, d->n_depots, d->n_customers, d->theta, d->has_tw,
+                   I->gnum, I->gden, I->nbr, I->nbr_len);
+  he = hipStreamSynchronize(S(stream));
+  if (he == hipSuccess) he = hipGetLastError();
+  if (he != hipSuccess) {
+    delete I;
+    return fail(MDVRP_EDEVICE, "granular lists: %s", hipGetErrorString(he));
+  }
+  *out = I;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_instance_info(const mdvrp_instance* I, int64_t out[8]) {
+  if (!I || !out) return fail(MDVRP_EINVAL, "null argument");
+  out[0] = I->Theta; out[1] = I->gnum; out[2] = I->gden; out[3] = I->w_depot;
+  out[4] = I->max_c; out[5] = I->min_c; out[6] = I->max_t; out[7] = I->len_guard;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_instance_copy_lists(const mdvrp_instance* I, int32_t* nbr, int32_t* len, void* stream) {
+  if (!I || !nbr || !len) return fail(MDVRP_EINVAL, "null argument");
+  HIP_TRY(hipMemcpyAsync(nbr, I->nbr, sizeof(int32_t) * (size_t)I->d.n_customers * I->d.theta,
+                         hipMemcpyDeviceToDevice, S(stream)));
+  HIP_TRY(hipMemcpyAsync(len, I->nbr_len, sizeof(int32_t) * I->d.n_customers, hipMemcpyDeviceToDevice, S(stream)));
+  return MDVRP_OK;
+}
+
+extern "C" void mdvrp_instance_destroy(mdvrp_instance* I) { delete I; }
+
+// ============================================================================ batch
+
+namespace {
+
+struct UnitSizes {
+  int nd, nc, n, R, cap, theta;
+  int64_t cand_cap;
+  int tiles[4];
+};
+
+UnitSizes unit_sizes(const mdvrp_instance* I) {
+  UnitSizes z;
+  z.nd = I->d.n_depots;
+  z.nc = I->d.n_customers;
+  z.n = z.nd + z.nc;
+  z.R = z.nc;
+  z.cap = 3 * z.nc + 64;
+  z.theta = I->d.theta;
+  z.cand_cap = 3ll * z.nc * z.theta + 2ll * z.nc * z.nd + 64;
+  z.tiles[0] = (int)(((int64_t)z.nc * z.theta + kTileItems - 1) / kTileItems);
+  z.tiles[1] = (int)(((int64_t)z.nc * z.nd + kTileItems - 1) / kTileItems);
+  z.tiles[2] = z.tiles[1];
+  z.tiles[3] = std::min(kRebuildMaxTiles, (z.R + 3) / 4);
+  return z;
+}
+
+// Per-unit device state; with base == nullptr only the size is measured.
+void carve_unit(Carve& cv, const mdvrp_instance* I, int has_tw, UnitDesc* U) {
+  const UnitSizes z = unit_sizes(I);
+  const size_t seg = has_tw ? sizeof(SegTW) : sizeof(SegNT);
+  UnitDesc u{};
+  u.rt = cv.take<int32_t>(z.n);
+  u.pos = cv.take<int32_t>(z.n);
+  u.r_len = cv.take<int32_t>(z.R);
+  u.r_start = cv.take<int32_t>(z.R);
+  u.r_end = cv.take<int32_t>(z.R);
+  u.r_off[0] = cv.take<int32_t>(z.R);
+  u.r_off[1] = cv.take<int32_t>(z.R);
+  u.r_tot = cv.take<int4>(z.R);
+  u.r_cost = cv.take<int64_t>(z.R);
+  for (int b = 0; b < 2; ++b) {
+    u.fw[b] = cv.take<char>(seg * z.cap);
+    u.bw[b] = cv.take<char>(seg * z.cap);
+  }
+  u.ndep = cv.take<int32_t>(z.nd);
+  u.ctl = cv.take<UnitCtl>(1);
+  u.cand_key = cv.take<uint64_t>(z.cand_cap);
+  u.cand_id = cv.take<uint64_t>(z.cand_cap);
+  u.cand_res = cv.take<int4>(z.cand_cap);
+  u.cand_alive = cv.take<uint8_t>(z.cand_cap);
+  u.resmin = cv.take<uint64_t>(z.R + z.nd);
+  u.taken = cv.take<int32_t>(z.R + z.nd);
+  u.dirty = cv.take<int32_t>(z.R);
+  u.plan_n = cv.take<int32_t>(z.R);
+  u.plan_se = cv.take<int32_t>(2 * (size_t)z.R);
+  u.plan_pc = cv.take<int4>((size_t)z.R * kMaxPieces);
+  u.slot_list = cv.take<int32_t>(z.R);
+  u.sel_id = cv.take<uint64_t>(z.R + 1);
+  u.sel_dF = cv.take<int64_t>(z.R + 1);
+  u.wg_best = cv.take<MoveRec>((size_t)z.tiles[0] + z.tiles[1] + z.tiles[2]);
+  if (U) *U = u;
+}
+
+mdvrp_status check_batch_args(const mdvrp_instance* const* insts, int32_t n_inst, const int32_t* unit_inst,
+                              int32_t n_units) {
+  if (!insts || n_inst < 1 || !unit_inst || n_units < 1) return fail(MDVRP_EINVAL, "empty batch");
+  for (int k = 0; k < n_inst; ++k)
+    if (!insts[k]) return fail(MDVRP_EINVAL, "null instance %d", k);
+  for (int k = 0; k < n_units; ++k)
+    if (unit_inst[k] < 0 || unit_inst[k] >= n_inst) return fail(MDVRP_EINVAL, "unit %d: bad instance index", k);
+  for (int k = 1; k < n_inst; ++k)
+    if (insts[k]->d.has_tw != insts[0]->d.has_tw || insts[k]->d.open_routes != insts[0]->d.open_routes)
+      return fail(MDVRP_EINVAL, "instances of a batch must agree on has_tw and open_routes");
+  return MDVRP_OK;
+}
+
+void carve_batch(Carve& cv, const mdvrp_instance* const* insts, const int32_t* unit_inst, int32_t n_units,
+                 mdvrp_batch* B) {
+  const int has_tw = insts[0]->d.has_tw;
+  UnitDesc* du = cv.take<UnitDesc>(n_units);
+  int32_t* to[4];
+  for (int k = 0; k < 4; ++k) to[k] = cv.take<int32_t>(n_units + 1);
+  int32_t* act = cv.take<int32_t>(1);
+  int32_t* nb = cv.take<int32_t>(n_units);
+  int32_t* rb = cv.take<int32_t>(n_units);
+  int64_t* stt = cv.take<int64_t>((size_t)n_units * 8);
+  if (B) {
+    B->d_units = du;
+    for (int k = 0; k < 4; ++k) B->d_tile_off[k] = to[k];
+    B->d_active = act;
+    B->d_node_base = nb;
+    B->d_route_base = rb;
+    B->d_state = stt;
+    B->h_units.resize(n_units);
+  }
+  for (int k = 0; k < n_units; ++k) carve_unit(cv, insts[unit_inst[k]], has_tw, B ? &B->h_units[k] : nullptr);
+}
+
+}  // namespace
+
+extern "C" mdvrp_status mdvrp_batch_workspace_query(const mdvrp_instance* const* insts, int32_t n_inst,
+                                                    const int32_t* unit_inst, int32_t n_units, size_t* bytes) {
+  mdvrp_status st = check_batch_args(insts, n_inst, unit_inst, n_units);
+  if (st) return st;
+  if (!bytes) return fail(MDVRP_EINVAL, "null bytes");
+  Carve cv(nullptr);
+  carve_batch(cv, insts, unit_inst, n_units, nullptr);
+  *bytes = cv.off + 256;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, int32_t n_inst,
+                                           const int32_t* unit_inst, int32_t n_units, void* ws, size_t ws_bytes,
+                                           void* stream, mdvrp_batch** out) {
+  mdvrp_status st = check_batch_args(insts, n_inst, unit_inst, n_units);
+  if (st) return st;
+  if (!out) return fail(MDVRP_EINVAL, "null out");
+  size_t need = 0;
+  mdvrp_batch_workspace_query(insts, n_inst, unit_inst, n_units, &need);
+  if (!ws || ws_bytes < need) return fail(MDVRP_ENOSPC, "batch workspace needs %zu bytes", need);
+  mdvrp_batch* B = new mdvrp_batch();
+  B->inst.assign(insts, insts + n_inst);
+  B->unit_inst.assign(unit_inst, unit_inst + n_units);
+  B->n_units = n_units;
+  B->has_tw = insts[0]->d.has_tw;
+  B->open = insts[0]->d.open_routes;
+  Carve cv(ws);
+  carve_batch(cv, insts, unit_inst, n_units, B);
+  for (int k = 0; k < 4; ++k) B->h_tile_off[k].assign(1, 0);
+  std::vector<int32_t> nbase(n_units), rbase(n_units);
+  int32_t nacc = 0, racc = 0;
+  for (int k = 0; k < n_units; ++k) {
+    const mdvrp_instance* I = insts[unit_inst[k]];
+    const UnitSizes z = unit_sizes(I);
+    UnitDesc& u = B->h_units[k];
+    u.c = I->d.c; u.t = I->d.t; u.q = I->d.q; u.s = I->d.s; u.e = I->d.e; u.l = I->d.l;
+    u.nbr = I->nbr; u.nbr_len = I->nbr_len;
+    u.nd = z.nd; u.nc = z.nc; u.n = z.n; u.theta = z.theta;
+    u.Q = I->d.Q; u.NV = I->d.NV; u.Dmax = I->d.Dmax;
+    u.w_tw = I->d.w_tw; u.w_load = I->d.w_load; u.w_dur = I->d.w_dur;
+    u.w_depot = I->w_depot;
+    u.R = z.R; u.cap = z.cap; u.t_is_c = I->t_is_c;
+    u.cand_cap = (int32_t)std::min<int64_t>(z.cand_cap, INT32_MAX);
+    u.len_guard = (int32_t)std::min<int64_t>(I->len_guard, INT32_MAX);
+    u.tile_base[0] = 0;
+    u.tile_base[1] = z.tiles[0];
+    u.tile_base[2] = z.tiles[0] + z.tiles[1];
+    u.tile_base[3] = z.tiles[0] + z.tiles[1] + z.tiles[2];
+    u.key_shift = 38;
+    for (int c = 0; c < 4; ++c) B->h_tile_off[c].push_back(B->h_tile_off[c].back() + z.tiles[c]);
+    nbase[k] = nacc;
+    rbase[k] = racc;
+    nacc += z.nc;
+    racc += z.nc + 1;
+  }
+  hipStream_t s = S(stream);
+  hipError_t he = hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * n_units, hipMemcpyHostToDevice, s);
+  for (int c = 0; c < 4 && he == hipSuccess; ++c)
+    he = hipMemcpyAsync(B->d_tile_off[c], B->h_tile_off[c].data(), sizeof(int32_t) * (n_units + 1),
+                        hipMemcpyHostToDevice, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(B->d_node_base, nbase.data(), sizeof(int32_t) * n_units, hipMemcpyHostToDevice, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(B->d_route_base, rbase.data(), sizeof(int32_t) * n_units, hipMemcpyHostToDevice, s);
+  for (int k = 0; k < n_units && he == hipSuccess; ++k) {
+    const UnitDesc& u = B->h_units[k];
+    he = hipMemsetAsync(u.ctl, 0, sizeof(UnitCtl), s);
+    if (he == hipSuccess) he = hipMemsetAsync(u.taken, 0, sizeof(int32_t) * (u.R + u.nd), s);
+    if (he == hipSuccess) he = hipMemsetAsync(u.dirty, 0, sizeof(int32_t) * u.R, s);
+    if (he == hipSuccess) he = hipMemsetAsync(u.r_len, 0, sizeof(int32_t) * u.R, s);
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) {
+    delete B;
+    return fail(MDVRP_EDEVICE, "batch create: %s", hipGetErrorString(he));
+  }
+  *out = B;
+  return MDVRP_OK;
+}
+
+extern "C" void mdvrp_batch_destroy(mdvrp_batch* B) { delete B; }
+
+extern "C" mdvrp_status mdvrp_validate_solutions_host(const mdvrp_instance_desc* descs, int32_t n_inst,
+                                                      const int32_t* unit_inst, int32_t n_units, const int32_t* nodes,
+                                                      const int32_t* offs, const int32_t* starts, const int32_t* ends,
+                                                      const int32_t* uro) {
+  if (!descs || !unit_inst || !nodes || !offs || !starts || !ends || !uro || n_inst < 1 || n_units < 1)
+    return fail(MDVRP_EINVAL, "null argument");
+  std::vector<int32_t> seen;
+  for (int k = 0; k < n_units; ++k) {
+    if (unit_inst[k] < 0 || unit_inst[k] >= n_inst) return fail(MDVRP_EINVAL, "unit %d: bad instance index", k);
+    const mdvrp_instance_desc& D = descs[unit_inst[k]];
+    const int nd = D.n_depots, nc = D.n_customers, n = nd + nc;
+    const int r0 = uro[k], r1 = uro[k + 1];
+    if (r1 < r0) return fail(MDVRP_EINVAL, "unit %d: decreasing route offsets", k);
+    if (r1 - r0 > nc) return fail(MDVRP_EINVAL, "unit %d: more routes than customers", k);
+    seen.assign(n, 0);
+    int count = 0;
+    for (int r = r0; r < r1; ++r) {
+      const int a = offs[r], b = offs[r + 1];
+      if (b <= a) return fail(MDVRP_EINVAL, "unit %d route %d: empty route", k, r - r0);
+      if (starts[r] < 0 || starts[r] >= nd) return fail(MDVRP_EINVAL, "unit %d route %d: start is not a depot", k, r - r0);
+      if (!D.open_routes && (ends[r] < 0 || ends[r] >= nd))
+        return fail(MDVRP_EINVAL, "unit %d route %d: end is not a depot", k, r - r0);
+      for (int p = a; p < b; ++p) {
+        const int x = nodes[p];
+        if (x < nd || x >= n) return fail(MDVRP_EINVAL, "unit %d: node %d is not a customer", k, x);
+        if (seen[x]++) return fail(MDVRP_EINVAL, "unit %d: customer %d visited twice", k, x);
+        ++count;
+      }
+    }
+    if (count != nc) return fail(MDVRP_EINVAL, "unit %d: %d of %d customers routed", k, count, nc);
+  }
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_solutions_load(mdvrp_batch* B, const int32_t* nodes, const int32_t* offs,
+                                             const int32_t* starts, const int32_t* ends, const int32_t* uro,
+                                             int32_t n_routes, int32_t n_nodes, void* stream) {
+  if (!B || !nodes || !offs || !starts || !ends || !uro) return fail(MDVRP_EINVAL, "null argument");
+  if (n_routes < 0 || n_nodes < 0) return fail(MDVRP_EINVAL, "negative sizes");
+  hipStream_t s = S(stream);
+  std::vector<int32_t> hn(std::max(n_nodes, 1)), ho(n_routes + 1), hs(std::max(n_routes, 1)),
+      he_(std::max(n_routes, 1)), hu(B->n_units + 1);
+  HIP_TRY(hipMemcpyAsync(hu.data(), uro, sizeof(int32_t) * (B->n_units + 1), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ho.data(), offs, sizeof(int32_t) * (n_routes + 1), hipMemcpyDeviceToHost, s));
+  if (n_nodes) HIP_TRY(hipMemcpyAsync(hn.data(), nodes, sizeof(int32_t) * n_nodes, hipMemcpyDeviceToHost, s));
+  if (n_routes) {
+    HIP_TRY(hipMemcpyAsync(hs.data(), starts, sizeof(int32_t) * n_routes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(he_.data(), ends, sizeof(int32_t) * n_routes, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hu[0] != 0 || hu[B->n_units] != n_routes) return fail(MDVRP_EINVAL, "unit route offsets do not span the routes");
+  if (ho[0] != 0 || ho[n_routes] != n_nodes) return fail(MDVRP_EINVAL, "route offsets do not span the nodes");
+  for (int r = 0; r < n_routes; ++r)
+    if (ho[r + 1] < ho[r]) return fail(MDVRP_EINVAL, "decreasing route offsets");
+  std::vector<mdvrp_instance_desc> descs;
+  for (const mdvrp_instance* I : B->inst) descs.push_back(I->d);
+  mdvrp_status st = mdvrp_validate_solutions_host(descs.data(), (int32_t)descs.size(), B->unit_inst.data(),
+                                                  B->n_units, hn.data(), ho.data(), hs.data(), he_.data(), hu.data());
+  if (st) return st;
+  const LaunchCtx L = B->ctx(stream);
+  launch_load(L, nodes, offs, starts, ends, uro);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_solutions_export(const mdvrp_batch* B, int32_t* nodes, int32_t* offs, int32_t* starts,
+                                               int32_t* ends, int32_t* counts, void* stream) {
+  if (!B || !nodes || !offs || !starts || !ends || !counts) return fail(MDVRP_EINVAL, "null argument");
+  const LaunchCtx L = B->ctx(stream);
+  launch_export(L, nodes, offs, starts, ends, counts, B->d_node_base, B->d_route_base);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_batch_cost(mdvrp_batch* B, int64_t* F, int64_t* terms, void* stream) {
+  if (!B || !F) return fail(MDVRP_EINVAL, "null argument");
+  launch_cost(B->ctx(stream), F, terms);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+static mdvrp_status batch_state(const mdvrp_batch* B, int64_t* out, void* stream) {
+  const LaunchCtx L = B->ctx(stream);
+  launch_state_export(L, B->d_state);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, B->d_state, sizeof(int64_t) * 8 * B->n_units, hipMemcpyDeviceToHost, L.stream));
+  HIP_TRY(hipStreamSynchronize(L.stream));
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_batch_state(const mdvrp_batch* B, int64_t* out) {
+  if (!B || !out) return fail(MDVRP_EINVAL, "null argument");
+  HIP_TRY(hipDeviceSynchronize());
+  return batch_state(B, out, nullptr);
+}
+
+// ============================================================================ hot path
+
+__global__ static void k_step_begin(const UnitDesc* units, int n_units) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_units) {
+    units[i].ctl->n_cand = 0;
+    units[i].ctl->last_eval = 0;
+    units[i].ctl->active = 1;
+  }
+}
+
+extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, uint32_t flags,
+                                                 mdvrp_dense_rec* dense, int64_t dense_cap,
+                                                 unsigned long long* dense_count, void* stream) {
+  if (!B) return fail(MDVRP_EINVAL, "null batch");
+  if (fam & ~MDVRP_FAM_ALL) return fail(MDVRP_EINVAL, "unknown family bits");
+  if ((flags & MDVRP_EVAL_DENSE) && (!dense || !dense_count || dense_cap < 0))
+    return fail(MDVRP_EINVAL, "dense output needs a buffer and a counter");
+  static_assert(sizeof(mdvrp_dense_rec) == sizeof(DenseRec), "dense record layout");
+  const LaunchCtx L = B->ctx(stream);
+  hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  DenseOut D{(DenseRec*)dense, dense_count, dense_cap};
+  launch_eval(L, fam, (flags & MDVRP_EVAL_DENSE) ? &D : nullptr);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_select_multimove(mdvrp_batch* B, uint32_t fam, int32_t leader_only, uint64_t* sel_ids,
+                                               int64_t* sel_dF, int32_t* sel_count, int32_t sel_cap, void* stream) {
+  if (!B) return fail(MDVRP_EINVAL, "null batch");
+  if (sel_ids && (!sel_dF || !sel_count || sel_cap < 1)) return fail(MDVRP_EINVAL, "selection output incomplete");
+  const LaunchCtx L = B->ctx(stream);
+  launch_select(L, fam, leader_only ? 1 : 0);
+  if (sel_ids) launch_sel_export(L, sel_ids, sel_dF, sel_count, sel_cap);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_apply_moves(mdvrp_batch* B, void* stream) {
+  if (!B) return fail(MDVRP_EINVAL, "null batch");
+  launch_rebuild(B->ctx(stream));
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+static mdvrp_status check_unit_errors(mdvrp_batch* B, std::vector<int64_t>& st, void* stream) {
+  st.resize((size_t)B->n_units * 8);
+  mdvrp_status s = batch_state(B, st.data(), stream);
+  if (s) return s;
+  for (int k = 0; k < B->n_units; ++k) {
+    const int64_t e = st[(size_t)k * 8 + 5];
+    if (e & 4) return fail(MDVRP_ERANGE, "unit %d: a route exceeded the int32-safe length", k);
+    if (e & 3) return fail(MDVRP_ENOSPC, "unit %d: internal capacity exceeded (bits %lld)", k, (long long)e);
+    if (e) return fail(MDVRP_ESTATE, "unit %d: internal invariant failed (bits %lld)", k, (long long)e);
+  }
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvrp_ls_options* o,
+                                                      mdvrp_ls_stats* stats, void* stream) {
+  if (!B || !o) return fail(MDVRP_EINVAL, "null argument");
+  if (o->mode != MDVRP_LS_PASSES && o->mode != MDVRP_LS_UNION) return fail(MDVRP_EINVAL, "unknown mode");
+  if (o->max_passes < 0) return fail(MDVRP_EINVAL, "max_passes must be >= 0");
+  const int poll = std::max(1, o->poll_every);
+  const LaunchCtx L = B->ctx(stream);
+  hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  int32_t active = B->n_units;
+  for (int64_t p = 0; o->max_passes == 0 || p < o->max_passes; ++p) {
+    launch_pass_begin(L);
+    int32_t fam[6];
+    int nf;
+    if (o->mode == MDVRP_LS_PASSES) {
+      nf = mdvrp_family_order(B->has_tw, o->seed, p, fam);
+    } else {
+      nf = 1;
+    }
+    for (int k = 0; k < nf; ++k) {
+      const uint32_t mask = o->mode == MDVRP_LS_PASSES ? (1u << fam[k]) : MDVRP_FAM_ALL;
+      launch_eval(L, mask, nullptr);
+      launch_select(L, mask, o->leader_only ? 1 : 0);
+      launch_rebuild(L);
+    }
+    launch_pass_end(L);
+    HIP_TRY(hipGetLastError());
+    if ((p + 1) % poll == 0) {
+      HIP_TRY(hipMemcpyAsync(&active, B->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, L.stream));
+      HIP_TRY(hipStreamSynchronize(L.stream));
+      if (active == 0) break;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(L.stream));
+  launch_cost(L, nullptr, nullptr);
+  std::vector<int64_t> st;
+  mdvrp_status s = check_unit_errors(B, st, stream);
+  if (stats) {
+    for (int k = 0; k < B->n_units; ++k) {
+      const int64_t* x = &st[(size_t)k * 8];
+      stats[k].F = x[0];
+      stats[k].evaluated = x[1];
+      stats[k].passes = x[2];
+      stats[k].steps = x[3];
+      stats[k].moves_applied = x[4];
+      stats[k].err = (int32_t)x[5];
+      stats[k].converged = x[6] ? 0 : 1;
+    }
+  }
+  return s;
+}

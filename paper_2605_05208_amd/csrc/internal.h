@@ -1,0 +1,498 @@
+// internal.h -- device-side data layout and shared device code of libmdvrp.
+//
+// Solution state of one unit (= one solution of one instance) lives in HBM as
+//   * node-indexed arrays rt[x] (route slot) and pos[x] (1..L in the route);
+//   * a route table over slots 0..R-1 (R = number of customers, the most
+//     non-empty routes a solution can have);
+//   * a flat, route-major position array per buffer (double-buffered):
+//     route r occupies positions off[r] .. off[r]+L+1 (0 = start depot,
+//     1..L customers, L+1 = end depot; open routes leave L+1 unused).
+//     Each position holds the forward segment fw (positions 0..k of its
+//     route) and the backward segment bw (positions k..end), both in
+//     array-of-structs form so that one random access touches one line.
+// Segments follow the sequence-concatenation evaluation the paper adopts
+// (Section 3.2.2): distance C and load Q are plain sums; with time windows,
+// duration D, time warp TW, earliest start E and latest start L combine by
+// Vidal's concatenation, which is associative, so prefixes are wave scans.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mdvrp {
+
+constexpr int kMaxPieces = 5;
+constexpr int kPairKindSlots = 14;  // kind/variant slots of one (u, v) anchor
+constexpr int64_t kNoMove = INT64_MAX;
+
+enum Kind { REL1 = 0, REL2 = 1, SWP11 = 2, SWP21 = 3, SWP12 = 4, SWP22 = 5, X2 = 6, TWOOPT = 7,
+            DINS = 8, DREP = 9 };
+enum Family { FAM_REL = 0, FAM_SWP = 1, FAM_X2 = 2, FAM_2OPT = 3, FAM_DINS = 4, FAM_DREP = 5 };
+
+// Segment without time windows: distance, load, duration (travel + service).
+struct alignas(16) SegNT {
+  int32_t C, Q, D, node;
+};
+// Segment with time windows; aux = travel time to the next position.
+struct alignas(32) SegTW {
+  int32_t C, Q, D, TW, E, L, node, aux;
+};
+
+// One move record: full key (dF, id), distance delta, follower flag, resources.
+struct MoveRec {
+  int64_t dF;
+  uint64_t id;
+  int32_t dD;
+  int32_t elig;
+  int32_t res[3];
+  int32_t pad;
+};
+
+// Dense debug record (every evaluated move).
+struct DenseRec {
+  int64_t dF, dD, dTW, dLX, dDX, dV4;
+  uint64_t id;
+  int32_t unit;
+  int32_t res[3];
+};
+
+// Per-unit control block.
+struct UnitCtl {
+  int32_t cur;           // buffer holding the current solution
+  int32_t active;        // 0 once a pass applied nothing
+  int32_t pass_applied;  // a step of this pass applied a move
+  int32_t n_sel;         // moves selected in the current step
+  int32_t n_cand;        // follower candidates appended by the evaluation
+  int32_t epoch;         // step counter used to tag resources
+  int32_t err;           // sticky error bits (1 = candidate overflow, 2 = slot overflow, 4 = length guard)
+  int32_t n_slots_alive;
+  int64_t F;             // running objective (sum of applied deltas)
+  int64_t evaluated;
+  int64_t passes, steps, moves_applied;
+  int64_t last_eval;     // evaluated moves of the latest step
+  MoveRec leader;
+};
+
+struct UnitDesc {
+  // instance
+  const int32_t *c, *t, *q, *s, *e, *l;
+  const int32_t *nbr, *nbr_len;
+  int32_t nd, nc, n, theta;
+  int32_t Q, NV, Dmax, w_tw, w_load, w_dur;
+  int64_t w_depot;
+  int32_t R, cap, t_is_c, pad0;
+  // solution state
+  int32_t *rt, *pos;
+  int32_t *r_len, *r_start, *r_end;
+  int32_t *r_off[2];
+  int4* r_tot;      // {C, Q, D, TW} of every route
+  int64_t* r_cost;  // penalised route cost
+  void* fw[2];
+  void* bw[2];
+  int32_t* ndep;
+  UnitCtl* ctl;
+  // step scratch
+  uint64_t* cand_key;
+  uint64_t* cand_id;
+  int4* cand_res;
+  uint8_t* cand_alive;
+  int32_t cand_cap, len_guard;
+  uint64_t* resmin;   // [R + nd]
+  int32_t* taken;     // [R + nd] epoch tags
+  int32_t* dirty;     // [R] epoch tags
+  int32_t* plan_n;    // [R] number of pieces of a rebuilt route (0 = deleted)
+  int32_t* plan_se;   // [2R] start, end depot of a rebuilt route
+  int4* plan_pc;      // [R * kMaxPieces] {slot, from, to, rev}
+  int32_t* slot_list; // [R] alive slots in flat order (current buffer)
+  uint64_t* sel_id;   // [R]
+  int64_t* sel_dF;    // [R]
+  MoveRec* wg_best;   // [tiles of this unit]
+  int32_t tile_base[4];  // first tile of each item class (pairs, dins, drep, end)
+  int32_t key_shift;     // bit position of dD in the packed follower key
+  int32_t pad1;
+};
+
+// ---------------------------------------------------------------------------- segment algebra
+
+__device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
+__device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
+
+__device__ __forceinline__ SegNT cat(const SegNT& a, int32_t cab, int32_t tab, const SegNT& b) {
+  SegNT r;
+  r.C = a.C + cab + b.C;
+  r.Q = a.Q + b.Q;
+  r.D = a.D + tab + b.D;
+  r.node = b.node;
+  return r;
+}
+
+// Vidal's concatenation of two time-window segments joined by travel time tab.
+__device__ __forceinline__ SegTW cat(const SegTW& a, int32_t cab, int32_t tab, const SegTW& b) {
+  int32_t delta = a.D - a.TW + tab;
+  int32_t wait = imax(b.E - delta - a.L, 0);
+  int32_t warp = imax(a.E + delta - b.L, 0);
+  SegTW r;
+  r.C = a.C + cab + b.C;
+  r.Q = a.Q + b.Q;
+  r.D = a.D + b.D + tab + wait;
+  r.TW = a.TW + b.TW + warp;
+  r.E = imax(b.E - delta, a.E) - wait;
+  r.L = imin(b.L - delta, a.L) + warp;
+  r.node = b.node;
+  r.aux = b.aux;
+  return r;
+}
+
+template <class SEG> __device__ __forceinline__ SEG node_seg(const UnitDesc& U, int x);
+template <> __device__ __forceinline__ SegNT node_seg<SegNT>(const UnitDesc& U, int x) {
+  SegNT r;
+  r.C = 0; r.Q = U.q[x]; r.D = U.s[x]; r.node = x;
+  return r;
+}
+template <> __device__ __forceinline__ SegTW node_seg<SegTW>(const UnitDesc& U, int x) {
+  SegTW r;
+  r.C = 0; r.Q = U.q[x]; r.D = U.s[x]; r.TW = 0; r.E = U.e[x]; r.L = U.l[x]; r.node = x; r.aux = 0;
+  return r;
+}
+
+__device__ __forceinline__ int32_t seg_tw(const SegNT&) { return 0; }
+__device__ __forceinline__ int32_t seg_tw(const SegTW& s) { return s.TW; }
+
+__device__ __forceinline__ int32_t arc_c(const UnitDesc& U, int a, int b) {
+  return U.c[(int64_t)a * U.n + b];
+}
+__device__ __forceinline__ int32_t arc_t(const UnitDesc& U, int a, int b) {
+  return U.t_is_c ? U.c[(int64_t)a * U.n + b] : U.t[(int64_t)a * U.n + b];
+}
+
+// Penalised cost of a complete route from its total segment (fixed-weight Eq. A.1 terms).
+struct RouteTerms {
+  int64_t cost;
+  int32_t C, TW, LX, DX;
+};
+template <class SEG>
+__device__ __forceinline__ RouteTerms route_terms(const UnitDesc& U, const SEG& s) {
+  RouteTerms r;
+  r.C = s.C;
+  r.TW = seg_tw(s);
+  r.LX = imax(s.Q - U.Q, 0);
+  r.DX = U.Dmax >= 0 ? imax(s.D - U.Dmax, 0) : 0;
+  r.cost = (int64_t)r.C + (int64_t)U.w_tw * r.TW + (int64_t)U.w_load * r.LX + (int64_t)U.w_dur * r.DX;
+  return r;
+}
+
+// ---------------------------------------------------------------------------- move recipes
+//
+// A move replaces one or two routes by one or two new routes, each described
+// as start depot + up to five pieces (customer position ranges of the current
+// routes, possibly reversed) + end depot. The same recipe drives the
+// evaluation (cost of the new routes from segments) and the apply step
+// (materialising the new routes).
+
+struct Piece {
+  int8_t src;   // which context route (0 = A, 1 = B)
+  int8_t rev;
+  int16_t pad;
+  int32_t from, to;  // inclusive customer positions (1..L)
+};
+
+struct RouteCtx {
+  int32_t slot, off, L, start, end;
+};
+
+struct Recipe {
+  int32_t nnew;        // new routes (1 or 2)
+  int32_t nold;        // old routes replaced (1 or 2), context order
+  int32_t fresh;       // 1: new route 1 goes to a free slot (Depot-Insert)
+  int32_t st[2], en[2];
+  int32_t np[2];
+  Piece pc[2][kMaxPieces];
+};
+
+__device__ __forceinline__ void rc_add(Recipe& R, int w, int src, int from, int to, int rev) {
+  if (from > to) return;
+  Piece& p = R.pc[w][R.np[w]++];
+  p.src = (int8_t)src;
+  p.rev = (int8_t)rev;
+  p.pad = 0;
+  p.from = from;
+  p.to = to;
+}
+
+// Relocate: block [xa, xb] of A (placed reversed when xrev) goes in front of position pv of B.
+__device__ __forceinline__ void rc_rel(Recipe& R, const RouteCtx& A, const RouteCtx& B, bool intra, int xa,
+                                       int xb, int xrev, int pv) {
+  R.np[0] = R.np[1] = 0;
+  R.fresh = 0;
+  R.st[0] = A.start; R.en[0] = A.end;
+  if (!intra) {
+    R.nnew = R.nold = 2;
+    rc_add(R, 0, 0, 1, xa - 1, 0);
+    rc_add(R, 0, 0, xb + 1, A.L, 0);
+    R.st[1] = B.start; R.en[1] = B.end;
+    rc_add(R, 1, 1, 1, pv - 1, 0);
+    rc_add(R, 1, 0, xa, xb, xrev);
+    rc_add(R, 1, 1, pv, B.L, 0);
+  } else {
+    R.nnew = R.nold = 1;
+    if (pv < xa) {
+      rc_add(R, 0, 0, 1, pv - 1, 0);
+      rc_add(R, 0, 0, xa, xb, xrev);
+      rc_add(R, 0, 0, pv, xa - 1, 0);
+      rc_add(R, 0, 0, xb + 1, A.L, 0);
+    } else {
+      rc_add(R, 0, 0, 1, xa - 1, 0);
+      rc_add(R, 0, 0, xb + 1, pv - 1, 0);
+      rc_add(R, 0, 0, xa, xb, xrev);
+      rc_add(R, 0, 0, pv, A.L, 0);
+    }
+  }
+}
+
+// Swap: block X = [xa, xb] of A goes to Y's place, block Y = [ya, yb] of B to X's place.
+__device__ __forceinline__ void rc_swp(Recipe& R, const RouteCtx& A, const RouteCtx& B, bool intra, int xa,
+                                       int xb, int xrev, int ya, int yb, int yrev) {
+  R.np[0] = R.np[1] = 0;
+  R.fresh = 0;
+  R.st[0] = A.start; R.en[0] = A.end;
+  if (!intra) {
+    R.nnew = R.nold = 2;
+    rc_add(R, 0, 0, 1, xa - 1, 0);
+    rc_add(R, 0, 1, ya, yb, yrev);
+    rc_add(R, 0, 0, xb + 1, A.L, 0);
+    R.st[1] = B.start; R.en[1] = B.end;
+    rc_add(R, 1, 1, 1, ya - 1, 0);
+    rc_add(R, 1, 0, xa, xb, xrev);
+    rc_add(R, 1, 1, yb + 1, B.L, 0);
+  } else {
+    R.nnew = R.nold = 1;
+    if (xa < ya) {
+      rc_add(R, 0, 0, 1, xa - 1, 0);
+      rc_add(R, 0, 0, ya, yb, yrev);
+      rc_add(R, 0, 0, xb + 1, ya - 1, 0);
+      rc_add(R, 0, 0, xa, xb, xrev);
+      rc_add(R, 0, 0, yb + 1, A.L, 0);
+    } else {
+      rc_add(R, 0, 0, 1, ya - 1, 0);
+      rc_add(R, 0, 0, xa, xb, xrev);
+      rc_add(R, 0, 0, yb + 1, xa - 1, 0);
+      rc_add(R, 0, 0, ya, yb, yrev);
+      rc_add(R, 0, 0, xb + 1, A.L, 0);
+    }
+  }
+}
+
+// X block of u for two-node kinds: o = 0 takes (p(u), u) as is; o = 1 takes (u, s(u))
+// and places it as (s(u), u). Returns false when the block does not exist.
+__device__ __forceinline__ bool x_block(const RouteCtx& A, int pu, int o, int& xa, int& xb, int& xrev) {
+  if (o == 0) {
+    if (pu < 2) return false;
+    xa = pu - 1; xb = pu; xrev = 0;
+  } else {
+    if (pu + 1 > A.L) return false;
+    xa = pu; xb = pu + 1; xrev = 1;
+  }
+  return true;
+}
+
+// Pair move anchored on u (position pu of A) and v (position pv of B); every pair
+// move creates the arc u -> v (Section 3.2.2 operators on granular lists, Section 3.2.3).
+__device__ __forceinline__ bool build_pair(int kind, int var, const RouteCtx& A, int pu, const RouteCtx& B,
+                                           int pv, bool intra, bool sym, Recipe& R) {
+  int xa, xb, xrev, ya, yb;
+  switch (kind) {
+    case REL1:
+      if (var != 0) return false;
+      if (intra && pv == pu + 1) return false;
+      rc_rel(R, A, B, intra, pu, pu, 0, pv);
+      return true;
+    case REL2:
+      if (var > 1 || (var == 1 && !sym)) return false;
+      if (!x_block(A, pu, var, xa, xb, xrev)) return false;
+      if (intra && ((pv >= xa && pv <= xb) || pv == pu + 1)) return false;
+      rc_rel(R, A, B, intra, xa, xb, xrev, pv);
+      return true;
+    case SWP11:
+      if (var != 0) return false;
+      if (pv < 2 || (intra && pv - 1 == pu)) return false;
+      rc_swp(R, A, B, intra, pu, pu, 0, pv - 1, pv - 1, 0);
+      return true;
+    case SWP21:
+      if (var > 1 || (var == 1 && !sym)) return false;
+      if (!x_block(A, pu, var, xa, xb, xrev)) return false;
+      if (pv < 2) return false;
+      ya = yb = pv - 1;
+      if (intra && ((ya >= xa && ya <= xb) || (pv >= xa && pv <= xb))) return false;
+      rc_swp(R, A, B, intra, xa, xb, xrev, ya, yb, 0);
+      return true;
+    case SWP12:
+      if (var > 1 || (var == 1 && !sym)) return false;
+      if (pv < 3) return false;
+      ya = pv - 2; yb = pv - 1;
+      if (intra && pu >= ya && pu <= yb) return false;
+      rc_swp(R, A, B, intra, pu, pu, 0, ya, yb, var);
+      return true;
+    case SWP22: {
+      if (var > 3) return false;
+      int ox = var & 1, oy = var >> 1;
+      if ((ox || oy) && !sym) return false;
+      if (!x_block(A, pu, ox, xa, xb, xrev)) return false;
+      if (pv < 3) return false;
+      ya = pv - 2; yb = pv - 1;
+      if (intra && ((ya <= xb && xa <= yb) || (pv >= xa && pv <= xb))) return false;
+      rc_swp(R, A, B, intra, xa, xb, xrev, ya, yb, oy);
+      return true;
+    }
+    case X2:
+      // 2-opt*: A' = A[..u] + B[v..] ending at B's depot, B' = B[..p(v)] + A[s(u)..] ending at A's.
+      if (var != 0 || intra) return false;
+      R.nnew = R.nold = 2;
+      R.fresh = 0;
+      R.np[0] = R.np[1] = 0;
+      R.st[0] = A.start; R.en[0] = B.end;
+      rc_add(R, 0, 0, 1, pu, 0);
+      rc_add(R, 0, 1, pv, B.L, 0);
+      R.st[1] = B.start; R.en[1] = A.end;
+      rc_add(R, 1, 1, 1, pv - 1, 0);
+      rc_add(R, 1, 0, pu + 1, A.L, 0);
+      return true;
+    case TWOOPT:
+      // 2-opt: reverse positions pu+1..pv of one route (creates u -> v and s(u) -> s(v)).
+      if (var != 0 || !intra || !sym || !(pu < pv - 1)) return false;
+      R.nnew = R.nold = 1;
+      R.fresh = 0;
+      R.np[0] = R.np[1] = 0;
+      R.st[0] = A.start; R.en[0] = A.end;
+      rc_add(R, 0, 0, 1, pu, 0);
+      rc_add(R, 0, 0, pu + 1, pv, 1);
+      rc_add(R, 0, 0, pv + 1, A.L, 0);
+      return true;
+    default:
+      return false;
+  }
+}
+
+// Depot-Insert (Fig. 1a): cut after position pu and insert depot d between the parts.
+__device__ __forceinline__ void build_dins(const RouteCtx& A, int pu, int d, bool open, Recipe& R) {
+  R.nnew = 2; R.nold = 1; R.fresh = 1;
+  R.np[0] = R.np[1] = 0;
+  R.st[0] = A.start; R.en[0] = open ? -1 : d;
+  rc_add(R, 0, 0, 1, pu, 0);
+  R.st[1] = d; R.en[1] = A.end;
+  rc_add(R, 1, 0, pu + 1, A.L, 0);
+}
+
+// Depot-Replace (Fig. 1b): case 0 departure depot, 1 arrival depot, 2 both.
+__device__ __forceinline__ void build_drep(const RouteCtx& A, int d, int cs, Recipe& R) {
+  R.nnew = 1; R.nold = 1; R.fresh = 0;
+  R.np[0] = R.np[1] = 0;
+  R.st[0] = (cs == 0 || cs == 2) ? d : A.start;
+  R.en[0] = (cs == 1 || cs == 2) ? d : A.end;
+  rc_add(R, 0, 0, 1, A.L, 0);
+}
+
+__device__ __forceinline__ uint64_t make_id(int kind, int var, int a, int b) {
+  return ((uint64_t)kind << 56) | ((uint64_t)var << 48) | ((uint64_t)a << 24) | (uint64_t)b;
+}
+
+// ---------------------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <class T> __device__ __forceinline__ T shfl_up_seg(const T& v, int off);
+template <> __device__ __forceinline__ SegNT shfl_up_seg<SegNT>(const SegNT& v, int off) {
+  SegNT r;
+  r.C = __shfl_up(v.C, off); r.Q = __shfl_up(v.Q, off); r.D = __shfl_up(v.D, off);
+  r.node = __shfl_up(v.node, off);
+  return r;
+}
+template <> __device__ __forceinline__ SegTW shfl_up_seg<SegTW>(const SegTW& v, int off) {
+  SegTW r;
+  r.C = __shfl_up(v.C, off); r.Q = __shfl_up(v.Q, off); r.D = __shfl_up(v.D, off);
+  r.TW = __shfl_up(v.TW, off); r.E = __shfl_up(v.E, off); r.L = __shfl_up(v.L, off);
+  r.node = __shfl_up(v.node, off); r.aux = __shfl_up(v.aux, off);
+  return r;
+}
+template <class T> __device__ __forceinline__ T shfl_down_seg(const T& v, int off);
+template <> __device__ __forceinline__ SegNT shfl_down_seg<SegNT>(const SegNT& v, int off) {
+  SegNT r;
+  r.C = __shfl_down(v.C, off); r.Q = __shfl_down(v.Q, off); r.D = __shfl_down(v.D, off);
+  r.node = __shfl_down(v.node, off);
+  return r;
+}
+template <> __device__ __forceinline__ SegTW shfl_down_seg<SegTW>(const SegTW& v, int off) {
+  SegTW r;
+  r.C = __shfl_down(v.C, off); r.Q = __shfl_down(v.Q, off); r.D = __shfl_down(v.D, off);
+  r.TW = __shfl_down(v.TW, off); r.E = __shfl_down(v.E, off); r.L = __shfl_down(v.L, off);
+  r.node = __shfl_down(v.node, off); r.aux = __shfl_down(v.aux, off);
+  return r;
+}
+template <class T> __device__ __forceinline__ T shfl_seg(const T& v, int src);
+template <> __device__ __forceinline__ SegNT shfl_seg<SegNT>(const SegNT& v, int src) {
+  SegNT r;
+  r.C = __shfl(v.C, src); r.Q = __shfl(v.Q, src); r.D = __shfl(v.D, src); r.node = __shfl(v.node, src);
+  return r;
+}
+template <> __device__ __forceinline__ SegTW shfl_seg<SegTW>(const SegTW& v, int src) {
+  SegTW r;
+  r.C = __shfl(v.C, src); r.Q = __shfl(v.Q, src); r.D = __shfl(v.D, src);
+  r.TW = __shfl(v.TW, src); r.E = __shfl(v.E, src); r.L = __shfl(v.L, src);
+  r.node = __shfl(v.node, src); r.aux = __shfl(v.aux, src);
+  return r;
+}
+
+// Exclusive scan of one int per thread over a block of NT threads (NT multiple of
+// 64, at most 4096); sh must hold 2*NT/64+1 ints. Returns the block total in *total.
+template <int NT>
+__device__ __forceinline__ int block_scan_excl(int v, int* sh, int* total) {
+  constexpr int NW = NT / 64;
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  int incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) sh[wave] = incl;
+  __syncthreads();
+  if (wave == 0) {
+    const int w = lane < NW ? sh[lane] : 0;
+    int wi = w;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(wi, off);
+      if (lane >= off) wi += y;
+    }
+    if (lane < NW) sh[NW + lane] = wi - w;
+    if (lane == NW - 1) sh[2 * NW] = wi;
+  }
+  __syncthreads();
+  const int r = sh[NW + wave] + incl - v;
+  *total = sh[2 * NW];
+  __syncthreads();
+  return r;
+}
+
+// Lexicographic (dF, id) order of move keys.
+__device__ __forceinline__ bool key_less(int64_t f1, uint64_t i1, int64_t f2, uint64_t i2) {
+  return f1 < f2 || (f1 == f2 && i1 < i2);
+}
+
+// Map a block index to a tile so that the tiles served by one XCD are contiguous
+// (blocks are dispatched round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+  const int nx = 8;
+  int per = nblocks / nx, rem = nblocks % nx;
+  int x = bid % nx, k = bid / nx;
+  int start = x * per + (x < rem ? x : rem);
+  return start + k;
+}
+
+// Find the unit of a tile by binary search over per-unit tile offsets.
+__device__ __forceinline__ int unit_of_tile(const int32_t* off, int n_units, int tile) {
+  int lo = 0, hi = n_units;  // off[lo] <= tile < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= tile) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace mdvrp

@@ -1,0 +1,52 @@
+// kernels.h -- host-side launch interface between the C-ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace mdvrp {
+
+struct DenseOut {
+  DenseRec* rec;
+  unsigned long long* count;
+  int64_t cap;
+};
+
+// Everything a launch needs about a batch.
+struct LaunchCtx {
+  hipStream_t stream;
+  const UnitDesc* units;    // device array [n_units]
+  int n_units;
+  int has_tw, open;
+  // item classes: 0 pairs, 1 depot-insert, 2 depot-replace, 3 route slots, 4 one block per unit
+  const int32_t* tile_off[4];  // device arrays [n_units + 1]
+  int tiles[4];
+  int32_t* active_count;       // device int
+};
+
+int eval_block_size();
+void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense);
+// Item classes an evaluation of fam_mask fills (bit 0 pairs, 1 depot-insert, 2 depot-replace).
+uint32_t eval_classes(const LaunchCtx& L, uint32_t fam_mask);
+void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only);
+void launch_rebuild(const LaunchCtx& L);
+void launch_pass_begin(const LaunchCtx& L);
+void launch_pass_end(const LaunchCtx& L);
+void launch_cost(const LaunchCtx& L, int64_t* F, int64_t* terms);
+void launch_export(const LaunchCtx& L, int32_t* nodes, int32_t* offs, int32_t* starts, int32_t* ends,
+                   int32_t* counts, const int32_t* node_base, const int32_t* route_base);
+void launch_load(const LaunchCtx& L, const int32_t* nodes, const int32_t* offs, const int32_t* starts,
+                 const int32_t* ends, const int32_t* unit_route_off);
+void launch_sel_export(const LaunchCtx& L, uint64_t* ids, int64_t* dF, int32_t* counts, int32_t cap_per_unit);
+void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][8] */);
+
+// instance preprocessing
+void launch_inst_stats(hipStream_t s, const int32_t* c, const int32_t* t, int n, int64_t* partial, int nblocks);
+int inst_stats_blocks(int n);
+void launch_inst_stats_final(hipStream_t s, const int64_t* partial, int nblocks, int64_t* out);
+void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* sv, const int32_t* ev,
+                      const int32_t* lv, int nd, int nc, int theta, int has_tw, int64_t gnum, int64_t gden,
+                      int32_t* nbr, int32_t* nbr_len);
+
+}  // namespace mdvrp

@@ -1,0 +1,193 @@
+// prep.hip -- instance preprocessing (once per instance).
+//
+// * Matrix statistics: max/min c over u != v (Theta = 2 max c - min c, the
+//   normaliser of Eq. A.1 used as the depot weight), sums of c and t (Gamma =
+//   sum c / sum t, Eq. 3), symmetry and sign checks.
+// * Granular lists (Section 3.2.3): arcs u -> v with e_u + s_u + t_uv > l_v
+//   are pruned (time windows only), the theta customers with the smallest
+//   eta_uv = c_uv + Gamma*(alpha*max(e_v - l_u - s_u - t_uv, 0) +
+//   beta*max(l_u + s_u + t_uv - l_v, 0)), alpha = 1, beta = 10, are kept,
+//   compared exactly as eta*den with Gamma = num/den; ties go to the lower id.
+//   One 256-thread block per customer streams the row in chunks of 256 and
+//   merges each chunk into a running sorted list with an LDS bitonic sort.
+#include "kernels.h"
+
+namespace mdvrp {
+
+constexpr int kStatsBlock = 256;
+// partial layout per block: max c, min c, sum c, sum t, asym flag, negative flag, max t, max s (unused)
+constexpr int kStatsFields = 8;
+
+__global__ __launch_bounds__(kStatsBlock) void k_inst_stats(const int32_t* __restrict__ c,
+                                                           const int32_t* __restrict__ t, int n,
+                                                           int64_t* __restrict__ partial) {
+  const int64_t total = (int64_t)n * n;
+  int64_t mx = INT64_MIN, mn = INT64_MAX, sc = 0, st = 0, asym = 0, neg = 0, mt = INT64_MIN;
+  for (int64_t i = (int64_t)blockIdx.x * kStatsBlock + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * kStatsBlock) {
+    const int a = (int)(i / n), b = (int)(i - (int64_t)a * n);
+    if (a == b) continue;
+    const int64_t cv = c[i], tv = t[i];
+    mx = cv > mx ? cv : mx;
+    mn = cv < mn ? cv : mn;
+    mt = tv > mt ? tv : mt;
+    sc += cv;
+    st += tv;
+    if (cv < 0 || tv < 0) neg = 1;
+    if (a < b) {
+      const int64_t j = (int64_t)b * n + a;
+      if (c[j] != cv || t[j] != tv) asym = 1;
+    }
+  }
+  __shared__ int64_t sh[kStatsFields][kStatsBlock / 64];
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t mx2 = __shfl_xor(mx, off), mn2 = __shfl_xor(mn, off), mt2 = __shfl_xor(mt, off);
+    mx = mx2 > mx ? mx2 : mx;
+    mn = mn2 < mn ? mn2 : mn;
+    mt = mt2 > mt ? mt2 : mt;
+    sc += __shfl_xor(sc, off);
+    st += __shfl_xor(st, off);
+    asym |= __shfl_xor(asym, off);
+    neg |= __shfl_xor(neg, off);
+  }
+  if (lane == 0) {
+    sh[0][w] = mx; sh[1][w] = mn; sh[2][w] = sc; sh[3][w] = st; sh[4][w] = asym; sh[5][w] = neg; sh[6][w] = mt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kStatsBlock / 64; ++k) {
+      sh[0][0] = sh[0][k] > sh[0][0] ? sh[0][k] : sh[0][0];
+      sh[1][0] = sh[1][k] < sh[1][0] ? sh[1][k] : sh[1][0];
+      sh[2][0] += sh[2][k];
+      sh[3][0] += sh[3][k];
+      sh[4][0] |= sh[4][k];
+      sh[5][0] |= sh[5][k];
+      sh[6][0] = sh[6][k] > sh[6][0] ? sh[6][k] : sh[6][0];
+    }
+    for (int f = 0; f < 7; ++f) partial[(int64_t)blockIdx.x * kStatsFields + f] = sh[f][0];
+    partial[(int64_t)blockIdx.x * kStatsFields + 7] = 0;
+  }
+}
+
+__global__ void k_inst_stats_final(const int64_t* __restrict__ partial, int nblocks, int64_t* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t r[kStatsFields] = {INT64_MIN, INT64_MAX, 0, 0, 0, 0, INT64_MIN, 0};
+  for (int b = 0; b < nblocks; ++b) {
+    const int64_t* p = partial + (int64_t)b * kStatsFields;
+    r[0] = p[0] > r[0] ? p[0] : r[0];
+    r[1] = p[1] < r[1] ? p[1] : r[1];
+    r[2] += p[2];
+    r[3] += p[3];
+    r[4] |= p[4];
+    r[5] |= p[5];
+    r[6] = p[6] > r[6] ? p[6] : r[6];
+  }
+  for (int f = 0; f < kStatsFields; ++f) out[f] = r[f];
+}
+
+int inst_stats_blocks(int n) {
+  const int64_t total = (int64_t)n * n;
+  int64_t b = (total + kStatsBlock * 16 - 1) / (kStatsBlock * 16);
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
+void launch_inst_stats(hipStream_t s, const int32_t* c, const int32_t* t, int n, int64_t* partial, int nblocks) {
+  hipLaunchKernelGGL(k_inst_stats, dim3(nblocks), dim3(kStatsBlock), 0, s, c, t, n, partial);
+}
+
+void launch_inst_stats_final(hipStream_t s, const int64_t* partial, int nblocks, int64_t* out) {
+  hipLaunchKernelGGL(k_inst_stats_final, dim3(1), dim3(64), 0, s, partial, nblocks, out);
+}
+
+// ---------------------------------------------------------------------------- granular lists
+
+constexpr int kNbrBlock = 256;
+constexpr int kNbrKeep = 128;                    // maximum theta
+constexpr int kNbrSort = 512;                    // kept list + one chunk, padded to a power of two
+
+__device__ __forceinline__ bool pair_less(int64_t ka, int va, int64_t kb, int vb) {
+  return ka < kb || (ka == kb && va < vb);
+}
+
+__global__ __launch_bounds__(kNbrBlock) void k_nbr_lists(const int32_t* __restrict__ c, const int32_t* __restrict__ t,
+                                                        const int32_t* __restrict__ sv, const int32_t* __restrict__ ev,
+                                                        const int32_t* __restrict__ lv, int nd, int nc, int theta,
+                                                        int has_tw, int64_t gnum, int64_t gden,
+                                                        int32_t* __restrict__ nbr, int32_t* __restrict__ nbr_len) {
+  __shared__ int64_t key[kNbrSort];
+  __shared__ int32_t vid[kNbrSort];
+  const int i = blockIdx.x;
+  const int n = nd + nc;
+  const int u = nd + i;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < kNbrSort; k += kNbrBlock) { key[k] = INT64_MAX; vid[k] = INT32_MAX; }
+  __syncthreads();
+  const int64_t eu = ev[u], lu = lv[u], su = sv[u];
+  for (int base = 0; base < nc; base += kNbrBlock) {
+    const int j = base + tid;
+    int64_t kk = INT64_MAX;
+    int vv = INT32_MAX;
+    if (j < nc) {
+      const int v = nd + j;
+      if (v != u) {
+        const int64_t cuv = c[(int64_t)u * n + v];
+        if (has_tw) {
+          const int64_t tuv = t[(int64_t)u * n + v];
+          const int64_t evv = ev[v], lvv = lv[v];
+          if (!(eu + su + tuv > lvv)) {
+            const int64_t early = evv - lu - su - tuv > 0 ? evv - lu - su - tuv : 0;
+            const int64_t late = lu + su + tuv - lvv > 0 ? lu + su + tuv - lvv : 0;
+            kk = cuv * gden + gnum * (early + 10 * late);
+            vv = v;
+          }
+        } else {
+          kk = cuv;
+          vv = v;
+        }
+      }
+    }
+    // skip the chunk when nothing beats the current theta-th entry
+    const int64_t thk = key[theta - 1];
+    const int thv = vid[theta - 1];
+    const bool better = vv != INT32_MAX && pair_less(kk, vv, thk, thv);
+    if (!__syncthreads_or(better)) continue;
+    key[kNbrKeep + tid] = kk;
+    vid[kNbrKeep + tid] = vv;
+    for (int k = kNbrKeep + kNbrBlock + tid; k < kNbrSort; k += kNbrBlock) { key[k] = INT64_MAX; vid[k] = INT32_MAX; }
+    for (int k = theta + tid; k < kNbrKeep; k += kNbrBlock) { key[k] = INT64_MAX; vid[k] = INT32_MAX; }
+    __syncthreads();
+    // bitonic sort of kNbrSort entries, two per thread per stage
+    for (int size = 2; size <= kNbrSort; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int x = tid; x < kNbrSort / 2; x += kNbrBlock) {
+          const int lo = 2 * x - (x & (stride - 1));
+          const int hi = lo + stride;
+          const bool up = ((lo & size) == 0);
+          const int64_t ka = key[lo], kb = key[hi];
+          const int va = vid[lo], vb = vid[hi];
+          const bool sw = up ? pair_less(kb, vb, ka, va) : pair_less(ka, va, kb, vb);
+          if (sw) { key[lo] = kb; key[hi] = ka; vid[lo] = vb; vid[hi] = va; }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  for (int k = tid; k < theta; k += kNbrBlock) nbr[(int64_t)i * theta + k] = vid[k] == INT32_MAX ? -1 : vid[k];
+  if (tid == 0) {
+    int cnt = 0;
+    for (int k = 0; k < theta; ++k) cnt += vid[k] != INT32_MAX;
+    nbr_len[i] = cnt;
+  }
+}
+
+void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* sv, const int32_t* ev,
+                      const int32_t* lv, int nd, int nc, int theta, int has_tw, int64_t gnum, int64_t gden,
+                      int32_t* nbr, int32_t* nbr_len) {
+  hipLaunchKernelGGL(k_nbr_lists, dim3(nc), dim3(kNbrBlock), 0, s, c, t, sv, ev, lv, nd, nc, theta, has_tw, gnum,
+                     gden, nbr, nbr_len);
+}
+
+}  // namespace mdvrp

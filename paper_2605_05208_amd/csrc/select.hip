@@ -1,0 +1,301 @@
+// select.hip -- leader-follower multi-move selection and the apply plan (Section 3.2.5).
+//
+// The paper takes the leader (best move by F), then scans the followers
+// (dD < 0, no penalty term changes) in ascending order and keeps each one that
+// shares no route with a move already kept. With a strict total order on keys
+// that greedy is the lexicographically first maximal independent set of the
+// conflict graph, which iterated "locally dominant" rounds reach exactly: a
+// move is taken when its key is the minimum among the live moves on every
+// resource it touches; taken resources kill the other moves; repeat.
+// Resources are route slots plus per-depot vehicle counts, so that the
+// multi-move keeps F additive.
+//
+// One 1024-thread workgroup per unit. After selection the same workgroup
+// turns each selected move into per-slot piece lists (the recipe of the
+// evaluation) and lays out the rebuilt solution's offsets.
+#include "eval_common.h"
+#include "kernels.h"
+
+namespace mdvrp {
+
+constexpr int kSelBlock = 1024;
+constexpr int kSelWaves = kSelBlock / 64;
+
+__device__ __forceinline__ int block_scan(int v, int* sh, int* total) {
+  return block_scan_excl<kSelBlock>(v, sh, total);
+}
+
+// resmin is only touched through device-scope atomics, so every access sees L2.
+__device__ __forceinline__ uint64_t ld_min(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void reset_min(uint64_t* p) {
+  __hip_atomic_store(p, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int64_t unpack_dD(uint64_t key) { return (int64_t)(key >> 38) - (1ll << 25); }
+
+template <bool OPEN>
+__device__ void plan_move(const UnitDesc& U, int cur, uint64_t id, int64_t dF, int fresh_slot, int epoch) {
+  const int kind = (int)(id >> 56), var = (int)((id >> 48) & 0xff);
+  const int a = (int)((id >> 24) & 0xffffff), b = (int)(id & 0xffffff);
+  RouteCtx rc[2];
+  Recipe R;
+  rc[0] = route_ctx(U, cur, U.rt[a]);
+  if (kind <= TWOOPT) {
+    rc[1] = route_ctx(U, cur, U.rt[b]);
+    build_pair(kind, var, rc[0], U.pos[a], rc[1], U.pos[b], rc[0].slot == rc[1].slot, /*sym=*/true, R);
+  } else if (kind == DINS) {
+    build_dins(rc[0], U.pos[a], b, OPEN, R);
+  } else {
+    build_drep(rc[0], b, var, R);
+  }
+  for (int k = 0; k < R.nold; ++k) atomicSub(&U.ndep[rc[k].start], 1);
+  for (int w = 0; w < R.nnew; ++w) {
+    const int slot = (R.fresh && w == 1) ? fresh_slot : rc[w].slot;
+    int len = 0;
+    for (int k = 0; k < R.np[w]; ++k) {
+      const Piece& p = R.pc[w][k];
+      U.plan_pc[(int64_t)slot * kMaxPieces + k] = make_int4(rc[p.src].slot, p.from, p.to, p.rev);
+      len += p.to - p.from + 1;
+    }
+    U.plan_n[slot] = R.np[w];
+    U.plan_se[2 * slot] = R.st[w];
+    U.plan_se[2 * slot + 1] = R.en[w];
+    U.dirty[slot] = epoch;
+    if (len > 0) atomicAdd(&U.ndep[R.st[w]], 1);
+    if (len > U.len_guard) atomicOr(&U.ctl->err, 4);
+  }
+  atomicAdd((unsigned long long*)&U.ctl->F, (unsigned long long)dF);
+}
+
+template <bool OPEN>
+__global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __restrict__ units, uint32_t cls_mask,
+                                                           int leader_only) {
+  const UnitDesc& U = units[blockIdx.x];
+  UnitCtl* ctl = U.ctl;
+  __shared__ int64_t shF[kSelWaves];
+  __shared__ uint64_t shI[kSelWaves];
+  __shared__ int shT[kSelWaves];
+  __shared__ int sh[2 * kSelWaves + 1];
+  __shared__ int s_nsel, s_alive, s_epoch, s_leader_tile, s_ndins;
+  if (!ctl->active) return;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int cur = ctl->cur;
+
+  // ---- leader: minimum (dF, id) over the block bests of the evaluated item classes
+  int64_t bf = kNoMove;
+  uint64_t bi = ~0ull;
+  int bt = -1;
+  for (int c = 0; c < 3; ++c) {
+    if (!(cls_mask >> c & 1)) continue;
+    for (int t = U.tile_base[c] + tid; t < U.tile_base[c + 1]; t += kSelBlock) {
+      const int64_t f = U.wg_best[t].dF;
+      const uint64_t i = U.wg_best[t].id;
+      if (key_less(f, i, bf, bi)) { bf = f; bi = i; bt = t; }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t f2 = __shfl_xor(bf, off);
+    const uint64_t i2 = __shfl_xor(bi, off);
+    const int t2 = __shfl_xor(bt, off);
+    if (key_less(f2, i2, bf, bi)) { bf = f2; bi = i2; bt = t2; }
+  }
+  if (lane == 0) { shF[wave] = bf; shI[wave] = bi; shT[wave] = bt; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < kSelWaves; ++w)
+      if (key_less(shF[w], shI[w], shF[0], shI[0])) { shF[0] = shF[w]; shI[0] = shI[w]; shT[0] = shT[w]; }
+    s_leader_tile = shT[0];
+    s_nsel = 0;
+    s_ndins = 0;
+    ctl->steps += 1;
+    if (shF[0] < 0) {
+      s_epoch = ctl->epoch + 1;
+      ctl->epoch = s_epoch;
+      ctl->leader = U.wg_best[shT[0]];
+    } else {
+      s_epoch = 0;
+      ctl->n_sel = 0;
+      ctl->n_cand = 0;
+    }
+  }
+  __syncthreads();
+  if (s_epoch == 0) return;  // no improving move: this step applies nothing
+  const int epoch = s_epoch;
+  const MoveRec lead = U.wg_best[s_leader_tile];
+  const int n_cand = imin(ctl->n_cand, U.cand_cap);
+
+  if (tid == 0) {
+    U.sel_id[0] = lead.id;
+    U.sel_dF[0] = lead.dF;
+    s_nsel = 1;
+    for (int k = 0; k < 3; ++k)
+      if (lead.res[k] >= 0) U.taken[lead.res[k]] = epoch;
+  }
+  __syncthreads();
+
+  // ---- followers: locally dominant rounds
+  if (!leader_only) {
+    for (int c = tid; c < n_cand; c += kSelBlock) {
+      const int4 r = U.cand_res[c];
+      bool live = U.cand_id[c] != lead.id;
+      live = live && !(r.x >= 0 && U.taken[r.x] == epoch) && !(r.y >= 0 && U.taken[r.y] == epoch) &&
+             !(r.z >= 0 && U.taken[r.z] == epoch);
+      U.cand_alive[c] = live ? 1 : 0;
+      if (live) {
+        if (r.x >= 0) reset_min(&U.resmin[r.x]);
+        if (r.y >= 0) reset_min(&U.resmin[r.y]);
+        if (r.z >= 0) reset_min(&U.resmin[r.z]);
+      }
+    }
+    __syncthreads();
+    for (int round = 0;; ++round) {
+      for (int c = tid; c < n_cand; c += kSelBlock) {
+        if (U.cand_alive[c] != 1) continue;
+        const int4 r = U.cand_res[c];
+        const uint64_t k = U.cand_key[c];
+        if (r.x >= 0) atomicMin((unsigned long long*)&U.resmin[r.x], (unsigned long long)k);
+        if (r.y >= 0) atomicMin((unsigned long long*)&U.resmin[r.y], (unsigned long long)k);
+        if (r.z >= 0) atomicMin((unsigned long long*)&U.resmin[r.z], (unsigned long long)k);
+      }
+      __syncthreads();
+      for (int c = tid; c < n_cand; c += kSelBlock) {
+        if (U.cand_alive[c] != 1) continue;
+        const int4 r = U.cand_res[c];
+        const uint64_t k = U.cand_key[c];
+        const bool dom = (r.x < 0 || ld_min(&U.resmin[r.x]) == k) && (r.y < 0 || ld_min(&U.resmin[r.y]) == k) &&
+                         (r.z < 0 || ld_min(&U.resmin[r.z]) == k);
+        if (dom) {
+          U.cand_alive[c] = 2;
+          const int s = atomicAdd(&s_nsel, 1);
+          U.sel_id[s] = U.cand_id[c];
+          U.sel_dF[s] = unpack_dD(k);
+          if (r.x >= 0) U.taken[r.x] = epoch;
+          if (r.y >= 0) U.taken[r.y] = epoch;
+          if (r.z >= 0) U.taken[r.z] = epoch;
+        }
+      }
+      if (tid == 0) s_alive = 0;
+      __syncthreads();
+      int alive = 0;
+      for (int c = tid; c < n_cand; c += kSelBlock) {
+        const uint8_t st = U.cand_alive[c];
+        if (st == 0) continue;
+        if (st == 2) { U.cand_alive[c] = 0; continue; }
+        const int4 r = U.cand_res[c];
+        if ((r.x >= 0 && U.taken[r.x] == epoch) || (r.y >= 0 && U.taken[r.y] == epoch) ||
+            (r.z >= 0 && U.taken[r.z] == epoch)) {
+          U.cand_alive[c] = 0;
+          continue;
+        }
+        if (r.x >= 0) reset_min(&U.resmin[r.x]);
+        if (r.y >= 0) reset_min(&U.resmin[r.y]);
+        if (r.z >= 0) reset_min(&U.resmin[r.z]);
+        ++alive;
+      }
+      if (alive) atomicAdd(&s_alive, alive);
+      __syncthreads();
+      if (s_alive == 0) break;
+      // every round takes at least the smallest live move; a round count beyond
+      // the candidate count means an invariant broke: stop and report it
+      if (round > n_cand + 1) {
+        if (tid == 0) atomicOr(&ctl->err, 16);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  const int n_sel = s_nsel;
+
+  // ---- plan: free slots for Depot-Insert routes, taken in key order
+  for (int s = tid; s < n_sel; s += kSelBlock)
+    if ((U.sel_id[s] >> 56) == DINS) atomicAdd(&s_ndins, 1);
+  __syncthreads();
+  const int n_dins = s_ndins;
+  // free slot list (slots empty before this step) into resmin's storage as int32
+  int32_t* free_list = (int32_t*)U.resmin;
+  if (n_dins > 0) {
+    int carry = 0;
+    for (int base = 0; base < U.R; base += kSelBlock) {
+      const int s = base + tid;
+      const int f = (s < U.R && U.r_len[s] == 0) ? 1 : 0;
+      int tot;
+      const int ex = block_scan(f, sh, &tot);
+      if (f && carry + ex < n_dins) free_list[carry + ex] = s;
+      carry += tot;
+    }
+    if (carry < n_dins && tid == 0) atomicOr(&ctl->err, 2);
+  }
+  __syncthreads();
+  for (int s = tid; s < n_sel; s += kSelBlock) {
+    const uint64_t id = U.sel_id[s];
+    const int64_t dF = U.sel_dF[s];
+    int fresh = -1;
+    if ((id >> 56) == DINS) {
+      int rank = 0;
+      for (int z = 0; z < n_sel; ++z) {
+        const uint64_t iz = U.sel_id[z];
+        if ((iz >> 56) == DINS && key_less(U.sel_dF[z], iz, dF, id)) ++rank;
+      }
+      fresh = rank < n_dins ? free_list[rank] : 0;
+    }
+    plan_move<OPEN>(U, cur, id, dF, fresh, epoch);
+  }
+  __syncthreads();
+
+  // ---- new route table and offsets of the other buffer
+  const int dst = cur ^ 1;
+  int carry = 0, alive_carry = 0;
+  for (int base = 0; base < U.R; base += kSelBlock) {
+    const int s = base + tid;
+    int len = 0;
+    if (s < U.R) {
+      if (U.dirty[s] == epoch) {
+        const int np = U.plan_n[s];
+        for (int k = 0; k < np; ++k) {
+          const int4 p = U.plan_pc[(int64_t)s * kMaxPieces + k];
+          len += p.z - p.y + 1;
+        }
+        U.r_len[s] = len;
+        if (len > 0) {
+          U.r_start[s] = U.plan_se[2 * s];
+          U.r_end[s] = U.plan_se[2 * s + 1];
+        }
+      } else {
+        len = U.r_len[s];
+      }
+    }
+    const int size = len > 0 ? len + 2 : 0;
+    int tot, tot2;
+    const int ex = block_scan(size, sh, &tot);
+    const int ax = block_scan(len > 0 ? 1 : 0, sh, &tot2);
+    if (s < U.R) {
+      U.r_off[dst][s] = carry + ex;
+      if (len > 0) U.slot_list[alive_carry + ax] = s;
+    }
+    carry += tot;
+    alive_carry += tot2;
+  }
+  if (tid == 0) {
+    if (carry > U.cap) atomicOr(&ctl->err, 2);
+    ctl->n_slots_alive = alive_carry;
+    ctl->n_sel = n_sel;
+    ctl->cur = dst;
+    ctl->moves_applied += n_sel;
+    ctl->pass_applied = 1;
+    ctl->n_cand = 0;
+  }
+}
+
+void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only) {
+  const uint32_t cls = eval_classes(L, fam_mask);
+  if (L.open)
+    hipLaunchKernelGGL(k_select_plan<true>, dim3(L.n_units), dim3(kSelBlock), 0, L.stream, L.units, cls,
+                       leader_only);
+  else
+    hipLaunchKernelGGL(k_select_plan<false>, dim3(L.n_units), dim3(kSelBlock), 0, L.stream, L.units, cls,
+                       leader_only);
+}
+
+}  // namespace mdvrp

@@ -1,0 +1,324 @@
+"""Thin Python binding of libmdvrp (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels. PyTorch only
+provides device memory (workspaces, input and output arrays) and the stream.
+Importing works without a GPU; creating objects needs one and fails loudly
+when the compiled library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdvrp.so")
+
+OK, EINVAL, ERANGE, ENOSPC, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
+FAM_RELOCATE, FAM_SWAP, FAM_2OPT_STAR, FAM_2OPT, FAM_DEPOT_INSERT, FAM_DEPOT_REPLACE = 1, 2, 4, 8, 16, 32
+FAM_ALL = 0x3F
+EVAL_DENSE = 1
+LS_PASSES, LS_UNION = 0, 1
+
+
+class MdvrpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libmdvrp status {status}: {msg}")
+        self.status = status
+
+
+class InstanceDesc(C.Structure):
+    _fields_ = [("n_depots", C.c_int32), ("n_customers", C.c_int32),
+                ("c", C.c_void_p), ("t", C.c_void_p), ("q", C.c_void_p), ("s", C.c_void_p),
+                ("e", C.c_void_p), ("l", C.c_void_p),
+                ("Q", C.c_int32), ("NV", C.c_int32), ("Dmax", C.c_int32),
+                ("open_routes", C.c_int32), ("has_tw", C.c_int32), ("theta", C.c_int32),
+                ("w_tw", C.c_int32), ("w_load", C.c_int32), ("w_dur", C.c_int32), ("w_depot", C.c_int32)]
+
+
+class LsOptions(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("leader_only", C.c_int32), ("max_passes", C.c_int32),
+                ("poll_every", C.c_int32), ("seed", C.c_uint64)]
+
+
+class LsStats(C.Structure):
+    _fields_ = [("passes", C.c_int64), ("steps", C.c_int64), ("moves_applied", C.c_int64),
+                ("evaluated", C.c_int64), ("F", C.c_int64), ("converged", C.c_int32), ("err", C.c_int32)]
+
+
+DENSE_DTYPE = np.dtype([("dF", np.int64), ("dD", np.int64), ("dTW", np.int64), ("dLX", np.int64),
+                        ("dDX", np.int64), ("dV4", np.int64), ("id", np.uint64), ("unit", np.int32),
+                        ("res", np.int32, (3,))])
+assert DENSE_DTYPE.itemsize == 72
+
+_lib = None
+
+EXPORTED = [
+    "mdvrp_validate_instance_host", "mdvrp_instance_workspace_query", "mdvrp_instance_create",
+    "mdvrp_instance_info", "mdvrp_instance_copy_lists", "mdvrp_instance_destroy",
+    "mdvrp_batch_workspace_query", "mdvrp_batch_create", "mdvrp_batch_destroy",
+    "mdvrp_validate_solutions_host", "mdvrp_solutions_load", "mdvrp_solutions_export", "mdvrp_batch_cost",
+    "mdvrp_batch_state", "mdvrp_eval_neighbourhood", "mdvrp_select_multimove", "mdvrp_apply_moves",
+    "mdvrp_local_search_to_optimum", "mdvrp_status_string", "mdvrp_last_error", "mdvrp_family_order",
+]
+
+
+def lib():
+    """Load libmdvrp.so; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (paper_2605_05208_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, u32, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_size_t
+        sig = {
+            "mdvrp_validate_instance_host": [p],
+            "mdvrp_instance_workspace_query": [p, p],
+            "mdvrp_instance_create": [p, p, sz, p, p],
+            "mdvrp_instance_info": [p, p],
+            "mdvrp_instance_copy_lists": [p, p, p, p],
+            "mdvrp_batch_workspace_query": [p, i32, p, i32, p],
+            "mdvrp_batch_create": [p, i32, p, i32, p, sz, p, p],
+            "mdvrp_validate_solutions_host": [p, i32, p, i32, p, p, p, p, p],
+            "mdvrp_solutions_load": [p, p, p, p, p, p, i32, i32, p],
+            "mdvrp_solutions_export": [p, p, p, p, p, p, p],
+            "mdvrp_batch_cost": [p, p, p, p],
+            "mdvrp_batch_state": [p, p],
+            "mdvrp_eval_neighbourhood": [p, u32, u32, p, i64, p, p],
+            "mdvrp_select_multimove": [p, u32, i32, p, p, p, i32, p],
+            "mdvrp_apply_moves": [p, p],
+            "mdvrp_local_search_to_optimum": [p, p, p, p],
+            "mdvrp_family_order": [i32, u64, i64, p],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int32
+        L.mdvrp_instance_destroy.argtypes = [p]
+        L.mdvrp_instance_destroy.restype = None
+        L.mdvrp_batch_destroy.argtypes = [p]
+        L.mdvrp_batch_destroy.restype = None
+        L.mdvrp_status_string.argtypes = [i32]
+        L.mdvrp_status_string.restype = C.c_char_p
+        L.mdvrp_last_error.argtypes = []
+        L.mdvrp_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != OK:
+        raise MdvrpError(status, lib().mdvrp_last_error().decode())
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _dev_i32(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to("cuda")
+
+
+def desc_from_host(inst) -> InstanceDesc:
+    """Descriptor whose array pointers are host numpy arrays (for host validation)."""
+    keep = [np.ascontiguousarray(x, dtype=np.int32) for x in (inst.c, inst.t, inst.q, inst.s, inst.e, inst.l)]
+    d = InstanceDesc(inst.n_depots, inst.n_customers, *[k.ctypes.data for k in keep],
+                     inst.Q, inst.NV, inst.Dmax, inst.open_routes, inst.has_tw, inst.theta,
+                     inst.w_tw, inst.w_load, inst.w_dur, inst.w_depot)
+    d._keep = keep
+    return d
+
+
+class Instance:
+    """Device-resident instance (c, t, node arrays) plus its preprocessing."""
+
+    def __init__(self, inst):
+        torch = _torch()
+        self.inst = inst
+        self.c = _dev_i32(inst.c)
+        self.t = self.c if inst.t is inst.c else _dev_i32(inst.t)
+        self.q, self.s, self.e, self.l = (_dev_i32(x) for x in (inst.q, inst.s, inst.e, inst.l))
+        self.desc = InstanceDesc(inst.n_depots, inst.n_customers, self.c.data_ptr(), self.t.data_ptr(),
+                                 self.q.data_ptr(), self.s.data_ptr(), self.e.data_ptr(), self.l.data_ptr(),
+                                 inst.Q, inst.NV, inst.Dmax, inst.open_routes, inst.has_tw, inst.theta,
+                                 inst.w_tw, inst.w_load, inst.w_dur, inst.w_depot)
+        nbytes = C.c_size_t(0)
+        check(lib().mdvrp_instance_workspace_query(C.byref(self.desc), C.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        check(lib().mdvrp_instance_create(C.byref(self.desc), _dptr(self.ws), nbytes.value, _stream(), C.byref(h)))
+        self.handle = h
+
+    def info(self):
+        out = np.zeros(8, np.int64)
+        check(lib().mdvrp_instance_info(self.handle, out.ctypes.data_as(C.c_void_p)))
+        keys = ["Theta", "gamma_num", "gamma_den", "w_depot", "max_c", "min_c", "max_t", "len_guard"]
+        return dict(zip(keys, (int(x) for x in out)))
+
+    def lists(self):
+        torch = _torch()
+        nc, th = self.inst.n_customers, self.inst.theta
+        a = torch.empty(nc * th, dtype=torch.int32, device="cuda")
+        b = torch.empty(nc, dtype=torch.int32, device="cuda")
+        check(lib().mdvrp_instance_copy_lists(self.handle, _dptr(a), _dptr(b), _stream()))
+        torch.cuda.synchronize()
+        return a.cpu().numpy(), b.cpu().numpy()
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.mdvrp_instance_destroy(h)
+            self.handle = None
+
+
+class Batch:
+    """Units = (instance, solution); one solution per unit."""
+
+    def __init__(self, instances, unit_inst):
+        torch = _torch()
+        self.instances = list(instances)
+        self.unit_inst = np.ascontiguousarray(unit_inst, dtype=np.int32)
+        self.n_units = len(self.unit_inst)
+        arr = (C.c_void_p * len(self.instances))(*[i.handle.value for i in self.instances])
+        self._arr = arr
+        nbytes = C.c_size_t(0)
+        check(lib().mdvrp_batch_workspace_query(arr, len(self.instances), self.unit_inst.ctypes.data_as(C.c_void_p),
+                                                self.n_units, C.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        check(lib().mdvrp_batch_create(arr, len(self.instances), self.unit_inst.ctypes.data_as(C.c_void_p),
+                                       self.n_units, _dptr(self.ws), nbytes.value, _stream(), C.byref(h)))
+        self.handle = h
+        self.nc = np.array([self.instances[i].inst.n_customers for i in self.unit_inst], np.int64)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.mdvrp_batch_destroy(h)
+            self.handle = None
+
+    # ------------------------------------------------------------------ solutions
+    def load(self, solutions):
+        from .gen import batch_flat
+        nodes, offs, st, en, so = batch_flat(solutions)
+        self._in = [_dev_i32(x) for x in (nodes if len(nodes) else np.zeros(1, np.int32), offs, st, en, so)]
+        n, o, s, e, u = self._in
+        check(lib().mdvrp_solutions_load(self.handle, _dptr(n), _dptr(o), _dptr(s), _dptr(e), _dptr(u),
+                                         len(st), len(nodes), _stream()))
+
+    def export(self):
+        from .gen import Solution
+        torch = _torch()
+        tot_n = int(self.nc.sum())
+        tot_r = int((self.nc + 1).sum())
+        nodes = torch.empty(max(tot_n, 1), dtype=torch.int32, device="cuda")
+        offs = torch.empty(tot_r + 1, dtype=torch.int32, device="cuda")
+        st = torch.empty(tot_r, dtype=torch.int32, device="cuda")
+        en = torch.empty(tot_r, dtype=torch.int32, device="cuda")
+        cnt = torch.empty(self.n_units, dtype=torch.int32, device="cuda")
+        check(lib().mdvrp_solutions_export(self.handle, _dptr(nodes), _dptr(offs), _dptr(st), _dptr(en), _dptr(cnt),
+                                           _stream()))
+        torch.cuda.synchronize()
+        nodes, offs, st, en, cnt = (x.cpu().numpy() for x in (nodes, offs, st, en, cnt))
+        out = []
+        rb = 0
+        for k in range(self.n_units):
+            routes = []
+            for r in range(int(cnt[k])):
+                a, b = int(offs[rb + r]), int(offs[rb + r + 1])
+                routes.append((int(st[rb + r]), [int(x) for x in nodes[a:b]], int(en[rb + r])))
+            out.append(Solution(routes))
+            rb += int(self.nc[k]) + 1
+        return out
+
+    def cost(self):
+        torch = _torch()
+        F = torch.empty(self.n_units, dtype=torch.int64, device="cuda")
+        T = torch.empty(self.n_units * 6, dtype=torch.int64, device="cuda")
+        check(lib().mdvrp_batch_cost(self.handle, _dptr(F), _dptr(T), _stream()))
+        torch.cuda.synchronize()
+        return F.cpu().numpy(), T.cpu().numpy().reshape(self.n_units, 6)
+
+    def state(self):
+        out = np.zeros(self.n_units * 8, np.int64)
+        check(lib().mdvrp_batch_state(self.handle, out.ctypes.data_as(C.c_void_p)))
+        return out.reshape(self.n_units, 8)
+
+    # ------------------------------------------------------------------ hot path
+    def eval_neighbourhood(self, fam_mask=FAM_ALL, dense_cap=0):
+        torch = _torch()
+        if dense_cap:
+            rec = torch.empty(dense_cap * DENSE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+            cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+            check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, EVAL_DENSE, _dptr(rec), dense_cap, _dptr(cnt),
+                                                 _stream()))
+            torch.cuda.synchronize()
+            n = int(cnt.item())
+            if n > dense_cap:
+                raise MdvrpError(ENOSPC, f"dense table needs {n} records")
+            return np.frombuffer(rec[:n * DENSE_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=DENSE_DTYPE)
+        check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, 0, None, 0, None, _stream()))
+        return None
+
+    def select_multimove(self, fam_mask=FAM_ALL, leader_only=0, want=True):
+        torch = _torch()
+        if not want:
+            check(lib().mdvrp_select_multimove(self.handle, fam_mask, leader_only, None, None, None, 0, _stream()))
+            return None
+        cap = int(self.nc.max()) + 1
+        ids = torch.empty(self.n_units * cap, dtype=torch.int64, device="cuda")
+        dF = torch.empty(self.n_units * cap, dtype=torch.int64, device="cuda")
+        cnt = torch.empty(self.n_units, dtype=torch.int32, device="cuda")
+        check(lib().mdvrp_select_multimove(self.handle, fam_mask, leader_only, _dptr(ids), _dptr(dF), _dptr(cnt), cap,
+                                           _stream()))
+        torch.cuda.synchronize()
+        ids = ids.cpu().numpy().view(np.uint64).reshape(self.n_units, cap)
+        dF = dF.cpu().numpy().reshape(self.n_units, cap)
+        cnt = cnt.cpu().numpy()
+        return [(ids[k, :cnt[k]].copy(), dF[k, :cnt[k]].copy()) for k in range(self.n_units)]
+
+    def apply_moves(self):
+        check(lib().mdvrp_apply_moves(self.handle, _stream()))
+
+    def local_search_to_optimum(self, mode=LS_PASSES, seed=0, max_passes=0, leader_only=0, poll_every=1):
+        opt = LsOptions(mode, leader_only, max_passes, poll_every, seed)
+        stats = (LsStats * self.n_units)()
+        check(lib().mdvrp_local_search_to_optimum(self.handle, C.byref(opt), stats, _stream()))
+        return [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F,
+                     converged=s.converged, err=s.err) for s in stats]
+
+
+def validate_solutions_host(instances, unit_inst, solutions):
+    """Host-only validation of solutions (no GPU needed); returns the status."""
+    from .gen import batch_flat
+    descs = (InstanceDesc * len(instances))(*[desc_from_host(i) for i in instances])
+    ui = np.ascontiguousarray(unit_inst, dtype=np.int32)
+    nodes, offs, st, en, so = batch_flat(solutions)
+    if len(nodes) == 0:
+        nodes = np.zeros(1, np.int32)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    return lib().mdvrp_validate_solutions_host(descs, len(instances), ptr(ui), len(ui), ptr(nodes), ptr(offs),
+                                               ptr(st), ptr(en), ptr(so))
+
+
+def validate_instance_host(inst):
+    d = desc_from_host(inst)
+    return lib().mdvrp_validate_instance_host(C.byref(d))
+
+
+def family_order(has_tw, seed, p):
+    fam = np.zeros(6, np.int32)
+    n = lib().mdvrp_family_order(has_tw, seed, p, fam.ctypes.data_as(C.c_void_p))
+    return [int(x) for x in fam[:n]]

@@ -1,0 +1,246 @@
+"""Parity of the HIP path (called through the C-ABI) with the CPU oracle.
+
+Integers everywhere, so every comparison is exact: granular lists, every
+evaluated move's deltas, the selected move sets, the applied solutions, F,
+and whole local-search trajectories (passes, steps, moves, evaluations).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ALL_FAMILIES, Ref
+from paper_2605_05208_amd import gen, mdvrp
+from paper_2605_05208_amd.gen import canonical
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dense_cap_for(insts):
+    return int(sum(i.n_customers * i.theta * 14 + 2 * i.n_customers * i.n_depots for i in insts)) + 1024
+
+
+def compare_dense(got, exp, R, tag):
+    assert len(got) == len(exp), f"{tag}: {len(got)} evaluated on GPU vs {len(exp)} in the oracle"
+    g = got[np.argsort(got["id"], kind="stable")]
+    e = exp[np.argsort(exp["id"], kind="stable")]
+    assert np.array_equal(g["id"], e["id"]), tag
+    for f in ("dF", "dD", "dTW", "dLX", "dDX", "dV4"):
+        bad = np.nonzero(g[f] != e[f])[0]
+        assert len(bad) == 0, f"{tag}: field {f} differs at id {hex(int(g['id'][bad[0]]))}: {g[f][bad[0]]} vs {e[f][bad[0]]}"
+    gr, er = g["res"].astype(np.int64), e["res"].astype(np.int64)
+    assert np.array_equal(((gr >= 0) & (gr < R)).sum(1), (er >= 0).sum(1)), f"{tag}: route resources"
+    big = np.int64(1) << 40
+    gd = np.sort(np.where(gr >= R, gr - R, big), axis=1)
+    ed = np.sort(np.where(er <= -2, -2 - er, big), axis=1)
+    assert np.array_equal(gd, ed), f"{tag}: depot resources"
+
+
+def make_batch(insts, sols_per_inst):
+    dev = [mdvrp.Instance(i) for i in insts]
+    unit_inst = [k for k, s in enumerate(sols_per_inst) for _ in s]
+    B = mdvrp.Batch(dev, unit_inst)
+    flat = [s for ss in sols_per_inst for s in ss]
+    B.load(flat)
+    return dev, B, flat
+
+
+# ----------------------------------------------------------------------------- instance preprocessing
+
+@pytest.mark.parametrize("which", ["config1", "config2", "tiny_tw", "tiny_theta3"])
+def test_granular_lists_and_theta(which):
+    inst = {"config1": gen.config1, "config2": gen.config2,
+            "tiny_tw": lambda: gen.tiny(11, has_tw=1), "tiny_theta3": lambda: gen.tiny(12, theta=3)}[which]()
+    log("lists", which)
+    I = mdvrp.Instance(inst)
+    ref = Ref(inst)
+    nbr, ln = I.lists()
+    rn, rl = ref.neighbours()
+    assert np.array_equal(ln, rl)
+    assert np.array_equal(nbr, rn)
+    info = I.info()
+    st = ref.stats()
+    assert info["Theta"] == st["Theta"] and info["w_depot"] == st["w_depot"]
+    assert (info["gamma_num"], info["gamma_den"]) == (st["gamma_num"], st["gamma_den"])
+
+
+# ----------------------------------------------------------------------------- dense move tables
+
+def _tiny_group(tw, open_r, n_inst=24, base=0):
+    insts = []
+    for k in range(n_inst):
+        seed = 90_000 + base + 100 * tw + 10 * open_r + k
+        theta = None if k % 3 else 3
+        Dmax = 40 if (k % 5 == 1 and not tw) else -1
+        insts.append(gen.tiny(seed, has_tw=tw, open_routes=open_r, theta=theta, Dmax=Dmax))
+    sols = [[gen.random_solution(i, 7 * k + 1), gen.start_solution(i, 7 * k + 2)] for k, i in enumerate(insts)]
+    return insts, sols
+
+
+@pytest.mark.parametrize("tw,open_r", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("fam", [ALL_FAMILIES, 1, 2, 4, 8, 16, 32])
+def test_dense_moves_tiny_multi_instance(tw, open_r, fam):
+    insts, sols = _tiny_group(tw, open_r)
+    log("dense tiny", tw, open_r, fam)
+    dev, B, flat = make_batch(insts, sols)
+    got = B.eval_neighbourhood(fam, dense_cap=dense_cap_for([insts[k] for k in B.unit_inst]))
+    u = 0
+    for k, inst in enumerate(insts):
+        ref = Ref(inst)
+        for sol in sols[k]:
+            exp = ref.eval(sol, fam)
+            compare_dense(got[got["unit"] == u], exp, inst.n_customers, f"inst {k} unit {u} fam {fam}")
+            u += 1
+
+
+@pytest.mark.parametrize("which", ["config1", "config2", "config3_closed", "config3_open"])
+def test_dense_moves_configs(which):
+    if which == "config1":
+        inst, n = gen.config1(), 3
+    elif which == "config2":
+        inst, n = gen.config2(), 2
+    else:
+        inst, n = gen.config3(open_routes=int(which.endswith("open"))), 1
+    log("dense", which)
+    sols = [gen.start_solution(inst, inst.seed * 1000 + k) for k in range(n)]
+    dev, B, flat = make_batch([inst], [sols])
+    ref = Ref(inst)
+    fams = [ALL_FAMILIES] if which != "config3_closed" else [1, 2, 4, 8, 16, 32]
+    for fam in fams:
+        got = B.eval_neighbourhood(fam, dense_cap=dense_cap_for([inst] * n))
+        for u, sol in enumerate(sols):
+            exp = ref.eval(sol, fam)
+            compare_dense(got[got["unit"] == u], exp, inst.n_customers, f"{which} unit {u} fam {fam}")
+
+
+# ----------------------------------------------------------------------------- selection + apply
+
+def _step_compare(B, refs, sols, fam, leader_only, tag):
+    B.eval_neighbourhood(fam)
+    sel = B.select_multimove(fam, leader_only)
+    B.apply_moves()
+    got = B.export()
+    Fg, _ = B.cost()
+    new_sols = []
+    for u, (ref, sol) in enumerate(zip(refs, sols)):
+        nsol, ids, dFs, _ = ref.step(sol, fam, leader_only)
+        gi, gd = sel[u]
+        assert len(gi) == len(ids), f"{tag} unit {u}: {len(gi)} selected vs {len(ids)}"
+        if len(ids):
+            assert int(gi[0]) == int(ids[0]), f"{tag} unit {u}: leader differs"
+            assert int(gd[0]) == int(dFs[0])
+        assert sorted(int(x) for x in gi) == sorted(int(x) for x in ids), f"{tag} unit {u}: selection differs"
+        assert canonical(got[u].routes) == canonical(nsol.routes), f"{tag} unit {u}: applied solution differs"
+        assert int(Fg[u]) == ref.cost(nsol)[0]
+        new_sols.append(nsol)
+    return new_sols
+
+
+@pytest.mark.parametrize("tw,open_r", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("leader_only", [0, 1])
+def test_steps_tiny_multi_instance(tw, open_r, leader_only):
+    insts, sols = _tiny_group(tw, open_r, base=500)
+    log("steps tiny", tw, open_r, leader_only)
+    dev, B, flat = make_batch(insts, sols)
+    refs = [Ref(insts[k]) for k in B.unit_inst]
+    cur = flat
+    fams = [ALL_FAMILIES, 1, 2, 4, 8, 16, 32] * 3
+    for s, fam in enumerate(fams):
+        cur = _step_compare(B, refs, cur, fam, leader_only, f"step {s} fam {fam}")
+
+
+@pytest.mark.parametrize("which", ["config1", "config2"])
+def test_steps_configs(which):
+    inst = gen.config1() if which == "config1" else gen.config2()
+    n = 3 if which == "config1" else 2
+    log("steps", which)
+    sols = [gen.start_solution(inst, inst.seed * 1000 + k) for k in range(n)]
+    dev, B, flat = make_batch([inst], [sols])
+    refs = [Ref(inst)] * n
+    cur = flat
+    order = [1, 2, 4, 8, 16, 32] if not inst.has_tw else [1, 2, 4, 16, 32]
+    for s in range(12):
+        cur = _step_compare(B, refs, cur, order[s % len(order)], 0, f"{which} step {s}")
+
+
+def test_steps_config3_first_pass():
+    """Full-size config-3 instance (10,020 nodes, 400 MB matrix): the first pass of
+    family steps on two of its solutions, selected sets and solutions exact."""
+    inst = gen.config3()
+    log("steps config3")
+    sols = [gen.start_solution(inst, inst.seed * 1000 + k) for k in range(2)]
+    dev, B, flat = make_batch([inst], [sols])
+    refs = [Ref(inst)] * 2
+    cur = flat
+    for fam in [1, 2, 4, 8, 16, 32]:
+        cur = _step_compare(B, refs, cur, fam, 0, f"config3 fam {fam}")
+
+
+# ----------------------------------------------------------------------------- local search to optimum
+
+def _ls_compare(insts, sols, mode, seed, leader_only=0, max_passes=0, tag=""):
+    dev, B, flat = make_batch(insts, sols)
+    st = B.local_search_to_optimum(mode=mode, seed=seed, leader_only=leader_only, max_passes=max_passes)
+    got = B.export()
+    Fg, _ = B.cost()
+    u = 0
+    for k, inst in enumerate(insts):
+        ref = Ref(inst)
+        out, rst = ref.local_search(sols[k], mode=mode, seed=seed, leader_only=leader_only, max_passes=max_passes)
+        for j in range(len(sols[k])):
+            g, r = st[u], rst[j]
+            tagu = f"{tag} inst {k} unit {u}"
+            assert canonical(got[u].routes) == canonical(out[j].routes), tagu
+            assert int(Fg[u]) == r["F"] == g["F"], tagu
+            for key in ("passes", "steps", "moves_applied", "evaluated"):
+                assert g[key] == r[key], f"{tagu}: {key} {g[key]} vs {r[key]}"
+            assert g["err"] == 0
+            u += 1
+
+
+@pytest.mark.parametrize("tw,open_r", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("mode,leader_only", [(0, 0), (1, 0), (0, 1)])
+def test_local_search_tiny_multi_instance(tw, open_r, mode, leader_only):
+    insts, sols = _tiny_group(tw, open_r, base=900)
+    log("ls tiny", tw, open_r, mode, leader_only)
+    _ls_compare(insts, sols, mode, 4242, leader_only, tag=f"tiny tw={tw} open={open_r}")
+
+
+def test_local_search_config1():
+    inst = gen.config1()
+    log("ls config1")
+    sols = [gen.start_solution(inst, inst.seed * 1000 + k) for k in range(4)]
+    _ls_compare([inst], [sols], 0, 7, tag="config1")
+    _ls_compare([inst], [sols[:1]], 1, 7, tag="config1 union")
+
+
+def test_local_search_config2_two_solutions():
+    inst = gen.config2()
+    log("ls config2")
+    sols = [gen.start_solution(inst, inst.seed * 1000 + k) for k in range(2)]
+    _ls_compare([inst], [sols], 0, 1, tag="config2")
+
+
+def test_local_search_depth_limit():
+    inst = gen.config1()
+    sols = [gen.start_solution(inst, inst.seed * 1000 + 5)]
+    _ls_compare([inst], [sols], 0, 3, max_passes=2, tag="config1 depth 2")
+
+
+def test_reload_and_rerun_is_deterministic():
+    inst = gen.config2()
+    sols = [gen.start_solution(inst, inst.seed * 1000 + k) for k in range(3)]
+    dev, B, flat = make_batch([inst], [sols])
+    st1 = B.local_search_to_optimum(seed=5)
+    e1 = [canonical(s.routes) for s in B.export()]
+    B.load(flat)
+    st2 = B.local_search_to_optimum(seed=5, poll_every=4)
+    e2 = [canonical(s.routes) for s in B.export()]
+    assert e1 == e2
+    assert [s["F"] for s in st1] == [s["F"] for s in st2]
+    assert [s["passes"] for s in st1] == [s["passes"] for s in st2]
