@@ -230,6 +230,36 @@ typedef struct {
 mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* batch, const mdvrp_ls_options* opts,
                                            mdvrp_ls_stats* stats, void* stream);
 
+/* ------------------------------------------------------------------------- profiling */
+
+/* Kernel classes of the profiler. */
+#define MDVRP_PROF_EVAL_PAIRS 0
+#define MDVRP_PROF_EVAL_DEPOT_INSERT 1
+#define MDVRP_PROF_EVAL_DEPOT_REPLACE 2
+#define MDVRP_PROF_SELECT 3
+#define MDVRP_PROF_APPLY 4
+
+/* Turn per-launch timing on (class_mask != 0) or off for a batch. Every launch
+ * of a kernel class whose bit (1 << MDVRP_PROF_*) is set in class_mask is
+ * bracketed by two HIP events on the launch stream (host objects; no device
+ * memory is allocated). Up to max_launches launches are kept pending before
+ * they are folded into totals. Resets the totals. */
+mdvrp_status mdvrp_profile_enable(mdvrp_batch* batch, uint32_t class_mask, int32_t max_launches);
+
+/* Per-class totals since enabling: launches[8] and elapsed milliseconds ms[8]
+ * (HOST arrays, indexed by MDVRP_PROF_*). Waits for pending events. */
+mdvrp_status mdvrp_profile_read(mdvrp_batch* batch, int64_t* launches, double* ms);
+
+/* Measurement variant of mdvrp_eval_neighbourhood: the same evaluation, which
+ * also marks every matrix entry it reads in a bitmap, giving the number of
+ * distinct c/t entries (the matrix part of a launch's compulsory traffic).
+ * bitmap: zeroed DEVICE array; instance k of the batch (order of the
+ * instance list given at creation) owns words [sum_{j<k} W_j, ...) with
+ * W_j = ceil(N_j*N_j / 32). bitmap_words must cover all instances.
+ * The results of the evaluation itself are discarded. Synchronises. */
+mdvrp_status mdvrp_eval_footprint(mdvrp_batch* batch, uint32_t family_mask, uint32_t* bitmap, int64_t bitmap_words,
+                                  void* stream);
+
 /* ------------------------------------------------------------------------- misc */
 
 const char* mdvrp_status_string(mdvrp_status s);

@@ -63,6 +63,7 @@ struct mdvrp_instance {
   int N = 0;
   int32_t* nbr = nullptr;
   int32_t* nbr_len = nullptr;
+  int4* attr = nullptr;
   int64_t* partial = nullptr;
   int64_t* stats = nullptr;
   int nblocks = 0;
@@ -71,7 +72,23 @@ struct mdvrp_instance {
   int t_is_c = 0;
 };
 
+// Opt-in per-launch timing with HIP events on the launch stream.
+struct Profiler {
+  bool on = false;
+  uint32_t mask = 0;  // kernel classes timed
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cls;  // kernel class of pending event pair k
+  int used = 0;
+  int64_t launches[8] = {0};
+  double ms[8] = {0};
+  void reset() {
+    used = 0;
+    for (int k = 0; k < 8; ++k) { launches[k] = 0; ms[k] = 0; }
+  }
+};
+
 struct mdvrp_batch {
+  Profiler prof;
   std::vector<const mdvrp_instance*> inst;
   std::vector<int> unit_inst;
   int n_units = 0;
@@ -180,11 +197,13 @@ static void carve_instance(Carve& cv, const mdvrp_instance_desc* d, mdvrp_instan
   const int nb = inst_stats_blocks(n);
   int32_t* nbr = cv.take<int32_t>((size_t)d->n_customers * d->theta);
   int32_t* nbl = cv.take<int32_t>(d->n_customers);
+  int4* attr = cv.take<int4>(n);
   int64_t* part = cv.take<int64_t>((size_t)nb * 8);
   int64_t* st = cv.take<int64_t>(8);
   if (I) {
     I->nbr = nbr;
     I->nbr_len = nbl;
+    I->attr = attr;
     I->partial = part;
     I->stats = st;
     I->nblocks = nb;
@@ -232,6 +251,7 @@ extern "C" mdvrp_status mdvrp_instance_create(const mdvrp_instance_desc* d, void
   I->t_is_c = d->t == d->c;
   Carve cv(ws);
   carve_instance(cv, d, I);
+  launch_node_attr(S(stream), d->q, d->s, d->e, d->l, n, I->attr);
   launch_inst_stats(S(stream), d->c, d->t, n, I->partial, I->nblocks);
   launch_inst_stats_final(S(stream), I->partial, I->nblocks, I->stats);
   int64_t h[8];
@@ -335,6 +355,8 @@ void carve_unit(Carve& cv, const mdvrp_instance* I, int has_tw, UnitDesc* U) {
   u.r_end = cv.take<int32_t>(z.R);
   u.r_off[0] = cv.take<int32_t>(z.R);
   u.r_off[1] = cv.take<int32_t>(z.R);
+  u.r_meta[0] = cv.take<int4>(z.R);
+  u.r_meta[1] = cv.take<int4>(z.R);
   u.r_tot = cv.take<int4>(z.R);
   u.r_cost = cv.take<int64_t>(z.R);
   for (int b = 0; b < 2; ++b) {
@@ -433,7 +455,7 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
     const UnitSizes z = unit_sizes(I);
     UnitDesc& u = B->h_units[k];
     u.c = I->d.c; u.t = I->d.t; u.q = I->d.q; u.s = I->d.s; u.e = I->d.e; u.l = I->d.l;
-    u.nbr = I->nbr; u.nbr_len = I->nbr_len;
+    u.nbr = I->nbr; u.nbr_len = I->nbr_len; u.attr = I->attr;
     u.nd = z.nd; u.nc = z.nc; u.n = z.n; u.theta = z.theta;
     u.Q = I->d.Q; u.NV = I->d.NV; u.Dmax = I->d.Dmax;
     u.w_tw = I->d.w_tw; u.w_load = I->d.w_load; u.w_dur = I->d.w_dur;
@@ -475,7 +497,67 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
   return MDVRP_OK;
 }
 
-extern "C" void mdvrp_batch_destroy(mdvrp_batch* B) { delete B; }
+extern "C" void mdvrp_batch_destroy(mdvrp_batch* B) {
+  if (!B) return;
+  for (hipEvent_t e : B->prof.ev) (void)hipEventDestroy(e);
+  delete B;
+}
+
+// ============================================================================ profiling
+
+extern "C" mdvrp_status mdvrp_profile_enable(mdvrp_batch* B, uint32_t class_mask, int32_t max_launches) {
+  if (!B || max_launches < 0) return fail(MDVRP_EINVAL, "bad argument");
+  Profiler& P = B->prof;
+  P.reset();
+  P.on = class_mask != 0;
+  P.mask = class_mask;
+  if (!P.on) return MDVRP_OK;
+  const size_t need = 2 * (size_t)std::max(max_launches, 1);
+  while (P.ev.size() < need) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    P.ev.push_back(e);
+  }
+  P.cls.assign(need / 2, 0);
+  return MDVRP_OK;
+}
+
+// Resolve pending event pairs into per-class totals (synchronises the events).
+static mdvrp_status profile_flush(Profiler& P) {
+  for (int k = 0; k < P.used; ++k) {
+    HIP_TRY(hipEventSynchronize(P.ev[2 * k + 1]));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, P.ev[2 * k], P.ev[2 * k + 1]));
+    P.launches[P.cls[k]] += 1;
+    P.ms[P.cls[k]] += t;
+  }
+  P.used = 0;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_profile_read(mdvrp_batch* B, int64_t* launches, double* ms) {
+  if (!B || !launches || !ms) return fail(MDVRP_EINVAL, "null argument");
+  mdvrp_status s = profile_flush(B->prof);
+  if (s) return s;
+  for (int k = 0; k < 8; ++k) { launches[k] = B->prof.launches[k]; ms[k] = B->prof.ms[k]; }
+  return MDVRP_OK;
+}
+
+namespace {
+// Launch one kernel class, bracketed by events when profiling is on.
+template <class F>
+void timed(mdvrp_batch* B, hipStream_t s, int cls, F&& launch) {
+  Profiler& P = B->prof;
+  if (!P.on || !(P.mask >> cls & 1)) { launch(); return; }
+  if (P.used * 2 + 2 > (int)P.ev.size()) profile_flush(P);
+  if (P.used * 2 + 2 > (int)P.ev.size()) { launch(); return; }
+  const int k = P.used++;
+  P.cls[k] = cls;
+  (void)hipEventRecord(P.ev[2 * k], s);
+  launch();
+  (void)hipEventRecord(P.ev[2 * k + 1], s);
+}
+}  // namespace
 
 extern "C" mdvrp_status mdvrp_validate_solutions_host(const mdvrp_instance_desc* descs, int32_t n_inst,
                                                       const int32_t* unit_inst, int32_t n_units, const int32_t* nodes,
@@ -596,8 +678,37 @@ extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, u
   const LaunchCtx L = B->ctx(stream);
   hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
   DenseOut D{(DenseRec*)dense, dense_count, dense_cap};
-  launch_eval(L, fam, (flags & MDVRP_EVAL_DENSE) ? &D : nullptr);
+  const uint32_t cls = eval_classes(L, fam);
+  for (int c = 0; c < 3; ++c)
+    if (cls >> c & 1)
+      timed(B, L.stream, c, [&] { launch_eval_class(L, fam, c, (flags & MDVRP_EVAL_DENSE) ? &D : nullptr); });
   HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_eval_footprint(mdvrp_batch* B, uint32_t fam, uint32_t* bitmap, int64_t words,
+                                             void* stream) {
+  if (!B || !bitmap) return fail(MDVRP_EINVAL, "null argument");
+  if (fam & ~MDVRP_FAM_ALL) return fail(MDVRP_EINVAL, "unknown family bits");
+  std::vector<int64_t> base(B->inst.size() + 1, 0);
+  for (size_t k = 0; k < B->inst.size(); ++k) {
+    const int64_t n = B->inst[k]->N;
+    base[k + 1] = base[k] + (n * n + 31) / 32;
+  }
+  if (words < base.back()) return fail(MDVRP_ENOSPC, "footprint bitmap needs %lld words", (long long)base.back());
+  hipStream_t s = S(stream);
+  std::vector<UnitDesc> u = B->h_units;
+  for (int k = 0; k < B->n_units; ++k) u[k].foot = bitmap + base[B->unit_inst[k]];
+  HIP_TRY(hipMemcpyAsync(B->d_units, u.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
+  const LaunchCtx L = B->ctx(stream);
+  hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  const uint32_t cls = eval_classes(L, fam);
+  for (int c = 0; c < 3; ++c)
+    if (cls >> c & 1) launch_eval_footprint(L, fam, c);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  HIP_TRY(hipStreamSynchronize(s));
   return MDVRP_OK;
 }
 
@@ -606,7 +717,7 @@ extern "C" mdvrp_status mdvrp_select_multimove(mdvrp_batch* B, uint32_t fam, int
   if (!B) return fail(MDVRP_EINVAL, "null batch");
   if (sel_ids && (!sel_dF || !sel_count || sel_cap < 1)) return fail(MDVRP_EINVAL, "selection output incomplete");
   const LaunchCtx L = B->ctx(stream);
-  launch_select(L, fam, leader_only ? 1 : 0);
+  timed(B, L.stream, 3, [&] { launch_select(L, fam, leader_only ? 1 : 0); });
   if (sel_ids) launch_sel_export(L, sel_ids, sel_dF, sel_count, sel_cap);
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
@@ -614,7 +725,8 @@ extern "C" mdvrp_status mdvrp_select_multimove(mdvrp_batch* B, uint32_t fam, int
 
 extern "C" mdvrp_status mdvrp_apply_moves(mdvrp_batch* B, void* stream) {
   if (!B) return fail(MDVRP_EINVAL, "null batch");
-  launch_rebuild(B->ctx(stream));
+  const LaunchCtx L = B->ctx(stream);
+  timed(B, L.stream, 4, [&] { launch_rebuild(L); });
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
 }
@@ -652,9 +764,11 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     }
     for (int k = 0; k < nf; ++k) {
       const uint32_t mask = o->mode == MDVRP_LS_PASSES ? (1u << fam[k]) : MDVRP_FAM_ALL;
-      launch_eval(L, mask, nullptr);
-      launch_select(L, mask, o->leader_only ? 1 : 0);
-      launch_rebuild(L);
+      const uint32_t cls = eval_classes(L, mask);
+      for (int c = 0; c < 3; ++c)
+        if (cls >> c & 1) timed(B, L.stream, c, [&] { launch_eval_class(L, mask, c, nullptr); });
+      timed(B, L.stream, 3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0); });
+      timed(B, L.stream, 4, [&] { launch_rebuild(L); });
     }
     launch_pass_end(L);
     HIP_TRY(hipGetLastError());

@@ -2,7 +2,10 @@
 //
 // One thread per item: an anchor pair (u, v in N(u)) for Relocate / Swap /
 // 2-opt* / 2-opt, or (customer, depot) for the depot operators (Section 3.2.2).
-// Each block belongs to one unit and writes
+// Inter-route anchors go through the specialised prefix/suffix evaluator;
+// intra-route anchors are packed into a block-level queue so that their
+// (longer) evaluation occupies as few wavefronts as possible. Each block
+// belongs to one unit and writes
 //   * its best improving move by (dF, id) -> the step's leader candidate;
 //   * the follower-eligible moves (dD < 0, no penalty term changes; Section
 //     3.2.5), reduced per resource set inside the item, appended to the
@@ -15,24 +18,30 @@ namespace mdvrp {
 
 constexpr int kEvalBlock = 256;
 
+// Per-thread results. Follower candidates are reduced per resource set; an
+// item has at most three distinct sets: {A, B} (or {A}), {A, B, depot of A},
+// {A, B, depot of B}. Slot z holds the best (packed) key of set z.
 struct ItemOut {
-  // leader candidate of this thread
   int64_t bF;
   uint64_t bid;
-  MoveEval bm;
-  // follower candidates, one per distinct resource set
-  int nc;
-  uint64_t ckey[3];
-  uint64_t cid[3];
-  int32_t cres[3][3];
+  int32_t b_dD, b_elig;
+  int32_t b_res0, b_res1, b_res2;
+  uint64_t k0, k1, k2;
+  uint64_t i0, i1, i2;
+  int4 r0, r1, r2;
   int64_t evaluated;
 };
 
 __device__ __forceinline__ void item_init(ItemOut& o) {
   o.bF = kNoMove;
   o.bid = ~0ull;
-  o.nc = 0;
+  o.b_dD = 0; o.b_elig = 0; o.b_res0 = o.b_res1 = o.b_res2 = -1;
+  o.k0 = o.k1 = o.k2 = ~0ull;
   o.evaluated = 0;
+}
+
+__device__ __forceinline__ bool same_res(const int4& r, const MoveEval& m) {
+  return r.x == m.res[0] && r.y == m.res[1] && r.z == m.res[2];
 }
 
 __device__ __forceinline__ void item_take(const UnitDesc& U, ItemOut& o, const MoveEval& m, uint64_t id) {
@@ -40,21 +49,19 @@ __device__ __forceinline__ void item_take(const UnitDesc& U, ItemOut& o, const M
   if (m.dF < 0 && key_less(m.dF, id, o.bF, o.bid)) {
     o.bF = m.dF;
     o.bid = id;
-    o.bm = m;
+    o.b_dD = m.dD;
+    o.b_elig = follower(m);
+    o.b_res0 = m.res[0]; o.b_res1 = m.res[1]; o.b_res2 = m.res[2];
   }
   if (follower(m)) {
     const uint64_t key = pack_key(U, m.dD, id);
-    for (int z = 0; z < o.nc; ++z) {
-      if (o.cres[z][0] == m.res[0] && o.cres[z][1] == m.res[1] && o.cres[z][2] == m.res[2]) {
-        if (key < o.ckey[z]) { o.ckey[z] = key; o.cid[z] = id; }
-        return;
-      }
-    }
-    if (o.nc < 3) {
-      const int z = o.nc++;
-      o.ckey[z] = key;
-      o.cid[z] = id;
-      o.cres[z][0] = m.res[0]; o.cres[z][1] = m.res[1]; o.cres[z][2] = m.res[2];
+    const int4 r = make_int4(m.res[0], m.res[1], m.res[2], 0);
+    if (o.k0 == ~0ull || same_res(o.r0, m)) {
+      if (key < o.k0) { o.k0 = key; o.i0 = id; o.r0 = r; }
+    } else if (o.k1 == ~0ull || same_res(o.r1, m)) {
+      if (key < o.k1) { o.k1 = key; o.i1 = id; o.r1 = r; }
+    } else if (o.k2 == ~0ull || same_res(o.r2, m)) {
+      if (key < o.k2) { o.k2 = key; o.i2 = id; o.r2 = r; }
     } else {
       atomicOr(&U.ctl->err, 8);
     }
@@ -71,7 +78,59 @@ __device__ __forceinline__ void dense_put(const DenseOut& D, int unit, const Mov
   D.rec[k] = r;
 }
 
-// Block-level epilogue: leader reduction, candidate append, evaluated count.
+// Result sink of the evaluators: leader/follower bookkeeping plus optional dense output.
+template <bool DENSE>
+struct Sink {
+  ItemOut* o;
+  DenseOut d;
+  int unit;
+};
+
+template <bool DENSE>
+__device__ __forceinline__ void take(const UnitDesc& U, Sink<DENSE>& s, const MoveEval& m, uint64_t id) {
+  item_take(U, *s.o, m, id);
+  if (DENSE) dense_put(s.d, s.unit, m, id);
+}
+
+}  // namespace mdvrp
+
+#include "eval_inter.h"
+#include "eval_intra.h"
+
+namespace mdvrp {
+
+__device__ __forceinline__ void cand_put(const UnitDesc& U, int at, uint64_t k, uint64_t id, const int4& r) {
+  if (at < U.cand_cap) {
+    U.cand_key[at] = k;
+    U.cand_id[at] = id;
+    U.cand_res[at] = r;
+  } else {
+    atomicOr(&U.ctl->err, 1);
+  }
+}
+
+// Append this wave's follower candidates with one atomic per wavefront.
+__device__ void cand_flush(const UnitDesc& U, ItemOut& o) {
+  const int lane = lane_id();
+  const int n = (o.k0 != ~0ull) + (o.k1 != ~0ull) + (o.k2 != ~0ull);
+  int incl = n;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  const int total = __shfl(incl, 63);
+  if (total == 0) return;
+  int base = 0;
+  if (lane == 63) base = atomicAdd(&U.ctl->n_cand, total);
+  base = __shfl(base, 63);
+  int at = base + incl - n;
+  if (o.k0 != ~0ull) cand_put(U, at++, o.k0, o.i0, o.r0);
+  if (o.k1 != ~0ull) cand_put(U, at++, o.k1, o.i1, o.r1);
+  if (o.k2 != ~0ull) cand_put(U, at++, o.k2, o.i2, o.r2);
+  o.k0 = o.k1 = o.k2 = ~0ull;
+}
+
+// Block-level epilogue: candidate append, leader reduction, evaluated count.
 __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
   __shared__ int64_t sF[kEvalBlock / 64];
   __shared__ uint64_t sI[kEvalBlock / 64];
@@ -79,8 +138,8 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
   __shared__ unsigned long long sEval;
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
+  cand_flush(U, o);
   if (threadIdx.x == 0) sEval = 0;
-  // wave-level argmin of (bF, bid)
   int64_t f = o.bF;
   uint64_t id = o.bid;
   int src = threadIdx.x;
@@ -90,28 +149,6 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
     const int s2 = __shfl_xor(src, off);
     if (key_less(f2, i2, f, id)) { f = f2; id = i2; src = s2; }
   }
-  // candidate append with one atomic per wave
-  int n = o.nc;
-  int incl = n;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(incl, off);
-    if (lane >= off) incl += y;
-  }
-  const int total = __shfl(incl, 63);
-  int base = 0;
-  if (lane == 63 && total > 0) base = atomicAdd(&U.ctl->n_cand, total);
-  base = __shfl(base, 63);
-  int at = base + incl - n;
-  for (int z = 0; z < n; ++z, ++at) {
-    if (at < U.cand_cap) {
-      U.cand_key[at] = o.ckey[z];
-      U.cand_id[at] = o.cid[z];
-      U.cand_res[at] = make_int4(o.cres[z][0], o.cres[z][1], o.cres[z][2], 0);
-    } else {
-      atomicOr(&U.ctl->err, 1);
-    }
-  }
-  // evaluated count
   unsigned long long ev = (unsigned long long)o.evaluated;
   for (int off = 32; off > 0; off >>= 1) ev += __shfl_xor(ev, off);
   __syncthreads();
@@ -127,7 +164,6 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
     for (int w = 1; w < kEvalBlock / 64; ++w)
       if (key_less(sF[w], sI[w], bf, bi)) { bf = sF[w]; bi = sI[w]; bs = sLane[w]; }
     sLane[0] = bs;
-    sF[0] = bf;
     atomicAdd((unsigned long long*)&U.ctl->evaluated, sEval);
     atomicAdd((unsigned long long*)&U.ctl->last_eval, sEval);
   }
@@ -136,13 +172,9 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
     MoveRec r;
     r.dF = o.bF;
     r.id = o.bid;
-    if (o.bF != kNoMove) {
-      r.dD = o.bm.dD;
-      r.elig = follower(o.bm);
-      r.res[0] = o.bm.res[0]; r.res[1] = o.bm.res[1]; r.res[2] = o.bm.res[2];
-    } else {
-      r.dD = 0; r.elig = 0; r.res[0] = r.res[1] = r.res[2] = -1;
-    }
+    r.dD = o.b_dD;
+    r.elig = o.b_elig;
+    r.res[0] = o.b_res0; r.res[1] = o.b_res1; r.res[2] = o.b_res2;
     r.pad = 0;
     U.wg_best[wg_slot] = r;
   }
@@ -150,10 +182,15 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
 
 // --------------------------------------------------------------------------- pair kinds
 
-template <class SEG, bool TW, bool DENSE>
+// KM != 0 fixes the kind mask at compile time (one lean kernel per family);
+// KM == 0 takes it from the argument.
+template <class SEG, bool TW, bool OPEN, bool DENSE, class AR, uint32_t KM>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __restrict__ units,
                                                           const int32_t* __restrict__ tile_off, int n_units,
-                                                          uint32_t kind_mask, DenseOut dense) {
+                                                          uint32_t kind_arg, DenseOut dense) {
+  const uint32_t kind_mask = KM ? KM : kind_arg;
+  __shared__ int s_q[kEvalBlock];
+  __shared__ int s_nq;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int ui = unit_of_tile(tile_off, n_units, tile);
   const UnitDesc& U = units[ui];
@@ -163,41 +200,55 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __res
   const int cur = U.ctl->cur;
   const SEG* fw = (const SEG*)U.fw[cur];
   const SEG* bw = (const SEG*)U.bw[cur];
-  const bool sym = !TW;
   ItemOut o;
   item_init(o);
+  Sink<DENSE> sk{&o, dense, ui};
+  AR ar;
+  if constexpr (sizeof(AR) > 1) ar.bits = U.foot;
+  if (threadIdx.x == 0) s_nq = 0;
+  __syncthreads();
+  const uint32_t intra_kinds = kind_mask & ~(1u << X2);
+  const uint32_t inter_kinds = kind_mask & ~(1u << TWOOPT);
   if (item < U.nc * U.theta) {
     const int i = item / U.theta;
     const int k = item - i * U.theta;
     const int v = U.nbr[item];
     if (k < U.nbr_len[i] && v >= 0) {
       const int u = U.nd + i;
-      RouteCtx rc[2];
       const int sa = U.rt[u], sb = U.rt[v];
-      rc[0] = route_ctx(U, cur, sa);
-      rc[1] = route_ctx(U, cur, sb);
-      const int pu = U.pos[u], pv = U.pos[v];
-      const bool intra = sa == sb;
-      Recipe R;
-      MoveEval m;
-      for (int kind = REL1; kind <= TWOOPT; ++kind) {
-        if (!(kind_mask >> kind & 1)) continue;
-        for (int var = 0; var < 4; ++var) {
-          if (!build_pair(kind, var, rc[0], pu, rc[1], pv, intra, sym, R)) continue;
-          eval_recipe<SEG, TW>(U, fw, bw, rc, R, m);
-          const uint64_t id = make_id(kind, var, u, v);
-          item_take(U, o, m, id);
-          if (DENSE) dense_put(dense, ui, m, id);
+      if (sa != sb) {
+        if (inter_kinds) {
+          const int4 ma = U.r_meta[cur][sa], mb = U.r_meta[cur][sb];
+          InterCtx x;
+          x.u = u; x.v = v; x.slotA = sa; x.slotB = sb;
+          x.LA = ma.y; x.LB = mb.y;
+          x.sA = ma.z; x.sB = mb.z;
+          x.eA = ma.w; x.eB = mb.w;
+          x.pu = U.pos[u]; x.pv = U.pos[v];
+          eval_inter<SEG, TW, OPEN>(U, fw, bw, ma.x, mb.x, x, inter_kinds, ar, sk);
         }
+      } else if (intra_kinds) {
+        s_q[atomicAdd(&s_nq, 1)] = item;
       }
     }
+  }
+  cand_flush(U, o);
+  __syncthreads();
+  // intra-route anchors of the block, packed into as few wavefronts as possible
+  const int nq = s_nq;
+  for (int e = threadIdx.x; e < nq; e += kEvalBlock) {
+    const int it = s_q[e];
+    const int i = it / U.theta;
+    const int u = U.nd + i, v = U.nbr[it];
+    const RouteCtx A = route_ctx(U, cur, U.rt[u]);
+    eval_intra<SEG, TW, OPEN>(U, fw, bw, A, u, v, U.pos[u], U.pos[v], intra_kinds, ar, sk);
   }
   item_flush(U, U.tile_base[0] + lt, o);
 }
 
 // --------------------------------------------------------------------------- depot operators
 
-template <class SEG, bool TW, bool OPEN, bool DENSE>
+template <class SEG, bool TW, bool OPEN, bool DENSE, class AR = ArcPlain>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_depot(const UnitDesc* __restrict__ units,
                                                           const int32_t* __restrict__ tile_off, int n_units,
                                                           int which, DenseOut dense) {
@@ -212,27 +263,24 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_depot(const UnitDesc* __res
   const SEG* bw = (const SEG*)U.bw[cur];
   ItemOut o;
   item_init(o);
+  Sink<DENSE> sk{&o, dense, ui};
+  AR ar;
+  if constexpr (sizeof(AR) > 1) ar.bits = U.foot;
   if (item < U.nc * U.nd) {
     const int i = item / U.nd;
     const int d = item - i * U.nd;
     const int u = U.nd + i;
-    RouteCtx rc[2];
-    rc[0] = route_ctx(U, cur, U.rt[u]);
+    const RouteCtx A = route_ctx(U, cur, U.rt[u]);
     const int pu = U.pos[u];
-    Recipe R;
     MoveEval m;
     if (which == 0) {
       // Depot-Insert: cut after u when s(u) is a customer.
-      if (pu < rc[0].L) {
-        build_dins(rc[0], pu, d, OPEN, R);
-        eval_recipe<SEG, TW>(U, fw, bw, rc, R, m);
-        const uint64_t id = make_id(DINS, 0, u, d);
-        item_take(U, o, m, id);
-        if (DENSE) dense_put(dense, ui, m, id);
+      if (pu < A.L) {
+        eval_dins<SEG, TW, OPEN>(U, fw, bw, A, pu, d, ar, m);
+        take(U, sk, m, make_id(DINS, 0, u, d));
       }
     } else if (pu == 1) {
       // Depot-Replace on the route whose first customer is u: best surviving case.
-      const RouteCtx& A = rc[0];
       bool have = false;
       MoveEval best;
       int bcase = 0;
@@ -248,15 +296,10 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_depot(const UnitDesc* __res
           if (!(s2 == A.start && e2 == A.end) && s2 == ns && e2 == ne) dup = true;
         }
         if (dup) continue;
-        build_drep(A, d, cs, R);
-        eval_recipe<SEG, TW>(U, fw, bw, rc, R, m);
+        eval_drep<SEG, TW, OPEN>(U, fw, bw, A, d, cs, ar, m);
         if (!have || m.dF < best.dF) { best = m; bcase = cs; have = true; }
       }
-      if (have) {
-        const uint64_t id = make_id(DREP, bcase, u, d);
-        item_take(U, o, best, id);
-        if (DENSE) dense_put(dense, ui, best, id);
-      }
+      if (have) take(U, sk, best, make_id(DREP, bcase, u, d));
     }
   }
   item_flush(U, U.tile_base[1 + which] + lt, o);
@@ -281,37 +324,57 @@ uint32_t eval_classes(const LaunchCtx& L, uint32_t fam_mask) {
   return cls;
 }
 
-template <class SEG, bool TW, bool OPEN>
-static void launch_eval_t(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense) {
-  const uint32_t kinds = pair_kinds(fam_mask, TW);
-  DenseOut D = dense ? *dense : DenseOut{nullptr, nullptr, 0};
-  if (kinds && L.tiles[0] > 0) {
-    if (dense)
-      hipLaunchKernelGGL((k_eval_pairs<SEG, TW, true>), dim3(L.tiles[0]), dim3(kEvalBlock), 0, L.stream, L.units,
-                         L.tile_off[0], L.n_units, kinds, D);
-    else
-      hipLaunchKernelGGL((k_eval_pairs<SEG, TW, false>), dim3(L.tiles[0]), dim3(kEvalBlock), 0, L.stream, L.units,
-                         L.tile_off[0], L.n_units, kinds, D);
+constexpr uint32_t kRelKinds = (1u << REL1) | (1u << REL2);
+constexpr uint32_t kSwpKinds = (1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (1u << SWP22);
+constexpr uint32_t kX2Kinds = 1u << X2;
+constexpr uint32_t k2optKinds = 1u << TWOOPT;
+
+template <class SEG, bool TW, bool OPEN, bool DENSE, class AR, uint32_t KM>
+static void launch_pairs(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) {
+  hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, DENSE, AR, KM>), dim3(L.tiles[0]), dim3(kEvalBlock), 0, L.stream,
+                     L.units, L.tile_off[0], L.n_units, kinds, D);
+}
+
+template <class SEG, bool TW, bool OPEN, bool DENSE, class AR>
+static void launch_class_t(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut& D) {
+  if (cls == 0) {
+    const uint32_t kinds = pair_kinds(fam_mask, TW);
+    if (!kinds || L.tiles[0] <= 0) return;
+    if (kinds == kRelKinds) launch_pairs<SEG, TW, OPEN, DENSE, AR, kRelKinds>(L, kinds, D);
+    else if (kinds == kSwpKinds) launch_pairs<SEG, TW, OPEN, DENSE, AR, kSwpKinds>(L, kinds, D);
+    else if (kinds == kX2Kinds) launch_pairs<SEG, TW, OPEN, DENSE, AR, kX2Kinds>(L, kinds, D);
+    else if (!TW && kinds == k2optKinds) launch_pairs<SEG, TW, OPEN, DENSE, AR, k2optKinds>(L, kinds, D);
+    else launch_pairs<SEG, TW, OPEN, DENSE, AR, 0u>(L, kinds, D);
+    return;
   }
-  for (int w = 0; w < 2; ++w) {
-    if (!(fam_mask >> (FAM_DINS + w) & 1) || L.tiles[1 + w] <= 0) continue;
-    if (dense)
-      hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, true>), dim3(L.tiles[1 + w]), dim3(kEvalBlock), 0, L.stream,
-                         L.units, L.tile_off[1 + w], L.n_units, w, D);
-    else
-      hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, false>), dim3(L.tiles[1 + w]), dim3(kEvalBlock), 0, L.stream,
-                         L.units, L.tile_off[1 + w], L.n_units, w, D);
+  const int w = cls - 1;
+  if (!(fam_mask >> (FAM_DINS + w) & 1) || L.tiles[1 + w] <= 0) return;
+  hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, DENSE, AR>), dim3(L.tiles[1 + w]), dim3(kEvalBlock), 0, L.stream,
+                     L.units, L.tile_off[1 + w], L.n_units, w, D);
+}
+
+template <bool DENSE, class AR>
+static void launch_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut& D) {
+  if (L.has_tw) {
+    if (L.open) launch_class_t<SegTW, true, true, DENSE, AR>(L, fam_mask, cls, D);
+    else launch_class_t<SegTW, true, false, DENSE, AR>(L, fam_mask, cls, D);
+  } else {
+    if (L.open) launch_class_t<SegNT, false, true, DENSE, AR>(L, fam_mask, cls, D);
+    else launch_class_t<SegNT, false, false, DENSE, AR>(L, fam_mask, cls, D);
   }
 }
 
+void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut* dense) {
+  if (dense) launch_class<true, ArcPlain>(L, fam_mask, cls, *dense);
+  else launch_class<false, ArcPlain>(L, fam_mask, cls, DenseOut{nullptr, nullptr, 0});
+}
+
 void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense) {
-  if (L.has_tw) {
-    if (L.open) launch_eval_t<SegTW, true, true>(L, fam_mask, dense);
-    else launch_eval_t<SegTW, true, false>(L, fam_mask, dense);
-  } else {
-    if (L.open) launch_eval_t<SegNT, false, true>(L, fam_mask, dense);
-    else launch_eval_t<SegNT, false, false>(L, fam_mask, dense);
-  }
+  for (int c = 0; c < 3; ++c) launch_eval_class(L, fam_mask, c, dense);
+}
+
+void launch_eval_footprint(const LaunchCtx& L, uint32_t fam_mask, int cls) {
+  launch_class<false, ArcFoot>(L, fam_mask, cls, DenseOut{nullptr, nullptr, 0});
 }
 
 int eval_block_size() { return kEvalBlock; }

@@ -34,7 +34,7 @@ __device__ __forceinline__ SegNT mid_range<SegNT, false>(const UnitDesc& U, cons
   SegNT r;
   r.C = b.C - a.C;
   r.Q = b.Q - p.Q;
-  r.D = b.D - a.D + U.s[a.node];
+  r.D = b.D - a.D + service(U, a.node);
   r.node = rev ? a.node : b.node;
   return r;
 }
@@ -53,10 +53,24 @@ __device__ __forceinline__ SegTW mid_range<SegTW, true>(const UnitDesc& U, const
   return acc;
 }
 
+// Matrix access policies: the plain one reads c and t; the footprint one also
+// marks every entry it reads in a bitmap (measurement of the distinct matrix
+// bytes a launch needs).
+struct ArcPlain {
+  __device__ __forceinline__ void mark(const UnitDesc&, int, int) const {}
+};
+struct ArcFoot {
+  uint32_t* bits;
+  __device__ __forceinline__ void mark(const UnitDesc& U, int a, int b) const {
+    const uint64_t i = (uint64_t)a * U.n + b;
+    atomicOr(&bits[i >> 5], 1u << (i & 31));
+  }
+};
+
 // Total segment of a new route: start depot, pieces, end depot (-1 = open).
-template <class SEG, bool TW>
+template <class SEG, bool TW, class AR = ArcPlain>
 __device__ SEG eval_route(const UnitDesc& U, const SEG* fw, const SEG* bw, const RouteCtx* rc, int start, int end,
-                          const Piece* pc, int np) {
+                          const Piece* pc, int np, const AR& ar = AR()) {
   SEG acc;
   int last;
   int k = 0;
@@ -79,6 +93,7 @@ __device__ SEG eval_route(const UnitDesc& U, const SEG* fw, const SEG* bw, const
     const Piece& p = pc[k];
     const RouteCtx& cx = rc[p.src];
     const int first = p.rev ? node_at(fw, cx.off + p.to) : node_at(fw, cx.off + p.from);
+    ar.mark(U, last, first);
     const int32_t cab = arc_c(U, last, first);
     const int32_t tab = TW ? arc_t(U, last, first) : (U.t_is_c ? cab : arc_t(U, last, first));
     if (k == np - 1 && !p.rev && p.to == cx.L && end == cx.end) {
@@ -94,6 +109,7 @@ __device__ SEG eval_route(const UnitDesc& U, const SEG* fw, const SEG* bw, const
     }
   }
   if (end >= 0) {
+    ar.mark(U, last, end);
     const int32_t cab = arc_c(U, last, end);
     const int32_t tab = U.t_is_c ? cab : arc_t(U, last, end);
     acc = cat(acc, cab, tab, node_seg<SEG>(U, end));
@@ -108,9 +124,9 @@ struct MoveEval {
 };
 
 // Delta of a recipe against the routes it replaces.
-template <class SEG, bool TW>
+template <class SEG, bool TW, class AR = ArcPlain>
 __device__ __forceinline__ void eval_recipe(const UnitDesc& U, const SEG* fw, const SEG* bw, const RouteCtx* rc,
-                                            const Recipe& R, MoveEval& o) {
+                                            const Recipe& R, MoveEval& o, const AR& ar = AR()) {
   int64_t dc = 0;
   int32_t dD = 0, dTW = 0, dLX = 0, dDX = 0, dCL = 0;
   int32_t dep[4], dd[4];
@@ -133,7 +149,7 @@ __device__ __forceinline__ void eval_recipe(const UnitDesc& U, const SEG* fw, co
   }
   for (int w = 0; w < R.nnew; ++w) {
     if (R.np[w] == 0) continue;  // an emptied route is deleted
-    const SEG s = eval_route<SEG, TW>(U, fw, bw, rc, R.st[w], R.en[w], R.pc[w], R.np[w]);
+    const SEG s = eval_route<SEG, TW, AR>(U, fw, bw, rc, R.st[w], R.en[w], R.pc[w], R.np[w], ar);
     const RouteTerms t = route_terms(U, s);
     dc += t.cost;
     dD += t.C;
@@ -167,12 +183,13 @@ __device__ __forceinline__ bool follower(const MoveEval& m) {
 }
 
 __device__ __forceinline__ RouteCtx route_ctx(const UnitDesc& U, int cur, int slot) {
+  const int4 m = U.r_meta[cur][slot];
   RouteCtx c;
   c.slot = slot;
-  c.off = U.r_off[cur][slot];
-  c.L = U.r_len[slot];
-  c.start = U.r_start[slot];
-  c.end = U.r_end[slot];
+  c.off = m.x;
+  c.L = m.y;
+  c.start = m.z;
+  c.end = m.w;
   return c;
 }
 

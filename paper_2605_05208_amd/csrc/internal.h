@@ -76,6 +76,7 @@ struct UnitDesc {
   // instance
   const int32_t *c, *t, *q, *s, *e, *l;
   const int32_t *nbr, *nbr_len;
+  const int4* attr;  // per node {q, s, e, l}
   int32_t nd, nc, n, theta;
   int32_t Q, NV, Dmax, w_tw, w_load, w_dur;
   int64_t w_depot;
@@ -84,6 +85,7 @@ struct UnitDesc {
   int32_t *rt, *pos;
   int32_t *r_len, *r_start, *r_end;
   int32_t *r_off[2];
+  int4* r_meta[2];  // per buffer and slot {offset, length, start depot, end depot}
   int4* r_tot;      // {C, Q, D, TW} of every route
   int64_t* r_cost;  // penalised route cost
   void* fw[2];
@@ -109,6 +111,7 @@ struct UnitDesc {
   int32_t tile_base[4];  // first tile of each item class (pairs, dins, drep, end)
   int32_t key_shift;     // bit position of dD in the packed follower key
   int32_t pad1;
+  uint32_t* foot;        // footprint bitmap of this unit's instance (measurement launches only)
 };
 
 // ---------------------------------------------------------------------------- segment algebra
@@ -144,15 +147,18 @@ __device__ __forceinline__ SegTW cat(const SegTW& a, int32_t cab, int32_t tab, c
 
 template <class SEG> __device__ __forceinline__ SEG node_seg(const UnitDesc& U, int x);
 template <> __device__ __forceinline__ SegNT node_seg<SegNT>(const UnitDesc& U, int x) {
+  const int4 a = U.attr[x];
   SegNT r;
-  r.C = 0; r.Q = U.q[x]; r.D = U.s[x]; r.node = x;
+  r.C = 0; r.Q = a.x; r.D = a.y; r.node = x;
   return r;
 }
 template <> __device__ __forceinline__ SegTW node_seg<SegTW>(const UnitDesc& U, int x) {
+  const int4 a = U.attr[x];
   SegTW r;
-  r.C = 0; r.Q = U.q[x]; r.D = U.s[x]; r.TW = 0; r.E = U.e[x]; r.L = U.l[x]; r.node = x; r.aux = 0;
+  r.C = 0; r.Q = a.x; r.D = a.y; r.TW = 0; r.E = a.z; r.L = a.w; r.node = x; r.aux = 0;
   return r;
 }
+__device__ __forceinline__ int32_t service(const UnitDesc& U, int x) { return U.attr[x].y; }
 
 __device__ __forceinline__ int32_t seg_tw(const SegNT&) { return 0; }
 __device__ __forceinline__ int32_t seg_tw(const SegTW& s) { return s.TW; }

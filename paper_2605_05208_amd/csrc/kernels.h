@@ -27,6 +27,10 @@ struct LaunchCtx {
 
 int eval_block_size();
 void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense);
+// One item class: 0 pair kinds, 1 depot-insert, 2 depot-replace (no launch when it has no work).
+void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut* dense);
+// Same evaluation, also marking every matrix entry read in the units' footprint bitmaps.
+void launch_eval_footprint(const LaunchCtx& L, uint32_t fam_mask, int cls);
 // Item classes an evaluation of fam_mask fills (bit 0 pairs, 1 depot-insert, 2 depot-replace).
 uint32_t eval_classes(const LaunchCtx& L, uint32_t fam_mask);
 void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only);
@@ -45,6 +49,9 @@ void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][8] */);
 void launch_inst_stats(hipStream_t s, const int32_t* c, const int32_t* t, int n, int64_t* partial, int nblocks);
 int inst_stats_blocks(int n);
 void launch_inst_stats_final(hipStream_t s, const int64_t* partial, int nblocks, int64_t* out);
+// Packs q, s, e, l into one int4 per node.
+void launch_node_attr(hipStream_t s, const int32_t* q, const int32_t* sv, const int32_t* e, const int32_t* l, int n,
+                      int4* attr);
 void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* sv, const int32_t* ev,
                       const int32_t* lv, int nd, int nc, int theta, int has_tw, int64_t gnum, int64_t gden,
                       int32_t* nbr, int32_t* nbr_len);

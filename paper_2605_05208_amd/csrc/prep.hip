@@ -183,6 +183,17 @@ __global__ __launch_bounds__(kNbrBlock) void k_nbr_lists(const int32_t* __restri
   }
 }
 
+__global__ void k_node_attr(const int32_t* __restrict__ q, const int32_t* __restrict__ sv,
+                            const int32_t* __restrict__ e, const int32_t* __restrict__ l, int n, int4* __restrict__ attr) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < n) attr[x] = make_int4(q[x], sv[x], e[x], l[x]);
+}
+
+void launch_node_attr(hipStream_t s, const int32_t* q, const int32_t* sv, const int32_t* e, const int32_t* l, int n,
+                      int4* attr) {
+  hipLaunchKernelGGL(k_node_attr, dim3((n + 255) / 256), dim3(256), 0, s, q, sv, e, l, n, attr);
+}
+
 void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* sv, const int32_t* ev,
                       const int32_t* lv, int nd, int nc, int theta, int has_tw, int64_t gnum, int64_t gden,
                       int32_t* nbr, int32_t* nbr_len) {

@@ -272,6 +272,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     const int ax = block_scan(len > 0 ? 1 : 0, sh, &tot2);
     if (s < U.R) {
       U.r_off[dst][s] = carry + ex;
+      U.r_meta[dst][s] = make_int4(carry + ex, len, len > 0 ? U.r_start[s] : -1, len > 0 ? U.r_end[s] : -1);
       if (len > 0) U.slot_list[alive_carry + ax] = s;
     }
     carry += tot;

@@ -188,6 +188,7 @@ __global__ __launch_bounds__(kUnitBlock) void k_load_table(const UnitDesc* __res
     const int e2 = block_scan_excl<kUnitBlock>(len > 0 ? 1 : 0, sh, &tot2);
     if (s < U.R) {
       U.r_off[0][s] = carry + e1;
+      U.r_meta[0][s] = make_int4(carry + e1, len, len > 0 ? U.r_start[s] : -1, len > 0 ? U.r_end[s] : -1);
       if (len > 0) U.slot_list[alive_carry + e2] = s;
     }
     carry += tot1;

@@ -61,7 +61,9 @@ EXPORTED = [
     "mdvrp_validate_solutions_host", "mdvrp_solutions_load", "mdvrp_solutions_export", "mdvrp_batch_cost",
     "mdvrp_batch_state", "mdvrp_eval_neighbourhood", "mdvrp_select_multimove", "mdvrp_apply_moves",
     "mdvrp_local_search_to_optimum", "mdvrp_status_string", "mdvrp_last_error", "mdvrp_family_order",
+    "mdvrp_profile_enable", "mdvrp_profile_read", "mdvrp_eval_footprint",
 ]
+PROF_CLASSES = ["eval_pairs", "eval_depot_insert", "eval_depot_replace", "select", "apply"]
 
 
 def lib():
@@ -90,6 +92,9 @@ def lib():
             "mdvrp_apply_moves": [p, p],
             "mdvrp_local_search_to_optimum": [p, p, p, p],
             "mdvrp_family_order": [i32, u64, i64, p],
+            "mdvrp_profile_enable": [p, u32, i32],
+            "mdvrp_profile_read": [p, p, p],
+            "mdvrp_eval_footprint": [p, u32, p, i64, p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -256,6 +261,21 @@ class Batch:
         check(lib().mdvrp_batch_state(self.handle, out.ctypes.data_as(C.c_void_p)))
         return out.reshape(self.n_units, 8)
 
+    def load_device(self, nodes, offs, starts, ends, unit_route_off, n_routes, n_nodes):
+        """Load from device tensors already resident in HBM (int32)."""
+        check(lib().mdvrp_solutions_load(self.handle, _dptr(nodes), _dptr(offs), _dptr(starts), _dptr(ends),
+                                         _dptr(unit_route_off), n_routes, n_nodes, _stream()))
+
+    def profile_enable(self, class_mask=0x1F, max_launches=1 << 16):
+        """Time the kernel classes in class_mask (bit k = PROF_CLASSES[k]); 0 turns timing off."""
+        check(lib().mdvrp_profile_enable(self.handle, class_mask, max_launches))
+
+    def profile_read(self):
+        n = np.zeros(8, np.int64)
+        ms = np.zeros(8, np.float64)
+        check(lib().mdvrp_profile_read(self.handle, n.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p)))
+        return {name: (int(n[k]), float(ms[k])) for k, name in enumerate(PROF_CLASSES)}
+
     # ------------------------------------------------------------------ hot path
     def eval_neighbourhood(self, fam_mask=FAM_ALL, dense_cap=0):
         torch = _torch()
@@ -271,6 +291,19 @@ class Batch:
             return np.frombuffer(rec[:n * DENSE_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=DENSE_DTYPE)
         check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, 0, None, 0, None, _stream()))
         return None
+
+    def eval_footprint(self, fam_mask=FAM_ALL):
+        """Distinct matrix entries (c/t) the evaluation of fam_mask reads, per instance."""
+        torch = _torch()
+        words = [(i.inst.N * i.inst.N + 31) // 32 for i in self.instances]
+        bits = torch.zeros(sum(words), dtype=torch.int32, device="cuda")
+        check(lib().mdvrp_eval_footprint(self.handle, fam_mask, _dptr(bits), sum(words), _stream()))
+        b = bits.cpu().numpy().view(np.uint32)
+        out, at = [], 0
+        for w in words:
+            out.append(int(np.unpackbits(b[at:at + w].view(np.uint8)).sum()))
+            at += w
+        return out
 
     def select_multimove(self, fam_mask=FAM_ALL, leader_only=0, want=True):
         torch = _torch()
