@@ -22,7 +22,8 @@ KIND_NAMES = ["REL1", "REL2", "SWP11", "SWP21", "SWP12", "SWP22", "X2", "2OPT", 
 
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-fopenmp", "-shared", "-fPIC", "-o", LIB_PATH] + srcs + ["-lm"]
+    cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-o", LIB_PATH] \
+        + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -77,6 +78,16 @@ def lib():
                                p, p, p, p, p, p, p, p, p]
         L.ref_local_search.argtypes = [p, p, p, C.c_int32, p, p, p, p, p, p, p, p, p, p, p, p]
         L.ref_apply_ids.argtypes = [p, C.c_int32, p, p, p, p, p, C.c_int32, p, p, p, p, p]
+        L.ref_filter_features.argtypes = [p, p, p, C.c_int32, p, p, p, p, p]
+        L.ref_mlp_param_count.restype = C.c_int32
+        L.ref_mlp_forward.argtypes = [p, p, C.c_int32, C.c_int32, p]
+        L.ref_mlp_backward.argtypes = [p, p, C.c_int32, p, C.c_int32, p]
+        L.ref_bce.argtypes = [p, p, p, C.c_int32]
+        L.ref_bce.restype = C.c_double
+        L.ref_adam.argtypes = [p, p, p, p, C.c_int32, C.c_float, C.c_int32]
+        L.ref_topk.argtypes = [p, p, C.c_int32, C.c_int32, p, C.c_int32, p]
+        L.ref_bf16.argtypes = [C.c_float]
+        L.ref_bf16.restype = C.c_uint16
         L.ref_family_order.argtypes = [C.c_int32, C.c_uint64, C.c_int64, p]
         L.ref_family_order.restype = C.c_int32
         _lib = L
@@ -200,6 +211,60 @@ class Ref:
         st_list = [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F)
                    for s in stats]
         return out, st_list
+
+
+    def features(self, sol):
+        nbr, ln = self.neighbours()
+        nodes, offs, st, en = sol.flat()
+        out = np.zeros(self.inst.n_customers * self.inst.theta * 32, np.uint16)
+        lib().ref_filter_features(self.dref, _ptr(nbr), _ptr(ln), len(st), _ptr(nodes), _ptr(offs), _ptr(st),
+                                  _ptr(en), _ptr(out))
+        return out.reshape(self.inst.n_customers * self.inst.theta, 32)
+
+
+N_PARAMS = 74497
+
+
+def mlp_forward(params, x, round_act=1):
+    params = np.ascontiguousarray(params, np.float32)
+    x = np.ascontiguousarray(x, np.uint16)
+    out = np.zeros(len(x), np.float64)
+    lib().ref_mlp_forward(_ptr(params), _ptr(x), len(x), round_act, _ptr(out))
+    return out
+
+
+def mlp_backward(params, x, dlogits, round_act=1):
+    params = np.ascontiguousarray(params, np.float32)
+    x = np.ascontiguousarray(x, np.uint16)
+    d = np.ascontiguousarray(dlogits, np.float64)
+    g = np.zeros(N_PARAMS, np.float64)
+    lib().ref_mlp_backward(_ptr(params), _ptr(x), len(x), _ptr(d), round_act, _ptr(g))
+    return g
+
+
+def bce(logits, labels, weights=None):
+    z = np.ascontiguousarray(logits, np.float64)
+    y = np.ascontiguousarray(labels, np.float32)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float32)
+    return lib().ref_bce(_ptr(z), _ptr(y), None if w is None else _ptr(w), len(z))
+
+
+def adam(params, m, v, grads, lr, step):
+    for a in (params, m, v):
+        assert a.dtype == np.float32 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grads, np.float32)
+    lib().ref_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(g), len(params), lr, step)
+
+
+def topk(nbr, nbr_len, n_customers, theta, score, k):
+    out = np.zeros(n_customers * k, np.int32)
+    lib().ref_topk(_ptr(np.ascontiguousarray(nbr, np.int32)), _ptr(np.ascontiguousarray(nbr_len, np.int32)),
+                   n_customers, theta, _ptr(np.ascontiguousarray(score, np.float32)), k, _ptr(out))
+    return out.reshape(n_customers, k)
+
+
+def bf16(x):
+    return np.array([lib().ref_bf16(float(v)) for v in np.ravel(x)], np.uint16)
 
 
 def family_order(has_tw: int, seed: int, p: int):

@@ -110,6 +110,32 @@ int ref_local_search(const ref_instance* I, const int32_t* nbr, const int32_t* n
                      const ref_ls_options* opt, int32_t* o_nodes, int32_t* o_offs,
                      int32_t* o_start, int32_t* o_end, int32_t* o_sol_offs, ref_ls_stats* stats);
 
+/* ---- learned move filter (mlp_ref.c) ---- */
+
+/* fp32 -> bf16, round to nearest even; bf16 -> fp32. */
+uint16_t ref_bf16(float f);
+float ref_bf16_to_f32(uint16_t h);
+
+/* 32 bf16 features of every anchor (u, k-th entry of N(u)):
+ * out[((u - n_depots)*theta + k)*32 + f]; rows of missing entries are zero. */
+int ref_filter_features(const ref_instance* I, const int32_t* nbr, const int32_t* nbr_len, int32_t n_routes,
+                        const int32_t* nodes, const int32_t* offs, const int32_t* start, const int32_t* end,
+                        uint16_t* out);
+
+/* MLP 32 -> 256 -> 256 -> 1 (ReLU). Parameters fp32, layout W1[256][32], b1[256],
+ * W2[256][256], b2[256], w3[256], b3. round_act = 1 rounds weights, input and
+ * hidden activations to bf16 where the GPU path does. */
+int ref_mlp_param_count(void);
+int ref_mlp_forward(const float* params, const uint16_t* x, int32_t n, int32_t round_act, double* logits);
+/* gradient of sum_p dlogits[p] * logit_p (fp64) */
+int ref_mlp_backward(const float* params, const uint16_t* x, int32_t n, const double* dlogits, int32_t round_act,
+                     double* grads);
+double ref_bce(const double* logits, const float* labels, const float* weights, int32_t n);
+int ref_adam(float* params, float* m, float* v, const float* grads, int32_t n, float lr, int32_t step);
+/* k largest scores per customer (ties -> lower customer id), -1 padding */
+int ref_topk(const int32_t* nbr, const int32_t* nbr_len, int32_t n_customers, int32_t theta, const float* score,
+             int32_t k, int32_t* out);
+
 /* Family order of pass p: Fisher-Yates driven by SplitMix64 seeded with seed ^ p. */
 int ref_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam_out);
 
