@@ -158,9 +158,10 @@ mdvrp_status mdvrp_solutions_export(const mdvrp_batch* batch, int32_t* route_nod
  * terms nullable). */
 mdvrp_status mdvrp_batch_cost(mdvrp_batch* batch, int64_t* F, int64_t* terms, void* stream);
 
-/* Host copy of per-unit counters, 8 per unit: running F, evaluated moves,
+/* Host copy of per-unit counters, 10 per unit: running F, evaluated moves,
  * passes, steps, moves applied, error bits, active flag, moves selected in
- * the latest step. Synchronises. */
+ * the latest step, full-list fallback passes of a filtered search, current
+ * list mode (0 full, 1 filtered, 2 full fallback pass). Synchronises. */
 mdvrp_status mdvrp_batch_state(const mdvrp_batch* batch, int64_t* out_host);
 
 /* ------------------------------------------------------------------------- hot path */
@@ -175,6 +176,9 @@ typedef struct {
 } mdvrp_dense_rec;
 
 #define MDVRP_EVAL_DENSE 0x1u
+/* Pair families evaluate the filtered candidate lists of an attached filter
+ * (mdvrp_filter_attach) instead of the granular lists. */
+#define MDVRP_EVAL_FILTERED 0x2u
 
 /* Evaluate, in parallel, the penalised delta of every move of the families in
  * family_mask for every active unit (paper Sections 3.2.1-3.2.4: Eq. A.1
@@ -209,21 +213,39 @@ mdvrp_status mdvrp_apply_moves(mdvrp_batch* batch, void* stream);
 #define MDVRP_LS_PASSES 0 /* Algorithm 2: per pass, every family in a seeded random order */
 #define MDVRP_LS_UNION 1  /* every step evaluates all families together */
 
+typedef struct mdvrp_mlp mdvrp_mlp;
+
+#define MDVRP_FILTER_NONE 0  /* pair moves over the granular lists */
+#define MDVRP_FILTER_LISTS 1 /* pair moves over the attached filter's lists as they stand */
+#define MDVRP_FILTER_MLP 2   /* lists re-ranked by the network whenever their features change */
+
 typedef struct {
   int32_t mode;        /* MDVRP_LS_PASSES or MDVRP_LS_UNION */
   int32_t leader_only; /* 1 = single-move steps (the paper's ETGA-S) */
   int32_t max_passes;  /* search depth delta; 0 = until a local optimum */
   int32_t poll_every;  /* passes between host convergence checks (>= 1) */
   uint64_t seed;       /* family order of pass p: Fisher-Yates with SplitMix64(seed ^ p) */
+  int32_t filter;      /* MDVRP_FILTER_*; a filter needs mdvrp_filter_attach first */
+  int32_t pad;
+  const mdvrp_mlp* mlp; /* network of MDVRP_FILTER_MLP, else ignored */
 } mdvrp_ls_options;
 
 typedef struct {
   int64_t passes, steps, moves_applied, evaluated, F;
+  int64_t fallback_passes; /* passes of a filtered search that evaluated the full lists */
   int32_t converged, err;
 } mdvrp_ls_stats;
 
 /* Local search to a local optimum for every unit of the batch (Algorithm 2 with
- * the multi-move step). A unit stops when a full pass applies nothing. stats
+ * the multi-move step). A unit stops when a full pass applies nothing. With a
+ * filter, pair moves are first drawn from the filtered lists; when a pass over
+ * the filtered lists applies nothing, the next pass evaluates the full
+ * granular lists: if that pass improves, the unit returns to the filtered
+ * lists, otherwise it stops -- at a local optimum of the full neighbourhood
+ * either way. With MDVRP_FILTER_MLP the lists of every customer whose
+ * features may have changed (its route, or the route of an entry of its
+ * granular list, was rebuilt since the last ranking) are re-ranked before
+ * each pair-family step; the first step ranks all of them. stats
  * (HOST array of n_units, nullable) receives per-unit results. Synchronises.
  * Errors: ERANGE when a route grew beyond the int32-safe length, ENOSPC on
  * internal capacity overflow, EDEVICE. */
@@ -238,6 +260,7 @@ mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* batch, const mdvrp_ls_op
 #define MDVRP_PROF_EVAL_DEPOT_REPLACE 2
 #define MDVRP_PROF_SELECT 3
 #define MDVRP_PROF_APPLY 4
+#define MDVRP_PROF_FILTER_SCORE 5
 
 /* Turn per-launch timing on (class_mask != 0) or off for a batch. Every launch
  * of a kernel class whose bit (1 << MDVRP_PROF_*) is set in class_mask is
@@ -259,6 +282,95 @@ mdvrp_status mdvrp_profile_read(mdvrp_batch* batch, int64_t* launches, double* m
  * The results of the evaluation itself are discarded. Synchronises. */
 mdvrp_status mdvrp_eval_footprint(mdvrp_batch* batch, uint32_t family_mask, uint32_t* bitmap, int64_t bitmap_words,
                                   void* stream);
+
+/* ------------------------------------------------------------------------- learned move filter
+ *
+ * The paper restricts every operator to granular lists (Section 3.2.3, Eq. 3).
+ * The filter ranks each customer u's granular list N(u) with a network and
+ * keeps the k best entries for exact evaluation.
+ *
+ * Features: 32 per anchor (u, v = k-th entry of N(u)), from exact integers:
+ *   0 c(u,v) 1 c(p(u),u) 2 c(u,s(u)) 3 c(p(u),s(u)) 4 c(p(v),v) 5 c(p(v),u)
+ *   6 distance delta of relocating u before v, 7 of the 2-opt* move joining
+ *   u -> v, 8 of swapping u with p(v) (s(u) of an open route's last customer
+ *   contributes 0; pp(v) = p(v) when p(v) is a depot);
+ *   9, 10 load - Q of u's and v's routes; 11 q_u; 12 q_v; 13, 14 duration -
+ *   Dmax of both routes (0 without a limit); 15, 16 time warp of both routes;
+ *   17, 18 window widths of u and v; 19 e_u; 20 e_v; 21 max(e_v - e_u - s_u -
+ *   t(u,v), 0); 22 max(e_u + s_u + t(u,v) - l_v, 0) (17..22 are 0 without
+ *   time windows); 23 same route; 24 same start depot; 25, 26 start depots;
+ *   27, 28 route lengths; 29, 30 positions of u and v; 31 k.
+ * Each integer is converted to fp32 and multiplied (one rounding) by an fp32
+ * scale, then rounded to bf16 (nearest even): 0..8 by 1/dbar, dbar = integer
+ * mean of c(u, first entry of N(u)) (at least 1); 9..12 by 1/Q; 13..22 by 1/H,
+ * H = l - e of depot 0 with time windows, else 1; 23, 24 by 1; 25, 26 by
+ * 1/n_depots; 27, 28 by 1/32; 29 by 1/length(u's route); 30 by 1/length(v's
+ * route); 31 by 1/theta.
+ * Network: logit = w3 . relu(W2 relu(W1 x + b1) + b2) + b3, 32 -> 256 -> 256
+ * -> 1; bf16 weights and inputs, fp32 accumulation, hidden activations
+ * rounded to bf16. Parameters (fp32 master copy, MDVRP_MLP_PARAMS floats):
+ * W1[256][32], b1[256], W2[256][256], b2[256], w3[256], b3.
+ * Per-anchor arrays of a batch (features, labels, logits) hold units in batch
+ * order, each n_customers * theta anchors, anchor (i, k) at i * theta + k. */
+#define MDVRP_MLP_PARAMS 74497
+
+mdvrp_status mdvrp_mlp_workspace_query(size_t* bytes);
+/* params_init: DEVICE fp32[MDVRP_MLP_PARAMS] copied in, or NULL for zeros.
+ * Adam moments start at zero. */
+mdvrp_status mdvrp_mlp_create(void* ws, size_t ws_bytes, const float* params_init, void* stream, mdvrp_mlp** out);
+/* Device pointer to the fp32 master parameters inside the workspace. After
+ * writing them, call mdvrp_mlp_sync. */
+mdvrp_status mdvrp_mlp_params(mdvrp_mlp* mlp, float** params);
+/* Refresh the bf16 operand copies from the master parameters; reset_adam = 1
+ * also zeroes the Adam moments. */
+mdvrp_status mdvrp_mlp_sync(mdvrp_mlp* mlp, int32_t reset_adam, void* stream);
+void mdvrp_mlp_destroy(mdvrp_mlp* mlp);
+/* Bytes of the activation workspace for n samples (training calls). */
+mdvrp_status mdvrp_mlp_act_bytes(int32_t n, size_t* bytes);
+/* logits[n] (DEVICE fp32) of x[n][32] (DEVICE bf16 bits). act_ws (nullable)
+ * keeps the hidden activations for mdvrp_mlp_backward. */
+mdvrp_status mdvrp_mlp_forward(const mdvrp_mlp* mlp, const uint16_t* x, int32_t n, float* logits, void* act_ws,
+                               size_t act_bytes, void* stream);
+/* grads (DEVICE fp32[MDVRP_MLP_PARAMS], overwritten) = gradient of
+ * sum_p dlogits[p] * logit_p, using the activations a forward pass over the
+ * same x and parameters left in act_ws. */
+mdvrp_status mdvrp_mlp_backward(const mdvrp_mlp* mlp, const uint16_t* x, const float* dlogits, int32_t n,
+                                float* grads, void* act_ws, size_t act_bytes, void* stream);
+/* Weighted mean binary cross-entropy with logits: *loss (DEVICE, nullable) =
+ * sum w_p l_p / sum w_p, dlogits_p = w_p (sigmoid(z_p) - y_p) / sum w_p;
+ * weights NULL = all 1. Uses the network's scratch. */
+mdvrp_status mdvrp_mlp_bce(mdvrp_mlp* mlp, const float* logits, const float* labels, const float* weights, int32_t n,
+                           float* dlogits, float* loss, void* stream);
+/* Adam (beta 0.9 / 0.999, eps 1e-8, bias-corrected, step >= 1) on the master
+ * parameters, then refresh of the bf16 copies. */
+mdvrp_status mdvrp_adam_step(mdvrp_mlp* mlp, const float* grads, float lr, int32_t step, void* stream);
+/* forward + BCE + backward + Adam on one batch of n samples. */
+mdvrp_status mdvrp_mlp_train_step(mdvrp_mlp* mlp, const uint16_t* x, const float* labels, const float* weights,
+                                  int32_t n, float lr, int32_t step, float* grads, float* logits, float* loss,
+                                  void* act_ws, size_t act_bytes, void* stream);
+
+/* Candidate lists of k entries per customer for every unit of a batch
+ * (1 <= k <= theta of every instance); attaching sets them to the first k
+ * entries of the granular lists. */
+mdvrp_status mdvrp_filter_workspace_query(const mdvrp_batch* batch, int32_t k, size_t* bytes);
+mdvrp_status mdvrp_filter_attach(mdvrp_batch* batch, int32_t k, void* ws, size_t ws_bytes, void* stream);
+/* Number of anchors of the batch (sum of n_customers * theta over units). */
+mdvrp_status mdvrp_filter_anchor_count(const mdvrp_batch* batch, int64_t* n);
+/* Features of every anchor of the current solutions: feats[anchor][32] (DEVICE
+ * bf16 bits; rows of missing list entries are zero). */
+mdvrp_status mdvrp_filter_features(mdvrp_batch* batch, uint16_t* feats, void* stream);
+/* Training labels: labels[anchor] (DEVICE, zeroed by the caller) is set to 1
+ * when some pair move of the families in family_mask anchored at it has
+ * dF < 0 in the current solution (the evaluation of the full lists). */
+mdvrp_status mdvrp_filter_labels(mdvrp_batch* batch, uint32_t family_mask, uint8_t* labels, void* stream);
+/* Rank every customer's granular list by the network and keep the k best
+ * entries (logit descending, customer id ascending; -1 padding); logits
+ * (DEVICE, nullable) receives every anchor's logit. */
+mdvrp_status mdvrp_filter_score_topk(mdvrp_batch* batch, const mdvrp_mlp* mlp, float* logits, void* stream);
+/* The heuristic lists: the first k entries of each granular list. */
+mdvrp_status mdvrp_filter_eta_lists(mdvrp_batch* batch, void* stream);
+/* cand[unit][customer][k] (DEVICE int32), units in batch order. */
+mdvrp_status mdvrp_filter_export(const mdvrp_batch* batch, int32_t* cand, void* stream);
 
 /* ------------------------------------------------------------------------- misc */
 

@@ -138,14 +138,26 @@ class Ref:
         lib().ref_cost(self.dref, len(st), _ptr(nodes), _ptr(offs), _ptr(st), _ptr(en), _ptr(F), _ptr(terms))
         return int(F[0]), terms
 
-    def eval(self, sol, fam_mask=ALL_FAMILIES):
-        nbr, ln = self.neighbours()
+    def _lists(self, lists):
+        """(descriptor, nbr, nbr_len) for the granular lists, or for caller lists
+        (nbr [n_customers * stride], nbr_len, stride) evaluated in their place."""
+        if lists is None:
+            nbr, ln = self.neighbours()
+            return self.dref, nbr, ln
+        nbr, ln, stride = lists
+        d = RefInstance(*[getattr(self.desc, f) for f, _ in RefInstance._fields_])
+        d.theta = int(stride)
+        self._keep_lists = (d, np.ascontiguousarray(nbr, np.int32), np.ascontiguousarray(ln, np.int32))
+        return C.byref(d), self._keep_lists[1], self._keep_lists[2]
+
+    def eval(self, sol, fam_mask=ALL_FAMILIES, lists=None):
+        dref, nbr, ln = self._lists(lists)
         nodes, offs, st, en = sol.flat()
         cnt = np.zeros(1, np.int64)
         cap = 1 << 16
         while True:
             out = np.zeros(cap, MOVE_DTYPE)
-            rc = lib().ref_eval(self.dref, _ptr(nbr), _ptr(ln), len(st), _ptr(nodes), _ptr(offs), _ptr(st),
+            rc = lib().ref_eval(dref, _ptr(nbr), _ptr(ln), len(st), _ptr(nodes), _ptr(offs), _ptr(st),
                                 _ptr(en), fam_mask, _ptr(out), cap, _ptr(cnt))
             if rc == -3:
                 cap = int(cnt[0])
@@ -153,9 +165,9 @@ class Ref:
             assert rc == 0, rc
             return out[:int(cnt[0])]
 
-    def step(self, sol, fam_mask, leader_only=0):
+    def step(self, sol, fam_mask, leader_only=0, lists=None):
         from paper_2605_05208_amd.gen import Solution
-        nbr, ln = self.neighbours()
+        dref, nbr, ln = self._lists(lists)
         nodes, offs, st, en = sol.flat()
         nc = self.inst.n_customers
         o_nr = np.zeros(1, np.int32)
@@ -167,7 +179,7 @@ class Ref:
         sel_dF = np.zeros(nc + 1, np.int64)
         n_sel = np.zeros(1, np.int32)
         n_eval = np.zeros(1, np.int64)
-        lib().ref_step(self.dref, _ptr(nbr), _ptr(ln), len(st), _ptr(nodes), _ptr(offs), _ptr(st), _ptr(en),
+        lib().ref_step(dref, _ptr(nbr), _ptr(ln), len(st), _ptr(nodes), _ptr(offs), _ptr(st), _ptr(en),
                        fam_mask, leader_only, _ptr(o_nr), _ptr(o_nodes), _ptr(o_offs), _ptr(o_st), _ptr(o_en),
                        _ptr(sel_ids), _ptr(sel_dF), _ptr(n_sel), _ptr(n_eval))
         nr = int(o_nr[0])

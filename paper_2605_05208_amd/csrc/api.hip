@@ -70,6 +70,12 @@ struct mdvrp_instance {
   int64_t Theta = 0, gnum = 1, gden = 1, w_depot = 0, max_c = 0, min_c = 0, max_t = 0;
   int64_t len_guard = 0;
   int t_is_c = 0;
+  float frcp[4] = {1.f, 1.f, 1.f, 1.f};  // feature scales of the learned filter
+};
+
+// Scoring network: device buffers carved from the caller's workspace.
+struct mdvrp_mlp {
+  MlpDev d{};
 };
 
 // Opt-in per-launch timing with HIP events on the launch stream.
@@ -101,6 +107,10 @@ struct mdvrp_batch {
   int32_t* d_node_base = nullptr;
   int32_t* d_route_base = nullptr;
   int64_t* d_state = nullptr;
+  int64_t n_anchors = 0;            // sum over units of n_customers * theta
+  int n_cust = 0;                   // sum over units of n_customers
+  int kc = 0;                       // filtered list length (0 = no filter attached)
+  int32_t* d_cust_off = nullptr;    // [n_units + 1] customer offsets (filter workspace)
   LaunchCtx ctx(void* stream) const {
     LaunchCtx L;
     L.stream = S(stream);
@@ -290,12 +300,23 @@ extern "C" mdvrp_status mdvrp_instance_create(const mdvrp_instance_desc* d, void
   }
   launch_nbr_lists(S(stream), d->c, d->t, d->s, d->e, d->l, d->n_depots, d->n_customers, d->theta, d->has_tw,
                    I->gnum, I->gden, I->nbr, I->nbr_len);
-  he = hipStreamSynchronize(S(stream));
+  launch_nn_sum(S(stream), d->c, I->nbr, I->nbr_len, d->n_depots, d->n_customers, d->theta, I->stats);
+  int64_t nn[2] = {0, 0};
+  he = hipMemcpyAsync(nn, I->stats, sizeof nn, hipMemcpyDeviceToHost, S(stream));
+  if (he == hipSuccess) he = hipStreamSynchronize(S(stream));
   if (he == hipSuccess) he = hipGetLastError();
   if (he != hipSuccess) {
     delete I;
     return fail(MDVRP_EDEVICE, "granular lists: %s", hipGetErrorString(he));
   }
+  // filter feature scales: mean distance to the first list entry (integer mean, at
+  // least 1), capacity, the time horizon of depot 0 (time windows only), depot count
+  const int64_t dscale = std::max<int64_t>(1, nn[1] ? nn[0] / nn[1] : 1);
+  const int64_t hscale = std::max<int64_t>(1, d->has_tw ? (int64_t)l[0] - e[0] : 1);
+  I->frcp[0] = 1.0f / (float)dscale;
+  I->frcp[1] = 1.0f / (float)d->Q;
+  I->frcp[2] = 1.0f / (float)hscale;
+  I->frcp[3] = 1.0f / (float)d->n_depots;
   *out = I;
   return MDVRP_OK;
 }
@@ -404,7 +425,7 @@ void carve_batch(Carve& cv, const mdvrp_instance* const* insts, const int32_t* u
   int32_t* act = cv.take<int32_t>(1);
   int32_t* nb = cv.take<int32_t>(n_units);
   int32_t* rb = cv.take<int32_t>(n_units);
-  int64_t* stt = cv.take<int64_t>((size_t)n_units * 8);
+  int64_t* stt = cv.take<int64_t>((size_t)n_units * kStateWords);
   if (B) {
     B->d_units = du;
     for (int k = 0; k < 4; ++k) B->d_tile_off[k] = to[k];
@@ -468,6 +489,10 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
     u.tile_base[2] = z.tiles[0] + z.tiles[1];
     u.tile_base[3] = z.tiles[0] + z.tiles[1] + z.tiles[2];
     u.key_shift = 38;
+    u.item_base = B->n_anchors;
+    B->n_anchors += (int64_t)z.nc * z.theta;
+    B->n_cust += z.nc;
+    for (int f = 0; f < 4; ++f) u.frcp[f] = I->frcp[f];
     for (int c = 0; c < 4; ++c) B->h_tile_off[c].push_back(B->h_tile_off[c].back() + z.tiles[c]);
     nbase[k] = nacc;
     rbase[k] = racc;
@@ -645,7 +670,7 @@ static mdvrp_status batch_state(const mdvrp_batch* B, int64_t* out, void* stream
   const LaunchCtx L = B->ctx(stream);
   launch_state_export(L, B->d_state);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(out, B->d_state, sizeof(int64_t) * 8 * B->n_units, hipMemcpyDeviceToHost, L.stream));
+  HIP_TRY(hipMemcpyAsync(out, B->d_state, sizeof(int64_t) * kStateWords * B->n_units, hipMemcpyDeviceToHost, L.stream));
   HIP_TRY(hipStreamSynchronize(L.stream));
   return MDVRP_OK;
 }
@@ -658,13 +683,23 @@ extern "C" mdvrp_status mdvrp_batch_state(const mdvrp_batch* B, int64_t* out) {
 
 // ============================================================================ hot path
 
-__global__ static void k_step_begin(const UnitDesc* units, int n_units) {
+// fmode: pair lists of the coming evaluations (0 full, 1 filtered); rescore = forget
+// which routes the filtered lists reflect.
+__global__ static void k_step_begin(const UnitDesc* units, int n_units, int fmode, int rescore) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_units) {
-    units[i].ctl->n_cand = 0;
-    units[i].ctl->last_eval = 0;
-    units[i].ctl->active = 1;
+    UnitCtl* c = units[i].ctl;
+    c->n_cand = 0;
+    c->last_eval = 0;
+    c->active = 1;
+    c->fmode = fmode;
+    if (rescore) c->scored_epoch = -1;
   }
+}
+
+static void step_begin(const LaunchCtx& L, int fmode, int rescore) {
+  hipLaunchKernelGGL(k_step_begin, dim3((L.n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units, fmode,
+                     rescore);
 }
 
 extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, uint32_t flags,
@@ -674,9 +709,11 @@ extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, u
   if (fam & ~MDVRP_FAM_ALL) return fail(MDVRP_EINVAL, "unknown family bits");
   if ((flags & MDVRP_EVAL_DENSE) && (!dense || !dense_count || dense_cap < 0))
     return fail(MDVRP_EINVAL, "dense output needs a buffer and a counter");
+  if (flags & ~(MDVRP_EVAL_DENSE | MDVRP_EVAL_FILTERED)) return fail(MDVRP_EINVAL, "unknown flags");
+  if ((flags & MDVRP_EVAL_FILTERED) && B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
   static_assert(sizeof(mdvrp_dense_rec) == sizeof(DenseRec), "dense record layout");
   const LaunchCtx L = B->ctx(stream);
-  hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  step_begin(L, (flags & MDVRP_EVAL_FILTERED) ? 1 : 0, 0);
   DenseOut D{(DenseRec*)dense, dense_count, dense_cap};
   const uint32_t cls = eval_classes(L, fam);
   for (int c = 0; c < 3; ++c)
@@ -701,13 +738,13 @@ extern "C" mdvrp_status mdvrp_eval_footprint(mdvrp_batch* B, uint32_t fam, uint3
   for (int k = 0; k < B->n_units; ++k) u[k].foot = bitmap + base[B->unit_inst[k]];
   HIP_TRY(hipMemcpyAsync(B->d_units, u.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
   const LaunchCtx L = B->ctx(stream);
-  hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  step_begin(L, 0, 0);
   const uint32_t cls = eval_classes(L, fam);
   for (int c = 0; c < 3; ++c)
     if (cls >> c & 1) launch_eval_footprint(L, fam, c);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  step_begin(L, 0, 0);
   HIP_TRY(hipStreamSynchronize(s));
   return MDVRP_OK;
 }
@@ -732,11 +769,11 @@ extern "C" mdvrp_status mdvrp_apply_moves(mdvrp_batch* B, void* stream) {
 }
 
 static mdvrp_status check_unit_errors(mdvrp_batch* B, std::vector<int64_t>& st, void* stream) {
-  st.resize((size_t)B->n_units * 8);
+  st.resize((size_t)B->n_units * kStateWords);
   mdvrp_status s = batch_state(B, st.data(), stream);
   if (s) return s;
   for (int k = 0; k < B->n_units; ++k) {
-    const int64_t e = st[(size_t)k * 8 + 5];
+    const int64_t e = st[(size_t)k * kStateWords + 5];
     if (e & 4) return fail(MDVRP_ERANGE, "unit %d: a route exceeded the int32-safe length", k);
     if (e & 3) return fail(MDVRP_ENOSPC, "unit %d: internal capacity exceeded (bits %lld)", k, (long long)e);
     if (e) return fail(MDVRP_ESTATE, "unit %d: internal invariant failed (bits %lld)", k, (long long)e);
@@ -749,9 +786,14 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   if (!B || !o) return fail(MDVRP_EINVAL, "null argument");
   if (o->mode != MDVRP_LS_PASSES && o->mode != MDVRP_LS_UNION) return fail(MDVRP_EINVAL, "unknown mode");
   if (o->max_passes < 0) return fail(MDVRP_EINVAL, "max_passes must be >= 0");
+  if (o->filter < MDVRP_FILTER_NONE || o->filter > MDVRP_FILTER_MLP) return fail(MDVRP_EINVAL, "unknown filter");
+  if (o->filter != MDVRP_FILTER_NONE && B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached to the batch");
+  if (o->filter == MDVRP_FILTER_MLP && !o->mlp) return fail(MDVRP_EINVAL, "the MLP filter needs a network");
   const int poll = std::max(1, o->poll_every);
   const LaunchCtx L = B->ctx(stream);
-  hipLaunchKernelGGL(k_step_begin, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  const bool rescoring = o->filter == MDVRP_FILTER_MLP;
+  step_begin(L, o->filter != MDVRP_FILTER_NONE ? 1 : 0, rescoring ? 1 : 0);
+  const uint32_t pair_fams = MDVRP_FAM_RELOCATE | MDVRP_FAM_SWAP | MDVRP_FAM_2OPT_STAR | MDVRP_FAM_2OPT;
   int32_t active = B->n_units;
   for (int64_t p = 0; o->max_passes == 0 || p < o->max_passes; ++p) {
     launch_pass_begin(L);
@@ -765,9 +807,14 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     for (int k = 0; k < nf; ++k) {
       const uint32_t mask = o->mode == MDVRP_LS_PASSES ? (1u << fam[k]) : MDVRP_FAM_ALL;
       const uint32_t cls = eval_classes(L, mask);
+      // re-rank the lists of filtered units whose features changed since the last scoring
+      const bool score = rescoring && (mask & pair_fams) && (cls & 1u);
+      if (score)
+        timed(B, L.stream, MDVRP_PROF_FILTER_SCORE,
+              [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, o->mlp->d, 1, nullptr); });
       for (int c = 0; c < 3; ++c)
         if (cls >> c & 1) timed(B, L.stream, c, [&] { launch_eval_class(L, mask, c, nullptr); });
-      timed(B, L.stream, 3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0); });
+      timed(B, L.stream, 3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0, score ? 1 : 0); });
       timed(B, L.stream, 4, [&] { launch_rebuild(L); });
     }
     launch_pass_end(L);
@@ -784,15 +831,308 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   mdvrp_status s = check_unit_errors(B, st, stream);
   if (stats) {
     for (int k = 0; k < B->n_units; ++k) {
-      const int64_t* x = &st[(size_t)k * 8];
+      const int64_t* x = &st[(size_t)k * kStateWords];
       stats[k].F = x[0];
       stats[k].evaluated = x[1];
       stats[k].passes = x[2];
       stats[k].steps = x[3];
       stats[k].moves_applied = x[4];
+      stats[k].fallback_passes = x[8];
       stats[k].err = (int32_t)x[5];
       stats[k].converged = x[6] ? 0 : 1;
     }
   }
   return s;
+}
+
+// ============================================================================ learned move filter
+
+namespace {
+
+void carve_mlp(Carve& cv, MlpDev* M) {
+  const int np = mlp_param_count();
+  MlpDev m{};
+  m.P = cv.take<float>(np);
+  m.m = cv.take<float>(np);
+  m.v = cv.take<float>(np);
+  m.w1f = cv.take<char>(16 * 64 * 16);
+  m.w2f = cv.take<char>(16 * 8 * 64 * 16);
+  m.w2h = cv.take<uint16_t>(256 * 256);
+  m.w3b = cv.take<float>(256);
+  m.scratch = cv.take<float>(4);
+  if (M) *M = m;
+}
+
+struct ActBufs {
+  uint16_t *h1, *h2, *G2, *G1;
+  float* dz;
+};
+
+// Activation workspace of n samples: h1, h2 (rows padded for the forward tiles), the
+// two backward gradients, and dlogits.
+void carve_act(Carve& cv, int n, ActBufs* A) {
+  const int pad = mlp_row_pad();
+  const size_t rows = ((size_t)std::max(n, 1) + pad - 1) / pad * pad;
+  ActBufs a{};
+  a.h1 = cv.take<uint16_t>(rows * 256);
+  a.h2 = cv.take<uint16_t>(rows * 256);
+  a.G2 = cv.take<uint16_t>(rows * 256);
+  a.G1 = cv.take<uint16_t>(rows * 256);
+  a.dz = cv.take<float>(rows);
+  if (A) *A = a;
+}
+
+mdvrp_status check_act(int32_t n, void* act_ws, size_t act_bytes, ActBufs* A) {
+  Carve need(nullptr);
+  carve_act(need, n, nullptr);
+  if (!act_ws || act_bytes < need.off + 256)
+    return fail(MDVRP_ENOSPC, "activation workspace needs %zu bytes", need.off + 256);
+  Carve cv(act_ws);
+  carve_act(cv, n, A);
+  return MDVRP_OK;
+}
+
+}  // namespace
+
+extern "C" mdvrp_status mdvrp_mlp_workspace_query(size_t* bytes) {
+  if (!bytes) return fail(MDVRP_EINVAL, "null bytes");
+  Carve cv(nullptr);
+  carve_mlp(cv, nullptr);
+  *bytes = cv.off + 256;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_mlp_create(void* ws, size_t ws_bytes, const float* params_init, void* stream,
+                                         mdvrp_mlp** out) {
+  if (!out) return fail(MDVRP_EINVAL, "null out");
+  size_t need = 0;
+  mdvrp_mlp_workspace_query(&need);
+  if (!ws || ws_bytes < need) return fail(MDVRP_ENOSPC, "MLP workspace needs %zu bytes", need);
+  mdvrp_mlp* M = new mdvrp_mlp();
+  Carve cv(ws);
+  carve_mlp(cv, &M->d);
+  const int np = mlp_param_count();
+  hipStream_t s = S(stream);
+  hipError_t he = hipSuccess;
+  if (params_init)
+    he = hipMemcpyAsync(M->d.P, params_init, sizeof(float) * np, hipMemcpyDeviceToDevice, s);
+  else
+    launch_mlp_zero(s, M->d.P, np);
+  launch_mlp_zero(s, M->d.m, np);
+  launch_mlp_zero(s, M->d.v, np);
+  launch_mlp_pack(s, M->d);
+  if (he == hipSuccess) he = hipGetLastError();
+  if (he != hipSuccess) {
+    delete M;
+    return fail(MDVRP_EDEVICE, "MLP create: %s", hipGetErrorString(he));
+  }
+  *out = M;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_mlp_params(mdvrp_mlp* M, float** params) {
+  if (!M || !params) return fail(MDVRP_EINVAL, "null argument");
+  *params = M->d.P;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_mlp_sync(mdvrp_mlp* M, int32_t reset_adam, void* stream) {
+  if (!M) return fail(MDVRP_EINVAL, "null network");
+  const int np = mlp_param_count();
+  if (reset_adam) {
+    launch_mlp_zero(S(stream), M->d.m, np);
+    launch_mlp_zero(S(stream), M->d.v, np);
+  }
+  launch_mlp_pack(S(stream), M->d);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" void mdvrp_mlp_destroy(mdvrp_mlp* M) { delete M; }
+
+extern "C" mdvrp_status mdvrp_mlp_act_bytes(int32_t n, size_t* bytes) {
+  if (!bytes || n < 0) return fail(MDVRP_EINVAL, "bad argument");
+  Carve cv(nullptr);
+  carve_act(cv, n, nullptr);
+  *bytes = cv.off + 256;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_mlp_forward(const mdvrp_mlp* M, const uint16_t* x, int32_t n, float* logits,
+                                          void* act_ws, size_t act_bytes, void* stream) {
+  if (!M || n < 0 || (n > 0 && (!x || !logits))) return fail(MDVRP_EINVAL, "bad argument");
+  ActBufs A{};
+  if (act_ws) {
+    mdvrp_status st = check_act(n, act_ws, act_bytes, &A);
+    if (st) return st;
+  }
+  launch_mlp_forward(S(stream), M->d, x, n, logits, act_ws ? A.h1 : nullptr, act_ws ? A.h2 : nullptr);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_mlp_backward(const mdvrp_mlp* M, const uint16_t* x, const float* dlogits, int32_t n,
+                                           float* grads, void* act_ws, size_t act_bytes, void* stream) {
+  if (!M || !grads || n < 0 || (n > 0 && (!x || !dlogits))) return fail(MDVRP_EINVAL, "bad argument");
+  ActBufs A{};
+  mdvrp_status st = check_act(n, act_ws, act_bytes, &A);
+  if (st) return st;
+  launch_mlp_zero(S(stream), grads, mlp_param_count());
+  launch_mlp_backward(S(stream), M->d, x, n, dlogits, A.h1, A.h2, grads, A.G2, A.G1);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_mlp_bce(mdvrp_mlp* M, const float* logits, const float* labels, const float* weights,
+                                      int32_t n, float* dlogits, float* loss, void* stream) {
+  if (!M || n < 0 || (n > 0 && (!logits || !labels || !dlogits))) return fail(MDVRP_EINVAL, "bad argument");
+  launch_bce(S(stream), logits, labels, weights, n, M->d.scratch, dlogits, loss);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_adam_step(mdvrp_mlp* M, const float* grads, float lr, int32_t step, void* stream) {
+  if (!M || !grads || step < 1 || !(lr >= 0.f)) return fail(MDVRP_EINVAL, "bad argument");
+  launch_adam(S(stream), M->d, grads, lr, step);
+  launch_mlp_pack(S(stream), M->d);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_mlp_train_step(mdvrp_mlp* M, const uint16_t* x, const float* labels,
+                                             const float* weights, int32_t n, float lr, int32_t step, float* grads,
+                                             float* logits, float* loss, void* act_ws, size_t act_bytes,
+                                             void* stream) {
+  if (!M || !x || !labels || !grads || !logits || n < 1 || step < 1 || !(lr >= 0.f))
+    return fail(MDVRP_EINVAL, "bad argument");
+  ActBufs A{};
+  mdvrp_status st = check_act(n, act_ws, act_bytes, &A);
+  if (st) return st;
+  hipStream_t s = S(stream);
+  launch_mlp_forward(s, M->d, x, n, logits, A.h1, A.h2);
+  launch_bce(s, logits, labels, weights, n, M->d.scratch, A.dz, loss);
+  launch_mlp_zero(s, grads, mlp_param_count());
+  launch_mlp_backward(s, M->d, x, n, A.dz, A.h1, A.h2, grads, A.G2, A.G1);
+  launch_adam(s, M->d, grads, lr, step);
+  launch_mlp_pack(s, M->d);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+// ---------------------------------------------------------------------------- filter on a batch
+
+namespace {
+
+mdvrp_status check_filter_k(const mdvrp_batch* B, int32_t k) {
+  if (k < 1) return fail(MDVRP_EINVAL, "list length must be >= 1");
+  for (const mdvrp_instance* I : B->inst)
+    if (k > I->d.theta) return fail(MDVRP_EINVAL, "list length %d exceeds theta %d", k, I->d.theta);
+  return MDVRP_OK;
+}
+
+void carve_filter(Carve& cv, const mdvrp_batch* B, int32_t k, std::vector<int32_t*>* lists, int32_t** cust_off) {
+  int32_t* co = cv.take<int32_t>(B->n_units + 1);
+  if (cust_off) *cust_off = co;
+  for (int u = 0; u < B->n_units; ++u) {
+    int32_t* p = cv.take<int32_t>((size_t)B->inst[B->unit_inst[u]]->d.n_customers * k);
+    if (lists) lists->push_back(p);
+  }
+}
+
+}  // namespace
+
+extern "C" mdvrp_status mdvrp_filter_workspace_query(const mdvrp_batch* B, int32_t k, size_t* bytes) {
+  if (!B || !bytes) return fail(MDVRP_EINVAL, "null argument");
+  mdvrp_status st = check_filter_k(B, k);
+  if (st) return st;
+  Carve cv(nullptr);
+  carve_filter(cv, B, k, nullptr, nullptr);
+  *bytes = cv.off + 256;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws, size_t ws_bytes, void* stream) {
+  if (!B) return fail(MDVRP_EINVAL, "null batch");
+  mdvrp_status st = check_filter_k(B, k);
+  if (st) return st;
+  size_t need = 0;
+  mdvrp_filter_workspace_query(B, k, &need);
+  if (!ws || ws_bytes < need) return fail(MDVRP_ENOSPC, "filter workspace needs %zu bytes", need);
+  Carve cv(ws);
+  std::vector<int32_t*> lists;
+  int32_t* co = nullptr;
+  carve_filter(cv, B, k, &lists, &co);
+  std::vector<int32_t> h_co(B->n_units + 1, 0);
+  for (int u = 0; u < B->n_units; ++u) {
+    UnitDesc& U = B->h_units[u];
+    U.fcand = lists[u];
+    U.kc = k;
+    U.ftiles = (int32_t)(((int64_t)U.nc * k + kTileItems - 1) / kTileItems);
+    h_co[u + 1] = h_co[u] + U.nc;
+  }
+  hipStream_t s = S(stream);
+  HIP_TRY(hipMemcpyAsync(co, h_co.data(), sizeof(int32_t) * (B->n_units + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
+  B->kc = k;
+  B->d_cust_off = co;
+  // start from the heuristic lists so that a filtered evaluation is always defined
+  launch_eta_lists(B->ctx(stream), co, B->n_cust);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_filter_anchor_count(const mdvrp_batch* B, int64_t* n) {
+  if (!B || !n) return fail(MDVRP_EINVAL, "null argument");
+  *n = B->n_anchors;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_filter_features(mdvrp_batch* B, uint16_t* feats, void* stream) {
+  if (!B || !feats) return fail(MDVRP_EINVAL, "null argument");
+  launch_features(B->ctx(stream), feats);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_filter_labels(mdvrp_batch* B, uint32_t fam, uint8_t* labels, void* stream) {
+  if (!B || !labels) return fail(MDVRP_EINVAL, "null argument");
+  if (fam & ~MDVRP_FAM_ALL) return fail(MDVRP_EINVAL, "unknown family bits");
+  const LaunchCtx L = B->ctx(stream);
+  step_begin(L, 0, 0);
+  DenseOut D;
+  D.label = labels;
+  if (eval_classes(L, fam) & 1u) launch_eval_class(L, fam, 0, &D);
+  step_begin(L, 0, 0);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_filter_score_topk(mdvrp_batch* B, const mdvrp_mlp* M, float* logits, void* stream) {
+  if (!B || !M) return fail(MDVRP_EINVAL, "null argument");
+  if (B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
+  const LaunchCtx L = B->ctx(stream);
+  timed(B, L.stream, MDVRP_PROF_FILTER_SCORE, [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, M->d, 0, logits); });
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_filter_eta_lists(mdvrp_batch* B, void* stream) {
+  if (!B) return fail(MDVRP_EINVAL, "null batch");
+  if (B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
+  launch_eta_lists(B->ctx(stream), B->d_cust_off, B->n_cust);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_filter_export(const mdvrp_batch* B, int32_t* cand, void* stream) {
+  if (!B || !cand) return fail(MDVRP_EINVAL, "null argument");
+  if (B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
+  size_t at = 0;
+  for (int u = 0; u < B->n_units; ++u) {
+    const size_t n = (size_t)B->h_units[u].nc * B->kc;
+    HIP_TRY(hipMemcpyAsync(cand + at, B->h_units[u].fcand, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, S(stream)));
+    at += n;
+  }
+  return MDVRP_OK;
 }

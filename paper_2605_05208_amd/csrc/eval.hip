@@ -78,18 +78,24 @@ __device__ __forceinline__ void dense_put(const DenseOut& D, int unit, const Mov
   D.rec[k] = r;
 }
 
-// Result sink of the evaluators: leader/follower bookkeeping plus optional dense output.
-template <bool DENSE>
+// Result sink of the evaluators: leader/follower bookkeeping plus, by mode SM,
+// nothing (0), the dense record of every evaluated move (1), or the anchor's
+// improving flag (2: label[item] = 1 when some move of the anchor has dF < 0).
+template <int SM>
 struct Sink {
   ItemOut* o;
   DenseOut d;
   int unit;
+  int64_t item;
 };
 
-template <bool DENSE>
-__device__ __forceinline__ void take(const UnitDesc& U, Sink<DENSE>& s, const MoveEval& m, uint64_t id) {
+template <int SM>
+__device__ __forceinline__ void take(const UnitDesc& U, Sink<SM>& s, const MoveEval& m, uint64_t id) {
   item_take(U, *s.o, m, id);
-  if (DENSE) dense_put(s.d, s.unit, m, id);
+  if constexpr (SM == 1) dense_put(s.d, s.unit, m, id);
+  if constexpr (SM == 2) {
+    if (m.dF < 0) s.d.label[U.item_base + s.item] = 1;
+  }
 }
 
 }  // namespace mdvrp
@@ -184,7 +190,7 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
 
 // KM != 0 fixes the kind mask at compile time (one lean kernel per family);
 // KM == 0 takes it from the argument.
-template <class SEG, bool TW, bool OPEN, bool DENSE, class AR, uint32_t KM>
+template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __restrict__ units,
                                                           const int32_t* __restrict__ tile_off, int n_units,
                                                           uint32_t kind_arg, DenseOut dense) {
@@ -196,28 +202,35 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __res
   const UnitDesc& U = units[ui];
   if (!U.ctl->active) return;
   const int lt = tile - tile_off[ui];
+  // Filtered units evaluate their candidate lists (kc entries per customer);
+  // the tiles beyond that smaller item space have nothing to do.
+  const bool filt = U.ctl->fmode == 1;
+  if (filt && lt >= U.ftiles) return;
+  const int th = filt ? U.kc : U.theta;
+  const int32_t* lists = filt ? U.fcand : U.nbr;
   const int item = lt * kEvalBlock + threadIdx.x;
   const int cur = U.ctl->cur;
   const SEG* fw = (const SEG*)U.fw[cur];
   const SEG* bw = (const SEG*)U.bw[cur];
   ItemOut o;
   item_init(o);
-  Sink<DENSE> sk{&o, dense, ui};
+  Sink<SM> sk{&o, dense, ui, 0};
   AR ar;
   if constexpr (sizeof(AR) > 1) ar.bits = U.foot;
   if (threadIdx.x == 0) s_nq = 0;
   __syncthreads();
   const uint32_t intra_kinds = kind_mask & ~(1u << X2);
   const uint32_t inter_kinds = kind_mask & ~(1u << TWOOPT);
-  if (item < U.nc * U.theta) {
-    const int i = item / U.theta;
-    const int k = item - i * U.theta;
-    const int v = U.nbr[item];
-    if (k < U.nbr_len[i] && v >= 0) {
+  if (item < U.nc * th) {
+    const int i = item / th;
+    const int k = item - i * th;
+    const int v = lists[item];
+    if ((filt || k < U.nbr_len[i]) && v >= 0) {
       const int u = U.nd + i;
       const int sa = U.rt[u], sb = U.rt[v];
       if (sa != sb) {
         if (inter_kinds) {
+          if constexpr (SM == 2) sk.item = item;
           const int4 ma = U.r_meta[cur][sa], mb = U.r_meta[cur][sb];
           InterCtx x;
           x.u = u; x.v = v; x.slotA = sa; x.slotB = sb;
@@ -238,8 +251,9 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __res
   const int nq = s_nq;
   for (int e = threadIdx.x; e < nq; e += kEvalBlock) {
     const int it = s_q[e];
-    const int i = it / U.theta;
-    const int u = U.nd + i, v = U.nbr[it];
+    const int i = it / th;
+    const int u = U.nd + i, v = lists[it];
+    if constexpr (SM == 2) sk.item = it;
     const RouteCtx A = route_ctx(U, cur, U.rt[u]);
     eval_intra<SEG, TW, OPEN>(U, fw, bw, A, u, v, U.pos[u], U.pos[v], intra_kinds, ar, sk);
   }
@@ -248,7 +262,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __res
 
 // --------------------------------------------------------------------------- depot operators
 
-template <class SEG, bool TW, bool OPEN, bool DENSE, class AR = ArcPlain>
+template <class SEG, bool TW, bool OPEN, int SM, class AR = ArcPlain>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_depot(const UnitDesc* __restrict__ units,
                                                           const int32_t* __restrict__ tile_off, int n_units,
                                                           int which, DenseOut dense) {
@@ -263,7 +277,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_depot(const UnitDesc* __res
   const SEG* bw = (const SEG*)U.bw[cur];
   ItemOut o;
   item_init(o);
-  Sink<DENSE> sk{&o, dense, ui};
+  Sink<SM> sk{&o, dense, ui, 0};
   AR ar;
   if constexpr (sizeof(AR) > 1) ar.bits = U.foot;
   if (item < U.nc * U.nd) {
@@ -329,44 +343,49 @@ constexpr uint32_t kSwpKinds = (1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (
 constexpr uint32_t kX2Kinds = 1u << X2;
 constexpr uint32_t k2optKinds = 1u << TWOOPT;
 
-template <class SEG, bool TW, bool OPEN, bool DENSE, class AR, uint32_t KM>
+template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM>
 static void launch_pairs(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) {
-  hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, DENSE, AR, KM>), dim3(L.tiles[0]), dim3(kEvalBlock), 0, L.stream,
+  hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, SM, AR, KM>), dim3(L.tiles[0]), dim3(kEvalBlock), 0, L.stream,
                      L.units, L.tile_off[0], L.n_units, kinds, D);
 }
 
-template <class SEG, bool TW, bool OPEN, bool DENSE, class AR>
+template <class SEG, bool TW, bool OPEN, int SM, class AR>
 static void launch_class_t(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut& D) {
   if (cls == 0) {
     const uint32_t kinds = pair_kinds(fam_mask, TW);
     if (!kinds || L.tiles[0] <= 0) return;
-    if (kinds == kRelKinds) launch_pairs<SEG, TW, OPEN, DENSE, AR, kRelKinds>(L, kinds, D);
-    else if (kinds == kSwpKinds) launch_pairs<SEG, TW, OPEN, DENSE, AR, kSwpKinds>(L, kinds, D);
-    else if (kinds == kX2Kinds) launch_pairs<SEG, TW, OPEN, DENSE, AR, kX2Kinds>(L, kinds, D);
-    else if (!TW && kinds == k2optKinds) launch_pairs<SEG, TW, OPEN, DENSE, AR, k2optKinds>(L, kinds, D);
-    else launch_pairs<SEG, TW, OPEN, DENSE, AR, 0u>(L, kinds, D);
+    if (kinds == kRelKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kRelKinds>(L, kinds, D);
+    else if (kinds == kSwpKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kSwpKinds>(L, kinds, D);
+    else if (kinds == kX2Kinds) launch_pairs<SEG, TW, OPEN, SM, AR, kX2Kinds>(L, kinds, D);
+    else if (!TW && kinds == k2optKinds) launch_pairs<SEG, TW, OPEN, SM, AR, k2optKinds>(L, kinds, D);
+    else launch_pairs<SEG, TW, OPEN, SM, AR, 0u>(L, kinds, D);
     return;
   }
   const int w = cls - 1;
   if (!(fam_mask >> (FAM_DINS + w) & 1) || L.tiles[1 + w] <= 0) return;
-  hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, DENSE, AR>), dim3(L.tiles[1 + w]), dim3(kEvalBlock), 0, L.stream,
+  hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, SM, AR>), dim3(L.tiles[1 + w]), dim3(kEvalBlock), 0, L.stream,
                      L.units, L.tile_off[1 + w], L.n_units, w, D);
 }
 
-template <bool DENSE, class AR>
+template <int SM, class AR>
 static void launch_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut& D) {
   if (L.has_tw) {
-    if (L.open) launch_class_t<SegTW, true, true, DENSE, AR>(L, fam_mask, cls, D);
-    else launch_class_t<SegTW, true, false, DENSE, AR>(L, fam_mask, cls, D);
+    if (L.open) launch_class_t<SegTW, true, true, SM, AR>(L, fam_mask, cls, D);
+    else launch_class_t<SegTW, true, false, SM, AR>(L, fam_mask, cls, D);
   } else {
-    if (L.open) launch_class_t<SegNT, false, true, DENSE, AR>(L, fam_mask, cls, D);
-    else launch_class_t<SegNT, false, false, DENSE, AR>(L, fam_mask, cls, D);
+    if (L.open) launch_class_t<SegNT, false, true, SM, AR>(L, fam_mask, cls, D);
+    else launch_class_t<SegNT, false, false, SM, AR>(L, fam_mask, cls, D);
   }
 }
 
 void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut* dense) {
-  if (dense) launch_class<true, ArcPlain>(L, fam_mask, cls, *dense);
-  else launch_class<false, ArcPlain>(L, fam_mask, cls, DenseOut{nullptr, nullptr, 0});
+  if (dense && dense->label) {
+    if (cls == 0) launch_class<2, ArcPlain>(L, fam_mask, cls, *dense);
+  } else if (dense) {
+    launch_class<1, ArcPlain>(L, fam_mask, cls, *dense);
+  } else {
+    launch_class<0, ArcPlain>(L, fam_mask, cls, DenseOut{});
+  }
 }
 
 void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense) {
@@ -374,7 +393,7 @@ void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense) {
 }
 
 void launch_eval_footprint(const LaunchCtx& L, uint32_t fam_mask, int cls) {
-  launch_class<false, ArcFoot>(L, fam_mask, cls, DenseOut{nullptr, nullptr, 0});
+  launch_class<0, ArcFoot>(L, fam_mask, cls, DenseOut{});
 }
 
 int eval_block_size() { return kEvalBlock; }

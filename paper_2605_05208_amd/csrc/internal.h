@@ -65,10 +65,13 @@ struct UnitCtl {
   int32_t epoch;         // step counter used to tag resources
   int32_t err;           // sticky error bits (1 = candidate overflow, 2 = slot overflow, 4 = length guard)
   int32_t n_slots_alive;
+  int32_t fmode;         // pair neighbourhood: 0 full lists, 1 filtered lists, 2 full fallback pass
+  int32_t scored_epoch;  // epoch up to which the filtered lists reflect the routes (-1 = none)
   int64_t F;             // running objective (sum of applied deltas)
   int64_t evaluated;
   int64_t passes, steps, moves_applied;
   int64_t last_eval;     // evaluated moves of the latest step
+  int64_t fallbacks;     // full-list fallback passes of a filtered search
   MoveRec leader;
 };
 
@@ -112,6 +115,11 @@ struct UnitDesc {
   int32_t key_shift;     // bit position of dD in the packed follower key
   int32_t pad1;
   uint32_t* foot;        // footprint bitmap of this unit's instance (measurement launches only)
+  // learned move filter
+  int32_t* fcand;        // [nc * kc] filtered candidate lists (-1 padding), null when not attached
+  int32_t kc, ftiles;    // list length, pair tiles of the filtered item space
+  int64_t item_base;     // first anchor of this unit in batch-wide per-anchor arrays
+  float frcp[4];         // feature scales: distance, load, time, depot index
 };
 
 // ---------------------------------------------------------------------------- segment algebra

@@ -7,10 +7,13 @@
 
 namespace mdvrp {
 
+// Optional outputs of an evaluation: every evaluated move (rec/count/cap), or
+// per-anchor improving flags (label, pair kinds only, full lists).
 struct DenseOut {
-  DenseRec* rec;
-  unsigned long long* count;
-  int64_t cap;
+  DenseRec* rec = nullptr;
+  unsigned long long* count = nullptr;
+  int64_t cap = 0;
+  uint8_t* label = nullptr;
 };
 
 // Everything a launch needs about a batch.
@@ -33,7 +36,8 @@ void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const Den
 void launch_eval_footprint(const LaunchCtx& L, uint32_t fam_mask, int cls);
 // Item classes an evaluation of fam_mask fills (bit 0 pairs, 1 depot-insert, 2 depot-replace).
 uint32_t eval_classes(const LaunchCtx& L, uint32_t fam_mask);
-void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only);
+// scored = the filtered lists were re-scored before this step's evaluation.
+void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only, int scored = 0);
 void launch_rebuild(const LaunchCtx& L);
 void launch_pass_begin(const LaunchCtx& L);
 void launch_pass_end(const LaunchCtx& L);
@@ -43,7 +47,36 @@ void launch_export(const LaunchCtx& L, int32_t* nodes, int32_t* offs, int32_t* s
 void launch_load(const LaunchCtx& L, const int32_t* nodes, const int32_t* offs, const int32_t* starts,
                  const int32_t* ends, const int32_t* unit_route_off);
 void launch_sel_export(const LaunchCtx& L, uint64_t* ids, int64_t* dF, int32_t* counts, int32_t cap_per_unit);
-void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][8] */);
+constexpr int kStateWords = 10;  // per-unit counters exported by launch_state_export
+void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][kStateWords] */);
+
+// ---- learned move filter
+// Device buffers of one network: fp32 master parameters, Adam moments, and the
+// bf16 operand copies the kernels read (W1 / W2 in MFMA fragment order, W2
+// row-major, w3 rounded and widened back to fp32); scratch holds two floats.
+struct MlpDev {
+  float *P, *m, *v;
+  void *w1f, *w2f;
+  uint16_t* w2h;
+  float* w3b;
+  float* scratch;
+};
+int mlp_param_count();
+int mlp_row_pad();  // activation buffers hold n rounded up to a multiple of this
+void launch_mlp_pack(hipStream_t s, const MlpDev& M);
+void launch_mlp_zero(hipStream_t s, float* p, int n);
+void launch_features(const LaunchCtx& L, uint16_t* out);
+// mode 0: score every customer; mode 1: stale customers of active filtered units.
+void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M, int mode,
+                       float* logits_out);
+void launch_eta_lists(const LaunchCtx& L, const int32_t* cust_off, int n_tasks);
+void launch_mlp_forward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, float* logits, uint16_t* h1,
+                        uint16_t* h2);
+void launch_bce(hipStream_t s, const float* z, const float* y, const float* w, int n, float* wsum, float* dz,
+                float* loss);
+void launch_mlp_backward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, const float* dz, const uint16_t* h1,
+                         const uint16_t* h2, float* g, uint16_t* G2, uint16_t* G1);
+void launch_adam(hipStream_t s, const MlpDev& M, const float* g, float lr, int step);
 
 // instance preprocessing
 void launch_inst_stats(hipStream_t s, const int32_t* c, const int32_t* t, int n, int64_t* partial, int nblocks);
@@ -52,6 +85,9 @@ void launch_inst_stats_final(hipStream_t s, const int64_t* partial, int nblocks,
 // Packs q, s, e, l into one int4 per node.
 void launch_node_attr(hipStream_t s, const int32_t* q, const int32_t* sv, const int32_t* e, const int32_t* l, int n,
                       int4* attr);
+// Sum of c(u, first list entry) over customers with a list, and their count (out[0..1]).
+void launch_nn_sum(hipStream_t s, const int32_t* c, const int32_t* nbr, const int32_t* nbr_len, int nd, int nc,
+                   int theta, int64_t* out);
 void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* sv, const int32_t* ev,
                       const int32_t* lv, int nd, int nc, int theta, int has_tw, int64_t gnum, int64_t gden,
                       int32_t* nbr, int32_t* nbr_len);

@@ -1,0 +1,687 @@
+// mlp.hip -- learned move filter: anchor features, the scoring network on the
+// matrix cores, per-customer top-k, and the network's training kernels.
+//
+// The paper prunes the neighbourhood with granular lists only (Section 3.2.3);
+// this filter ranks each customer's granular list with a small network and
+// evaluates the k best entries exactly, falling back to the full lists when the
+// filtered neighbourhood has no improving move left.
+//
+// Network: 32 bf16 features -> 256 -> 256 -> 1 with ReLU. Operands are bf16,
+// accumulation fp32 (MFMA 16x16x32), hidden activations are rounded to bf16
+// between layers. The forward runs transposed (h^T = W x^T): a layer's output
+// fragment (lane: one sample, four consecutive features) is, after bias, ReLU
+// and rounding, exactly the B operand of the next layer, so activations stay
+// in registers. W2 (128 KB in bf16) sits in LDS in fragment order, one 16-byte
+// read per lane per MFMA, each read shared by T sample tiles.
+//
+// Parameter layout (fp32 master copy): W1[256][32], b1[256], W2[256][256],
+// b2[256], w3[256], b3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "eval_common.h"
+#include "kernels.h"
+
+namespace mdvrp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kH = 256, kF = 32;
+constexpr int P_W1 = 0, P_B1 = P_W1 + kH * kF, P_W2 = P_B1 + kH, P_B2 = P_W2 + kH * kH, P_W3 = P_B2 + kH,
+              P_B3 = P_W3 + kH, P_N = P_B3 + 1;
+
+// fp32 -> bf16 bits, round to nearest even (quiet NaN kept).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ __bf16 as_bf(uint16_t h) { return __builtin_bit_cast(__bf16, h); }
+
+__device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Orders this wave's LDS accesses (a lane reads what another lane wrote).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint4 pack8(const uint16_t* f) {
+  uint4 w;
+  w.x = (uint32_t)f[0] | ((uint32_t)f[1] << 16);
+  w.y = (uint32_t)f[2] | ((uint32_t)f[3] << 16);
+  w.z = (uint32_t)f[4] | ((uint32_t)f[5] << 16);
+  w.w = (uint32_t)f[6] | ((uint32_t)f[7] << 16);
+  return w;
+}
+
+// ---------------------------------------------------------------------------- weights in fragment order
+
+// MFMA 16x16x32 operand layout: lane l holds A[l % 16][8 (l / 16) + e] and
+// B[8 (l / 16) + e][l % 16], e = 0..7; the result D[4 (l / 16) + r][l % 16], r = 0..3.
+// W1 fragment (ob, lane): W1[16 ob + lane % 16][8 (lane / 16) + e].
+// W2 fragment (ob, j, lane): row 16 ob + lane % 16; columns 32 j + 4 (lane / 16) + e for
+// e < 4 and 32 j + 16 + 4 (lane / 16) + e - 4 for e >= 4 -- the order in which layer 1's
+// output fragments of blocks 2j and 2j+1 land in a lane.
+__global__ void k_mlp_pack(const float* __restrict__ P, bf16x8* __restrict__ w1f, bf16x8* __restrict__ w2f,
+                           uint16_t* __restrict__ w2h, float* __restrict__ w3b) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 16 * 64) {
+    const int ob = t / 64, lane = t % 64;
+    bf16x8 v;
+    for (int e = 0; e < 8; ++e) v[e] = as_bf(f2bf(P[P_W1 + (ob * 16 + lane % 16) * kF + 8 * (lane / 16) + e]));
+    w1f[t] = v;
+  }
+  if (t < 16 * 8 * 64) {
+    const int ob = t / 512, j = (t / 64) % 8, lane = t % 64;
+    const int row = ob * 16 + lane % 16;
+    bf16x8 v;
+    for (int e = 0; e < 8; ++e) {
+      const int col = e < 4 ? 32 * j + 4 * (lane / 16) + e : 32 * j + 16 + 4 * (lane / 16) + (e - 4);
+      v[e] = as_bf(f2bf(P[P_W2 + row * kH + col]));
+    }
+    w2f[t] = v;
+  }
+  if (t < kH * kH) w2h[t] = f2bf(P[P_W2 + t]);
+  if (t < kH) w3b[t] = bf2f(f2bf(P[P_W3 + t]));
+}
+
+// ---------------------------------------------------------------------------- forward core
+
+struct MlpSmem {
+  bf16x8 w2f[16 * 8 * 64];  // 128 KB
+  float b1[kH], b2[kH], w3[kH];
+};
+
+__device__ void mlp_stage(MlpSmem& S, const bf16x8* __restrict__ w2f, const float* __restrict__ P,
+                          const float* __restrict__ w3b) {
+  for (int t = threadIdx.x; t < 16 * 8 * 64; t += blockDim.x) S.w2f[t] = w2f[t];
+  for (int t = threadIdx.x; t < kH; t += blockDim.x) {
+    S.b1[t] = P[P_B1 + t];
+    S.b2[t] = P[P_B2 + t];
+    S.w3[t] = w3b[t];
+  }
+  __syncthreads();
+}
+
+// Writes four consecutive rounded activations of one sample (8-byte store).
+__device__ __forceinline__ void put4(uint16_t* row, int f, const uint16_t h[4]) {
+  uint2 w;
+  w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+  w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+  *(uint2*)(row + f) = w;
+}
+
+// One wave, T tiles of 16 samples. xb[t] = this lane's B fragment of tile t (sample
+// 16 t + lane % 16, features 8 (lane / 16) .. + 7). z[t] = logit of sample 16 t + lane % 16
+// (the four lanes of a sample agree). With h1o / h2o the rounded activations of the
+// 16 T samples are written row-major (256 bf16 per sample, row 16 t + lane % 16).
+template <int T>
+__device__ void mlp_tiles(const MlpSmem& S, const bf16x8* __restrict__ w1f, const bf16x8 (&xb)[T], float b3,
+                          float (&z)[T], uint16_t* __restrict__ h1o, uint16_t* __restrict__ h2o) {
+  const int lane = lane_id(), g = lane >> 4, col = lane & 15;
+  bf16x8 hb[T][8];
+#pragma unroll
+  for (int ob = 0; ob < 16; ++ob) {
+    const bf16x8 a = w1f[ob * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma(a, xb[t], acc);
+      uint16_t h[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[r] + S.b1[ob * 16 + 4 * g + r];
+        v = v > 0.f ? v : 0.f;
+        h[r] = f2bf(v);
+        hb[t][ob >> 1][(ob & 1) * 4 + r] = as_bf(h[r]);
+      }
+      if (h1o) put4(h1o + (16 * t + col) * kH, ob * 16 + 4 * g, h);
+    }
+  }
+  float part[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) part[t] = 0.f;
+#pragma unroll 1
+  for (int ob = 0; ob < 16; ob += 2) {
+    f32x4 acc[2][T];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bf16x8 a0 = S.w2f[(ob * 8 + j) * 64 + lane];
+      const bf16x8 a1 = S.w2f[((ob + 1) * 8 + j) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        acc[0][t] = mfma(a0, hb[t][j], acc[0][t]);
+        acc[1][t] = mfma(a1, hb[t][j], acc[1][t]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        uint16_t h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int f = (ob + q) * 16 + 4 * g + r;
+          float v = acc[q][t][r] + S.b2[f];
+          v = v > 0.f ? v : 0.f;
+          h[r] = f2bf(v);
+          part[t] += S.w3[f] * bf2f(h[r]);
+        }
+        if (h2o) put4(h2o + (16 * t + col) * kH, (ob + q) * 16 + 4 * g, h);
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    float p = part[t];
+    p += __shfl_xor(p, 16);
+    p += __shfl_xor(p, 32);
+    z[t] = p + b3;
+  }
+}
+
+// ---------------------------------------------------------------------------- features
+
+// The 32 integer features of anchor (u, v), each scaled by one fp32 multiplication
+// and rounded to bf16. Route facts come from the segment state of the current buffer.
+template <class SEG, bool TW>
+__device__ void pair_features(const UnitDesc& U, int cur, int u, int v, int rank, uint16_t (&out)[kF]) {
+  const SEG* fw = (const SEG*)U.fw[cur];
+  const int sa = U.rt[u], sb = U.rt[v];
+  const int4 ma = U.r_meta[cur][sa], mb = U.r_meta[cur][sb];
+  const int pu = U.pos[u], pv = U.pos[v];
+  const int p_u = fw[ma.x + pu - 1].node;
+  const int s_u = pu + 1 <= ma.y ? fw[ma.x + pu + 1].node : ma.w;  // ma.w = -1 for open routes
+  const int p_v = fw[mb.x + pv - 1].node;
+  const int pp_v = pv >= 2 ? fw[mb.x + pv - 2].node : p_v;
+  const int c_uv = arc_c(U, u, v), c_pu_u = arc_c(U, p_u, u);
+  const int c_u_su = s_u >= 0 ? arc_c(U, u, s_u) : 0;
+  const int c_pu_su = s_u >= 0 ? arc_c(U, p_u, s_u) : 0;
+  const int c_pv_v = arc_c(U, p_v, v), c_pv_u = arc_c(U, p_v, u);
+  const int c_pv_su = s_u >= 0 ? arc_c(U, p_v, s_u) : 0;
+  const int4 ta = U.r_tot[sa], tb = U.r_tot[sb];
+  const int4 au = U.attr[u], av = U.attr[v];
+  int iv[kF];
+  iv[0] = c_uv;
+  iv[1] = c_pu_u;
+  iv[2] = c_u_su;
+  iv[3] = c_pu_su;
+  iv[4] = c_pv_v;
+  iv[5] = c_pv_u;
+  iv[6] = c_pu_su - c_pu_u - c_u_su + c_pv_u + c_uv - c_pv_v;  // relocate u before v
+  iv[7] = c_uv + c_pv_su - c_u_su - c_pv_v;                     // 2-opt* joining u -> v
+  iv[8] = arc_c(U, p_u, p_v) + c_pv_su + arc_c(U, pp_v, u) + c_uv - c_pu_u - c_u_su - arc_c(U, pp_v, p_v) -
+          c_pv_v;                                               // swap u with p(v)
+  iv[9] = ta.y - U.Q;
+  iv[10] = tb.y - U.Q;
+  iv[11] = au.x;
+  iv[12] = av.x;
+  iv[13] = U.Dmax >= 0 ? ta.z - U.Dmax : 0;
+  iv[14] = U.Dmax >= 0 ? tb.z - U.Dmax : 0;
+  iv[15] = TW ? ta.w : 0;
+  iv[16] = TW ? tb.w : 0;
+  if (TW) {
+    const int tuv = arc_t(U, u, v);
+    iv[17] = au.w - au.z;
+    iv[18] = av.w - av.z;
+    iv[19] = au.z;
+    iv[20] = av.z;
+    iv[21] = imax(av.z - au.z - au.y - tuv, 0);
+    iv[22] = imax(au.z + au.y + tuv - av.w, 0);
+  } else {
+#pragma unroll
+    for (int z = 17; z <= 22; ++z) iv[z] = 0;
+  }
+  iv[23] = sa == sb;
+  iv[24] = ma.z == mb.z;
+  iv[25] = ma.z;
+  iv[26] = mb.z;
+  iv[27] = ma.y;
+  iv[28] = mb.y;
+  iv[29] = pu;
+  iv[30] = pv;
+  iv[31] = rank;
+  auto S = [](int x, float r) -> uint16_t { return f2bf(__fmul_rn((float)x, r)); };
+#pragma unroll
+  for (int z = 0; z <= 8; ++z) out[z] = S(iv[z], U.frcp[0]);
+#pragma unroll
+  for (int z = 9; z <= 12; ++z) out[z] = S(iv[z], U.frcp[1]);
+#pragma unroll
+  for (int z = 13; z <= 22; ++z) out[z] = S(iv[z], U.frcp[2]);
+  out[23] = S(iv[23], 1.0f);
+  out[24] = S(iv[24], 1.0f);
+  out[25] = S(iv[25], U.frcp[3]);
+  out[26] = S(iv[26], U.frcp[3]);
+  out[27] = S(iv[27], 1.0f / 32.0f);
+  out[28] = S(iv[28], 1.0f / 32.0f);
+  out[29] = S(iv[29], __fdiv_rn(1.0f, (float)ma.y));
+  out[30] = S(iv[30], __fdiv_rn(1.0f, (float)mb.y));
+  out[31] = S(iv[31], __fdiv_rn(1.0f, (float)U.theta));
+}
+
+// Features of every anchor of every unit: out[(item_base + i * theta + k) * 32 + f];
+// rows of missing list entries are zero.
+template <class SEG, bool TW>
+__global__ __launch_bounds__(256) void k_features(const UnitDesc* __restrict__ units,
+                                                  const int32_t* __restrict__ tile_off, int n_units,
+                                                  uint16_t* __restrict__ out) {
+  const int tile = blockIdx.x;
+  const int ui = unit_of_tile(tile_off, n_units, tile);
+  const UnitDesc& U = units[ui];
+  const int item = (tile - tile_off[ui]) * 256 + threadIdx.x;
+  if (item >= U.nc * U.theta) return;
+  uint16_t f[kF];
+  const int i = item / U.theta, k = item - i * U.theta;
+  const int v = U.nbr[item];
+  if (k < U.nbr_len[i] && v >= 0) {
+    pair_features<SEG, TW>(U, U.ctl->cur, U.nd + i, v, k, f);
+  } else {
+#pragma unroll
+    for (int z = 0; z < kF; ++z) f[z] = 0;
+  }
+  uint4* o = (uint4*)(out + (U.item_base + item) * kF);
+#pragma unroll
+  for (int z = 0; z < 4; ++z) o[z] = pack8(f + 8 * z);
+}
+
+// ---------------------------------------------------------------------------- scoring + top-k
+
+constexpr int kScoreWaves = 8;
+constexpr int kScoreT = 2;      // sample tiles per pass through W2
+constexpr int kMaxTheta = 128;  // list entries scored per customer
+
+// One wave per (unit, customer) task: features of the customer's list entries, their
+// logits, and the kc best (logit descending, customer id ascending) into fcand.
+// mode 0: every customer of every unit; mode 1: active filtered units only, and only
+// customers whose features may have changed since the last scoring (the route of u or
+// of some v in N(u) was rebuilt after scored_epoch).
+template <class SEG, bool TW>
+__global__ __launch_bounds__(64 * kScoreWaves) void k_score_topk(
+    const UnitDesc* __restrict__ units, const int32_t* __restrict__ cust_off, int n_units,
+    const bf16x8* __restrict__ w1f, const bf16x8* __restrict__ w2f, const float* __restrict__ P,
+    const float* __restrict__ w3b, int mode, float* __restrict__ logits_out) {
+  __shared__ MlpSmem S;
+  __shared__ __attribute__((aligned(16))) uint16_t xs[kScoreWaves][16 * kScoreT * kF];
+  __shared__ float lg[kScoreWaves][kMaxTheta];
+  mlp_stage(S, w2f, P, w3b);
+  const float b3 = P[P_B3];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int n_tasks = cust_off[n_units];
+  for (int task = blockIdx.x * kScoreWaves + wave; task < n_tasks; task += gridDim.x * kScoreWaves) {
+    const int ui = unit_of_tile(cust_off, n_units, task);
+    const UnitDesc& U = units[ui];
+    const int i = task - cust_off[ui];
+    const int u = U.nd + i;
+    const int len = imin(U.nbr_len[i], kMaxTheta);
+    const int32_t* nb = U.nbr + (int64_t)i * U.theta;
+    if (mode == 1) {
+      const UnitCtl* c = U.ctl;
+      if (!c->active || c->fmode != 1) continue;
+      const int se = c->scored_epoch;
+      bool st = lane == 0 && U.dirty[U.rt[u]] > se;
+      for (int k = lane; k < len; k += 64) st = st || U.dirty[U.rt[nb[k]]] > se;
+      if (!__any(st)) continue;
+    }
+    const int cur = U.ctl->cur;
+    for (int base = 0; base < len; base += 16 * kScoreT) {
+      // features of entries base .. base + 16 T - 1, one row per lane of the first 16 T lanes
+      if (lane < 16 * kScoreT) {
+        uint16_t f[kF];
+        const int k = base + lane;
+        if (k < len) {
+          pair_features<SEG, TW>(U, cur, u, nb[k], k, f);
+        } else {
+#pragma unroll
+          for (int z = 0; z < kF; ++z) f[z] = 0;
+        }
+        uint4* row = (uint4*)&xs[wave][lane * kF];
+#pragma unroll
+        for (int z = 0; z < 4; ++z) row[z] = pack8(f + 8 * z);
+      }
+      wave_lds_sync();
+      bf16x8 xb[kScoreT];
+#pragma unroll
+      for (int t = 0; t < kScoreT; ++t)
+        xb[t] = *(const bf16x8*)&xs[wave][(16 * t + (lane & 15)) * kF + 8 * (lane >> 4)];
+      float z[kScoreT];
+      mlp_tiles<kScoreT>(S, w1f, xb, b3, z, nullptr, nullptr);
+#pragma unroll
+      for (int t = 0; t < kScoreT; ++t) {
+        const int k = base + 16 * t + (lane & 15);
+        if (lane < 16 && k < len) lg[wave][k] = z[t];
+      }
+      wave_lds_sync();
+    }
+    // top-kc by repeated wave arg-max; each lane holds entries lane and lane + 64
+    float s0 = -INFINITY, s1 = -INFINITY;
+    int v0 = INT32_MAX, v1 = INT32_MAX;
+    if (lane < len) { s0 = lg[wave][lane]; v0 = nb[lane]; }
+    if (lane + 64 < len) { s1 = lg[wave][lane + 64]; v1 = nb[lane + 64]; }
+    wave_lds_sync();
+    if (logits_out) {
+      float* lo = logits_out + U.item_base + (int64_t)i * U.theta;
+      if (lane < len) lo[lane] = s0;
+      if (lane + 64 < len) lo[lane + 64] = s1;
+    }
+    int32_t* out = U.fcand + (int64_t)i * U.kc;
+    for (int j = 0; j < U.kc; ++j) {
+      float bs = s0;
+      int bv = v0, src = lane, which = 0;
+      if (s1 > bs || (s1 == bs && v1 < bv)) { bs = s1; bv = v1; which = 1; }
+      for (int off = 32; off > 0; off >>= 1) {
+        const float s2 = __shfl_xor(bs, off);
+        const int v2 = __shfl_xor(bv, off);
+        const int src2 = __shfl_xor(src, off);
+        const int w2 = __shfl_xor(which, off);
+        if (s2 > bs || (s2 == bs && v2 < bv)) { bs = s2; bv = v2; src = src2; which = w2; }
+      }
+      if (lane == 0) out[j] = bv == INT32_MAX ? -1 : bv;
+      if (lane == src) {
+        if (which == 0) { s0 = -INFINITY; v0 = INT32_MAX; }
+        else { s1 = -INFINITY; v1 = INT32_MAX; }
+      }
+    }
+  }
+}
+
+// The heuristic filter: the first kc entries of each granular list (eta order).
+__global__ void k_eta_lists(const UnitDesc* __restrict__ units, const int32_t* __restrict__ cust_off, int n_units) {
+  const int task = blockIdx.x * blockDim.x + threadIdx.x;
+  if (task >= cust_off[n_units]) return;
+  const int ui = unit_of_tile(cust_off, n_units, task);
+  const UnitDesc& U = units[ui];
+  const int i = task - cust_off[ui];
+  const int len = U.nbr_len[i];
+  for (int j = 0; j < U.kc; ++j) U.fcand[(int64_t)i * U.kc + j] = j < len ? U.nbr[(int64_t)i * U.theta + j] : -1;
+}
+
+// ---------------------------------------------------------------------------- training forward
+
+constexpr int kFwdT = 2;
+
+// Forward over n samples x[n][32] (bf16): logits[n] and, when h1 / h2 are given, the
+// rounded activations [n rounded up to 16 T][256] for the backward pass.
+__global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t* __restrict__ x, int n,
+                                                     const bf16x8* __restrict__ w1f, const bf16x8* __restrict__ w2f,
+                                                     const float* __restrict__ P, const float* __restrict__ w3b,
+                                                     float* __restrict__ logits, uint16_t* __restrict__ h1,
+                                                     uint16_t* __restrict__ h2) {
+  __shared__ MlpSmem S;
+  mlp_stage(S, w2f, P, w3b);
+  const float b3 = P[P_B3];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int groups = (n + 16 * kFwdT - 1) / (16 * kFwdT);
+  for (int gi = blockIdx.x * 4 + wave; gi < groups; gi += gridDim.x * 4) {
+    bf16x8 xb[kFwdT];
+#pragma unroll
+    for (int t = 0; t < kFwdT; ++t) {
+      const int sample = (gi * kFwdT + t) * 16 + (lane & 15);
+      if (sample < n) {
+        xb[t] = *(const bf16x8*)&x[(int64_t)sample * kF + 8 * (lane >> 4)];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xb[t][e] = as_bf(0);
+      }
+    }
+    float z[kFwdT];
+    const int64_t row0 = (int64_t)gi * kFwdT * 16;
+    mlp_tiles<kFwdT>(S, w1f, xb, b3, z, h1 ? h1 + row0 * kH : nullptr, h2 ? h2 + row0 * kH : nullptr);
+#pragma unroll
+    for (int t = 0; t < kFwdT; ++t) {
+      const int sample = (gi * kFwdT + t) * 16 + (lane & 15);
+      if (lane < 16 && sample < n) logits[sample] = z[t];
+    }
+  }
+}
+
+int mlp_row_pad() { return 16 * kFwdT; }
+
+// ---------------------------------------------------------------------------- loss and backward
+
+// wsum = sum of weights (n when weights is null); zeroes the loss accumulator. One block.
+__global__ void k_bce_prep(const float* __restrict__ w, int n, float* __restrict__ wsum, float* __restrict__ loss) {
+  __shared__ float sh[16];
+  float s = 0.f;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) s += w ? w[p] : 1.f;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+    *wsum = t;
+    if (loss) *loss = 0.f;
+  }
+}
+
+// Weighted mean BCE with logits: dz_p = w_p (sigmoid(z_p) - y_p) / sum w, loss += w_p l_p / sum w.
+__global__ void k_bce(const float* __restrict__ z, const float* __restrict__ y, const float* __restrict__ w, int n,
+                      const float* __restrict__ wsum, float* __restrict__ dz, float* __restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const float ws = *wsum;
+  const float inv = ws > 0.f ? 1.f / ws : 0.f;
+  float l = 0.f;
+  if (p < n) {
+    const float wp = w ? w[p] : 1.f;
+    const float zp = z[p];
+    const float sg = 1.f / (1.f + expf(-zp));
+    dz[p] = wp * (sg - y[p]) * inv;
+    l = wp * ((zp > 0.f ? zp : 0.f) - zp * y[p] + log1pf(expf(-fabsf(zp)))) * inv;
+  }
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+  if (lane_id() == 0 && loss) atomicAdd(loss, l);
+}
+
+__global__ void k_zero(float* __restrict__ g, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = 0.f;
+}
+
+// Output layer: g[w3] += sum_p dz_p h2_p, g[b3] += sum dz, g[b2] += sum_p G2_p and
+// G2[p][o] = dz_p w3[o] [h2[p][o] > 0] rounded to bf16 (the layer-2 output gradient).
+__global__ __launch_bounds__(256) void k_back_out(const float* __restrict__ dz, const uint16_t* __restrict__ h2,
+                                                  const float* __restrict__ w3b, int n, float* __restrict__ g,
+                                                  uint16_t* __restrict__ G2) {
+  const int o = threadIdx.x;
+  float aw = 0.f, ab2 = 0.f, ab3 = 0.f;
+  for (int p = blockIdx.x; p < n; p += gridDim.x) {
+    const float d = dz[p];
+    const float h = bf2f(h2[(int64_t)p * kH + o]);
+    aw += d * h;
+    ab3 += d;
+    const float gv = h > 0.f ? d * w3b[o] : 0.f;
+    ab2 += gv;
+    G2[(int64_t)p * kH + o] = f2bf(gv);
+  }
+  atomicAdd(&g[P_W3 + o], aw);
+  atomicAdd(&g[P_B2 + o], ab2);
+  if (o == 0) atomicAdd(&g[P_B3], ab3);
+}
+
+// G1 = (G2 W2) masked by [h1 > 0], rounded to bf16; one wave per 16 x 16 output tile.
+// A(m, k) = G2[m][k] (row-major, 16-byte loads), B(k, n) = W2[k][n].
+__global__ __launch_bounds__(256) void k_back_hidden(const uint16_t* __restrict__ G2, const uint16_t* __restrict__ w2h,
+                                                     const uint16_t* __restrict__ h1, int n, uint16_t* __restrict__ G1) {
+  const int wave = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4;
+  const int tm = (n + 15) / 16, tn = kH / 16;
+  for (int t = blockIdx.x * 4 + wave; t < tm * tn; t += gridDim.x * 4) {
+    const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
+    const int m = m0 + (lane & 15), nn = n0 + (lane & 15);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int k0 = 0; k0 < kH; k0 += 32) {
+      bf16x8 a, b;
+      if (m < n) {
+        a = *(const bf16x8*)&G2[(int64_t)m * kH + k0 + 8 * g];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[e] = as_bf(0);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[e] = as_bf(w2h[(k0 + 8 * g + e) * kH + nn]);
+      acc = mfma(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mr = m0 + 4 * g + r;
+      if (mr < n) {
+        const int64_t at = (int64_t)mr * kH + nn;
+        G1[at] = f2bf(bf2f(h1[at]) > 0.f ? acc[r] : 0.f);
+      }
+    }
+  }
+}
+
+// g[off + o] += sum_p G[p][o] over bf16 rows of 256.
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ G, int n, float* __restrict__ g, int off) {
+  const int o = threadIdx.x;
+  float acc = 0.f;
+  for (int p = blockIdx.x; p < n; p += gridDim.x) acc += bf2f(G[(int64_t)p * kH + o]);
+  atomicAdd(&g[off + o], acc);
+}
+
+constexpr int kSplitK = 1024;  // samples per wave in the weight-gradient products
+
+// Weight gradient C[M][N] += sum_p L[p][m] R[p][n] over the samples (both bf16, row-major
+// with row lengths M and N), split over the samples; one wave per (16 x 16 tile, chunk).
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ Lm, int M, const uint16_t* __restrict__ Rm,
+                                               int N, int n, float* __restrict__ C) {
+  const int wave = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4;
+  const int tm = M / 16, tn = N / 16, chunks = (n + kSplitK - 1) / kSplitK;
+  for (int t = blockIdx.x * 4 + wave; t < tm * tn * chunks; t += gridDim.x * 4) {
+    const int tile = t % (tm * tn), ch = t / (tm * tn);
+    const int m = (tile / tn) * 16 + (lane & 15), nn = (tile % tn) * 16 + (lane & 15);
+    const int p0 = ch * kSplitK, p1 = min(n, p0 + kSplitK);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = p0; k0 < p1; k0 += 32) {
+      bf16x8 a, b;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int p = k0 + 8 * g + e;
+        a[e] = as_bf(p < p1 ? Lm[(int64_t)p * M + m] : (uint16_t)0);
+        b[e] = as_bf(p < p1 ? Rm[(int64_t)p * N + nn] : (uint16_t)0);
+      }
+      acc = mfma(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) atomicAdd(&C[((tile / tn) * 16 + 4 * g + r) * N + nn], acc[r]);
+  }
+}
+
+// Adam on the fp32 master parameters (bias-corrected moments).
+__global__ void k_adam(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
+                       int n, float lr, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  P[i] = P[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------- launchers
+
+static int grid_for(int64_t work, int per_block, int cap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (work + per_block - 1) / per_block));
+}
+
+void launch_mlp_pack(hipStream_t s, const MlpDev& M) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((kH * kH + 255) / 256), dim3(256), 0, s, (const float*)M.P, (bf16x8*)M.w1f,
+                     (bf16x8*)M.w2f, M.w2h, M.w3b);
+}
+
+void launch_mlp_zero(hipStream_t s, float* p, int n) {
+  if (n > 0) hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+}
+
+template <class SEG, bool TW>
+static void features_t(const LaunchCtx& L, uint16_t* out) {
+  hipLaunchKernelGGL((k_features<SEG, TW>), dim3(L.tiles[0]), dim3(256), 0, L.stream, L.units, L.tile_off[0],
+                     L.n_units, out);
+}
+
+void launch_features(const LaunchCtx& L, uint16_t* out) {
+  if (L.tiles[0] <= 0) return;
+  if (L.has_tw) features_t<SegTW, true>(L, out);
+  else features_t<SegNT, false>(L, out);
+}
+
+template <class SEG, bool TW>
+static void score_t(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M, int mode,
+                    float* logits_out) {
+  const int blocks = grid_for(n_tasks, kScoreWaves, 256);
+  hipLaunchKernelGGL((k_score_topk<SEG, TW>), dim3(blocks), dim3(64 * kScoreWaves), 0, L.stream, L.units, cust_off,
+                     L.n_units, (const bf16x8*)M.w1f, (const bf16x8*)M.w2f, (const float*)M.P, (const float*)M.w3b,
+                     mode, logits_out);
+}
+
+void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M, int mode,
+                       float* logits_out) {
+  if (n_tasks <= 0) return;
+  if (L.has_tw) score_t<SegTW, true>(L, cust_off, n_tasks, M, mode, logits_out);
+  else score_t<SegNT, false>(L, cust_off, n_tasks, M, mode, logits_out);
+}
+
+void launch_eta_lists(const LaunchCtx& L, const int32_t* cust_off, int n_tasks) {
+  if (n_tasks <= 0) return;
+  hipLaunchKernelGGL(k_eta_lists, dim3((n_tasks + 255) / 256), dim3(256), 0, L.stream, L.units, cust_off, L.n_units);
+}
+
+void launch_mlp_forward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, float* logits, uint16_t* h1,
+                        uint16_t* h2) {
+  if (n <= 0) return;
+  const int groups = (n + 16 * kFwdT - 1) / (16 * kFwdT);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid_for(groups, 4, 1024)), dim3(256), 0, s, x, n, (const bf16x8*)M.w1f,
+                     (const bf16x8*)M.w2f, (const float*)M.P, (const float*)M.w3b, logits, h1, h2);
+}
+
+void launch_bce(hipStream_t s, const float* z, const float* y, const float* w, int n, float* wsum, float* dz,
+                float* loss) {
+  hipLaunchKernelGGL(k_bce_prep, dim3(1), dim3(1024), 0, s, w, n, wsum, loss);
+  if (n > 0) hipLaunchKernelGGL(k_bce, dim3((n + 255) / 256), dim3(256), 0, s, z, y, w, n, wsum, dz, loss);
+}
+
+// Gradient of sum_p dz_p logit_p accumulated into g (the caller zeroes g); h1, h2 from
+// the forward pass; G2, G1 scratch of [n][256] bf16 each.
+void launch_mlp_backward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, const float* dz, const uint16_t* h1,
+                         const uint16_t* h2, float* g, uint16_t* G2, uint16_t* G1) {
+  if (n <= 0) return;
+  const int rows = grid_for(n, 1, 1024);
+  hipLaunchKernelGGL(k_back_out, dim3(rows), dim3(kH), 0, s, dz, h2, (const float*)M.w3b, n, g, G2);
+  const int chunks = (n + kSplitK - 1) / kSplitK;
+  // dW2[o2][o1] = sum_p G2[p][o2] h1[p][o1]
+  hipLaunchKernelGGL(k_wgrad, dim3(grid_for((int64_t)(kH / 16) * (kH / 16) * chunks, 4, 4096)), dim3(256), 0, s,
+                     (const uint16_t*)G2, kH, h1, kH, n, g + P_W2);
+  const int64_t tiles = (int64_t)(n + 15) / 16 * (kH / 16);
+  hipLaunchKernelGGL(k_back_hidden, dim3(grid_for(tiles, 4, 4096)), dim3(256), 0, s, (const uint16_t*)G2,
+                     (const uint16_t*)M.w2h, h1, n, G1);
+  hipLaunchKernelGGL(k_colsum, dim3(rows), dim3(kH), 0, s, (const uint16_t*)G1, n, g, P_B1);
+  // dW1[o1][i] = sum_p G1[p][o1] x[p][i]
+  hipLaunchKernelGGL(k_wgrad, dim3(grid_for((int64_t)(kH / 16) * (kF / 16) * chunks, 4, 4096)), dim3(256), 0, s,
+                     (const uint16_t*)G1, kH, x, kF, n, g + P_W1);
+}
+
+void launch_adam(hipStream_t s, const MlpDev& M, const float* g, float lr, int step) {
+  const double c1 = 1.0 - std::pow(0.9, step), c2 = 1.0 - std::pow(0.999, step);
+  hipLaunchKernelGGL(k_adam, dim3((P_N + 255) / 256), dim3(256), 0, s, M.P, M.m, M.v, g, P_N, lr, (float)c1,
+                     (float)c2);
+}
+
+int mlp_param_count() { return P_N; }
+
+}  // namespace mdvrp

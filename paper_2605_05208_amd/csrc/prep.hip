@@ -202,3 +202,36 @@ void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const i
 }
 
 }  // namespace mdvrp
+
+namespace mdvrp {
+
+// out[0] = sum over customers with a non-empty list of c(u, first list entry), out[1] = their count.
+__global__ __launch_bounds__(1024) void k_nn_sum(const int32_t* __restrict__ c, const int32_t* __restrict__ nbr,
+                                                 const int32_t* __restrict__ nbr_len, int nd, int nc, int theta,
+                                                 int64_t* __restrict__ out) {
+  __shared__ unsigned long long s_sum, s_cnt;
+  if (threadIdx.x == 0) { s_sum = 0; s_cnt = 0; }
+  __syncthreads();
+  const int64_t n = (int64_t)nd + nc;
+  unsigned long long sum = 0, cnt = 0;
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    if (nbr_len[i] > 0) {
+      sum += (unsigned long long)c[(int64_t)(nd + i) * n + nbr[(int64_t)i * theta]];
+      cnt += 1;
+    }
+  }
+  atomicAdd(&s_sum, sum);
+  atomicAdd(&s_cnt, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = (int64_t)s_sum;
+    out[1] = (int64_t)s_cnt;
+  }
+}
+
+void launch_nn_sum(hipStream_t s, const int32_t* c, const int32_t* nbr, const int32_t* nbr_len, int nd, int nc,
+                   int theta, int64_t* out) {
+  hipLaunchKernelGGL(k_nn_sum, dim3(1), dim3(1024), 0, s, c, nbr, nbr_len, nd, nc, theta, out);
+}
+
+}  // namespace mdvrp

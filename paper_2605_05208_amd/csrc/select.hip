@@ -71,7 +71,7 @@ __device__ void plan_move(const UnitDesc& U, int cur, uint64_t id, int64_t dF, i
 
 template <bool OPEN>
 __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __restrict__ units, uint32_t cls_mask,
-                                                           int leader_only) {
+                                                           int leader_only, int scored) {
   const UnitDesc& U = units[blockIdx.x];
   UnitCtl* ctl = U.ctl;
   __shared__ int64_t shF[kSelWaves];
@@ -89,7 +89,9 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   int bt = -1;
   for (int c = 0; c < 3; ++c) {
     if (!(cls_mask >> c & 1)) continue;
-    for (int t = U.tile_base[c] + tid; t < U.tile_base[c + 1]; t += kSelBlock) {
+    // a filtered unit's pair tiles cover its candidate lists only
+    const int t_end = (c == 0 && ctl->fmode == 1) ? U.tile_base[0] + U.ftiles : U.tile_base[c + 1];
+    for (int t = U.tile_base[c] + tid; t < t_end; t += kSelBlock) {
       const int64_t f = U.wg_best[t].dF;
       const uint64_t i = U.wg_best[t].id;
       if (key_less(f, i, bf, bi)) { bf = f; bi = i; bt = t; }
@@ -110,6 +112,8 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     s_nsel = 0;
     s_ndins = 0;
     ctl->steps += 1;
+    // the lists scored before this step's evaluation reflect every route up to this epoch
+    if (scored && ctl->fmode == 1) ctl->scored_epoch = ctl->epoch;
     if (shF[0] < 0) {
       s_epoch = ctl->epoch + 1;
       ctl->epoch = s_epoch;
@@ -289,14 +293,14 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   }
 }
 
-void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only) {
+void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only, int scored) {
   const uint32_t cls = eval_classes(L, fam_mask);
   if (L.open)
     hipLaunchKernelGGL(k_select_plan<true>, dim3(L.n_units), dim3(kSelBlock), 0, L.stream, L.units, cls,
-                       leader_only);
+                       leader_only, scored);
   else
     hipLaunchKernelGGL(k_select_plan<false>, dim3(L.n_units), dim3(kSelBlock), 0, L.stream, L.units, cls,
-                       leader_only);
+                       leader_only, scored);
 }
 
 }  // namespace mdvrp

@@ -212,6 +212,9 @@ __global__ __launch_bounds__(kUnitBlock) void k_load_table(const UnitDesc* __res
     ctl->steps = 0;
     ctl->moves_applied = 0;
     ctl->last_eval = 0;
+    ctl->fallbacks = 0;
+    ctl->fmode = 0;
+    ctl->scored_epoch = -1;
   }
 }
 
@@ -258,7 +261,21 @@ __global__ void k_pass_end(const UnitDesc* __restrict__ units, int n_units, int3
   __syncthreads();
   for (int i = threadIdx.x; i < n_units; i += blockDim.x) {
     UnitCtl* c = units[i].ctl;
-    if (c->active && !c->pass_applied) c->active = 0;
+    if (c->active) {
+      if (c->fmode == 1) {
+        // filtered optimum: the next pass evaluates the full lists
+        if (!c->pass_applied) {
+          c->fmode = 2;
+          c->fallbacks += 1;
+        }
+      } else if (c->fmode == 2) {
+        // a full pass that improved returns to the filtered lists; one that did not ends the search
+        if (c->pass_applied) c->fmode = 1;
+        else c->active = 0;
+      } else if (!c->pass_applied) {
+        c->active = 0;
+      }
+    }
     if (c->active) atomicAdd(&cnt, 1);
   }
   __syncthreads();
@@ -348,9 +365,9 @@ __global__ void k_state_export(const UnitDesc* __restrict__ units, int n_units, 
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n_units) return;
   const UnitCtl* c = units[u].ctl;
-  int64_t* o = out + (int64_t)u * 8;
+  int64_t* o = out + (int64_t)u * kStateWords;
   o[0] = c->F; o[1] = c->evaluated; o[2] = c->passes; o[3] = c->steps; o[4] = c->moves_applied;
-  o[5] = c->err; o[6] = c->active; o[7] = c->n_sel;
+  o[5] = c->err; o[6] = c->active; o[7] = c->n_sel; o[8] = c->fallbacks; o[9] = c->fmode;
 }
 
 // --------------------------------------------------------------------------- launchers

@@ -18,8 +18,11 @@ LIB_PATH = os.path.join(HERE, "libmdvrp.so")
 OK, EINVAL, ERANGE, ENOSPC, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 FAM_RELOCATE, FAM_SWAP, FAM_2OPT_STAR, FAM_2OPT, FAM_DEPOT_INSERT, FAM_DEPOT_REPLACE = 1, 2, 4, 8, 16, 32
 FAM_ALL = 0x3F
-EVAL_DENSE = 1
+EVAL_DENSE, EVAL_FILTERED = 1, 2
 LS_PASSES, LS_UNION = 0, 1
+FILTER_NONE, FILTER_LISTS, FILTER_MLP = 0, 1, 2
+MLP_PARAMS = 74497
+PAIR_FAMILIES = FAM_RELOCATE | FAM_SWAP | FAM_2OPT_STAR | FAM_2OPT
 
 
 class MdvrpError(RuntimeError):
@@ -39,12 +42,14 @@ class InstanceDesc(C.Structure):
 
 class LsOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("leader_only", C.c_int32), ("max_passes", C.c_int32),
-                ("poll_every", C.c_int32), ("seed", C.c_uint64)]
+                ("poll_every", C.c_int32), ("seed", C.c_uint64), ("filter", C.c_int32), ("pad", C.c_int32),
+                ("mlp", C.c_void_p)]
 
 
 class LsStats(C.Structure):
     _fields_ = [("passes", C.c_int64), ("steps", C.c_int64), ("moves_applied", C.c_int64),
-                ("evaluated", C.c_int64), ("F", C.c_int64), ("converged", C.c_int32), ("err", C.c_int32)]
+                ("evaluated", C.c_int64), ("F", C.c_int64), ("fallback_passes", C.c_int64),
+                ("converged", C.c_int32), ("err", C.c_int32)]
 
 
 DENSE_DTYPE = np.dtype([("dF", np.int64), ("dD", np.int64), ("dTW", np.int64), ("dLX", np.int64),
@@ -62,8 +67,14 @@ EXPORTED = [
     "mdvrp_batch_state", "mdvrp_eval_neighbourhood", "mdvrp_select_multimove", "mdvrp_apply_moves",
     "mdvrp_local_search_to_optimum", "mdvrp_status_string", "mdvrp_last_error", "mdvrp_family_order",
     "mdvrp_profile_enable", "mdvrp_profile_read", "mdvrp_eval_footprint",
+    "mdvrp_mlp_workspace_query", "mdvrp_mlp_create", "mdvrp_mlp_params", "mdvrp_mlp_sync", "mdvrp_mlp_destroy",
+    "mdvrp_mlp_act_bytes", "mdvrp_mlp_forward", "mdvrp_mlp_backward", "mdvrp_mlp_bce", "mdvrp_adam_step",
+    "mdvrp_mlp_train_step", "mdvrp_filter_workspace_query", "mdvrp_filter_attach", "mdvrp_filter_anchor_count",
+    "mdvrp_filter_features", "mdvrp_filter_labels", "mdvrp_filter_score_topk", "mdvrp_filter_eta_lists",
+    "mdvrp_filter_export",
 ]
-PROF_CLASSES = ["eval_pairs", "eval_depot_insert", "eval_depot_replace", "select", "apply"]
+PROF_CLASSES = ["eval_pairs", "eval_depot_insert", "eval_depot_replace", "select", "apply", "filter_score"]
+STATE_WORDS = 10
 
 
 def lib():
@@ -95,6 +106,24 @@ def lib():
             "mdvrp_profile_enable": [p, u32, i32],
             "mdvrp_profile_read": [p, p, p],
             "mdvrp_eval_footprint": [p, u32, p, i64, p],
+            "mdvrp_mlp_workspace_query": [p],
+            "mdvrp_mlp_create": [p, sz, p, p, p],
+            "mdvrp_mlp_params": [p, p],
+            "mdvrp_mlp_sync": [p, i32, p],
+            "mdvrp_mlp_act_bytes": [i32, p],
+            "mdvrp_mlp_forward": [p, p, i32, p, p, sz, p],
+            "mdvrp_mlp_backward": [p, p, p, i32, p, p, sz, p],
+            "mdvrp_mlp_bce": [p, p, p, p, i32, p, p, p],
+            "mdvrp_adam_step": [p, p, C.c_float, i32, p],
+            "mdvrp_mlp_train_step": [p, p, p, p, i32, C.c_float, i32, p, p, p, p, sz, p],
+            "mdvrp_filter_workspace_query": [p, i32, p],
+            "mdvrp_filter_attach": [p, i32, p, sz, p],
+            "mdvrp_filter_anchor_count": [p, p],
+            "mdvrp_filter_features": [p, p, p],
+            "mdvrp_filter_labels": [p, u32, p, p],
+            "mdvrp_filter_score_topk": [p, p, p, p],
+            "mdvrp_filter_eta_lists": [p, p],
+            "mdvrp_filter_export": [p, p, p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -104,6 +133,8 @@ def lib():
         L.mdvrp_instance_destroy.restype = None
         L.mdvrp_batch_destroy.argtypes = [p]
         L.mdvrp_batch_destroy.restype = None
+        L.mdvrp_mlp_destroy.argtypes = [p]
+        L.mdvrp_mlp_destroy.restype = None
         L.mdvrp_status_string.argtypes = [i32]
         L.mdvrp_status_string.restype = C.c_char_p
         L.mdvrp_last_error.argtypes = []
@@ -257,9 +288,9 @@ class Batch:
         return F.cpu().numpy(), T.cpu().numpy().reshape(self.n_units, 6)
 
     def state(self):
-        out = np.zeros(self.n_units * 8, np.int64)
+        out = np.zeros(self.n_units * STATE_WORDS, np.int64)
         check(lib().mdvrp_batch_state(self.handle, out.ctypes.data_as(C.c_void_p)))
-        return out.reshape(self.n_units, 8)
+        return out.reshape(self.n_units, STATE_WORDS)
 
     def load_device(self, nodes, offs, starts, ends, unit_route_off, n_routes, n_nodes):
         """Load from device tensors already resident in HBM (int32)."""
@@ -277,19 +308,20 @@ class Batch:
         return {name: (int(n[k]), float(ms[k])) for k, name in enumerate(PROF_CLASSES)}
 
     # ------------------------------------------------------------------ hot path
-    def eval_neighbourhood(self, fam_mask=FAM_ALL, dense_cap=0):
+    def eval_neighbourhood(self, fam_mask=FAM_ALL, dense_cap=0, filtered=False):
         torch = _torch()
+        fl = EVAL_FILTERED if filtered else 0
         if dense_cap:
             rec = torch.empty(dense_cap * DENSE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
             cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-            check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, EVAL_DENSE, _dptr(rec), dense_cap, _dptr(cnt),
-                                                 _stream()))
+            check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, EVAL_DENSE | fl, _dptr(rec), dense_cap,
+                                                 _dptr(cnt), _stream()))
             torch.cuda.synchronize()
             n = int(cnt.item())
             if n > dense_cap:
                 raise MdvrpError(ENOSPC, f"dense table needs {n} records")
             return np.frombuffer(rec[:n * DENSE_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=DENSE_DTYPE)
-        check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, 0, None, 0, None, _stream()))
+        check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, fl, None, 0, None, _stream()))
         return None
 
     def eval_footprint(self, fam_mask=FAM_ALL):
@@ -325,12 +357,172 @@ class Batch:
     def apply_moves(self):
         check(lib().mdvrp_apply_moves(self.handle, _stream()))
 
-    def local_search_to_optimum(self, mode=LS_PASSES, seed=0, max_passes=0, leader_only=0, poll_every=1):
-        opt = LsOptions(mode, leader_only, max_passes, poll_every, seed)
+    def local_search_to_optimum(self, mode=LS_PASSES, seed=0, max_passes=0, leader_only=0, poll_every=1,
+                                filter=FILTER_NONE, mlp=None):
+        opt = LsOptions(mode, leader_only, max_passes, poll_every, seed, filter, 0,
+                        mlp.handle.value if mlp is not None else None)
         stats = (LsStats * self.n_units)()
         check(lib().mdvrp_local_search_to_optimum(self.handle, C.byref(opt), stats, _stream()))
         return [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F,
-                     converged=s.converged, err=s.err) for s in stats]
+                     fallback_passes=s.fallback_passes, converged=s.converged, err=s.err) for s in stats]
+
+    # ------------------------------------------------------------------ learned filter
+    def filter_attach(self, k):
+        torch = _torch()
+        nbytes = C.c_size_t(0)
+        check(lib().mdvrp_filter_workspace_query(self.handle, k, C.byref(nbytes)))
+        self.filter_ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        check(lib().mdvrp_filter_attach(self.handle, k, _dptr(self.filter_ws), nbytes.value, _stream()))
+        self.kc = k
+
+    def anchor_count(self):
+        n = C.c_int64(0)
+        check(lib().mdvrp_filter_anchor_count(self.handle, C.byref(n)))
+        return n.value
+
+    def features(self, as_numpy=True):
+        """bf16 bits of every anchor's features, [anchors][32]."""
+        torch = _torch()
+        out = torch.empty((self.anchor_count(), 32), dtype=torch.int16, device="cuda")
+        check(lib().mdvrp_filter_features(self.handle, _dptr(out), _stream()))
+        if not as_numpy:
+            return out
+        torch.cuda.synchronize()
+        return out.cpu().numpy().view(np.uint16)
+
+    def labels(self, fam_mask=PAIR_FAMILIES, as_numpy=True):
+        torch = _torch()
+        out = torch.zeros(self.anchor_count(), dtype=torch.uint8, device="cuda")
+        check(lib().mdvrp_filter_labels(self.handle, fam_mask, _dptr(out), _stream()))
+        if not as_numpy:
+            return out
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    def score_topk(self, mlp, want_logits=True):
+        torch = _torch()
+        lg = torch.full((self.anchor_count(),), float("nan"), dtype=torch.float32, device="cuda") if want_logits else None
+        check(lib().mdvrp_filter_score_topk(self.handle, mlp.handle, _dptr(lg) if lg is not None else None, _stream()))
+        if lg is None:
+            return None
+        torch.cuda.synchronize()
+        return lg.cpu().numpy()
+
+    def eta_lists(self):
+        check(lib().mdvrp_filter_eta_lists(self.handle, _stream()))
+
+    def filter_lists(self):
+        """Candidate lists per unit: list of [n_customers][k] arrays."""
+        torch = _torch()
+        out = torch.empty(int(self.nc.sum()) * self.kc, dtype=torch.int32, device="cuda")
+        check(lib().mdvrp_filter_export(self.handle, _dptr(out), _stream()))
+        torch.cuda.synchronize()
+        a = out.cpu().numpy()
+        res, at = [], 0
+        for n in self.nc:
+            res.append(a[at:at + n * self.kc].reshape(n, self.kc).copy())
+            at += n * self.kc
+        return res
+
+
+class Mlp:
+    """Scoring network (32 -> 256 -> 256 -> 1) with fp32 master weights and Adam state on the device."""
+
+    def __init__(self, params=None):
+        torch = _torch()
+        nbytes = C.c_size_t(0)
+        check(lib().mdvrp_mlp_workspace_query(C.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        init = None
+        if params is not None:
+            init = torch.as_tensor(np.ascontiguousarray(params, np.float32)).to("cuda")
+        h = C.c_void_p()
+        check(lib().mdvrp_mlp_create(_dptr(self.ws), nbytes.value, _dptr(init) if init is not None else None,
+                                     _stream(), C.byref(h)))
+        self.handle = h
+        torch.cuda.synchronize()
+        self._act = None
+        self._act_n = -1
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.mdvrp_mlp_destroy(h)
+            self.handle = None
+
+    def get_params(self):
+        """Host copy of the fp32 master parameters."""
+        torch = _torch()
+        p = C.c_void_p()
+        check(lib().mdvrp_mlp_params(self.handle, C.byref(p)))
+        off = p.value - self.ws.data_ptr()
+        torch.cuda.synchronize()
+        return self.ws[off:off + 4 * MLP_PARAMS].view(torch.float32).cpu().numpy().copy()
+
+    def set_params(self, params, reset_adam=True):
+        torch = _torch()
+        p = C.c_void_p()
+        check(lib().mdvrp_mlp_params(self.handle, C.byref(p)))
+        off = p.value - self.ws.data_ptr()
+        src = torch.as_tensor(np.ascontiguousarray(params, np.float32)).to("cuda")
+        self.ws[off:off + 4 * MLP_PARAMS].view(torch.float32).copy_(src)
+        check(lib().mdvrp_mlp_sync(self.handle, 1 if reset_adam else 0, _stream()))
+
+    def act(self, n):
+        torch = _torch()
+        if self._act is None or self._act_n < n:
+            b = C.c_size_t(0)
+            check(lib().mdvrp_mlp_act_bytes(n, C.byref(b)))
+            self._act = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+            self._act_n = n
+            self._act_bytes = b.value
+        return self._act, self._act_bytes
+
+    def forward(self, x, keep=False):
+        """x: device int16 tensor [n][32] of bf16 bits; returns device fp32 logits."""
+        torch = _torch()
+        n = x.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device="cuda")
+        if keep:
+            a, ab = self.act(n)
+            check(lib().mdvrp_mlp_forward(self.handle, _dptr(x), n, _dptr(z), _dptr(a), ab, _stream()))
+        else:
+            check(lib().mdvrp_mlp_forward(self.handle, _dptr(x), n, _dptr(z), None, 0, _stream()))
+        return z
+
+    def backward(self, x, dz):
+        """Gradient of sum dz * logit after forward(x, keep=True); device fp32 [MLP_PARAMS]."""
+        torch = _torch()
+        n = x.shape[0]
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        a, ab = self.act(n)
+        check(lib().mdvrp_mlp_backward(self.handle, _dptr(x), _dptr(dz), n, _dptr(g), _dptr(a), ab, _stream()))
+        return g
+
+    def bce(self, z, y, w=None):
+        torch = _torch()
+        n = z.shape[0]
+        dz = torch.empty(n, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        check(lib().mdvrp_mlp_bce(self.handle, _dptr(z), _dptr(y), _dptr(w) if w is not None else None, n, _dptr(dz),
+                                  _dptr(loss), _stream()))
+        return dz, loss
+
+    def adam(self, g, lr, step):
+        check(lib().mdvrp_adam_step(self.handle, _dptr(g), float(lr), int(step), _stream()))
+
+    def train_step(self, x, y, w, lr, step):
+        """One optimiser step on (x, y[, w]); returns device (logits, loss, grads)."""
+        torch = _torch()
+        n = x.shape[0]
+        a, ab = self.act(n)
+        z = torch.empty(n, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        check(lib().mdvrp_mlp_train_step(self.handle, _dptr(x), _dptr(y), _dptr(w) if w is not None else None, n,
+                                         float(lr), int(step), _dptr(g), _dptr(z), _dptr(loss), _dptr(a), ab,
+                                         _stream()))
+        return z, loss, g
 
 
 def validate_solutions_host(instances, unit_inst, solutions):
