@@ -219,6 +219,9 @@ typedef struct mdvrp_mlp mdvrp_mlp;
 #define MDVRP_FILTER_LISTS 1 /* pair moves over the attached filter's lists as they stand */
 #define MDVRP_FILTER_MLP 2   /* lists re-ranked by the network whenever their features change */
 
+#define MDVRP_RESCORE_STEP 0 /* re-rank stale lists before every pair-family step */
+#define MDVRP_RESCORE_PASS 1 /* re-rank stale lists before the first pair-family step of a pass */
+
 typedef struct {
   int32_t mode;        /* MDVRP_LS_PASSES or MDVRP_LS_UNION */
   int32_t leader_only; /* 1 = single-move steps (the paper's ETGA-S) */
@@ -226,7 +229,7 @@ typedef struct {
   int32_t poll_every;  /* passes between host convergence checks (>= 1) */
   uint64_t seed;       /* family order of pass p: Fisher-Yates with SplitMix64(seed ^ p) */
   int32_t filter;      /* MDVRP_FILTER_*; a filter needs mdvrp_filter_attach first */
-  int32_t pad;
+  int32_t rescore;     /* MDVRP_RESCORE_*: when MDVRP_FILTER_MLP re-ranks stale lists */
   const mdvrp_mlp* mlp; /* network of MDVRP_FILTER_MLP, else ignored */
 } mdvrp_ls_options;
 
@@ -245,7 +248,8 @@ typedef struct {
  * either way. With MDVRP_FILTER_MLP the lists of every customer whose
  * features may have changed (its route, or the route of an entry of its
  * granular list, was rebuilt since the last ranking) are re-ranked before
- * each pair-family step; the first step ranks all of them. stats
+ * each pair-family step (MDVRP_RESCORE_STEP) or before the first one of each
+ * pass (MDVRP_RESCORE_PASS); the first ranking covers all of them. stats
  * (HOST array of n_units, nullable) receives per-unit results. Synchronises.
  * Errors: ERANGE when a route grew beyond the int32-safe length, ENOSPC on
  * internal capacity overflow, EDEVICE. */

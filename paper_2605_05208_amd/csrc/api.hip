@@ -111,6 +111,7 @@ struct mdvrp_batch {
   int n_cust = 0;                   // sum over units of n_customers
   int kc = 0;                       // filtered list length (0 = no filter attached)
   int32_t* d_cust_off = nullptr;    // [n_units + 1] customer offsets (filter workspace)
+  FilterQueue stale{};              // stale-customer queue of the re-ranking (filter workspace)
   LaunchCtx ctx(void* stream) const {
     LaunchCtx L;
     L.stream = S(stream);
@@ -789,6 +790,7 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   if (o->filter < MDVRP_FILTER_NONE || o->filter > MDVRP_FILTER_MLP) return fail(MDVRP_EINVAL, "unknown filter");
   if (o->filter != MDVRP_FILTER_NONE && B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached to the batch");
   if (o->filter == MDVRP_FILTER_MLP && !o->mlp) return fail(MDVRP_EINVAL, "the MLP filter needs a network");
+  if (o->rescore != MDVRP_RESCORE_STEP && o->rescore != MDVRP_RESCORE_PASS) return fail(MDVRP_EINVAL, "unknown rescore");
   const int poll = std::max(1, o->poll_every);
   const LaunchCtx L = B->ctx(stream);
   const bool rescoring = o->filter == MDVRP_FILTER_MLP;
@@ -804,14 +806,20 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     } else {
       nf = 1;
     }
+    bool ranked_this_pass = false;
     for (int k = 0; k < nf; ++k) {
       const uint32_t mask = o->mode == MDVRP_LS_PASSES ? (1u << fam[k]) : MDVRP_FAM_ALL;
       const uint32_t cls = eval_classes(L, mask);
-      // re-rank the lists of filtered units whose features changed since the last scoring
-      const bool score = rescoring && (mask & pair_fams) && (cls & 1u);
-      if (score)
+      // re-rank the lists of filtered units whose features changed since the last ranking:
+      // before every pair-family step, or before the first one of a pass
+      const bool pair_step = (mask & pair_fams) && (cls & 1u);
+      const bool score = rescoring && pair_step && !(o->rescore == MDVRP_RESCORE_PASS && ranked_this_pass);
+      if (pair_step) ranked_this_pass = true;
+      if (score) {
         timed(B, L.stream, MDVRP_PROF_FILTER_SCORE,
-              [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, o->mlp->d, 1, nullptr); });
+              [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, o->mlp->d, &B->stale, nullptr); });
+        B->stale.parity ^= 1;
+      }
       for (int c = 0; c < 3; ++c)
         if (cls >> c & 1) timed(B, L.stream, c, [&] { launch_eval_class(L, mask, c, nullptr); });
       timed(B, L.stream, 3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0, score ? 1 : 0); });
@@ -1030,9 +1038,13 @@ mdvrp_status check_filter_k(const mdvrp_batch* B, int32_t k) {
   return MDVRP_OK;
 }
 
-void carve_filter(Carve& cv, const mdvrp_batch* B, int32_t k, std::vector<int32_t*>* lists, int32_t** cust_off) {
+void carve_filter(Carve& cv, const mdvrp_batch* B, int32_t k, std::vector<int32_t*>* lists, int32_t** cust_off,
+                  FilterQueue* stale) {
   int32_t* co = cv.take<int32_t>(B->n_units + 1);
   if (cust_off) *cust_off = co;
+  int32_t* q = cv.take<int32_t>(B->n_cust);
+  int32_t* qc = cv.take<int32_t>(2);
+  if (stale) *stale = FilterQueue{q, qc, 0};
   for (int u = 0; u < B->n_units; ++u) {
     int32_t* p = cv.take<int32_t>((size_t)B->inst[B->unit_inst[u]]->d.n_customers * k);
     if (lists) lists->push_back(p);
@@ -1046,7 +1058,7 @@ extern "C" mdvrp_status mdvrp_filter_workspace_query(const mdvrp_batch* B, int32
   mdvrp_status st = check_filter_k(B, k);
   if (st) return st;
   Carve cv(nullptr);
-  carve_filter(cv, B, k, nullptr, nullptr);
+  carve_filter(cv, B, k, nullptr, nullptr, nullptr);
   *bytes = cv.off + 256;
   return MDVRP_OK;
 }
@@ -1061,7 +1073,8 @@ extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws,
   Carve cv(ws);
   std::vector<int32_t*> lists;
   int32_t* co = nullptr;
-  carve_filter(cv, B, k, &lists, &co);
+  FilterQueue fq{};
+  carve_filter(cv, B, k, &lists, &co, &fq);
   std::vector<int32_t> h_co(B->n_units + 1, 0);
   for (int u = 0; u < B->n_units; ++u) {
     UnitDesc& U = B->h_units[u];
@@ -1072,9 +1085,12 @@ extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws,
   }
   hipStream_t s = S(stream);
   HIP_TRY(hipMemcpyAsync(co, h_co.data(), sizeof(int32_t) * (B->n_units + 1), hipMemcpyHostToDevice, s));
+  const int32_t zero2[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(fq.count, zero2, sizeof zero2, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
   B->kc = k;
   B->d_cust_off = co;
+  B->stale = fq;
   // start from the heuristic lists so that a filtered evaluation is always defined
   launch_eta_lists(B->ctx(stream), co, B->n_cust);
   HIP_TRY(hipGetLastError());
@@ -1112,7 +1128,8 @@ extern "C" mdvrp_status mdvrp_filter_score_topk(mdvrp_batch* B, const mdvrp_mlp*
   if (!B || !M) return fail(MDVRP_EINVAL, "null argument");
   if (B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
   const LaunchCtx L = B->ctx(stream);
-  timed(B, L.stream, MDVRP_PROF_FILTER_SCORE, [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, M->d, 0, logits); });
+  timed(B, L.stream, MDVRP_PROF_FILTER_SCORE,
+        [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, M->d, nullptr, logits); });
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
 }

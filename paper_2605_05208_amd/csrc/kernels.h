@@ -66,9 +66,16 @@ int mlp_row_pad();  // activation buffers hold n rounded up to a multiple of thi
 void launch_mlp_pack(hipStream_t s, const MlpDev& M);
 void launch_mlp_zero(hipStream_t s, float* p, int n);
 void launch_features(const LaunchCtx& L, uint16_t* out);
-// mode 0: score every customer; mode 1: stale customers of active filtered units.
-void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M, int mode,
-                       float* logits_out);
+// Queue of stale customers: queue[n_customers of the batch], two counters used in
+// alternation (parity): a use clears the other one, which the next use takes.
+struct FilterQueue {
+  int32_t* queue;
+  int32_t* count;
+  int parity;
+};
+// stale == null: rank every customer; else only the stale customers of active filtered units.
+void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M,
+                       const FilterQueue* stale, float* logits_out);
 void launch_eta_lists(const LaunchCtx& L, const int32_t* cust_off, int n_tasks);
 void launch_mlp_forward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, float* logits, uint16_t* h1,
                         uint16_t* h2);

@@ -302,38 +302,70 @@ constexpr int kScoreWaves = 8;
 constexpr int kScoreT = 2;      // sample tiles per pass through W2
 constexpr int kMaxTheta = 128;  // list entries scored per customer
 
+// Stale customers: one thread per (unit, customer) of every active filtered unit; a
+// customer is stale when its route, or the route of some entry of N(u), was rebuilt
+// after the unit's last ranking (dirty tag above scored_epoch). Stale tasks are
+// appended to queue[*count] (one atomic per wavefront); clear_count (the counter of
+// the next use) is zeroed here so that no separate launch is needed.
+__global__ __launch_bounds__(256) void k_stale_mark(const UnitDesc* __restrict__ units,
+                                                    const int32_t* __restrict__ cust_off, int n_units,
+                                                    int32_t* __restrict__ queue, int32_t* __restrict__ count,
+                                                    int32_t* __restrict__ clear_count) {
+  const int task = blockIdx.x * blockDim.x + threadIdx.x;
+  if (task == 0) *clear_count = 0;
+  bool st = false;
+  if (task < cust_off[n_units]) {
+    const int ui = unit_of_tile(cust_off, n_units, task);
+    const UnitDesc& U = units[ui];
+    const UnitCtl* c = U.ctl;
+    if (c->active && c->fmode == 1) {
+      const int i = task - cust_off[ui];
+      const int se = c->scored_epoch;
+      const int32_t* nb = U.nbr + (int64_t)i * U.theta;
+      const int len = U.nbr_len[i];
+      st = U.dirty[U.rt[U.nd + i]] > se;
+      for (int k0 = 0; k0 < len && !st; k0 += 8) {
+        int slot[8];
+#pragma unroll
+        for (int z = 0; z < 8; ++z) slot[z] = k0 + z < len ? U.rt[nb[k0 + z]] : -1;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) st = st || (slot[z] >= 0 && U.dirty[slot[z]] > se);
+      }
+    }
+  }
+  const uint64_t m = __ballot(st);
+  if (!m) return;
+  const int lane = lane_id();
+  int base = 0;
+  if (lane == 0) base = atomicAdd(count, __popcll(m));
+  base = __shfl(base, 0);
+  if (st) queue[base + __popcll(m & ((1ull << lane) - 1))] = task;
+}
+
 // One wave per (unit, customer) task: features of the customer's list entries, their
 // logits, and the kc best (logit descending, customer id ascending) into fcand.
-// mode 0: every customer of every unit; mode 1: active filtered units only, and only
-// customers whose features may have changed since the last scoring (the route of u or
-// of some v in N(u) was rebuilt after scored_epoch).
+// Tasks: queue[0 .. *qcount) when a queue is given, else every customer of every unit.
 template <class SEG, bool TW>
 __global__ __launch_bounds__(64 * kScoreWaves) void k_score_topk(
     const UnitDesc* __restrict__ units, const int32_t* __restrict__ cust_off, int n_units,
     const bf16x8* __restrict__ w1f, const bf16x8* __restrict__ w2f, const float* __restrict__ P,
-    const float* __restrict__ w3b, int mode, float* __restrict__ logits_out) {
+    const float* __restrict__ w3b, const int32_t* __restrict__ queue, const int32_t* __restrict__ qcount,
+    float* __restrict__ logits_out) {
   __shared__ MlpSmem S;
   __shared__ __attribute__((aligned(16))) uint16_t xs[kScoreWaves][16 * kScoreT * kF];
   __shared__ float lg[kScoreWaves][kMaxTheta];
   mlp_stage(S, w2f, P, w3b);
   const float b3 = P[P_B3];
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  const int n_tasks = cust_off[n_units];
-  for (int task = blockIdx.x * kScoreWaves + wave; task < n_tasks; task += gridDim.x * kScoreWaves) {
+  const int n_tasks = queue ? *qcount : cust_off[n_units];
+  for (int q = blockIdx.x * kScoreWaves + wave; q < n_tasks; q += gridDim.x * kScoreWaves) {
+    const int task = queue ? queue[q] : q;
     const int ui = unit_of_tile(cust_off, n_units, task);
     const UnitDesc& U = units[ui];
     const int i = task - cust_off[ui];
     const int u = U.nd + i;
     const int len = imin(U.nbr_len[i], kMaxTheta);
     const int32_t* nb = U.nbr + (int64_t)i * U.theta;
-    if (mode == 1) {
-      const UnitCtl* c = U.ctl;
-      if (!c->active || c->fmode != 1) continue;
-      const int se = c->scored_epoch;
-      bool st = lane == 0 && U.dirty[U.rt[u]] > se;
-      for (int k = lane; k < len; k += 64) st = st || U.dirty[U.rt[nb[k]]] > se;
-      if (!__any(st)) continue;
-    }
     const int cur = U.ctl->cur;
     for (int base = 0; base < len; base += 16 * kScoreT) {
       // features of entries base .. base + 16 T - 1, one row per lane of the first 16 T lanes
@@ -622,19 +654,29 @@ void launch_features(const LaunchCtx& L, uint16_t* out) {
 }
 
 template <class SEG, bool TW>
-static void score_t(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M, int mode,
-                    float* logits_out) {
+static void score_t(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M,
+                    const int32_t* queue, const int32_t* qcount, float* logits_out) {
   const int blocks = grid_for(n_tasks, kScoreWaves, 256);
   hipLaunchKernelGGL((k_score_topk<SEG, TW>), dim3(blocks), dim3(64 * kScoreWaves), 0, L.stream, L.units, cust_off,
                      L.n_units, (const bf16x8*)M.w1f, (const bf16x8*)M.w2f, (const float*)M.P, (const float*)M.w3b,
-                     mode, logits_out);
+                     queue, qcount, logits_out);
 }
 
-void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M, int mode,
-                       float* logits_out) {
+void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M,
+                       const FilterQueue* stale, float* logits_out) {
   if (n_tasks <= 0) return;
-  if (L.has_tw) score_t<SegTW, true>(L, cust_off, n_tasks, M, mode, logits_out);
-  else score_t<SegNT, false>(L, cust_off, n_tasks, M, mode, logits_out);
+  const int32_t* queue = nullptr;
+  const int32_t* qcount = nullptr;
+  if (stale) {
+    int32_t* cnt = stale->count + stale->parity;
+    int32_t* other = stale->count + (stale->parity ^ 1);
+    hipLaunchKernelGGL(k_stale_mark, dim3((n_tasks + 255) / 256), dim3(256), 0, L.stream, L.units, cust_off,
+                       L.n_units, stale->queue, cnt, other);
+    queue = stale->queue;
+    qcount = cnt;
+  }
+  if (L.has_tw) score_t<SegTW, true>(L, cust_off, n_tasks, M, queue, qcount, logits_out);
+  else score_t<SegNT, false>(L, cust_off, n_tasks, M, queue, qcount, logits_out);
 }
 
 void launch_eta_lists(const LaunchCtx& L, const int32_t* cust_off, int n_tasks) {

@@ -21,6 +21,7 @@ FAM_ALL = 0x3F
 EVAL_DENSE, EVAL_FILTERED = 1, 2
 LS_PASSES, LS_UNION = 0, 1
 FILTER_NONE, FILTER_LISTS, FILTER_MLP = 0, 1, 2
+RESCORE_STEP, RESCORE_PASS = 0, 1
 MLP_PARAMS = 74497
 PAIR_FAMILIES = FAM_RELOCATE | FAM_SWAP | FAM_2OPT_STAR | FAM_2OPT
 
@@ -42,7 +43,7 @@ class InstanceDesc(C.Structure):
 
 class LsOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("leader_only", C.c_int32), ("max_passes", C.c_int32),
-                ("poll_every", C.c_int32), ("seed", C.c_uint64), ("filter", C.c_int32), ("pad", C.c_int32),
+                ("poll_every", C.c_int32), ("seed", C.c_uint64), ("filter", C.c_int32), ("rescore", C.c_int32),
                 ("mlp", C.c_void_p)]
 
 
@@ -358,8 +359,8 @@ class Batch:
         check(lib().mdvrp_apply_moves(self.handle, _stream()))
 
     def local_search_to_optimum(self, mode=LS_PASSES, seed=0, max_passes=0, leader_only=0, poll_every=1,
-                                filter=FILTER_NONE, mlp=None):
-        opt = LsOptions(mode, leader_only, max_passes, poll_every, seed, filter, 0,
+                                filter=FILTER_NONE, mlp=None, rescore=RESCORE_STEP):
+        opt = LsOptions(mode, leader_only, max_passes, poll_every, seed, filter, rescore,
                         mlp.handle.value if mlp is not None else None)
         stats = (LsStats * self.n_units)()
         check(lib().mdvrp_local_search_to_optimum(self.handle, C.byref(opt), stats, _stream()))
