@@ -1,5 +1,6 @@
 #!/usr/bin/env python3
-"""Benchmark: penalised move evaluations per second and time to local optimum.
+"""Benchmark: penalised move evaluations per second, time to local optimum, and
+the learned filter against full evaluation.
 
 One step = load 64 seeded start solutions of the 8-depot / 1000-customer
 MDVRPTW instance (already resident in HBM) into the segment state and run the
@@ -9,6 +10,13 @@ pass applies nothing). The line reports whole-job move evaluations per second,
 the time per step, the roofline of the dominant kernel (HIP events on the
 library's stream; compulsory bytes per launch, see the design notes) and the
 CPU oracle timed on a bounded sample of the same workload.
+
+The `filter` object compares, on the 20-depot / 10000-customer MDVRPTW
+instance with 16 solutions, the local search over the full granular lists
+with the searches over 8-entry lists ranked by the trained network and by the
+eta order: GPU time, and the gap of the local-optimum cost per seed. The
+network is trained first, on the GPU, from logs of full-list searches of the
+1000-customer instance and of uneven instances (not timed in the comparison).
 """
 from __future__ import annotations
 
@@ -89,6 +97,130 @@ def cpu_baseline(inst, sols, n_sample, seed):
                        f"{ev} evaluated moves in {dt:.1f} s", seconds=round(dt, 2))
 
 
+def ls_run(B, sols, **kw):
+    """Local search of the batch from `sols`; returns (seconds, stats, profile)."""
+    import torch
+    B.load(sols)
+    if kw.pop("eta", False):
+        B.eta_lists()
+    torch.cuda.synchronize()
+    B.profile_enable(0x3F)
+    t0 = time.perf_counter()
+    st = B.local_search_to_optimum(seed=1, poll_every=4, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = B.profile_read()
+    B.profile_enable(0)
+    assert all(s["converged"] and s["err"] == 0 for s in st)
+    return dt, st, prof
+
+
+def filter_study(n_sol=16, k=8, epochs=6):
+    """Full vs filtered local search on the 20 x 10000 MDVRPTW instance."""
+    import torch
+
+    from paper_2605_05208_amd import filter_train as ft
+    from paper_2605_05208_amd import gen, mdvrp
+    t0 = time.perf_counter()
+    insts = ft.training_instances(8)
+    dev = [mdvrp.Instance(i) for i in insts]
+    unit_inst = [0] * 16 + list(range(1, len(insts)))
+    sols = [gen.start_solution(insts[0], insts[0].seed * 1000 + j) for j in range(16)]
+    sols += [gen.start_solution(insts[j], insts[j].seed * 1000) for j in range(1, len(insts))]
+    TB = mdvrp.Batch(dev, unit_inst)
+    x, y, w, snaps = ft.log_states(TB, sols, chunk=2, max_chunks=40)
+    torch.cuda.synchronize()
+    t_log = time.perf_counter() - t0
+    M = mdvrp.Mlp(None)
+    M.set_params(ft.init_params(0))
+    losses, t_train = ft.train(M, x, y, w, epochs=epochs, lr=1e-3)
+    del TB, dev
+
+    I5 = gen.config5()
+    s5 = [gen.start_solution(I5, I5.seed * 1000 + j) for j in range(n_sol)]
+    B5 = mdvrp.Batch([mdvrp.Instance(I5)], [0] * n_sol)
+    B5.filter_attach(k)
+    runs = {}
+    for name, kw in (("full", {}), ("eta", dict(filter=mdvrp.FILTER_LISTS, eta=True)),
+                     ("mlp", dict(filter=mdvrp.FILTER_MLP, mlp=M, rescore=mdvrp.RESCORE_PASS))):
+        dt, st, prof = ls_run(B5, s5, **kw)
+        runs[name] = (dt, np.array([s["F"] for s in st], np.float64), st, prof)
+    full_dt, full_F = runs["full"][0], runs["full"][1]
+    out = dict(workload=f"{I5.name}: {n_sol} solutions, local search to a local optimum of the full neighbourhood",
+               k=k, full_ms=round(full_dt * 1e3, 1), full_F_mean=float(full_F.mean()),
+               full_evaluated=int(sum(s["evaluated"] for s in runs["full"][2])),
+               train=dict(samples=int(x.shape[0]), positives=int(y.sum().item()), snapshots=snaps,
+                          log_s=round(t_log, 2), train_s=round(t_train, 2), epochs=epochs,
+                          loss_first=round(losses[0], 4), loss_last=round(losses[-1], 4)))
+    for name in ("mlp", "eta"):
+        dt, F, st, prof = runs[name]
+        gap = (F - full_F) / full_F
+        out[name] = dict(ms=round(dt * 1e3, 1), speedup=round(full_dt / dt, 3), gap_mean=float(gap.mean()),
+                         gap_max=float(gap.max()), F_mean=float(F.mean()),
+                         evaluated=int(sum(s["evaluated"] for s in st)),
+                         fallback_passes_max=int(max(s["fallback_passes"] for s in st)),
+                         score_ms=round(prof["filter_score"][1], 1))
+    return out
+
+
+MLP_FWD_FLOP = 2 * (32 * 256 + 256 * 256 + 256)  # per scored anchor / forward sample
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_probe(n_sol=16, reps=5, n_train=65536):
+    """Scoring every list of the 20 x 10000 MDVRPTW batch and training steps, timed with
+    HIP events on the library's stream (MFMA-bound kernels of the filter)."""
+    import torch
+
+    from paper_2605_05208_amd import filter_train as ft
+    from paper_2605_05208_amd import gen, mdvrp
+    I5 = gen.config5()
+    B5 = mdvrp.Batch([mdvrp.Instance(I5)], [0] * n_sol)
+    B5.filter_attach(8)
+    B5.load([gen.start_solution(I5, I5.seed * 1000 + j) for j in range(n_sol)])
+    M = mdvrp.Mlp(ft.init_params(0))
+    B5.score_topk(M, want_logits=False)
+    torch.cuda.synchronize()
+    B5.profile_enable(1 << 5)
+    for _ in range(reps):
+        B5.score_topk(M, want_logits=False)
+    n_l, ms = B5.profile_read()["filter_score"]
+    B5.profile_enable(0)
+    anchors = B5.anchor_count()
+    score_s = ms / n_l / 1e3
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x = (torch.randint(0, 1 << 14, (n_train, 32), dtype=torch.int16, device="cuda", generator=g) & 0x3FFF) - 0x2000
+    y = (torch.rand(n_train, device="cuda", generator=g) < 0.3).float()
+    M.train_step(x, y, None, 1e-3, 1)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for k in range(reps):
+        M.train_step(x, y, None, 1e-3, k + 2)
+    e1.record(s)
+    torch.cuda.synchronize()
+    train_s = e0.elapsed_time(e1) / reps / 1e3
+    score_tf = anchors * MLP_FWD_FLOP / score_s / 1e12
+    train_tf = n_train * 3 * MLP_FWD_FLOP / train_s / 1e12
+    return dict(anchors=anchors, score_ms=round(score_s * 1e3, 3), score_tflops=round(score_tf, 1),
+                score_frac=round(score_tf / MFMA_BF16_PEAK_TFLOPS, 4), train_samples=n_train,
+                train_step_ms=round(train_s * 1e3, 3), train_tflops=round(train_tf, 1),
+                train_frac=round(train_tf / MFMA_BF16_PEAK_TFLOPS, 4))
+
+
+def calibrate_copy(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of known size (reference for the HBM byte counters)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +230,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=8, help="solutions for the CPU oracle leg (0 = skip)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-filter", action="store_true", help="skip the learned-filter comparison")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB copy (counter reference)")
+    ap.add_argument("--mlp-probe", action="store_true", help="only time the filter's scoring and training kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the local search of a population is data parallel over "
@@ -106,6 +241,13 @@ def main():
         return 2
 
     import torch
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return 0
+    if args.mlp_probe:
+        print(json.dumps(mlp_probe()), flush=True)
+        return 0
 
     from paper_2605_05208_amd import mdvrp
     from paper_2605_05208_amd.gen import batch_flat
@@ -155,6 +297,7 @@ def main():
     cpu = None
     if args.cpu_sample > 0:
         cpu = cpu_baseline(inst, sols, args.cpu_sample, args.seed)
+    filt = None if args.no_filter else filter_study()
 
     F = [int(s["F"]) for s in stats]
     line = {
@@ -184,6 +327,7 @@ def main():
         "eval_pairs_ms_per_step": round(prof["eval_pairs"][1] / args.steps, 3),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "filter": filt,
     }
     print(json.dumps(line), flush=True)
     return 0

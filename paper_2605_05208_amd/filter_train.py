@@ -129,6 +129,19 @@ def recall_at_k(batch: mdvrp.Batch, mlp: mdvrp.Mlp | None, k: int):
     return hit / max(tot, 1), tot
 
 
+def init_params(seed=0):
+    """He-initialised hidden layers, zero biases, a small output layer."""
+    rng = np.random.default_rng(seed)
+    H, F = 256, 32
+    P = np.zeros(mdvrp.MLP_PARAMS, np.float32)
+    P[0:H * F] = rng.standard_normal(H * F) * np.sqrt(2.0 / F)
+    w2 = H * F + H
+    P[w2:w2 + H * H] = rng.standard_normal(H * H) * np.sqrt(2.0 / H)
+    w3 = w2 + H * H + H
+    P[w3:w3 + H] = rng.standard_normal(H) * np.sqrt(1.0 / H)
+    return P
+
+
 def training_instances(n_config4=8):
     """Instances whose full runs provide the logs: config 2 and a spread of config-4 sizes."""
     insts = [gen.config2()]
