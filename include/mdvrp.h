@@ -158,10 +158,12 @@ mdvrp_status mdvrp_solutions_export(const mdvrp_batch* batch, int32_t* route_nod
  * terms nullable). */
 mdvrp_status mdvrp_batch_cost(mdvrp_batch* batch, int64_t* F, int64_t* terms, void* stream);
 
-/* Host copy of per-unit counters, 10 per unit: running F, evaluated moves,
+/* Host copy of per-unit counters, 12 per unit: running F, evaluated moves,
  * passes, steps, moves applied, error bits, active flag, moves selected in
  * the latest step, full-list fallback passes of a filtered search, current
- * list mode (0 full, 1 filtered, 2 full fallback pass). Synchronises. */
+ * list mode (0 full, 1 filtered, 2 full fallback pass), device clock at the
+ * start of the latest search and at the end of the unit's latest pass.
+ * Synchronises. */
 mdvrp_status mdvrp_batch_state(const mdvrp_batch* batch, int64_t* out_host);
 
 /* ------------------------------------------------------------------------- hot path */
@@ -231,11 +233,17 @@ typedef struct {
   int32_t filter;      /* MDVRP_FILTER_*; a filter needs mdvrp_filter_attach first */
   int32_t rescore;     /* MDVRP_RESCORE_*: when MDVRP_FILTER_MLP re-ranks stale lists */
   const mdvrp_mlp* mlp; /* network of MDVRP_FILTER_MLP, else ignored */
+  int32_t graph;       /* 1 = each pass runs as a HIP graph, captured once per distinct launch
+                          sequence (family order and options) and replayed; per-launch
+                          profiling is off for captured passes */
+  int32_t pad2;
 } mdvrp_ls_options;
 
 typedef struct {
   int64_t passes, steps, moves_applied, evaluated, F;
   int64_t fallback_passes; /* passes of a filtered search that evaluated the full lists */
+  double device_ms;        /* device clock from the start of the search to the end of this
+                              unit's last pass (its time to the local optimum) */
   int32_t converged, err;
 } mdvrp_ls_stats;
 

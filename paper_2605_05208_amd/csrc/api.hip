@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -112,6 +113,15 @@ struct mdvrp_batch {
   int kc = 0;                       // filtered list length (0 = no filter attached)
   int32_t* d_cust_off = nullptr;    // [n_units + 1] customer offsets (filter workspace)
   FilterQueue stale{};              // stale-customer queue of the re-ranking (filter workspace)
+  // captured passes of the local search, keyed by everything the launch sequence depends on
+  std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+  hipStream_t own = nullptr;        // capture stream used when the caller passes the null stream
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  double clock_khz = 0;             // device wall-clock rate
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+  }
   LaunchCtx ctx(void* stream) const {
     LaunchCtx L;
     L.stream = S(stream);
@@ -505,6 +515,12 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
   for (int c = 0; c < 4 && he == hipSuccess; ++c)
     he = hipMemcpyAsync(B->d_tile_off[c], B->h_tile_off[c].data(), sizeof(int32_t) * (n_units + 1),
                         hipMemcpyHostToDevice, s);
+  if (he == hipSuccess) {
+    int dev = 0, khz = 0;
+    he = hipGetDevice(&dev);
+    if (he == hipSuccess) he = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    B->clock_khz = khz;
+  }
   if (he == hipSuccess) he = hipMemcpyAsync(B->d_node_base, nbase.data(), sizeof(int32_t) * n_units, hipMemcpyHostToDevice, s);
   if (he == hipSuccess) he = hipMemcpyAsync(B->d_route_base, rbase.data(), sizeof(int32_t) * n_units, hipMemcpyHostToDevice, s);
   for (int k = 0; k < n_units && he == hipSuccess; ++k) {
@@ -526,6 +542,10 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
 extern "C" void mdvrp_batch_destroy(mdvrp_batch* B) {
   if (!B) return;
   for (hipEvent_t e : B->prof.ev) (void)hipEventDestroy(e);
+  B->drop_graphs();
+  if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+  if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  if (B->own) (void)hipStreamDestroy(B->own);
   delete B;
 }
 
@@ -695,6 +715,8 @@ __global__ static void k_step_begin(const UnitDesc* units, int n_units, int fmod
     c->active = 1;
     c->fmode = fmode;
     if (rescore) c->scored_epoch = -1;
+    c->t_start = (int64_t)wall_clock64();
+    c->t_end = c->t_start;
   }
 }
 
@@ -782,6 +804,42 @@ static mdvrp_status check_unit_errors(mdvrp_batch* B, std::vector<int64_t>& st, 
   return MDVRP_OK;
 }
 
+namespace {
+
+// Launch sequence of one pass of the local search (Algorithm 2): the families in
+// the pass's order, each evaluated, selected and applied; optional re-ranking of
+// the filtered lists. With time = false nothing is timed (graph capture).
+void launch_pass(mdvrp_batch* B, const LaunchCtx& L, const mdvrp_ls_options* o, const int32_t* fam, int nf,
+                 bool time) {
+  const uint32_t pair_fams = MDVRP_FAM_RELOCATE | MDVRP_FAM_SWAP | MDVRP_FAM_2OPT_STAR | MDVRP_FAM_2OPT;
+  const bool rescoring = o->filter == MDVRP_FILTER_MLP;
+  auto run = [&](int cls, auto&& f) {
+    if (time) timed(B, L.stream, cls, f);
+    else f();
+  };
+  launch_pass_begin(L);
+  bool ranked_this_pass = false;
+  for (int k = 0; k < nf; ++k) {
+    const uint32_t mask = o->mode == MDVRP_LS_PASSES ? (1u << fam[k]) : MDVRP_FAM_ALL;
+    const uint32_t cls = eval_classes(L, mask);
+    // re-rank the lists of filtered units whose features changed since the last ranking:
+    // before every pair-family step, or before the first one of a pass
+    const bool pair_step = (mask & pair_fams) && (cls & 1u);
+    const bool score = rescoring && pair_step && !(o->rescore == MDVRP_RESCORE_PASS && ranked_this_pass);
+    if (pair_step) ranked_this_pass = true;
+    if (score)
+      run(MDVRP_PROF_FILTER_SCORE,
+          [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, o->mlp->d, &B->stale, nullptr); });
+    for (int c = 0; c < 3; ++c)
+      if (cls >> c & 1) run(c, [&] { launch_eval_class(L, mask, c, nullptr); });
+    run(3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0, score ? 1 : 0); });
+    run(4, [&] { launch_rebuild(L); });
+  }
+  launch_pass_end(L);
+}
+
+}  // namespace
+
 extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvrp_ls_options* o,
                                                       mdvrp_ls_stats* stats, void* stream) {
   if (!B || !o) return fail(MDVRP_EINVAL, "null argument");
@@ -791,61 +849,72 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   if (o->filter != MDVRP_FILTER_NONE && B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached to the batch");
   if (o->filter == MDVRP_FILTER_MLP && !o->mlp) return fail(MDVRP_EINVAL, "the MLP filter needs a network");
   if (o->rescore != MDVRP_RESCORE_STEP && o->rescore != MDVRP_RESCORE_PASS) return fail(MDVRP_EINVAL, "unknown rescore");
+  if (o->graph != 0 && o->graph != 1) return fail(MDVRP_EINVAL, "graph must be 0 or 1");
   const int poll = std::max(1, o->poll_every);
-  const LaunchCtx L = B->ctx(stream);
-  const bool rescoring = o->filter == MDVRP_FILTER_MLP;
-  step_begin(L, o->filter != MDVRP_FILTER_NONE ? 1 : 0, rescoring ? 1 : 0);
-  const uint32_t pair_fams = MDVRP_FAM_RELOCATE | MDVRP_FAM_SWAP | MDVRP_FAM_2OPT_STAR | MDVRP_FAM_2OPT;
+  // A pass captured as a graph needs a capturable stream: the null stream is
+  // replaced by the batch's own stream, ordered after and before the caller's work.
+  hipStream_t st = S(stream);
+  const bool use_own = o->graph && st == nullptr;
+  if (use_own) {
+    if (!B->own) {
+      HIP_TRY(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(B->ev_in, st));
+    HIP_TRY(hipStreamWaitEvent(B->own, B->ev_in, 0));
+    st = B->own;
+  }
+  const LaunchCtx L = B->ctx(st);
+  step_begin(L, o->filter != MDVRP_FILTER_NONE ? 1 : 0, o->filter == MDVRP_FILTER_MLP ? 1 : 0);
   int32_t active = B->n_units;
   for (int64_t p = 0; o->max_passes == 0 || p < o->max_passes; ++p) {
-    launch_pass_begin(L);
     int32_t fam[6];
-    int nf;
-    if (o->mode == MDVRP_LS_PASSES) {
-      nf = mdvrp_family_order(B->has_tw, o->seed, p, fam);
+    const int nf = o->mode == MDVRP_LS_PASSES ? mdvrp_family_order(B->has_tw, o->seed, p, fam) : 1;
+    if (!o->graph) {
+      launch_pass(B, L, o, fam, nf, true);
     } else {
-      nf = 1;
-    }
-    bool ranked_this_pass = false;
-    for (int k = 0; k < nf; ++k) {
-      const uint32_t mask = o->mode == MDVRP_LS_PASSES ? (1u << fam[k]) : MDVRP_FAM_ALL;
-      const uint32_t cls = eval_classes(L, mask);
-      // re-rank the lists of filtered units whose features changed since the last ranking:
-      // before every pair-family step, or before the first one of a pass
-      const bool pair_step = (mask & pair_fams) && (cls & 1u);
-      const bool score = rescoring && pair_step && !(o->rescore == MDVRP_RESCORE_PASS && ranked_this_pass);
-      if (pair_step) ranked_this_pass = true;
-      if (score) {
-        timed(B, L.stream, MDVRP_PROF_FILTER_SCORE,
-              [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, o->mlp->d, &B->stale, nullptr); });
-        B->stale.parity ^= 1;
+      std::vector<int64_t> key = {o->mode, o->leader_only, o->filter, o->rescore, (int64_t)(intptr_t)o->mlp, nf};
+      for (int k = 0; k < nf; ++k) key.push_back(fam[k]);
+      auto it = B->graphs.find(key);
+      if (it == B->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        launch_pass(B, L, o, fam, nf, false);
+        HIP_TRY(hipStreamEndCapture(st, &g));
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(MDVRP_EDEVICE, "graph instantiation: %s", hipGetErrorString(e));
+        it = B->graphs.emplace(key, ex).first;
       }
-      for (int c = 0; c < 3; ++c)
-        if (cls >> c & 1) timed(B, L.stream, c, [&] { launch_eval_class(L, mask, c, nullptr); });
-      timed(B, L.stream, 3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0, score ? 1 : 0); });
-      timed(B, L.stream, 4, [&] { launch_rebuild(L); });
+      HIP_TRY(hipGraphLaunch(it->second, st));
     }
-    launch_pass_end(L);
     HIP_TRY(hipGetLastError());
     if ((p + 1) % poll == 0) {
-      HIP_TRY(hipMemcpyAsync(&active, B->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, L.stream));
-      HIP_TRY(hipStreamSynchronize(L.stream));
+      HIP_TRY(hipMemcpyAsync(&active, B->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
       if (active == 0) break;
     }
   }
-  HIP_TRY(hipStreamSynchronize(L.stream));
+  HIP_TRY(hipStreamSynchronize(st));
   launch_cost(L, nullptr, nullptr);
-  std::vector<int64_t> st;
-  mdvrp_status s = check_unit_errors(B, st, stream);
+  std::vector<int64_t> stv;
+  mdvrp_status s = check_unit_errors(B, stv, st);
+  if (use_own) {
+    HIP_TRY(hipEventRecord(B->ev_out, st));
+    HIP_TRY(hipStreamWaitEvent(S(stream), B->ev_out, 0));
+  }
   if (stats) {
     for (int k = 0; k < B->n_units; ++k) {
-      const int64_t* x = &st[(size_t)k * kStateWords];
+      const int64_t* x = &stv[(size_t)k * kStateWords];
       stats[k].F = x[0];
       stats[k].evaluated = x[1];
       stats[k].passes = x[2];
       stats[k].steps = x[3];
       stats[k].moves_applied = x[4];
       stats[k].fallback_passes = x[8];
+      stats[k].device_ms = B->clock_khz > 0 ? (double)(x[11] - x[10]) / B->clock_khz : -1.0;
       stats[k].err = (int32_t)x[5];
       stats[k].converged = x[6] ? 0 : 1;
     }
@@ -1043,8 +1112,8 @@ void carve_filter(Carve& cv, const mdvrp_batch* B, int32_t k, std::vector<int32_
   int32_t* co = cv.take<int32_t>(B->n_units + 1);
   if (cust_off) *cust_off = co;
   int32_t* q = cv.take<int32_t>(B->n_cust);
-  int32_t* qc = cv.take<int32_t>(2);
-  if (stale) *stale = FilterQueue{q, qc, 0};
+  int32_t* qc = cv.take<int32_t>(1);
+  if (stale) *stale = FilterQueue{q, qc};
   for (int u = 0; u < B->n_units; ++u) {
     int32_t* p = cv.take<int32_t>((size_t)B->inst[B->unit_inst[u]]->d.n_customers * k);
     if (lists) lists->push_back(p);
@@ -1085,9 +1154,8 @@ extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws,
   }
   hipStream_t s = S(stream);
   HIP_TRY(hipMemcpyAsync(co, h_co.data(), sizeof(int32_t) * (B->n_units + 1), hipMemcpyHostToDevice, s));
-  const int32_t zero2[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(fq.count, zero2, sizeof zero2, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
+  B->drop_graphs();  // captured passes refer to the previous filter state
   B->kc = k;
   B->d_cust_off = co;
   B->stale = fq;

@@ -72,6 +72,8 @@ struct UnitCtl {
   int64_t passes, steps, moves_applied;
   int64_t last_eval;     // evaluated moves of the latest step
   int64_t fallbacks;     // full-list fallback passes of a filtered search
+  int64_t t_start;       // device clock at the start of the latest search
+  int64_t t_end;         // device clock at the end of this unit's latest pass
   MoveRec leader;
 };
 

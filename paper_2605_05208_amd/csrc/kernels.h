@@ -47,7 +47,7 @@ void launch_export(const LaunchCtx& L, int32_t* nodes, int32_t* offs, int32_t* s
 void launch_load(const LaunchCtx& L, const int32_t* nodes, const int32_t* offs, const int32_t* starts,
                  const int32_t* ends, const int32_t* unit_route_off);
 void launch_sel_export(const LaunchCtx& L, uint64_t* ids, int64_t* dF, int32_t* counts, int32_t cap_per_unit);
-constexpr int kStateWords = 10;  // per-unit counters exported by launch_state_export
+constexpr int kStateWords = 12;  // per-unit counters exported by launch_state_export
 void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][kStateWords] */);
 
 // ---- learned move filter
@@ -66,12 +66,10 @@ int mlp_row_pad();  // activation buffers hold n rounded up to a multiple of thi
 void launch_mlp_pack(hipStream_t s, const MlpDev& M);
 void launch_mlp_zero(hipStream_t s, float* p, int n);
 void launch_features(const LaunchCtx& L, uint16_t* out);
-// Queue of stale customers: queue[n_customers of the batch], two counters used in
-// alternation (parity): a use clears the other one, which the next use takes.
+// Queue of stale customers: queue[n_customers of the batch] and its length.
 struct FilterQueue {
   int32_t* queue;
   int32_t* count;
-  int parity;
 };
 // stale == null: rank every customer; else only the stale customers of active filtered units.
 void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M,

@@ -302,17 +302,16 @@ constexpr int kScoreWaves = 8;
 constexpr int kScoreT = 2;      // sample tiles per pass through W2
 constexpr int kMaxTheta = 128;  // list entries scored per customer
 
+__global__ void k_queue_reset(int32_t* __restrict__ count) { *count = 0; }
+
 // Stale customers: one thread per (unit, customer) of every active filtered unit; a
 // customer is stale when its route, or the route of some entry of N(u), was rebuilt
 // after the unit's last ranking (dirty tag above scored_epoch). Stale tasks are
-// appended to queue[*count] (one atomic per wavefront); clear_count (the counter of
-// the next use) is zeroed here so that no separate launch is needed.
+// appended to queue[*count] (one atomic per wavefront).
 __global__ __launch_bounds__(256) void k_stale_mark(const UnitDesc* __restrict__ units,
                                                     const int32_t* __restrict__ cust_off, int n_units,
-                                                    int32_t* __restrict__ queue, int32_t* __restrict__ count,
-                                                    int32_t* __restrict__ clear_count) {
+                                                    int32_t* __restrict__ queue, int32_t* __restrict__ count) {
   const int task = blockIdx.x * blockDim.x + threadIdx.x;
-  if (task == 0) *clear_count = 0;
   bool st = false;
   if (task < cust_off[n_units]) {
     const int ui = unit_of_tile(cust_off, n_units, task);
@@ -668,12 +667,12 @@ void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks,
   const int32_t* queue = nullptr;
   const int32_t* qcount = nullptr;
   if (stale) {
-    int32_t* cnt = stale->count + stale->parity;
-    int32_t* other = stale->count + (stale->parity ^ 1);
+    // a fill kernel rather than a memset: the sequence may be captured in a graph
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, L.stream, stale->count);
     hipLaunchKernelGGL(k_stale_mark, dim3((n_tasks + 255) / 256), dim3(256), 0, L.stream, L.units, cust_off,
-                       L.n_units, stale->queue, cnt, other);
+                       L.n_units, stale->queue, stale->count);
     queue = stale->queue;
-    qcount = cnt;
+    qcount = stale->count;
   }
   if (L.has_tw) score_t<SegTW, true>(L, cust_off, n_tasks, M, queue, qcount, logits_out);
   else score_t<SegNT, false>(L, cust_off, n_tasks, M, queue, qcount, logits_out);

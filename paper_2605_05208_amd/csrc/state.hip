@@ -262,6 +262,7 @@ __global__ void k_pass_end(const UnitDesc* __restrict__ units, int n_units, int3
   for (int i = threadIdx.x; i < n_units; i += blockDim.x) {
     UnitCtl* c = units[i].ctl;
     if (c->active) {
+      c->t_end = (int64_t)wall_clock64();
       if (c->fmode == 1) {
         // filtered optimum: the next pass evaluates the full lists
         if (!c->pass_applied) {
@@ -368,6 +369,7 @@ __global__ void k_state_export(const UnitDesc* __restrict__ units, int n_units, 
   int64_t* o = out + (int64_t)u * kStateWords;
   o[0] = c->F; o[1] = c->evaluated; o[2] = c->passes; o[3] = c->steps; o[4] = c->moves_applied;
   o[5] = c->err; o[6] = c->active; o[7] = c->n_sel; o[8] = c->fallbacks; o[9] = c->fmode;
+  o[10] = c->t_start; o[11] = c->t_end;
 }
 
 // --------------------------------------------------------------------------- launchers

@@ -44,13 +44,13 @@ class InstanceDesc(C.Structure):
 class LsOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("leader_only", C.c_int32), ("max_passes", C.c_int32),
                 ("poll_every", C.c_int32), ("seed", C.c_uint64), ("filter", C.c_int32), ("rescore", C.c_int32),
-                ("mlp", C.c_void_p)]
+                ("mlp", C.c_void_p), ("graph", C.c_int32), ("pad2", C.c_int32)]
 
 
 class LsStats(C.Structure):
     _fields_ = [("passes", C.c_int64), ("steps", C.c_int64), ("moves_applied", C.c_int64),
                 ("evaluated", C.c_int64), ("F", C.c_int64), ("fallback_passes", C.c_int64),
-                ("converged", C.c_int32), ("err", C.c_int32)]
+                ("device_ms", C.c_double), ("converged", C.c_int32), ("err", C.c_int32)]
 
 
 DENSE_DTYPE = np.dtype([("dF", np.int64), ("dD", np.int64), ("dTW", np.int64), ("dLX", np.int64),
@@ -75,7 +75,7 @@ EXPORTED = [
     "mdvrp_filter_export",
 ]
 PROF_CLASSES = ["eval_pairs", "eval_depot_insert", "eval_depot_replace", "select", "apply", "filter_score"]
-STATE_WORDS = 10
+STATE_WORDS = 12
 
 
 def lib():
@@ -359,13 +359,14 @@ class Batch:
         check(lib().mdvrp_apply_moves(self.handle, _stream()))
 
     def local_search_to_optimum(self, mode=LS_PASSES, seed=0, max_passes=0, leader_only=0, poll_every=1,
-                                filter=FILTER_NONE, mlp=None, rescore=RESCORE_STEP):
+                                filter=FILTER_NONE, mlp=None, rescore=RESCORE_STEP, graph=False):
         opt = LsOptions(mode, leader_only, max_passes, poll_every, seed, filter, rescore,
-                        mlp.handle.value if mlp is not None else None)
+                        mlp.handle.value if mlp is not None else None, 1 if graph else 0, 0)
         stats = (LsStats * self.n_units)()
         check(lib().mdvrp_local_search_to_optimum(self.handle, C.byref(opt), stats, _stream()))
         return [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F,
-                     fallback_passes=s.fallback_passes, converged=s.converged, err=s.err) for s in stats]
+                     fallback_passes=s.fallback_passes, device_ms=s.device_ms, converged=s.converged, err=s.err)
+                for s in stats]
 
     # ------------------------------------------------------------------ learned filter
     def filter_attach(self, k):
