@@ -50,6 +50,29 @@ def workload(name):
     return inst, sols
 
 
+PAIR_KERNEL_SOURCES = ("eval.hip", "eval_common.h", "eval_inter.h", "eval_intra.h", "internal.h")
+PAIR_PROFILE = os.path.join(ROOT, "profiles", "k_eval_pairs_mdvrptw-8x1000_64sol.md")
+
+
+def measured_traffic():
+    """HBM bytes per pair-evaluation launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy), or None when the kernel sources changed since."""
+    import hashlib
+    try:
+        text = open(PAIR_PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in PAIR_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_05208_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = dict(line.split(":", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch:", "kernel-source-sha256:")))
+    if vals.get("kernel-source-sha256", "").split()[:1] != [h.hexdigest()]:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def non_matrix_bytes(inst, n_routes):
     """Compulsory bytes of one pair-evaluation launch for one unit, matrix excluded:
     granular lists, node state (rt, pos), node attributes, both segment arrays over
@@ -140,6 +163,8 @@ def filter_study(n_sol=16, k=8, epochs=6):
     s5 = [gen.start_solution(I5, I5.seed * 1000 + j) for j in range(n_sol)]
     B5 = mdvrp.Batch([mdvrp.Instance(I5)], [0] * n_sol)
     B5.filter_attach(k)
+    B5.load(s5)
+    shapes = B5.autotune(reps=2)
     runs = {}
     for name, kw in (("full", {}), ("eta", dict(filter=mdvrp.FILTER_LISTS, eta=True)),
                      ("mlp", dict(filter=mdvrp.FILTER_MLP, mlp=M, rescore=mdvrp.RESCORE_PASS))):
@@ -147,7 +172,7 @@ def filter_study(n_sol=16, k=8, epochs=6):
         runs[name] = (dt, np.array([s["F"] for s in st], np.float64), st, prof)
     full_dt, full_F = runs["full"][0], runs["full"][1]
     out = dict(workload=f"{I5.name}: {n_sol} solutions, local search to a local optimum of the full neighbourhood",
-               k=k, full_ms=round(full_dt * 1e3, 1), full_F_mean=float(full_F.mean()),
+               k=k, full_ms=round(full_dt * 1e3, 1), full_F_mean=float(full_F.mean()), tile_threads_per_family=shapes,
                full_evaluated=int(sum(s["evaluated"] for s in runs["full"][2])),
                train=dict(samples=int(x.shape[0]), positives=int(y.sum().item()), snapshots=snaps,
                           log_s=round(t_log, 2), train_s=round(t_train, 2), epochs=epochs,
@@ -179,6 +204,8 @@ def batch_study(n_inst=256, graph=True):
     dev = [mdvrp.Instance(I) for I in insts]
     B = mdvrp.Batch(dev, list(range(n_inst)))
     sols = [gen.start_solution(I, I.seed * 1000) for I in insts]
+    B.load(sols)
+    shapes = B.autotune(reps=2)
     runs = []
     for _ in range(2):  # the first run captures the graphs
         B.load(sols)
@@ -199,6 +226,7 @@ def batch_study(n_inst=256, graph=True):
                 per_instance_ms_p99=round(float(np.percentile(per, 99)), 2),
                 per_instance_ms_max=round(float(per.max()), 2),
                 passes_max=int(max(s["passes"] for s in st)), first_run_s=round(runs[0][0], 3),
+                tile_threads_per_family=shapes,
                 generate_s=round(t_gen, 1))
 
 
@@ -271,6 +299,7 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-filter", action="store_true", help="skip the learned-filter comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance uneven batch")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes (no autotuning)")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB copy (counter reference)")
     ap.add_argument("--mlp-probe", action="store_true", help="only time the filter's scoring and training kernels")
     args = ap.parse_args()
@@ -298,6 +327,9 @@ def main():
     nodes, offs, st, en, so = batch_flat(sols)
     d_in = [torch.from_numpy(x).to("cuda") for x in (nodes, offs, st, en, so)]
     n_routes, n_nodes = len(st), len(nodes)
+
+    B.load_device(*d_in, n_routes, n_nodes)
+    shapes = B.autotune(reps=3) if not args.no_tune else None
 
     def step():
         B.load_device(*d_in, n_routes, n_nodes)
@@ -330,8 +362,9 @@ def main():
         n_l, ms_l = prof["eval_pairs"]
         avg_s = ms_l / max(n_l, 1) / 1e3
         achieved = b_alg / avg_s / 1e9
+        traffic = measured_traffic() if args.workload == "config2" else None
         roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None, kernel="k_eval_pairs",
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic, kernel="k_eval_pairs",
                     bytes_per_launch=int(b_alg), launches=n_l, avg_launch_us=round(avg_s * 1e6, 2))
 
     cpu = None
@@ -366,6 +399,7 @@ def main():
         "moves_applied_per_step": int(sum(s["moves_applied"] for s in stats)),
         "F_mean": float(np.mean(F)),
         "eval_pairs_ms_per_step": round(prof["eval_pairs"][1] / args.steps, 3),
+        "tile_threads_per_family": shapes,
         "roofline": roof,
         "cpu_baseline": cpu,
         "filter": filt,

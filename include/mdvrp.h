@@ -222,7 +222,8 @@ typedef struct mdvrp_mlp mdvrp_mlp;
 #define MDVRP_FILTER_MLP 2   /* lists re-ranked by the network whenever their features change */
 
 #define MDVRP_RESCORE_STEP 0 /* re-rank stale lists before every pair-family step */
-#define MDVRP_RESCORE_PASS 1 /* re-rank stale lists before the first pair-family step of a pass */
+#define MDVRP_RESCORE_PASS 1 /* re-rank stale lists before the first pair-family step of a pass;
+                                n > 1: of every n-th pass */
 
 typedef struct {
   int32_t mode;        /* MDVRP_LS_PASSES or MDVRP_LS_UNION */
@@ -231,7 +232,8 @@ typedef struct {
   int32_t poll_every;  /* passes between host convergence checks (>= 1) */
   uint64_t seed;       /* family order of pass p: Fisher-Yates with SplitMix64(seed ^ p) */
   int32_t filter;      /* MDVRP_FILTER_*; a filter needs mdvrp_filter_attach first */
-  int32_t rescore;     /* MDVRP_RESCORE_*: when MDVRP_FILTER_MLP re-ranks stale lists */
+  int32_t rescore;     /* when MDVRP_FILTER_MLP re-ranks stale lists: MDVRP_RESCORE_STEP, or
+                          n >= 1 = at the first pair-family step of every n-th pass */
   const mdvrp_mlp* mlp; /* network of MDVRP_FILTER_MLP, else ignored */
   int32_t graph;       /* 1 = each pass runs as a HIP graph, captured once per distinct launch
                           sequence (family order and options) and replayed; per-launch
@@ -256,8 +258,11 @@ typedef struct {
  * either way. With MDVRP_FILTER_MLP the lists of every customer whose
  * features may have changed (its route, or the route of an entry of its
  * granular list, was rebuilt since the last ranking) are re-ranked before
- * each pair-family step (MDVRP_RESCORE_STEP) or before the first one of each
- * pass (MDVRP_RESCORE_PASS); the first ranking covers all of them. stats
+ * each pair-family step (MDVRP_RESCORE_STEP) or before the first one of every
+ * n-th pass (rescore = n >= 1); the first ranking covers all of them. The
+ * lists in between may lag the routes; they stay valid candidate sets, every
+ * move is still evaluated exactly, and the fallback passes keep the end state
+ * a local optimum of the full neighbourhood. stats
  * (HOST array of n_units, nullable) receives per-unit results. Synchronises.
  * Errors: ERANGE when a route grew beyond the int32-safe length, ENOSPC on
  * internal capacity overflow, EDEVICE. */
@@ -294,6 +299,23 @@ mdvrp_status mdvrp_profile_read(mdvrp_batch* batch, int64_t* launches, double* m
  * The results of the evaluation itself are discarded. Synchronises. */
 mdvrp_status mdvrp_eval_footprint(mdvrp_batch* batch, uint32_t family_mask, uint32_t* bitmap, int64_t bitmap_words,
                                   void* stream);
+
+/* ------------------------------------------------------------------------- autotuner
+ *
+ * An evaluation tile is 256 items (anchors, or (customer, depot) pairs); a
+ * block of 256, 128 or 64 threads covers it with 1, 2 or 4 items per thread.
+ * Results never depend on the shape. mdvrp_autotune times every shape of the
+ * evaluation of each family in family_mask on the batch's current solutions
+ * (reps launches each, HIP events on the stream), keeps the fastest for the
+ * local search and the single-family evaluations, and writes the chosen
+ * threads per block of each family (6 entries, family bit order) to
+ * shapes_out (HOST, nullable). Call it after loading solutions and before a
+ * search: it resets the follower candidates and keeps the evaluation
+ * counters. Synchronises. */
+mdvrp_status mdvrp_autotune(mdvrp_batch* batch, uint32_t family_mask, int32_t reps, int32_t* shapes_out,
+                            void* stream);
+/* Set the threads per block of each family (6 entries, each 256, 128 or 64). */
+mdvrp_status mdvrp_set_tile_shapes(mdvrp_batch* batch, const int32_t* threads);
 
 /* ------------------------------------------------------------------------- learned move filter
  *

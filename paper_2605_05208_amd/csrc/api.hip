@@ -54,7 +54,7 @@ struct Carve {
 hipStream_t S(void* s) { return (hipStream_t)s; }
 
 constexpr int kMaxTheta = 128;
-constexpr int kTileItems = 256;
+constexpr int kTileItems = kTileSize;
 constexpr int kRebuildMaxTiles = 128;
 
 }  // namespace
@@ -118,6 +118,13 @@ struct mdvrp_batch {
   hipStream_t own = nullptr;        // capture stream used when the caller passes the null stream
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   double clock_khz = 0;             // device wall-clock rate
+  int shape[6] = {0, 0, 0, 0, 0, 0};  // tile shape of each family's evaluation (autotuner)
+  // tile shape of an evaluation of fam_mask: the tuned one of a single family, else the default
+  int shape_for(uint32_t fam_mask) const {
+    for (int f = 0; f < 6; ++f)
+      if (fam_mask == (1u << f)) return shape[f];
+    return 0;
+  }
   void drop_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     graphs.clear();
@@ -741,7 +748,10 @@ extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, u
   const uint32_t cls = eval_classes(L, fam);
   for (int c = 0; c < 3; ++c)
     if (cls >> c & 1)
-      timed(B, L.stream, c, [&] { launch_eval_class(L, fam, c, (flags & MDVRP_EVAL_DENSE) ? &D : nullptr); });
+      timed(B, L.stream, c, [&] {
+        launch_eval_class(L, fam, c, (flags & MDVRP_EVAL_DENSE) ? &D : nullptr,
+                          (flags & MDVRP_EVAL_DENSE) ? 0 : B->shape_for(fam));
+      });
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
 }
@@ -810,7 +820,7 @@ namespace {
 // the pass's order, each evaluated, selected and applied; optional re-ranking of
 // the filtered lists. With time = false nothing is timed (graph capture).
 void launch_pass(mdvrp_batch* B, const LaunchCtx& L, const mdvrp_ls_options* o, const int32_t* fam, int nf,
-                 bool time) {
+                 int64_t pass, bool time) {
   const uint32_t pair_fams = MDVRP_FAM_RELOCATE | MDVRP_FAM_SWAP | MDVRP_FAM_2OPT_STAR | MDVRP_FAM_2OPT;
   const bool rescoring = o->filter == MDVRP_FILTER_MLP;
   auto run = [&](int cls, auto&& f) {
@@ -823,15 +833,16 @@ void launch_pass(mdvrp_batch* B, const LaunchCtx& L, const mdvrp_ls_options* o, 
     const uint32_t mask = o->mode == MDVRP_LS_PASSES ? (1u << fam[k]) : MDVRP_FAM_ALL;
     const uint32_t cls = eval_classes(L, mask);
     // re-rank the lists of filtered units whose features changed since the last ranking:
-    // before every pair-family step, or before the first one of a pass
+    // before every pair-family step, or before the first one of every rescore-th pass
     const bool pair_step = (mask & pair_fams) && (cls & 1u);
-    const bool score = rescoring && pair_step && !(o->rescore == MDVRP_RESCORE_PASS && ranked_this_pass);
+    const bool rank_pass = o->rescore == MDVRP_RESCORE_STEP || pass % o->rescore == 0;
+    const bool score = rescoring && pair_step && rank_pass && !(o->rescore > 0 && ranked_this_pass);
     if (pair_step) ranked_this_pass = true;
     if (score)
       run(MDVRP_PROF_FILTER_SCORE,
-          [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, o->mlp->d, &B->stale, nullptr); });
+          [&] { launch_rank(L, B->d_cust_off, B->n_cust, o->mlp->d, B->stale, 0); });
     for (int c = 0; c < 3; ++c)
-      if (cls >> c & 1) run(c, [&] { launch_eval_class(L, mask, c, nullptr); });
+      if (cls >> c & 1) run(c, [&] { launch_eval_class(L, mask, c, nullptr, B->shape_for(mask)); });
     run(3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0, score ? 1 : 0); });
     run(4, [&] { launch_rebuild(L); });
   }
@@ -848,7 +859,7 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   if (o->filter < MDVRP_FILTER_NONE || o->filter > MDVRP_FILTER_MLP) return fail(MDVRP_EINVAL, "unknown filter");
   if (o->filter != MDVRP_FILTER_NONE && B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached to the batch");
   if (o->filter == MDVRP_FILTER_MLP && !o->mlp) return fail(MDVRP_EINVAL, "the MLP filter needs a network");
-  if (o->rescore != MDVRP_RESCORE_STEP && o->rescore != MDVRP_RESCORE_PASS) return fail(MDVRP_EINVAL, "unknown rescore");
+  if (o->rescore < 0) return fail(MDVRP_EINVAL, "rescore must be >= 0");
   if (o->graph != 0 && o->graph != 1) return fail(MDVRP_EINVAL, "graph must be 0 or 1");
   const int poll = std::max(1, o->poll_every);
   // A pass captured as a graph needs a capturable stream: the null stream is
@@ -872,16 +883,18 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     int32_t fam[6];
     const int nf = o->mode == MDVRP_LS_PASSES ? mdvrp_family_order(B->has_tw, o->seed, p, fam) : 1;
     if (!o->graph) {
-      launch_pass(B, L, o, fam, nf, true);
+      launch_pass(B, L, o, fam, nf, p, true);
     } else {
-      std::vector<int64_t> key = {o->mode, o->leader_only, o->filter, o->rescore, (int64_t)(intptr_t)o->mlp, nf};
+      const int64_t rank_phase = o->rescore > 0 ? (p % o->rescore == 0) : 0;
+      std::vector<int64_t> key = {o->mode, o->leader_only, o->filter, o->rescore, rank_phase, (int64_t)(intptr_t)o->mlp,
+                                  nf};
       for (int k = 0; k < nf; ++k) key.push_back(fam[k]);
       auto it = B->graphs.find(key);
       if (it == B->graphs.end()) {
         hipGraph_t g = nullptr;
         hipGraphExec_t ex = nullptr;
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        launch_pass(B, L, o, fam, nf, false);
+        launch_pass(B, L, o, fam, nf, p, false);
         HIP_TRY(hipStreamEndCapture(st, &g));
         const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -920,6 +933,79 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     }
   }
   return s;
+}
+
+// ============================================================================ autotuner
+
+__global__ static void k_restore_counts(const UnitDesc* units, int n_units, const int64_t* saved) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_units) {
+    units[i].ctl->evaluated = saved[(int64_t)i * kStateWords + 1];
+    units[i].ctl->last_eval = 0;
+    units[i].ctl->n_cand = 0;
+  }
+}
+
+extern "C" mdvrp_status mdvrp_autotune(mdvrp_batch* B, uint32_t fam_mask, int32_t reps, int32_t* shapes_out,
+                                       void* stream) {
+  if (!B || reps < 1) return fail(MDVRP_EINVAL, "bad argument");
+  if (fam_mask & ~MDVRP_FAM_ALL) return fail(MDVRP_EINVAL, "unknown family bits");
+  const LaunchCtx L = B->ctx(stream);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  launch_state_export(L, B->d_state);  // evaluation counters, restored below
+  mdvrp_status st = MDVRP_OK;
+  for (int f = 0; f < 6 && st == MDVRP_OK; ++f) {
+    const uint32_t mask = 1u << f;
+    const uint32_t cls = eval_classes(L, mask);
+    if (!(fam_mask & mask) || !cls) continue;
+    const int c = cls & 1u ? 0 : (cls & 2u ? 1 : 2);
+    float best_ms = 0;
+    int best = 0;
+    for (int shape = 0; shape < kNumTileShapes; ++shape) {
+      step_begin(L, 0, 0);
+      launch_eval_class(L, mask, c, nullptr, shape);  // warm-up
+      step_begin(L, 0, 0);
+      (void)hipEventRecord(e0, L.stream);
+      for (int r = 0; r < reps; ++r) {
+        launch_eval_class(L, mask, c, nullptr, shape);
+        step_begin(L, 0, 0);
+      }
+      (void)hipEventRecord(e1, L.stream);
+      hipError_t he = hipEventSynchronize(e1);
+      float ms = 0;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) { st = fail(MDVRP_EDEVICE, "autotune: %s", hipGetErrorString(he)); break; }
+      if (shape == 0 || ms < best_ms) { best_ms = ms; best = shape; }
+    }
+    B->shape[f] = best;
+  }
+  hipLaunchKernelGGL(k_restore_counts, dim3((B->n_units + 255) / 256), dim3(256), 0, L.stream, L.units, B->n_units,
+                     (const int64_t*)B->d_state);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  B->drop_graphs();  // captured passes hold the previous shapes
+  if (st) return st;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(L.stream));
+  if (shapes_out)
+    for (int f = 0; f < 6; ++f) shapes_out[f] = tile_shape_threads(B->shape[f]);
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_set_tile_shapes(mdvrp_batch* B, const int32_t* threads) {
+  if (!B || !threads) return fail(MDVRP_EINVAL, "null argument");
+  int sh[6];
+  for (int f = 0; f < 6; ++f) {
+    sh[f] = -1;
+    for (int k = 0; k < kNumTileShapes; ++k)
+      if (tile_shape_threads(k) == threads[f]) sh[f] = k;
+    if (sh[f] < 0) return fail(MDVRP_EINVAL, "family %d: no tile shape with %d threads", f, threads[f]);
+  }
+  for (int f = 0; f < 6; ++f) B->shape[f] = sh[f];
+  B->drop_graphs();
+  return MDVRP_OK;
 }
 
 // ============================================================================ learned move filter
@@ -1102,6 +1188,7 @@ namespace {
 
 mdvrp_status check_filter_k(const mdvrp_batch* B, int32_t k) {
   if (k < 1) return fail(MDVRP_EINVAL, "list length must be >= 1");
+  if (B->n_anchors >= INT32_MAX) return fail(MDVRP_ERANGE, "more than 2^31 - 1 anchors in one batch");
   for (const mdvrp_instance* I : B->inst)
     if (k > I->d.theta) return fail(MDVRP_EINVAL, "list length %d exceeds theta %d", k, I->d.theta);
   return MDVRP_OK;
@@ -1111,9 +1198,14 @@ void carve_filter(Carve& cv, const mdvrp_batch* B, int32_t k, std::vector<int32_
                   FilterQueue* stale) {
   int32_t* co = cv.take<int32_t>(B->n_units + 1);
   if (cust_off) *cust_off = co;
-  int32_t* q = cv.take<int32_t>(B->n_cust);
-  int32_t* qc = cv.take<int32_t>(1);
-  if (stale) *stale = FilterQueue{q, qc};
+  FilterQueue q{};
+  q.lcache = cv.take<float>(B->n_anchors);
+  q.queue = cv.take<int32_t>(B->n_anchors);
+  q.count = cv.take<int32_t>(1);
+  q.cmark = cv.take<uint8_t>(B->n_cust);
+  q.anchor_off = cv.take<int64_t>(B->n_units + 1);
+  q.n_anchors = B->n_anchors;
+  if (stale) *stale = q;
   for (int u = 0; u < B->n_units; ++u) {
     int32_t* p = cv.take<int32_t>((size_t)B->inst[B->unit_inst[u]]->d.n_customers * k);
     if (lists) lists->push_back(p);
@@ -1145,6 +1237,8 @@ extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws,
   FilterQueue fq{};
   carve_filter(cv, B, k, &lists, &co, &fq);
   std::vector<int32_t> h_co(B->n_units + 1, 0);
+  std::vector<int64_t> h_ao(B->n_units + 1, 0);
+  for (int u = 0; u < B->n_units; ++u) h_ao[u + 1] = h_ao[u] + (int64_t)B->h_units[u].nc * B->h_units[u].theta;
   for (int u = 0; u < B->n_units; ++u) {
     UnitDesc& U = B->h_units[u];
     U.fcand = lists[u];
@@ -1154,6 +1248,9 @@ extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws,
   }
   hipStream_t s = S(stream);
   HIP_TRY(hipMemcpyAsync(co, h_co.data(), sizeof(int32_t) * (B->n_units + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync((void*)fq.anchor_off, h_ao.data(), sizeof(int64_t) * (B->n_units + 1), hipMemcpyHostToDevice,
+                         s));
+  HIP_TRY(hipMemsetAsync(fq.cmark, 0, B->n_cust, s));
   HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
   B->drop_graphs();  // captured passes refer to the previous filter state
   B->kc = k;
@@ -1196,8 +1293,9 @@ extern "C" mdvrp_status mdvrp_filter_score_topk(mdvrp_batch* B, const mdvrp_mlp*
   if (!B || !M) return fail(MDVRP_EINVAL, "null argument");
   if (B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
   const LaunchCtx L = B->ctx(stream);
-  timed(B, L.stream, MDVRP_PROF_FILTER_SCORE,
-        [&] { launch_score_topk(L, B->d_cust_off, B->n_cust, M->d, nullptr, logits); });
+  timed(B, L.stream, MDVRP_PROF_FILTER_SCORE, [&] { launch_rank(L, B->d_cust_off, B->n_cust, M->d, B->stale, 1); });
+  if (logits)
+    HIP_TRY(hipMemcpyAsync(logits, B->stale.lcache, sizeof(float) * B->n_anchors, hipMemcpyDeviceToDevice, L.stream));
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
 }

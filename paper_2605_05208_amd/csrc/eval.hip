@@ -16,7 +16,7 @@
 
 namespace mdvrp {
 
-constexpr int kEvalBlock = 256;
+constexpr int kEvalBlock = kTileSize;
 
 // Per-thread results. Follower candidates are reduced per resource set; an
 // item has at most three distinct sets: {A, B} (or {A}), {A, B, depot of A},
@@ -137,10 +137,11 @@ __device__ void cand_flush(const UnitDesc& U, ItemOut& o) {
 }
 
 // Block-level epilogue: candidate append, leader reduction, evaluated count.
+template <int TPB>
 __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
-  __shared__ int64_t sF[kEvalBlock / 64];
-  __shared__ uint64_t sI[kEvalBlock / 64];
-  __shared__ int sLane[kEvalBlock / 64];
+  __shared__ int64_t sF[TPB / 64];
+  __shared__ uint64_t sI[TPB / 64];
+  __shared__ int sLane[TPB / 64];
   __shared__ unsigned long long sEval;
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
@@ -167,7 +168,7 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
     int64_t bf = sF[0];
     uint64_t bi = sI[0];
     int bs = sLane[0];
-    for (int w = 1; w < kEvalBlock / 64; ++w)
+    for (int w = 1; w < TPB / 64; ++w)
       if (key_less(sF[w], sI[w], bf, bi)) { bf = sF[w]; bi = sI[w]; bs = sLane[w]; }
     sLane[0] = bs;
     atomicAdd((unsigned long long*)&U.ctl->evaluated, sEval);
@@ -189,13 +190,16 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
 // --------------------------------------------------------------------------- pair kinds
 
 // KM != 0 fixes the kind mask at compile time (one lean kernel per family);
-// KM == 0 takes it from the argument.
-template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM>
-__global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __restrict__ units,
-                                                          const int32_t* __restrict__ tile_off, int n_units,
-                                                          uint32_t kind_arg, DenseOut dense) {
+// KM == 0 takes it from the argument. A tile is kTileSize items; a block of TPB
+// threads covers it with kTileSize / TPB items per thread (the tile shape the
+// autotuner picks; results do not depend on it).
+template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
+__global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__ units,
+                                                   const int32_t* __restrict__ tile_off, int n_units,
+                                                   uint32_t kind_arg, DenseOut dense) {
+  constexpr int IPT = kTileSize / TPB;
   const uint32_t kind_mask = KM ? KM : kind_arg;
-  __shared__ int s_q[kEvalBlock];
+  __shared__ int s_q[kTileSize];
   __shared__ int s_nq;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int ui = unit_of_tile(tile_off, n_units, tile);
@@ -208,7 +212,6 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __res
   if (filt && lt >= U.ftiles) return;
   const int th = filt ? U.kc : U.theta;
   const int32_t* lists = filt ? U.fcand : U.nbr;
-  const int item = lt * kEvalBlock + threadIdx.x;
   const int cur = U.ctl->cur;
   const SEG* fw = (const SEG*)U.fw[cur];
   const SEG* bw = (const SEG*)U.bw[cur];
@@ -221,57 +224,69 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_pairs(const UnitDesc* __res
   __syncthreads();
   const uint32_t intra_kinds = kind_mask & ~(1u << X2);
   const uint32_t inter_kinds = kind_mask & ~(1u << TWOOPT);
-  if (item < U.nc * th) {
-    const int i = item / th;
-    const int k = item - i * th;
-    const int v = lists[item];
-    if ((filt || k < U.nbr_len[i]) && v >= 0) {
-      const int u = U.nd + i;
-      const int sa = U.rt[u], sb = U.rt[v];
-      if (sa != sb) {
-        if (inter_kinds) {
-          if constexpr (SM == 2) sk.item = item;
-          const int4 ma = U.r_meta[cur][sa], mb = U.r_meta[cur][sb];
-          InterCtx x;
-          x.u = u; x.v = v; x.slotA = sa; x.slotB = sb;
-          x.LA = ma.y; x.LB = mb.y;
-          x.sA = ma.z; x.sB = mb.z;
-          x.eA = ma.w; x.eB = mb.w;
-          x.pu = U.pos[u]; x.pv = U.pos[v];
-          eval_inter<SEG, TW, OPEN>(U, fw, bw, ma.x, mb.x, x, inter_kinds, ar, sk);
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int item = lt * kTileSize + r * TPB + threadIdx.x;
+    if (item < U.nc * th) {
+      const int i = item / th;
+      const int k = item - i * th;
+      const int v = lists[item];
+      if ((filt || k < U.nbr_len[i]) && v >= 0) {
+        const int u = U.nd + i;
+        const int sa = U.rt[u], sb = U.rt[v];
+        if (sa != sb) {
+          if (inter_kinds) {
+            if constexpr (SM == 2) sk.item = item;
+            const int4 ma = U.r_meta[cur][sa], mb = U.r_meta[cur][sb];
+            InterCtx x;
+            x.u = u; x.v = v; x.slotA = sa; x.slotB = sb;
+            x.LA = ma.y; x.LB = mb.y;
+            x.sA = ma.z; x.sB = mb.z;
+            x.eA = ma.w; x.eB = mb.w;
+            x.pu = U.pos[u]; x.pv = U.pos[v];
+            eval_inter<SEG, TW, OPEN>(U, fw, bw, ma.x, mb.x, x, inter_kinds, ar, sk);
+          }
+        } else if (intra_kinds) {
+          s_q[atomicAdd(&s_nq, 1)] = item;
         }
-      } else if (intra_kinds) {
-        s_q[atomicAdd(&s_nq, 1)] = item;
       }
     }
+    cand_flush(U, o);
   }
-  cand_flush(U, o);
   __syncthreads();
   // intra-route anchors of the block, packed into as few wavefronts as possible
   const int nq = s_nq;
-  for (int e = threadIdx.x; e < nq; e += kEvalBlock) {
-    const int it = s_q[e];
-    const int i = it / th;
-    const int u = U.nd + i, v = lists[it];
-    if constexpr (SM == 2) sk.item = it;
-    const RouteCtx A = route_ctx(U, cur, U.rt[u]);
-    eval_intra<SEG, TW, OPEN>(U, fw, bw, A, u, v, U.pos[u], U.pos[v], intra_kinds, ar, sk);
+  for (int e0 = 0; e0 < nq; e0 += TPB) {
+    const int e = e0 + threadIdx.x;
+    if (e < nq) {
+      const int it = s_q[e];
+      const int i = it / th;
+      const int u = U.nd + i, v = lists[it];
+      if constexpr (SM == 2) sk.item = it;
+      const RouteCtx A = route_ctx(U, cur, U.rt[u]);
+      eval_intra<SEG, TW, OPEN>(U, fw, bw, A, u, v, U.pos[u], U.pos[v], intra_kinds, ar, sk);
+    }
+    cand_flush(U, o);
   }
-  item_flush(U, U.tile_base[0] + lt, o);
+  item_flush<TPB>(U, U.tile_base[0] + lt, o);
 }
 
 // --------------------------------------------------------------------------- depot operators
 
-template <class SEG, bool TW, bool OPEN, int SM, class AR = ArcPlain>
-__global__ __launch_bounds__(kEvalBlock) void k_eval_depot(const UnitDesc* __restrict__ units,
-                                                          const int32_t* __restrict__ tile_off, int n_units,
-                                                          int which, DenseOut dense) {
+template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
+__global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__ units,
+                                                   const int32_t* __restrict__ tile_off, int n_units, int which,
+                                                   DenseOut dense) {
+  constexpr int IPT = kTileSize / TPB;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int ui = unit_of_tile(tile_off, n_units, tile);
   const UnitDesc& U = units[ui];
   if (!U.ctl->active) return;
   const int lt = tile - tile_off[ui];
-  const int item = lt * kEvalBlock + threadIdx.x;
+  // Depot-Replace items cover the alive routes only; the tiles beyond them have
+  // nothing to do (the selection reads as many tiles as the items need).
+  const int n_drep = which == 1 ? U.ctl->n_slots_alive * U.nd : 0;
+  if (which == 1 && lt * kTileSize >= n_drep) return;
   const int cur = U.ctl->cur;
   const SEG* fw = (const SEG*)U.fw[cur];
   const SEG* bw = (const SEG*)U.bw[cur];
@@ -280,43 +295,51 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_depot(const UnitDesc* __res
   Sink<SM> sk{&o, dense, ui, 0};
   AR ar;
   if constexpr (sizeof(AR) > 1) ar.bits = U.foot;
-  if (item < U.nc * U.nd) {
-    const int i = item / U.nd;
-    const int d = item - i * U.nd;
-    const int u = U.nd + i;
-    const RouteCtx A = route_ctx(U, cur, U.rt[u]);
-    const int pu = U.pos[u];
-    MoveEval m;
-    if (which == 0) {
-      // Depot-Insert: cut after u when s(u) is a customer.
+  MoveEval m;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+  const int item = lt * kTileSize + r * TPB + threadIdx.x;
+  if (which == 0) {
+    // Depot-Insert: one item per (customer u, depot d); cut after u when s(u) is a customer.
+    if (item < U.nc * U.nd) {
+      const int i = item / U.nd;
+      const int d = item - i * U.nd;
+      const int u = U.nd + i;
+      const RouteCtx A = route_ctx(U, cur, U.rt[u]);
+      const int pu = U.pos[u];
       if (pu < A.L) {
         eval_dins<SEG, TW, OPEN>(U, fw, bw, A, pu, d, ar, m);
         take(U, sk, m, make_id(DINS, 0, u, d));
       }
-    } else if (pu == 1) {
-      // Depot-Replace on the route whose first customer is u: best surviving case.
-      bool have = false;
-      MoveEval best;
-      int bcase = 0;
-      for (int cs = 0; cs < 3; ++cs) {
-        if (OPEN && cs != 0) continue;
-        const int ns = (cs == 0 || cs == 2) ? d : A.start;
-        const int ne = (cs == 1 || cs == 2) ? d : A.end;
-        if (ns == A.start && ne == A.end) continue;
-        bool dup = false;
-        for (int c2 = 0; c2 < cs; ++c2) {
-          const int s2 = (c2 == 0 || c2 == 2) ? d : A.start;
-          const int e2 = (c2 == 1 || c2 == 2) ? d : A.end;
-          if (!(s2 == A.start && e2 == A.end) && s2 == ns && e2 == ne) dup = true;
-        }
-        if (dup) continue;
-        eval_drep<SEG, TW, OPEN>(U, fw, bw, A, d, cs, ar, m);
-        if (!have || m.dF < best.dF) { best = m; bcase = cs; have = true; }
-      }
-      if (have) take(U, sk, best, make_id(DREP, bcase, u, d));
     }
+  } else if (item < n_drep) {
+    // Depot-Replace: one item per (alive route, depot), the best surviving case.
+    const int d = item % U.nd;
+    const RouteCtx A = route_ctx(U, cur, U.slot_list[item / U.nd]);
+    const int u = fw[A.off + 1].node;
+    bool have = false;
+    MoveEval best;
+    int bcase = 0;
+    for (int cs = 0; cs < 3; ++cs) {
+      if (OPEN && cs != 0) continue;
+      const int ns = (cs == 0 || cs == 2) ? d : A.start;
+      const int ne = (cs == 1 || cs == 2) ? d : A.end;
+      if (ns == A.start && ne == A.end) continue;
+      bool dup = false;
+      for (int c2 = 0; c2 < cs; ++c2) {
+        const int s2 = (c2 == 0 || c2 == 2) ? d : A.start;
+        const int e2 = (c2 == 1 || c2 == 2) ? d : A.end;
+        if (!(s2 == A.start && e2 == A.end) && s2 == ns && e2 == ne) dup = true;
+      }
+      if (dup) continue;
+      eval_drep<SEG, TW, OPEN>(U, fw, bw, A, d, cs, ar, m);
+      if (!have || m.dF < best.dF) { best = m; bcase = cs; have = true; }
+    }
+    if (have) take(U, sk, best, make_id(DREP, bcase, u, d));
   }
-  item_flush(U, U.tile_base[1 + which] + lt, o);
+  cand_flush(U, o);
+  }
+  item_flush<TPB>(U, U.tile_base[1 + which] + lt, o);
 }
 
 // --------------------------------------------------------------------------- launchers
@@ -343,48 +366,57 @@ constexpr uint32_t kSwpKinds = (1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (
 constexpr uint32_t kX2Kinds = 1u << X2;
 constexpr uint32_t k2optKinds = 1u << TWOOPT;
 
-template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM>
+template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
 static void launch_pairs(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) {
-  hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, SM, AR, KM>), dim3(L.tiles[0]), dim3(kEvalBlock), 0, L.stream,
-                     L.units, L.tile_off[0], L.n_units, kinds, D);
+  hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, SM, AR, KM, TPB>), dim3(L.tiles[0]), dim3(TPB), 0, L.stream, L.units,
+                     L.tile_off[0], L.n_units, kinds, D);
 }
 
-template <class SEG, bool TW, bool OPEN, int SM, class AR>
+template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
 static void launch_class_t(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut& D) {
   if (cls == 0) {
     const uint32_t kinds = pair_kinds(fam_mask, TW);
     if (!kinds || L.tiles[0] <= 0) return;
-    if (kinds == kRelKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kRelKinds>(L, kinds, D);
-    else if (kinds == kSwpKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kSwpKinds>(L, kinds, D);
-    else if (kinds == kX2Kinds) launch_pairs<SEG, TW, OPEN, SM, AR, kX2Kinds>(L, kinds, D);
-    else if (!TW && kinds == k2optKinds) launch_pairs<SEG, TW, OPEN, SM, AR, k2optKinds>(L, kinds, D);
-    else launch_pairs<SEG, TW, OPEN, SM, AR, 0u>(L, kinds, D);
+    if (kinds == kRelKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kRelKinds, TPB>(L, kinds, D);
+    else if (kinds == kSwpKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kSwpKinds, TPB>(L, kinds, D);
+    else if (kinds == kX2Kinds) launch_pairs<SEG, TW, OPEN, SM, AR, kX2Kinds, TPB>(L, kinds, D);
+    else if (!TW && kinds == k2optKinds) launch_pairs<SEG, TW, OPEN, SM, AR, k2optKinds, TPB>(L, kinds, D);
+    else launch_pairs<SEG, TW, OPEN, SM, AR, 0u, kTileSize>(L, kinds, D);
     return;
   }
   const int w = cls - 1;
   if (!(fam_mask >> (FAM_DINS + w) & 1) || L.tiles[1 + w] <= 0) return;
-  hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, SM, AR>), dim3(L.tiles[1 + w]), dim3(kEvalBlock), 0, L.stream,
-                     L.units, L.tile_off[1 + w], L.n_units, w, D);
+  hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, SM, AR, TPB>), dim3(L.tiles[1 + w]), dim3(TPB), 0, L.stream, L.units,
+                     L.tile_off[1 + w], L.n_units, w, D);
 }
 
-template <int SM, class AR>
+template <int SM, class AR, int TPB>
 static void launch_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut& D) {
   if (L.has_tw) {
-    if (L.open) launch_class_t<SegTW, true, true, SM, AR>(L, fam_mask, cls, D);
-    else launch_class_t<SegTW, true, false, SM, AR>(L, fam_mask, cls, D);
+    if (L.open) launch_class_t<SegTW, true, true, SM, AR, TPB>(L, fam_mask, cls, D);
+    else launch_class_t<SegTW, true, false, SM, AR, TPB>(L, fam_mask, cls, D);
   } else {
-    if (L.open) launch_class_t<SegNT, false, true, SM, AR>(L, fam_mask, cls, D);
-    else launch_class_t<SegNT, false, false, SM, AR>(L, fam_mask, cls, D);
+    if (L.open) launch_class_t<SegNT, false, true, SM, AR, TPB>(L, fam_mask, cls, D);
+    else launch_class_t<SegNT, false, false, SM, AR, TPB>(L, fam_mask, cls, D);
   }
 }
 
-void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut* dense) {
+// Tile shapes of the search path (threads per block; a tile is always kTileSize items).
+static const int kTileShapes[kNumTileShapes] = {256, 128, 64};
+
+int tile_shape_threads(int shape) { return kTileShapes[shape < 0 || shape >= kNumTileShapes ? 0 : shape]; }
+
+void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut* dense, int shape) {
   if (dense && dense->label) {
-    if (cls == 0) launch_class<2, ArcPlain>(L, fam_mask, cls, *dense);
+    if (cls == 0) launch_class<2, ArcPlain, kTileSize>(L, fam_mask, cls, *dense);
   } else if (dense) {
-    launch_class<1, ArcPlain>(L, fam_mask, cls, *dense);
+    launch_class<1, ArcPlain, kTileSize>(L, fam_mask, cls, *dense);
+  } else if (shape == 1) {
+    launch_class<0, ArcPlain, 128>(L, fam_mask, cls, DenseOut{});
+  } else if (shape == 2) {
+    launch_class<0, ArcPlain, 64>(L, fam_mask, cls, DenseOut{});
   } else {
-    launch_class<0, ArcPlain>(L, fam_mask, cls, DenseOut{});
+    launch_class<0, ArcPlain, kTileSize>(L, fam_mask, cls, DenseOut{});
   }
 }
 
@@ -393,7 +425,7 @@ void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense) {
 }
 
 void launch_eval_footprint(const LaunchCtx& L, uint32_t fam_mask, int cls) {
-  launch_class<0, ArcFoot>(L, fam_mask, cls, DenseOut{});
+  launch_class<0, ArcFoot, kTileSize>(L, fam_mask, cls, DenseOut{});
 }
 
 int eval_block_size() { return kEvalBlock; }

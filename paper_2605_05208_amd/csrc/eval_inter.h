@@ -64,7 +64,7 @@ template <class SEG, bool TW, bool OPEN, class AR, class OUT>
 __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, const SEG* bw, int offA, int offB,
                                            const InterCtx& x, uint32_t kinds, const AR& ar, OUT& o) {
   const bool sym = !TW;
-  const int pu = x.pu, pv = x.pv, LA = x.LA, LB = x.LB;
+  const int pu = x.pu, pv = x.pv, LA = x.LA;
   // ---------------------------------------------------------------- loads
   const SEG fa0 = fw[offA + pu];       // prefix to u
   const SEG fa1 = fw[offA + pu - 1];   // prefix to p(u)

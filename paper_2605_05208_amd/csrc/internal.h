@@ -21,6 +21,7 @@
 namespace mdvrp {
 
 constexpr int kMaxPieces = 5;
+constexpr int kTileSize = 256;  // items per evaluation tile (one block, one leader record)
 constexpr int kPairKindSlots = 14;  // kind/variant slots of one (u, v) anchor
 constexpr int64_t kNoMove = INT64_MAX;
 

@@ -31,7 +31,11 @@ struct LaunchCtx {
 int eval_block_size();
 void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense);
 // One item class: 0 pair kinds, 1 depot-insert, 2 depot-replace (no launch when it has no work).
-void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut* dense);
+// shape: tile shape index (threads per block = tile_shape_threads(shape)); dense, label and
+// footprint launches always use shape 0.
+constexpr int kNumTileShapes = 3;
+int tile_shape_threads(int shape);
+void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut* dense, int shape = 0);
 // Same evaluation, also marking every matrix entry read in the units' footprint bitmaps.
 void launch_eval_footprint(const LaunchCtx& L, uint32_t fam_mask, int cls);
 // Item classes an evaluation of fam_mask fills (bit 0 pairs, 1 depot-insert, 2 depot-replace).
@@ -66,14 +70,20 @@ int mlp_row_pad();  // activation buffers hold n rounded up to a multiple of thi
 void launch_mlp_pack(hipStream_t s, const MlpDev& M);
 void launch_mlp_zero(hipStream_t s, float* p, int n);
 void launch_features(const LaunchCtx& L, uint16_t* out);
-// Queue of stale customers: queue[n_customers of the batch] and its length.
+// Incremental ranking state of a batch: cached logits of every anchor, the queue of
+// anchors to rescore and its length, per-customer flags, anchor offsets per unit.
 struct FilterQueue {
-  int32_t* queue;
-  int32_t* count;
+  float* lcache;         // [n_anchors]
+  int32_t* queue;        // [n_anchors]
+  int32_t* count;        // [1]
+  uint8_t* cmark;        // [n_customers of the batch]
+  const int64_t* anchor_off;  // [n_units + 1]
+  int64_t n_anchors;
 };
-// stale == null: rank every customer; else only the stale customers of active filtered units.
-void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M,
-                       const FilterQueue* stale, float* logits_out);
+// Rank the lists: all = 1 every anchor of every unit, all = 0 the stale anchors of
+// active filtered units; then the top-k of every customer that owns a rescored anchor.
+void launch_rank(const LaunchCtx& L, const int32_t* cust_off, int n_cust, const MlpDev& M, const FilterQueue& Q,
+                 int all);
 void launch_eta_lists(const LaunchCtx& L, const int32_t* cust_off, int n_tasks);
 void launch_mlp_forward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, float* logits, uint16_t* h1,
                         uint16_t* h2);

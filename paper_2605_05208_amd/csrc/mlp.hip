@@ -297,133 +297,151 @@ __global__ __launch_bounds__(256) void k_features(const UnitDesc* __restrict__ u
 }
 
 // ---------------------------------------------------------------------------- scoring + top-k
+//
+// Ranking is incremental at the level of anchors: every anchor's logit is cached
+// (lcache[item_base + i * theta + k]); a ranking step recomputes only the anchors
+// whose features may have changed -- the route of u or the route of v was rebuilt
+// after the unit's last ranking (dirty tag above scored_epoch) -- and then redoes
+// the top-k of the customers that own such an anchor from the cached logits.
 
 constexpr int kScoreWaves = 8;
-constexpr int kScoreT = 2;      // sample tiles per pass through W2
-constexpr int kMaxTheta = 128;  // list entries scored per customer
+constexpr int kScoreT = 2;  // sample tiles per pass through W2
 
 __global__ void k_queue_reset(int32_t* __restrict__ count) { *count = 0; }
 
-// Stale customers: one thread per (unit, customer) of every active filtered unit; a
-// customer is stale when its route, or the route of some entry of N(u), was rebuilt
-// after the unit's last ranking (dirty tag above scored_epoch). Stale tasks are
-// appended to queue[*count] (one atomic per wavefront).
-__global__ __launch_bounds__(256) void k_stale_mark(const UnitDesc* __restrict__ units,
-                                                    const int32_t* __restrict__ cust_off, int n_units,
-                                                    int32_t* __restrict__ queue, int32_t* __restrict__ count) {
-  const int task = blockIdx.x * blockDim.x + threadIdx.x;
+// Unit of a batch-wide anchor index (binary search over the units' first anchors).
+__device__ __forceinline__ int unit_of_anchor(const int64_t* __restrict__ off, int n_units, int64_t a) {
+  int lo = 0, hi = n_units;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= a) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// One thread per anchor. all = 1: every anchor of every unit; all = 0: the stale
+// anchors of active filtered units. Marked anchors go to queue (one atomic per
+// wavefront); their customers are flagged in cmark.
+__global__ __launch_bounds__(256) void k_anchor_mark(const UnitDesc* __restrict__ units,
+                                                     const int64_t* __restrict__ anchor_off,
+                                                     const int32_t* __restrict__ cust_off, int n_units, int all,
+                                                     int32_t* __restrict__ queue, int32_t* __restrict__ count,
+                                                     uint8_t* __restrict__ cmark) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool st = false;
-  if (task < cust_off[n_units]) {
-    const int ui = unit_of_tile(cust_off, n_units, task);
+  int cust = 0;
+  if (a < anchor_off[n_units]) {
+    const int ui = unit_of_anchor(anchor_off, n_units, a);
     const UnitDesc& U = units[ui];
     const UnitCtl* c = U.ctl;
-    if (c->active && c->fmode == 1) {
-      const int i = task - cust_off[ui];
-      const int se = c->scored_epoch;
-      const int32_t* nb = U.nbr + (int64_t)i * U.theta;
-      const int len = U.nbr_len[i];
-      st = U.dirty[U.rt[U.nd + i]] > se;
-      for (int k0 = 0; k0 < len && !st; k0 += 8) {
-        int slot[8];
-#pragma unroll
-        for (int z = 0; z < 8; ++z) slot[z] = k0 + z < len ? U.rt[nb[k0 + z]] : -1;
-#pragma unroll
-        for (int z = 0; z < 8; ++z) st = st || (slot[z] >= 0 && U.dirty[slot[z]] > se);
+    const int item = (int)(a - anchor_off[ui]);
+    const int i = item / U.theta, k = item - i * U.theta;
+    cust = cust_off[ui] + i;
+    if (k < U.nbr_len[i]) {
+      if (all) {
+        st = true;
+      } else if (c->active && c->fmode == 1) {
+        const int se = c->scored_epoch;
+        st = U.dirty[U.rt[U.nd + i]] > se || U.dirty[U.rt[U.nbr[item]]] > se;
       }
     }
   }
+  if (st) cmark[cust] = 1;
   const uint64_t m = __ballot(st);
   if (!m) return;
   const int lane = lane_id();
   int base = 0;
   if (lane == 0) base = atomicAdd(count, __popcll(m));
   base = __shfl(base, 0);
-  if (st) queue[base + __popcll(m & ((1ull << lane) - 1))] = task;
+  if (st) queue[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)a;
 }
 
-// One wave per (unit, customer) task: features of the customer's list entries, their
-// logits, and the kc best (logit descending, customer id ascending) into fcand.
-// Tasks: queue[0 .. *qcount) when a queue is given, else every customer of every unit.
+// Logits of the queued anchors: each wavefront takes 16 T anchors at a time, builds
+// their features (one anchor per lane of the first 16 T lanes), stages them in LDS
+// as B fragments, and runs the network on the matrix cores.
 template <class SEG, bool TW>
-__global__ __launch_bounds__(64 * kScoreWaves) void k_score_topk(
-    const UnitDesc* __restrict__ units, const int32_t* __restrict__ cust_off, int n_units,
+__global__ __launch_bounds__(64 * kScoreWaves) void k_score_anchors(
+    const UnitDesc* __restrict__ units, const int64_t* __restrict__ anchor_off, int n_units,
     const bf16x8* __restrict__ w1f, const bf16x8* __restrict__ w2f, const float* __restrict__ P,
     const float* __restrict__ w3b, const int32_t* __restrict__ queue, const int32_t* __restrict__ qcount,
-    float* __restrict__ logits_out) {
+    float* __restrict__ lcache) {
   __shared__ MlpSmem S;
   __shared__ __attribute__((aligned(16))) uint16_t xs[kScoreWaves][16 * kScoreT * kF];
-  __shared__ float lg[kScoreWaves][kMaxTheta];
+  const int n = *qcount;
+  if (n == 0) return;
   mlp_stage(S, w2f, P, w3b);
   const float b3 = P[P_B3];
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  const int n_tasks = queue ? *qcount : cust_off[n_units];
-  for (int q = blockIdx.x * kScoreWaves + wave; q < n_tasks; q += gridDim.x * kScoreWaves) {
-    const int task = queue ? queue[q] : q;
-    const int ui = unit_of_tile(cust_off, n_units, task);
-    const UnitDesc& U = units[ui];
-    const int i = task - cust_off[ui];
-    const int u = U.nd + i;
-    const int len = imin(U.nbr_len[i], kMaxTheta);
-    const int32_t* nb = U.nbr + (int64_t)i * U.theta;
-    const int cur = U.ctl->cur;
-    for (int base = 0; base < len; base += 16 * kScoreT) {
-      // features of entries base .. base + 16 T - 1, one row per lane of the first 16 T lanes
-      if (lane < 16 * kScoreT) {
-        uint16_t f[kF];
-        const int k = base + lane;
-        if (k < len) {
-          pair_features<SEG, TW>(U, cur, u, nb[k], k, f);
-        } else {
+  constexpr int G = 16 * kScoreT;
+  for (int g0 = (blockIdx.x * kScoreWaves + wave) * G; g0 < n; g0 += gridDim.x * kScoreWaves * G) {
+    if (lane < G) {
+      uint16_t f[kF];
+      const int q = g0 + lane;
+      if (q < n) {
+        const int64_t a = queue[q];
+        const int ui = unit_of_anchor(anchor_off, n_units, a);
+        const UnitDesc& U = units[ui];
+        const int item = (int)(a - anchor_off[ui]);
+        const int i = item / U.theta, k = item - i * U.theta;
+        pair_features<SEG, TW>(U, U.ctl->cur, U.nd + i, U.nbr[item], k, f);
+      } else {
 #pragma unroll
-          for (int z = 0; z < kF; ++z) f[z] = 0;
-        }
-        uint4* row = (uint4*)&xs[wave][lane * kF];
-#pragma unroll
-        for (int z = 0; z < 4; ++z) row[z] = pack8(f + 8 * z);
+        for (int z = 0; z < kF; ++z) f[z] = 0;
       }
-      wave_lds_sync();
-      bf16x8 xb[kScoreT];
+      uint4* row = (uint4*)&xs[wave][lane * kF];
 #pragma unroll
-      for (int t = 0; t < kScoreT; ++t)
-        xb[t] = *(const bf16x8*)&xs[wave][(16 * t + (lane & 15)) * kF + 8 * (lane >> 4)];
-      float z[kScoreT];
-      mlp_tiles<kScoreT>(S, w1f, xb, b3, z, nullptr, nullptr);
-#pragma unroll
-      for (int t = 0; t < kScoreT; ++t) {
-        const int k = base + 16 * t + (lane & 15);
-        if (lane < 16 && k < len) lg[wave][k] = z[t];
-      }
-      wave_lds_sync();
+      for (int z = 0; z < 4; ++z) row[z] = pack8(f + 8 * z);
     }
-    // top-kc by repeated wave arg-max; each lane holds entries lane and lane + 64
-    float s0 = -INFINITY, s1 = -INFINITY;
-    int v0 = INT32_MAX, v1 = INT32_MAX;
-    if (lane < len) { s0 = lg[wave][lane]; v0 = nb[lane]; }
-    if (lane + 64 < len) { s1 = lg[wave][lane + 64]; v1 = nb[lane + 64]; }
     wave_lds_sync();
-    if (logits_out) {
-      float* lo = logits_out + U.item_base + (int64_t)i * U.theta;
-      if (lane < len) lo[lane] = s0;
-      if (lane + 64 < len) lo[lane + 64] = s1;
+    bf16x8 xb[kScoreT];
+#pragma unroll
+    for (int t = 0; t < kScoreT; ++t) xb[t] = *(const bf16x8*)&xs[wave][(16 * t + (lane & 15)) * kF + 8 * (lane >> 4)];
+    wave_lds_sync();
+    float z[kScoreT];
+    mlp_tiles<kScoreT>(S, w1f, xb, b3, z, nullptr, nullptr);
+#pragma unroll
+    for (int t = 0; t < kScoreT; ++t) {
+      const int q = g0 + 16 * t + lane;
+      if (lane < 16 && q < n) lcache[queue[q]] = z[t];
     }
-    int32_t* out = U.fcand + (int64_t)i * U.kc;
-    for (int j = 0; j < U.kc; ++j) {
-      float bs = s0;
-      int bv = v0, src = lane, which = 0;
-      if (s1 > bs || (s1 == bs && v1 < bv)) { bs = s1; bv = v1; which = 1; }
-      for (int off = 32; off > 0; off >>= 1) {
-        const float s2 = __shfl_xor(bs, off);
-        const int v2 = __shfl_xor(bv, off);
-        const int src2 = __shfl_xor(src, off);
-        const int w2 = __shfl_xor(which, off);
-        if (s2 > bs || (s2 == bs && v2 < bv)) { bs = s2; bv = v2; src = src2; which = w2; }
-      }
-      if (lane == 0) out[j] = bv == INT32_MAX ? -1 : bv;
-      if (lane == src) {
-        if (which == 0) { s0 = -INFINITY; v0 = INT32_MAX; }
-        else { s1 = -INFINITY; v1 = INT32_MAX; }
-      }
+  }
+}
+
+// Top-kc of every flagged customer from the cached logits (logit descending, customer
+// id ascending; -1 padding); clears the flag. One thread per customer.
+__global__ __launch_bounds__(256) void k_topk_marked(const UnitDesc* __restrict__ units,
+                                                     const int32_t* __restrict__ cust_off, int n_units,
+                                                     const float* __restrict__ lcache, uint8_t* __restrict__ cmark) {
+  const int task = blockIdx.x * blockDim.x + threadIdx.x;
+  if (task >= cust_off[n_units] || !cmark[task]) return;
+  cmark[task] = 0;
+  const int ui = unit_of_tile(cust_off, n_units, task);
+  const UnitDesc& U = units[ui];
+  const int i = task - cust_off[ui];
+  const int len = U.nbr_len[i];
+  const int32_t* nb = U.nbr + (int64_t)i * U.theta;
+  const float* lg = lcache + U.item_base + (int64_t)i * U.theta;
+  int32_t* out = U.fcand + (int64_t)i * U.kc;
+  // selection of the best remaining entry, kc times; taken entries are skipped by
+  // comparing against the previous pick (score, id), which is a strict total order
+  float ps = INFINITY;
+  int pv = -1;
+  for (int j = 0; j < U.kc; ++j) {
+    float bs = -INFINITY;
+    int bv = INT32_MAX;
+    for (int k = 0; k < len; ++k) {
+      const float sk = lg[k];
+      const int vk = nb[k];
+      const bool after_prev = sk < ps || (sk == ps && vk > pv);
+      if (after_prev && (sk > bs || (sk == bs && vk < bv))) { bs = sk; bv = vk; }
     }
+    if (bv == INT32_MAX) {
+      for (; j < U.kc; ++j) out[j] = -1;
+      break;
+    }
+    out[j] = bv;
+    ps = bs;
+    pv = bv;
   }
 }
 
@@ -653,29 +671,25 @@ void launch_features(const LaunchCtx& L, uint16_t* out) {
 }
 
 template <class SEG, bool TW>
-static void score_t(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M,
-                    const int32_t* queue, const int32_t* qcount, float* logits_out) {
-  const int blocks = grid_for(n_tasks, kScoreWaves, 256);
-  hipLaunchKernelGGL((k_score_topk<SEG, TW>), dim3(blocks), dim3(64 * kScoreWaves), 0, L.stream, L.units, cust_off,
-                     L.n_units, (const bf16x8*)M.w1f, (const bf16x8*)M.w2f, (const float*)M.P, (const float*)M.w3b,
-                     queue, qcount, logits_out);
+static void score_anchors_t(const LaunchCtx& L, const int64_t* anchor_off, const MlpDev& M, const FilterQueue& Q,
+                            int64_t max_anchors) {
+  const int blocks = grid_for(max_anchors, kScoreWaves * 16 * kScoreT, 256);
+  hipLaunchKernelGGL((k_score_anchors<SEG, TW>), dim3(blocks), dim3(64 * kScoreWaves), 0, L.stream, L.units,
+                     anchor_off, L.n_units, (const bf16x8*)M.w1f, (const bf16x8*)M.w2f, (const float*)M.P,
+                     (const float*)M.w3b, Q.queue, Q.count, Q.lcache);
 }
 
-void launch_score_topk(const LaunchCtx& L, const int32_t* cust_off, int n_tasks, const MlpDev& M,
-                       const FilterQueue* stale, float* logits_out) {
-  if (n_tasks <= 0) return;
-  const int32_t* queue = nullptr;
-  const int32_t* qcount = nullptr;
-  if (stale) {
-    // a fill kernel rather than a memset: the sequence may be captured in a graph
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, L.stream, stale->count);
-    hipLaunchKernelGGL(k_stale_mark, dim3((n_tasks + 255) / 256), dim3(256), 0, L.stream, L.units, cust_off,
-                       L.n_units, stale->queue, stale->count);
-    queue = stale->queue;
-    qcount = stale->count;
-  }
-  if (L.has_tw) score_t<SegTW, true>(L, cust_off, n_tasks, M, queue, qcount, logits_out);
-  else score_t<SegNT, false>(L, cust_off, n_tasks, M, queue, qcount, logits_out);
+void launch_rank(const LaunchCtx& L, const int32_t* cust_off, int n_cust, const MlpDev& M, const FilterQueue& Q,
+                 int all) {
+  if (n_cust <= 0 || Q.n_anchors <= 0) return;
+  // a fill kernel rather than a memset: the sequence may be captured in a graph
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, L.stream, Q.count);
+  hipLaunchKernelGGL(k_anchor_mark, dim3((unsigned)((Q.n_anchors + 255) / 256)), dim3(256), 0, L.stream, L.units,
+                     Q.anchor_off, cust_off, L.n_units, all, Q.queue, Q.count, Q.cmark);
+  if (L.has_tw) score_anchors_t<SegTW, true>(L, Q.anchor_off, M, Q, Q.n_anchors);
+  else score_anchors_t<SegNT, false>(L, Q.anchor_off, M, Q, Q.n_anchors);
+  hipLaunchKernelGGL(k_topk_marked, dim3((n_cust + 255) / 256), dim3(256), 0, L.stream, L.units, cust_off, L.n_units,
+                     (const float*)Q.lcache, Q.cmark);
 }
 
 void launch_eta_lists(const LaunchCtx& L, const int32_t* cust_off, int n_tasks) {

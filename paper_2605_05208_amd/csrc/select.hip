@@ -89,8 +89,11 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   int bt = -1;
   for (int c = 0; c < 3; ++c) {
     if (!(cls_mask >> c & 1)) continue;
-    // a filtered unit's pair tiles cover its candidate lists only
-    const int t_end = (c == 0 && ctl->fmode == 1) ? U.tile_base[0] + U.ftiles : U.tile_base[c + 1];
+    // a filtered unit's pair tiles cover its candidate lists only; Depot-Replace tiles
+    // cover the alive routes only
+    int t_end = U.tile_base[c + 1];
+    if (c == 0 && ctl->fmode == 1) t_end = U.tile_base[0] + U.ftiles;
+    if (c == 2) t_end = imin(t_end, U.tile_base[2] + (ctl->n_slots_alive * U.nd + kTileSize - 1) / kTileSize);
     for (int t = U.tile_base[c] + tid; t < t_end; t += kSelBlock) {
       const int64_t f = U.wg_best[t].dF;
       const uint64_t i = U.wg_best[t].id;

@@ -39,11 +39,14 @@ def valid_anchors(batch: mdvrp.Batch):
 
 
 def log_states(batch: mdvrp.Batch, solutions, seed=1, chunk=2, max_chunks=40, neg_ratio=4.0, rng_seed=0,
-               max_samples=None):
+               max_samples=None, pos_budget=None):
     """Run the full-list local search of `solutions` in chunks of `chunk` passes and log
     (features, label, weight) of sub-sampled anchors after every chunk (the start state
-    included). Returns device tensors x [n][32] (int16 bf16 bits), y [n], w [n] and the
-    number of snapshots."""
+    included). With pos_budget, at most that many positives are kept per snapshot, with
+    weight 1, so that the early states, where most anchors improve, do not dominate the
+    logs; negatives are weighted by the inverse of their keep rate, which restores each
+    snapshot's ratio of negatives to kept positives. Returns device tensors x [n][32]
+    (int16 bf16 bits), y [n], w [n] and the number of snapshots."""
     torch = _torch()
     g = torch.Generator(device="cuda")
     g.manual_seed(rng_seed)
@@ -58,14 +61,16 @@ def log_states(batch: mdvrp.Batch, solutions, seed=1, chunk=2, max_chunks=40, ne
         pos = valid & (lab == 1)
         neg = valid & (lab == 0)
         n_pos, n_neg = int(pos.sum()), int(neg.sum())
-        p = 1.0 if n_neg == 0 else min(1.0, neg_ratio * max(n_pos, 1) / n_neg)
-        keep_neg = neg & (torch.rand(neg.shape, device="cuda", generator=g) < p)
-        sel = pos | keep_neg
-        idx = torch.nonzero(sel).squeeze(1)
+        pp = 1.0 if not pos_budget or n_pos <= pos_budget else pos_budget / n_pos
+        kept_pos = n_pos * pp
+        p = 1.0 if n_neg == 0 else min(1.0, neg_ratio * max(kept_pos, 1) / n_neg)
+        r = torch.rand(neg.shape, device="cuda", generator=g)
+        keep = (pos & (r < pp)) | (neg & (r < p))
+        idx = torch.nonzero(keep).squeeze(1)
         xs.append(feats[idx])
         ys.append(lab[idx].float())
         ws.append(torch.where(pos[idx], torch.ones_like(idx, dtype=torch.float32),
-                              torch.full_like(idx, 1.0 / p, dtype=torch.float32)))
+                              torch.full_like(idx, pp / p, dtype=torch.float32)))
         total += len(idx)
         snaps += 1
         if max_samples and total >= max_samples:

@@ -72,7 +72,7 @@ EXPORTED = [
     "mdvrp_mlp_act_bytes", "mdvrp_mlp_forward", "mdvrp_mlp_backward", "mdvrp_mlp_bce", "mdvrp_adam_step",
     "mdvrp_mlp_train_step", "mdvrp_filter_workspace_query", "mdvrp_filter_attach", "mdvrp_filter_anchor_count",
     "mdvrp_filter_features", "mdvrp_filter_labels", "mdvrp_filter_score_topk", "mdvrp_filter_eta_lists",
-    "mdvrp_filter_export",
+    "mdvrp_filter_export", "mdvrp_autotune", "mdvrp_set_tile_shapes",
 ]
 PROF_CLASSES = ["eval_pairs", "eval_depot_insert", "eval_depot_replace", "select", "apply", "filter_score"]
 STATE_WORDS = 12
@@ -125,6 +125,8 @@ def lib():
             "mdvrp_filter_score_topk": [p, p, p, p],
             "mdvrp_filter_eta_lists": [p, p],
             "mdvrp_filter_export": [p, p, p],
+            "mdvrp_autotune": [p, u32, i32, p, p],
+            "mdvrp_set_tile_shapes": [p, p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -367,6 +369,17 @@ class Batch:
         return [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F,
                      fallback_passes=s.fallback_passes, device_ms=s.device_ms, converged=s.converged, err=s.err)
                 for s in stats]
+
+    # ------------------------------------------------------------------ autotuner
+    def autotune(self, fam_mask=FAM_ALL, reps=3):
+        """Pick the fastest tile shape of each family's evaluation; returns threads per block."""
+        out = np.zeros(6, np.int32)
+        check(lib().mdvrp_autotune(self.handle, fam_mask, reps, out.ctypes.data_as(C.c_void_p), _stream()))
+        return [int(x) for x in out]
+
+    def set_tile_shapes(self, threads):
+        arr = np.ascontiguousarray(threads, dtype=np.int32)
+        check(lib().mdvrp_set_tile_shapes(self.handle, arr.ctypes.data_as(C.c_void_p)))
 
     # ------------------------------------------------------------------ learned filter
     def filter_attach(self, k):

@@ -123,3 +123,43 @@ def test_graph_passes_with_the_learned_filter():
     for rescore in (mdvrp.RESCORE_STEP, mdvrp.RESCORE_PASS):
         _eager_vs_graph(B, flat, seed=2, reps=2, filter=mdvrp.FILTER_MLP, mlp=M, rescore=rescore)
     del rng
+
+
+# ----------------------------------------------------------------------------- tile shapes and autotuner
+
+def _ls_fingerprint(B, sols, **kw):
+    B.load(sols)
+    st = B.local_search_to_optimum(**kw)
+    return [canonical(s.routes) for s in B.export()], [(s["passes"], s["steps"], s["moves_applied"], s["evaluated"],
+                                                         s["F"]) for s in st]
+
+
+@pytest.mark.parametrize("tw,open_r", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_tile_shapes_give_identical_searches(tw, open_r):
+    insts = [gen.tiny(73_000 + 10 * tw + open_r + k, has_tw=tw, open_routes=open_r, nc=40 + 9 * k) for k in range(3)]
+    groups = [[gen.start_solution(I, I.seed * 1000 + j) for j in range(2)] for I in insts]
+    dev, B, flat = make_batch(insts, groups)
+    ref = _ls_fingerprint(B, flat, seed=5)
+    ref_union = _ls_fingerprint(B, flat, seed=5, mode=1)
+    for threads in (128, 64):
+        B.set_tile_shapes([threads] * 6)
+        assert _ls_fingerprint(B, flat, seed=5) == ref, f"{threads} threads per block"
+        assert _ls_fingerprint(B, flat, seed=5, graph=True) == ref, f"{threads} threads per block, graph"
+    B.set_tile_shapes([256, 128, 64, 128, 64, 256])
+    assert _ls_fingerprint(B, flat, seed=5) == ref
+    assert _ls_fingerprint(B, flat, seed=5, mode=1) == ref_union
+
+
+def test_autotune_on_config2_keeps_results_and_counters():
+    I = gen.config2()
+    sols = [gen.start_solution(I, I.seed * 1000 + j) for j in range(8)]
+    dev, B, flat = make_batch([I], [sols])
+    ref = _ls_fingerprint(B, flat, seed=1, poll_every=4)
+    B.load(flat)
+    before = B.state()[:, 1].copy()
+    shapes = B.autotune(reps=2)
+    log("  tuned threads per block", shapes)
+    assert all(x in (256, 128, 64) for x in shapes)
+    assert np.array_equal(B.state()[:, 1], before), "autotuning changed the evaluation counters"
+    assert _ls_fingerprint(B, flat, seed=1, poll_every=4) == ref
+    assert _ls_fingerprint(B, flat, seed=1, poll_every=4, graph=True) == ref
