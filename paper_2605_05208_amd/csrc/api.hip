@@ -71,6 +71,7 @@ struct mdvrp_instance {
   int64_t Theta = 0, gnum = 1, gden = 1, w_depot = 0, max_c = 0, min_c = 0, max_t = 0;
   int64_t len_guard = 0;
   int t_is_c = 0;
+  int64_t route_est = 1;                // routes a solution is expected to hold: 2 * ceil(sum q / Q)
   float frcp[4] = {1.f, 1.f, 1.f, 1.f};  // feature scales of the learned filter
 };
 
@@ -277,6 +278,11 @@ extern "C" mdvrp_status mdvrp_instance_create(const mdvrp_instance_desc* d, void
   I->d = *d;
   I->N = n;
   I->t_is_c = d->t == d->c;
+  {
+    int64_t sq = 0;
+    for (int x = 0; x < n; ++x) sq += q[x];
+    I->route_est = std::max<int64_t>(1, 2 * ((sq + d->Q - 1) / d->Q));
+  }
   Carve cv(ws);
   carve_instance(cv, d, I);
   launch_node_attr(S(stream), d->q, d->s, d->e, d->l, n, I->attr);
@@ -372,13 +378,17 @@ UnitSizes unit_sizes(const mdvrp_instance* I) {
   z.nc = I->d.n_customers;
   z.n = z.nd + z.nc;
   z.R = z.nc;
-  z.cap = 3 * z.nc + 64;
+  // positions of one buffer: a solution takes n_customers + 2 M <= 3 n_customers of them;
+  // the rest is room for rebuilt routes appended in place between relayouts
+  z.cap = 6 * z.nc + 256;
   z.theta = I->d.theta;
   z.cand_cap = 3ll * z.nc * z.theta + 2ll * z.nc * z.nd + 64;
   z.tiles[0] = (int)(((int64_t)z.nc * z.theta + kTileItems - 1) / kTileItems);
   z.tiles[1] = (int)(((int64_t)z.nc * z.nd + kTileItems - 1) / kTileItems);
   z.tiles[2] = z.tiles[1];
-  z.tiles[3] = std::min(kRebuildMaxTiles, (z.R + 3) / 4);
+  // rebuild blocks (4 wavefronts, one route each, grid-stride over the alive routes):
+  // enough for the routes a solution is expected to hold
+  z.tiles[3] = (int)std::max<int64_t>(1, std::min<int64_t>({kRebuildMaxTiles, (z.R + 3) / 4, (I->route_est + 3) / 4}));
   return z;
 }
 
@@ -415,6 +425,9 @@ void carve_unit(Carve& cv, const mdvrp_instance* I, int has_tw, UnitDesc* U) {
   u.plan_se = cv.take<int32_t>(2 * (size_t)z.R);
   u.plan_pc = cv.take<int4>((size_t)z.R * kMaxPieces);
   u.slot_list = cv.take<int32_t>(z.R);
+  u.sel_size = cv.take<int32_t>(z.R + 1);
+  u.sel_slot = cv.take<int32_t>(2 * ((size_t)z.R + 1));
+  u.build_list = cv.take<int32_t>(z.R);
   u.sel_id = cv.take<uint64_t>(z.R + 1);
   u.sel_dF = cv.take<int64_t>(z.R + 1);
   u.wg_best = cv.take<MoveRec>((size_t)z.tiles[0] + z.tiles[1] + z.tiles[2]);

@@ -68,6 +68,10 @@ struct UnitCtl {
   int32_t n_slots_alive;
   int32_t fmode;         // pair neighbourhood: 0 full lists, 1 filtered lists, 2 full fallback pass
   int32_t scored_epoch;  // epoch up to which the filtered lists reflect the routes (-1 = none)
+  int32_t arena_top;     // first free position of the current buffer (rebuilt routes are appended)
+  int32_t rebuild_mode;  // latest step: 0 = rebuilt routes appended in place, 1 = full relayout
+  int32_t n_build;       // routes to build in place (mode 0)
+  int32_t pad_ctl;
   int64_t F;             // running objective (sum of applied deltas)
   int64_t evaluated;
   int64_t passes, steps, moves_applied;
@@ -109,8 +113,11 @@ struct UnitDesc {
   int32_t* dirty;     // [R] epoch tags
   int32_t* plan_n;    // [R] number of pieces of a rebuilt route (0 = deleted)
   int32_t* plan_se;   // [2R] start, end depot of a rebuilt route
-  int4* plan_pc;      // [R * kMaxPieces] {slot, from, to, rev}
-  int32_t* slot_list; // [R] alive slots in flat order (current buffer)
+  int4* plan_pc;      // [R * kMaxPieces] {old offset of the source route, from, to, rev}
+  int32_t* slot_list; // [R] alive slots in increasing order
+  int32_t* sel_size;  // [R + 1] per selected move: positions its new routes take (then their offsets)
+  int32_t* sel_slot;  // [2 (R + 1)] per selected move: slots of its new routes (-1 = none)
+  int32_t* build_list;  // [R] routes to build in place
   uint64_t* sel_id;   // [R]
   int64_t* sel_dF;    // [R]
   MoveRec* wg_best;   // [tiles of this unit]

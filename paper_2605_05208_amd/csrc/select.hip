@@ -35,8 +35,11 @@ __device__ __forceinline__ void reset_min(uint64_t* p) {
 
 __device__ __forceinline__ int64_t unpack_dD(uint64_t key) { return (int64_t)(key >> 38) - (1ll << 25); }
 
+// Move s of the selection: per new route the pieces of the old routes it is made of
+// (with the old routes' absolute offsets, so the rebuild can read them wherever the
+// new routes go), its length, depots and slot; the positions the new routes take.
 template <bool OPEN>
-__device__ void plan_move(const UnitDesc& U, int cur, uint64_t id, int64_t dF, int fresh_slot, int epoch) {
+__device__ void plan_move(const UnitDesc& U, int cur, uint64_t id, int64_t dF, int fresh_slot, int epoch, int s) {
   const int kind = (int)(id >> 56), var = (int)((id >> 48) & 0xff);
   const int a = (int)((id >> 24) & 0xffffff), b = (int)(id & 0xffffff);
   RouteCtx rc[2];
@@ -51,21 +54,31 @@ __device__ void plan_move(const UnitDesc& U, int cur, uint64_t id, int64_t dF, i
     build_drep(rc[0], b, var, R);
   }
   for (int k = 0; k < R.nold; ++k) atomicSub(&U.ndep[rc[k].start], 1);
+  int size = 0;
+  U.sel_slot[2 * s + 1] = -1;
   for (int w = 0; w < R.nnew; ++w) {
     const int slot = (R.fresh && w == 1) ? fresh_slot : rc[w].slot;
     int len = 0;
     for (int k = 0; k < R.np[w]; ++k) {
       const Piece& p = R.pc[w][k];
-      U.plan_pc[(int64_t)slot * kMaxPieces + k] = make_int4(rc[p.src].slot, p.from, p.to, p.rev);
+      U.plan_pc[(int64_t)slot * kMaxPieces + k] = make_int4(rc[p.src].off, p.from, p.to, p.rev);
       len += p.to - p.from + 1;
     }
     U.plan_n[slot] = R.np[w];
     U.plan_se[2 * slot] = R.st[w];
     U.plan_se[2 * slot + 1] = R.en[w];
     U.dirty[slot] = epoch;
-    if (len > 0) atomicAdd(&U.ndep[R.st[w]], 1);
+    U.r_len[slot] = len;
+    if (len > 0) {
+      U.r_start[slot] = R.st[w];
+      U.r_end[slot] = R.en[w];
+      size += len + 2;
+      atomicAdd(&U.ndep[R.st[w]], 1);
+    }
+    U.sel_slot[2 * s + w] = slot;
     if (len > U.len_guard) atomicOr(&U.ctl->err, 4);
   }
+  U.sel_size[s] = size;
   atomicAdd((unsigned long long*)&U.ctl->F, (unsigned long long)dF);
 }
 
@@ -78,7 +91,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   __shared__ uint64_t shI[kSelWaves];
   __shared__ int shT[kSelWaves];
   __shared__ int sh[2 * kSelWaves + 1];
-  __shared__ int s_nsel, s_alive, s_epoch, s_leader_tile, s_ndins;
+  __shared__ int s_nsel, s_alive, s_epoch, s_leader_tile, s_ndins, s_nbuild, s_alive_changed;
   if (!ctl->active) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int cur = ctl->cur;
@@ -114,6 +127,8 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     s_leader_tile = shT[0];
     s_nsel = 0;
     s_ndins = 0;
+    s_nbuild = 0;
+    s_alive_changed = 0;
     ctl->steps += 1;
     // the lists scored before this step's evaluation reflect every route up to this epoch
     if (scored && ctl->fmode == 1) ctl->scored_epoch = ctl->epoch;
@@ -247,49 +262,90 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
       }
       fresh = rank < n_dins ? free_list[rank] : 0;
     }
-    plan_move<OPEN>(U, cur, id, dF, fresh, epoch);
+    plan_move<OPEN>(U, cur, id, dF, fresh, epoch, s);
   }
   __syncthreads();
 
-  // ---- new route table and offsets of the other buffer
-  const int dst = cur ^ 1;
-  int carry = 0, alive_carry = 0;
-  for (int base = 0; base < U.R; base += kSelBlock) {
-    const int s = base + tid;
-    int len = 0;
-    if (s < U.R) {
-      if (U.dirty[s] == epoch) {
-        const int np = U.plan_n[s];
-        for (int k = 0; k < np; ++k) {
-          const int4 p = U.plan_pc[(int64_t)s * kMaxPieces + k];
-          len += p.z - p.y + 1;
-        }
-        U.r_len[s] = len;
+  // ---- where the new routes go: appended at the end of the current buffer when they
+  // fit (the other routes stay where they are), else a relayout of every route into
+  // the other buffer
+  int total = 0;
+  for (int base = 0; base < n_sel; base += kSelBlock) {
+    const int k = base + tid;
+    const int sz = k < n_sel ? U.sel_size[k] : 0;
+    int tot;
+    const int ex = block_scan(sz, sh, &tot);
+    if (k < n_sel) U.sel_size[k] = total + ex;  // exclusive offset of move k's routes
+    total += tot;
+  }
+  __syncthreads();
+  const int top = ctl->arena_top;
+  if ((int64_t)top + total <= U.cap) {
+    for (int k = tid; k < n_sel; k += kSelBlock) {
+      int at = top + U.sel_size[k];
+      for (int w = 0; w < 2; ++w) {
+        const int slot = U.sel_slot[2 * k + w];
+        if (slot < 0) continue;
+        const int len = U.r_len[slot];
         if (len > 0) {
-          U.r_start[s] = U.plan_se[2 * s];
-          U.r_end[s] = U.plan_se[2 * s + 1];
+          U.r_off[cur][slot] = at;
+          U.r_meta[cur][slot] = make_int4(at, len, U.r_start[slot], U.r_end[slot]);
+          U.build_list[atomicAdd(&s_nbuild, 1)] = slot;
+          at += len + 2;
+        } else {
+          U.r_meta[cur][slot] = make_int4(0, 0, -1, -1);
+          s_alive_changed = 1;
         }
-      } else {
-        len = U.r_len[s];
       }
+      if ((U.sel_id[k] >> 56) == DINS) s_alive_changed = 1;  // a route in a slot that was empty
     }
-    const int size = len > 0 ? len + 2 : 0;
-    int tot, tot2;
-    const int ex = block_scan(size, sh, &tot);
-    const int ax = block_scan(len > 0 ? 1 : 0, sh, &tot2);
-    if (s < U.R) {
-      U.r_off[dst][s] = carry + ex;
-      U.r_meta[dst][s] = make_int4(carry + ex, len, len > 0 ? U.r_start[s] : -1, len > 0 ? U.r_end[s] : -1);
-      if (len > 0) U.slot_list[alive_carry + ax] = s;
+    __syncthreads();
+    if (s_alive_changed) {
+      int alive_carry = 0;
+      for (int base = 0; base < U.R; base += kSelBlock) {
+        const int s = base + tid;
+        const int alive = s < U.R && U.r_len[s] > 0 ? 1 : 0;
+        int tot;
+        const int ax = block_scan(alive, sh, &tot);
+        if (alive) U.slot_list[alive_carry + ax] = s;
+        alive_carry += tot;
+      }
+      if (tid == 0) ctl->n_slots_alive = alive_carry;
     }
-    carry += tot;
-    alive_carry += tot2;
+    if (tid == 0) {
+      ctl->arena_top = top + total;
+      ctl->rebuild_mode = 0;
+      ctl->n_build = s_nbuild;
+    }
+  } else {
+    const int dst = cur ^ 1;
+    int carry = 0, alive_carry = 0;
+    for (int base = 0; base < U.R; base += kSelBlock) {
+      const int s = base + tid;
+      const int len = s < U.R ? U.r_len[s] : 0;
+      const int size = len > 0 ? len + 2 : 0;
+      int tot, tot2;
+      const int ex = block_scan(size, sh, &tot);
+      const int ax = block_scan(len > 0 ? 1 : 0, sh, &tot2);
+      if (s < U.R) {
+        U.r_off[dst][s] = carry + ex;
+        U.r_meta[dst][s] = make_int4(carry + ex, len, len > 0 ? U.r_start[s] : -1, len > 0 ? U.r_end[s] : -1);
+        if (len > 0) U.slot_list[alive_carry + ax] = s;
+      }
+      carry += tot;
+      alive_carry += tot2;
+    }
+    if (tid == 0) {
+      if (carry > U.cap) atomicOr(&ctl->err, 2);
+      ctl->n_slots_alive = alive_carry;
+      ctl->cur = dst;
+      ctl->arena_top = carry;
+      ctl->rebuild_mode = 1;
+      ctl->n_build = 0;
+    }
   }
   if (tid == 0) {
-    if (carry > U.cap) atomicOr(&ctl->err, 2);
-    ctl->n_slots_alive = alive_carry;
     ctl->n_sel = n_sel;
-    ctl->cur = dst;
     ctl->moves_applied += n_sel;
     ctl->pass_applied = 1;
     ctl->n_cand = 0;

@@ -109,18 +109,22 @@ __global__ __launch_bounds__(kRebuildBlock) void k_rebuild(const UnitDesc* __res
   const int waves_per_block = kRebuildBlock / 64;
   const int w0 = lt * waves_per_block + (threadIdx.x >> 6);
   const int stride = ntiles * waves_per_block;
-  const int dst = ctl->cur, src = dst ^ 1;
+  // mode 0: the step's new routes were given fresh space at the end of the current
+  // buffer; only they are built. mode 1: full relayout into the other buffer (the
+  // current one after the flip): untouched routes are copied, new ones built.
+  const bool in_place = ctl->rebuild_mode == 0;
+  const int dst = ctl->cur, src = in_place ? dst : dst ^ 1;
   const int epoch = ctl->epoch;
-  const int n_alive = ctl->n_slots_alive;
+  const int n_items = in_place ? ctl->n_build : ctl->n_slots_alive;
   const SEG* fws = (const SEG*)U.fw[src];
   const SEG* bws = (const SEG*)U.bw[src];
   SEG* fwd = (SEG*)U.fw[dst];
   SEG* bwd = (SEG*)U.bw[dst];
   const int lane = lane_id();
-  for (int k = w0; k < n_alive; k += stride) {
-    const int slot = U.slot_list[k];
+  for (int k = w0; k < n_items; k += stride) {
+    const int slot = in_place ? U.build_list[k] : U.slot_list[k];
     const int L = U.r_len[slot];
-    if (U.dirty[slot] != epoch) {
+    if (!in_place && U.dirty[slot] != epoch) {
       const int P = OPEN ? L + 1 : L + 2;
       const int64_t so = U.r_off[src][slot], d0 = U.r_off[dst][slot];
       for (int p = lane; p < P; p += 64) {
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(kRebuildBlock) void k_rebuild(const UnitDesc* __res
     int po[kMaxPieces];
     for (int j = 0; j < np; ++j) {
       pc[j] = U.plan_pc[(int64_t)slot * kMaxPieces + j];
-      po[j] = U.r_off[src][pc[j].x];
+      po[j] = pc[j].x;
     }
     auto nodeAt = [&](int p) -> int {
       int q = p;
@@ -215,6 +219,9 @@ __global__ __launch_bounds__(kUnitBlock) void k_load_table(const UnitDesc* __res
     ctl->fallbacks = 0;
     ctl->fmode = 0;
     ctl->scored_epoch = -1;
+    ctl->arena_top = carry;
+    ctl->rebuild_mode = 1;
+    ctl->n_build = 0;
   }
 }
 
