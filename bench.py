@@ -138,7 +138,7 @@ def ls_run(B, sols, **kw):
     return dt, st, prof
 
 
-def filter_study(n_sol=16, k=8, epochs=6):
+def filter_study(n_sol=16, k=8, epochs=6, rescore=4):
     """Full vs filtered local search on the 20 x 10000 MDVRPTW instance."""
     import torch
 
@@ -167,12 +167,13 @@ def filter_study(n_sol=16, k=8, epochs=6):
     shapes = B5.autotune(reps=2)
     runs = {}
     for name, kw in (("full", {}), ("eta", dict(filter=mdvrp.FILTER_LISTS, eta=True)),
-                     ("mlp", dict(filter=mdvrp.FILTER_MLP, mlp=M, rescore=mdvrp.RESCORE_PASS))):
+                     ("mlp", dict(filter=mdvrp.FILTER_MLP, mlp=M, rescore=rescore))):
         dt, st, prof = ls_run(B5, s5, **kw)
         runs[name] = (dt, np.array([s["F"] for s in st], np.float64), st, prof)
     full_dt, full_F = runs["full"][0], runs["full"][1]
     out = dict(workload=f"{I5.name}: {n_sol} solutions, local search to a local optimum of the full neighbourhood",
-               k=k, full_ms=round(full_dt * 1e3, 1), full_F_mean=float(full_F.mean()), tile_threads_per_family=shapes,
+               k=k, rescore_every_passes=rescore, full_ms=round(full_dt * 1e3, 1), full_F_mean=float(full_F.mean()),
+               tile_threads_per_family=shapes,
                full_evaluated=int(sum(s["evaluated"] for s in runs["full"][2])),
                train=dict(samples=int(x.shape[0]), positives=int(y.sum().item()), snapshots=snaps,
                           log_s=round(t_log, 2), train_s=round(t_train, 2), epochs=epochs,

@@ -1218,6 +1218,8 @@ void carve_filter(Carve& cv, const mdvrp_batch* B, int32_t k, std::vector<int32_
   q.cmark = cv.take<uint8_t>(B->n_cust);
   q.anchor_off = cv.take<int64_t>(B->n_units + 1);
   q.n_anchors = B->n_anchors;
+  q.max_unit_anchors = 0;
+  for (const UnitDesc& U : B->h_units) q.max_unit_anchors = std::max<int64_t>(q.max_unit_anchors, (int64_t)U.nc * U.theta);
   if (stale) *stale = q;
   for (int u = 0; u < B->n_units; ++u) {
     int32_t* p = cv.take<int32_t>((size_t)B->inst[B->unit_inst[u]]->d.n_customers * k);

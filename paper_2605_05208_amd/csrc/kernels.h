@@ -79,6 +79,7 @@ struct FilterQueue {
   uint8_t* cmark;        // [n_customers of the batch]
   const int64_t* anchor_off;  // [n_units + 1]
   int64_t n_anchors;
+  int64_t max_unit_anchors;   // largest n_customers * theta of a unit
 };
 // Rank the lists: all = 1 every anchor of every unit, all = 0 the stale anchors of
 // active filtered units; then the top-k of every customer that owns a rescored anchor.

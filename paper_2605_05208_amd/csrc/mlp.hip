@@ -319,41 +319,44 @@ __device__ __forceinline__ int unit_of_anchor(const int64_t* __restrict__ off, i
   return lo;
 }
 
-// One thread per anchor. all = 1: every anchor of every unit; all = 0: the stale
-// anchors of active filtered units. Marked anchors go to queue (one atomic per
-// wavefront); their customers are flagged in cmark.
+// Stale anchors of active filtered units: grid (anchor blocks, unit), one thread per
+// anchor; an anchor is stale when the route of u or of v was rebuilt after the unit's
+// last ranking. Marked anchors go to queue (one atomic per block); their customers
+// are flagged in cmark.
 __global__ __launch_bounds__(256) void k_anchor_mark(const UnitDesc* __restrict__ units,
                                                      const int64_t* __restrict__ anchor_off,
-                                                     const int32_t* __restrict__ cust_off, int n_units, int all,
-                                                     int32_t* __restrict__ queue, int32_t* __restrict__ count,
-                                                     uint8_t* __restrict__ cmark) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                     const int32_t* __restrict__ cust_off, int32_t* __restrict__ queue,
+                                                     int32_t* __restrict__ count, uint8_t* __restrict__ cmark) {
+  __shared__ int s_cnt[4], s_base;
+  const int ui = blockIdx.y;
+  const UnitDesc& U = units[ui];
+  const UnitCtl* c = U.ctl;
+  const int item = blockIdx.x * 256 + threadIdx.x;
+  const int n_items = U.nc * U.theta;
+  if (blockIdx.x * 256 >= n_items || !c->active || c->fmode != 1) return;  // uniform per block
   bool st = false;
-  int cust = 0;
-  if (a < anchor_off[n_units]) {
-    const int ui = unit_of_anchor(anchor_off, n_units, a);
-    const UnitDesc& U = units[ui];
-    const UnitCtl* c = U.ctl;
-    const int item = (int)(a - anchor_off[ui]);
+  if (item < n_items) {
     const int i = item / U.theta, k = item - i * U.theta;
-    cust = cust_off[ui] + i;
     if (k < U.nbr_len[i]) {
-      if (all) {
-        st = true;
-      } else if (c->active && c->fmode == 1) {
-        const int se = c->scored_epoch;
-        st = U.dirty[U.rt[U.nd + i]] > se || U.dirty[U.rt[U.nbr[item]]] > se;
-      }
+      const int se = c->scored_epoch;
+      st = U.dirty[U.rt[U.nd + i]] > se || U.dirty[U.rt[U.nbr[item]]] > se;
+      if (st) cmark[cust_off[ui] + i] = 1;
     }
   }
-  if (st) cmark[cust] = 1;
   const uint64_t m = __ballot(st);
-  if (!m) return;
-  const int lane = lane_id();
-  int base = 0;
-  if (lane == 0) base = atomicAdd(count, __popcll(m));
-  base = __shfl(base, 0);
-  if (st) queue[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)a;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  if (lane == 0) s_cnt[wave] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    s_base = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+  if (st) {
+    int at = s_base + __popcll(m & ((1ull << lane) - 1));
+    for (int w = 0; w < wave; ++w) at += s_cnt[w];
+    queue[at] = (int32_t)(anchor_off[ui] + item);
+  }
 }
 
 // Logits of the queued anchors: each wavefront takes 16 T anchors at a time, builds
@@ -367,7 +370,9 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score_anchors(
     float* __restrict__ lcache) {
   __shared__ MlpSmem S;
   __shared__ __attribute__((aligned(16))) uint16_t xs[kScoreWaves][16 * kScoreT * kF];
-  const int n = *qcount;
+  // without a queue every anchor of the batch is scored (missing list entries get zero
+  // features; nothing reads their logits)
+  const int n = queue ? *qcount : (int)anchor_off[n_units];
   if (n == 0) return;
   mlp_stage(S, w2f, P, w3b);
   const float b3 = P[P_B3];
@@ -377,14 +382,19 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score_anchors(
     if (lane < G) {
       uint16_t f[kF];
       const int q = g0 + lane;
+      bool have = false;
       if (q < n) {
-        const int64_t a = queue[q];
+        const int64_t a = queue ? queue[q] : q;
         const int ui = unit_of_anchor(anchor_off, n_units, a);
         const UnitDesc& U = units[ui];
         const int item = (int)(a - anchor_off[ui]);
         const int i = item / U.theta, k = item - i * U.theta;
-        pair_features<SEG, TW>(U, U.ctl->cur, U.nd + i, U.nbr[item], k, f);
-      } else {
+        if (k < U.nbr_len[i]) {  // queued anchors always are; in the all-anchors mode some are not
+          pair_features<SEG, TW>(U, U.ctl->cur, U.nd + i, U.nbr[item], k, f);
+          have = true;
+        }
+      }
+      if (!have) {
 #pragma unroll
         for (int z = 0; z < kF; ++z) f[z] = 0;
       }
@@ -402,47 +412,52 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score_anchors(
 #pragma unroll
     for (int t = 0; t < kScoreT; ++t) {
       const int q = g0 + 16 * t + lane;
-      if (lane < 16 && q < n) lcache[queue[q]] = z[t];
+      if (lane < 16 && q < n) lcache[queue ? queue[q] : q] = z[t];
     }
   }
 }
 
-// Top-kc of every flagged customer from the cached logits (logit descending, customer
-// id ascending; -1 padding); clears the flag. One thread per customer.
+// Top-kc of every flagged customer (all = 1: every customer) from the cached logits
+// (logit descending, customer id ascending; -1 padding); clears the flag. One
+// wavefront per customer, lanes hold entries lane and lane + 64, kc rounds of a wave
+// arg-max.
 __global__ __launch_bounds__(256) void k_topk_marked(const UnitDesc* __restrict__ units,
                                                      const int32_t* __restrict__ cust_off, int n_units,
-                                                     const float* __restrict__ lcache, uint8_t* __restrict__ cmark) {
-  const int task = blockIdx.x * blockDim.x + threadIdx.x;
-  if (task >= cust_off[n_units] || !cmark[task]) return;
-  cmark[task] = 0;
+                                                     const float* __restrict__ lcache, uint8_t* __restrict__ cmark,
+                                                     int all) {
+  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = lane_id();
+  if (task >= cust_off[n_units]) return;
+  if (!all && !cmark[task]) return;
   const int ui = unit_of_tile(cust_off, n_units, task);
   const UnitDesc& U = units[ui];
   const int i = task - cust_off[ui];
   const int len = U.nbr_len[i];
   const int32_t* nb = U.nbr + (int64_t)i * U.theta;
   const float* lg = lcache + U.item_base + (int64_t)i * U.theta;
+  float s0 = -INFINITY, s1 = -INFINITY;
+  int v0 = INT32_MAX, v1 = INT32_MAX;
+  if (lane < len) { s0 = lg[lane]; v0 = nb[lane]; }
+  if (lane + 64 < len) { s1 = lg[lane + 64]; v1 = nb[lane + 64]; }
   int32_t* out = U.fcand + (int64_t)i * U.kc;
-  // selection of the best remaining entry, kc times; taken entries are skipped by
-  // comparing against the previous pick (score, id), which is a strict total order
-  float ps = INFINITY;
-  int pv = -1;
   for (int j = 0; j < U.kc; ++j) {
-    float bs = -INFINITY;
-    int bv = INT32_MAX;
-    for (int k = 0; k < len; ++k) {
-      const float sk = lg[k];
-      const int vk = nb[k];
-      const bool after_prev = sk < ps || (sk == ps && vk > pv);
-      if (after_prev && (sk > bs || (sk == bs && vk < bv))) { bs = sk; bv = vk; }
+    float bs = s0;
+    int bv = v0, src = lane, which = 0;
+    if (s1 > bs || (s1 == bs && v1 < bv)) { bs = s1; bv = v1; which = 1; }
+    for (int off = 32; off > 0; off >>= 1) {
+      const float s2 = __shfl_xor(bs, off);
+      const int v2 = __shfl_xor(bv, off);
+      const int src2 = __shfl_xor(src, off);
+      const int w2 = __shfl_xor(which, off);
+      if (s2 > bs || (s2 == bs && v2 < bv)) { bs = s2; bv = v2; src = src2; which = w2; }
     }
-    if (bv == INT32_MAX) {
-      for (; j < U.kc; ++j) out[j] = -1;
-      break;
+    if (lane == 0) out[j] = bv == INT32_MAX ? -1 : bv;
+    if (lane == src) {
+      if (which == 0) { s0 = -INFINITY; v0 = INT32_MAX; }
+      else { s1 = -INFINITY; v1 = INT32_MAX; }
     }
-    out[j] = bv;
-    ps = bs;
-    pv = bv;
   }
+  if (lane == 0) cmark[task] = 0;
 }
 
 // The heuristic filter: the first kc entries of each granular list (eta order).
@@ -682,14 +697,18 @@ static void score_anchors_t(const LaunchCtx& L, const int64_t* anchor_off, const
 void launch_rank(const LaunchCtx& L, const int32_t* cust_off, int n_cust, const MlpDev& M, const FilterQueue& Q,
                  int all) {
   if (n_cust <= 0 || Q.n_anchors <= 0) return;
-  // a fill kernel rather than a memset: the sequence may be captured in a graph
-  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, L.stream, Q.count);
-  hipLaunchKernelGGL(k_anchor_mark, dim3((unsigned)((Q.n_anchors + 255) / 256)), dim3(256), 0, L.stream, L.units,
-                     Q.anchor_off, cust_off, L.n_units, all, Q.queue, Q.count, Q.cmark);
-  if (L.has_tw) score_anchors_t<SegTW, true>(L, Q.anchor_off, M, Q, Q.n_anchors);
-  else score_anchors_t<SegNT, false>(L, Q.anchor_off, M, Q, Q.n_anchors);
-  hipLaunchKernelGGL(k_topk_marked, dim3((n_cust + 255) / 256), dim3(256), 0, L.stream, L.units, cust_off, L.n_units,
-                     (const float*)Q.lcache, Q.cmark);
+  if (!all) {
+    // a fill kernel rather than a memset: the sequence may be captured in a graph
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, L.stream, Q.count);
+    hipLaunchKernelGGL(k_anchor_mark, dim3((unsigned)((Q.max_unit_anchors + 255) / 256), L.n_units), dim3(256), 0,
+                       L.stream, L.units, Q.anchor_off, cust_off, Q.queue, Q.count, Q.cmark);
+  }
+  FilterQueue q = Q;
+  if (all) q.queue = nullptr;
+  if (L.has_tw) score_anchors_t<SegTW, true>(L, Q.anchor_off, M, q, Q.n_anchors);
+  else score_anchors_t<SegNT, false>(L, Q.anchor_off, M, q, Q.n_anchors);
+  hipLaunchKernelGGL(k_topk_marked, dim3((n_cust + 3) / 4), dim3(256), 0, L.stream, L.units, cust_off, L.n_units,
+                     (const float*)Q.lcache, Q.cmark, all);
 }
 
 void launch_eta_lists(const LaunchCtx& L, const int32_t* cust_off, int n_tasks) {

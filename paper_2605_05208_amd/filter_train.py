@@ -39,14 +39,16 @@ def valid_anchors(batch: mdvrp.Batch):
 
 
 def log_states(batch: mdvrp.Batch, solutions, seed=1, chunk=2, max_chunks=40, neg_ratio=4.0, rng_seed=0,
-               max_samples=None, pos_budget=None):
+               max_samples=None, pos_budget=None, search=None):
     """Run the full-list local search of `solutions` in chunks of `chunk` passes and log
     (features, label, weight) of sub-sampled anchors after every chunk (the start state
     included). With pos_budget, at most that many positives are kept per snapshot, with
     weight 1, so that the early states, where most anchors improve, do not dominate the
     logs; negatives are weighted by the inverse of their keep rate, which restores each
-    snapshot's ratio of negatives to kept positives. Returns device tensors x [n][32]
-    (int16 bf16 bits), y [n], w [n] and the number of snapshots."""
+    snapshot's ratio of negatives to kept positives. `search` (keyword arguments of the
+    local search) selects the trajectory, e.g. a filtered search; the labels always
+    come from the full lists. Returns device tensors x [n][32] (int16 bf16 bits), y [n],
+    w [n] and the number of snapshots."""
     torch = _torch()
     g = torch.Generator(device="cuda")
     g.manual_seed(rng_seed)
@@ -75,7 +77,7 @@ def log_states(batch: mdvrp.Batch, solutions, seed=1, chunk=2, max_chunks=40, ne
         snaps += 1
         if max_samples and total >= max_samples:
             break
-        st = batch.local_search_to_optimum(seed=seed + c, max_passes=chunk)
+        st = batch.local_search_to_optimum(seed=seed + c, max_passes=chunk, **(search or {}))
         if all(s["converged"] for s in st) or n_pos == 0:
             break
     return torch.cat(xs), torch.cat(ys), torch.cat(ws), snaps

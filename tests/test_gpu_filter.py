@@ -372,3 +372,49 @@ def test_mlp_filtered_local_search_reaches_a_full_local_optimum(which):
         moves = ref.eval(out[u], ALL_FAMILIES)
         assert len(moves) == 0 or moves["dF"].min() >= 0, f"unit {u}: improving move left"
     log("  filtered F", [s["F"] for s in st], "evaluated", [s["evaluated"] for s in st])
+
+
+# ----------------------------------------------------------------------------- what the trained network gains
+
+def test_trained_filter_gains_over_full_evaluation():
+    """Train on logs of full-list searches of the 1000-customer instance (GPU kernels end
+    to end), then search held-out uneven instances: the filtered search must reach a
+    certified local optimum of the full neighbourhood, evaluate far fewer moves than the
+    full search, and rank the improving anchors of mid-search states better than an
+    untrained network does."""
+    from paper_2605_05208_amd import filter_train as ft
+    I2 = gen.config2()
+    dev2, TB, flat2 = make_batch([I2], [[gen.start_solution(I2, I2.seed * 1000 + j) for j in range(8)]])
+    x, y, w, snaps = ft.log_states(TB, flat2, chunk=2, max_chunks=30)
+    trained = mdvrp.Mlp(ft.init_params(0))
+    losses, _ = ft.train(trained, x, y, w, epochs=4, lr=1e-3)
+    log(f"  {x.shape[0]} samples from {snaps} snapshots, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert losses[-1] < losses[0]
+    untrained = mdvrp.Mlp(ft.init_params(0))
+    insts = [gen.config4_instance(i) for i in (3, 11, 29)]
+    groups = [[gen.start_solution(I, I.seed * 1000 + j) for j in range(2)] for I in insts]
+    dev, B, flat = make_batch(insts, groups)
+    B.filter_attach(8)
+    full = B.local_search_to_optimum(seed=3)
+    B.load(flat)
+    filt = B.local_search_to_optimum(seed=3, filter=mdvrp.FILTER_MLP, mlp=trained, rescore=4)
+    out = B.export()
+    unit_inst = [k for k, s in enumerate(groups) for _ in s]
+    for u, k in enumerate(unit_inst):
+        ref = Ref(insts[k])
+        moves = ref.eval(out[u], ALL_FAMILIES)
+        assert len(moves) == 0 or moves["dF"].min() >= 0, f"unit {u}: improving move left"
+        assert ref.cost(out[u])[0] == filt[u]["F"]
+    ev_full = sum(s["evaluated"] for s in full)
+    ev_filt = sum(s["evaluated"] for s in filt)
+    F_full = np.mean([s["F"] for s in full])
+    F_filt = np.mean([s["F"] for s in filt])
+    log(f"  evaluated {ev_filt} vs {ev_full} full; mean F {F_filt:.0f} vs {F_full:.0f} full")
+    assert ev_filt * 2 < ev_full
+    # ranking quality at a mid-search state of the held-out instances
+    B.load(flat)
+    B.local_search_to_optimum(seed=3, max_passes=6)
+    r_trained, n_pos = ft.recall_at_k(B, trained, 8)
+    r_untrained, _ = ft.recall_at_k(B, untrained, 8)
+    log(f"  recall@8 of the {n_pos} improving anchors: trained {r_trained:.3f}, untrained {r_untrained:.3f}")
+    assert r_trained > r_untrained
