@@ -44,6 +44,8 @@ def workload(name):
         inst, n = gen.config3(), 16
     elif name == "config3_open":
         inst, n = gen.config3(open_routes=1), 16
+    elif name == "config5":
+        inst, n = gen.config5(), 16
     else:
         raise SystemExit(f"unknown workload {name}")
     sols = [gen.start_solution(inst, inst.seed * 1000 + k) for k in range(n)]
@@ -51,15 +53,18 @@ def workload(name):
 
 
 PAIR_KERNEL_SOURCES = ("eval.hip", "eval_common.h", "eval_inter.h", "eval_intra.h", "internal.h")
-PAIR_PROFILE = os.path.join(ROOT, "profiles", "k_eval_pairs_mdvrptw-8x1000_64sol.md")
+PAIR_PROFILES = {"config2": "k_eval_pairs_mdvrptw-8x1000_64sol.md", "config5": "k_eval_pairs_mdvrptw-20x10000_16sol.md"}
 
 
-def measured_traffic():
-    """HBM bytes per pair-evaluation launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain copy), or None when the kernel sources changed since."""
+def measured_traffic(workload):
+    """HBM bytes per pair-evaluation launch from the committed counter summary of the workload
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when there is none or the
+    kernel sources changed since the counters were taken."""
     import hashlib
+    if workload not in PAIR_PROFILES:
+        return None
     try:
-        text = open(PAIR_PROFILE).read()
+        text = open(os.path.join(ROOT, "profiles", PAIR_PROFILES[workload])).read()
     except OSError:
         return None
     h = hashlib.sha256()
@@ -363,7 +368,7 @@ def main():
         n_l, ms_l = prof["eval_pairs"]
         avg_s = ms_l / max(n_l, 1) / 1e3
         achieved = b_alg / avg_s / 1e9
-        traffic = measured_traffic() if args.workload == "config2" else None
+        traffic = measured_traffic(args.workload)
         roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic, kernel="k_eval_pairs",
                     bytes_per_launch=int(b_alg), launches=n_l, avg_launch_us=round(avg_s * 1e6, 2))

@@ -77,7 +77,19 @@ typedef struct {
   int32_t theta;                 /* granular list size, 1..128 (>= n_customers-1: full) */
   int32_t w_tw, w_load, w_dur;   /* fixed penalty weights (>= 0) */
   int32_t w_depot;               /* < 0: 2*max c - min c (the Eq. A.1 normaliser) */
+  int32_t layout;                /* MDVRP_LAYOUT_*: memory layout of the matrices the kernels read */
 } mdvrp_instance_desc;
+
+/* Matrix layout. The evaluations read c(x, y) for nodes close to each other; with
+ * MDVRP_LAYOUT_ORDERED the instance keeps a copy of c (and t) whose rows and
+ * columns follow an order in which nearby nodes get nearby indices (derived from
+ * c: the Morton code of each node's distances to three far-apart landmarks), so
+ * those reads share cache lines. The copy lives in the instance workspace (N*N
+ * int32 per matrix). Results do not depend on the layout. MDVRP_LAYOUT_AUTO
+ * (0, the default) orders instances whose matrix exceeds 64 MiB. */
+#define MDVRP_LAYOUT_AUTO 0
+#define MDVRP_LAYOUT_GIVEN 1
+#define MDVRP_LAYOUT_ORDERED 2
 
 /* ------------------------------------------------------------------------- instance */
 

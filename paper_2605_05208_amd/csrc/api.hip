@@ -72,6 +72,9 @@ struct mdvrp_instance {
   int64_t len_guard = 0;
   int t_is_c = 0;
   int64_t route_est = 1;                // routes a solution is expected to hold: 2 * ceil(sum q / Q)
+  int32_t *cl = nullptr, *tl = nullptr, *pi = nullptr, *inv = nullptr, *corder = nullptr;  // locality layout
+  int64_t* lm = nullptr;
+  uint64_t* keys = nullptr;
   float frcp[4] = {1.f, 1.f, 1.f, 1.f};  // feature scales of the learned filter
 };
 
@@ -131,6 +134,8 @@ struct mdvrp_batch {
     graphs.clear();
   }
   LaunchCtx ctx(void* stream) const {
+    bool layout_all = true;
+    for (const mdvrp_instance* I : inst) layout_all = layout_all && I->pi != nullptr;
     LaunchCtx L;
     L.stream = S(stream);
     L.units = d_units;
@@ -140,6 +145,12 @@ struct mdvrp_batch {
     for (int k = 0; k < 4; ++k) {
       L.tile_off[k] = d_tile_off[k];
       L.tiles[k] = h_tile_off[k].empty() ? 0 : h_tile_off[k].back();
+      // unit-interleaved tile order: for instances kept in the locality layout (large
+      // matrices), when every unit has the same tile count
+      int per = n_units > 1 && layout_all && L.tiles[k] % n_units == 0 ? L.tiles[k] / n_units : 0;
+      for (int u = 0; u < n_units && per > 0; ++u)
+        if (h_tile_off[k][u + 1] - h_tile_off[k][u] != per) per = 0;
+      L.per_unit[k] = per;
     }
     L.active_count = d_active;
     return L;
@@ -200,6 +211,7 @@ static mdvrp_status check_scalars(const mdvrp_instance_desc* d) {
   if (d->w_tw < 0 || d->w_load < 0 || d->w_dur < 0) return fail(MDVRP_EINVAL, "penalty weights must be >= 0");
   if (d->open_routes != 0 && d->open_routes != 1) return fail(MDVRP_EINVAL, "open_routes must be 0 or 1");
   if (d->has_tw != 0 && d->has_tw != 1) return fail(MDVRP_EINVAL, "has_tw must be 0 or 1");
+  if (d->layout < MDVRP_LAYOUT_AUTO || d->layout > MDVRP_LAYOUT_ORDERED) return fail(MDVRP_EINVAL, "unknown layout");
   if (!d->c || !d->t || !d->q || !d->s || !d->e || !d->l) return fail(MDVRP_EINVAL, "null array");
   return MDVRP_OK;
 }
@@ -221,6 +233,15 @@ extern "C" mdvrp_status mdvrp_validate_instance_host(const mdvrp_instance_desc* 
   return check_node_arrays(d, d->q, d->s, d->e, d->l);
 }
 
+// Whether an instance keeps a locality-ordered copy of its matrices: asked for, or
+// by default for matrices beyond what the caches hold.
+static bool uses_layout(const mdvrp_instance_desc* d) {
+  const int64_t n = (int64_t)d->n_depots + d->n_customers;
+  if (d->layout == MDVRP_LAYOUT_GIVEN) return false;
+  if (d->layout == MDVRP_LAYOUT_ORDERED) return true;
+  return n * n * 4 > ((int64_t)64 << 20);
+}
+
 static void carve_instance(Carve& cv, const mdvrp_instance_desc* d, mdvrp_instance* I) {
   const int n = d->n_depots + d->n_customers;
   const int nb = inst_stats_blocks(n);
@@ -236,6 +257,18 @@ static void carve_instance(Carve& cv, const mdvrp_instance_desc* d, mdvrp_instan
     I->partial = part;
     I->stats = st;
     I->nblocks = nb;
+  }
+  if (uses_layout(d)) {
+    int32_t* cl = cv.take<int32_t>((size_t)n * n);
+    int32_t* tl = d->t != d->c ? cv.take<int32_t>((size_t)n * n) : nullptr;
+    int32_t* pi = cv.take<int32_t>(n);
+    int32_t* inv = cv.take<int32_t>(n);
+    int32_t* co = cv.take<int32_t>(d->n_customers);
+    int64_t* lm = cv.take<int64_t>(8);
+    uint64_t* keys = cv.take<uint64_t>(n);
+    if (I) {
+      I->cl = cl; I->tl = tl; I->pi = pi; I->inv = inv; I->corder = co; I->lm = lm; I->keys = keys;
+    }
   }
 }
 
@@ -325,6 +358,8 @@ extern "C" mdvrp_status mdvrp_instance_create(const mdvrp_instance_desc* d, void
   launch_nbr_lists(S(stream), d->c, d->t, d->s, d->e, d->l, d->n_depots, d->n_customers, d->theta, d->has_tw,
                    I->gnum, I->gden, I->nbr, I->nbr_len);
   launch_nn_sum(S(stream), d->c, I->nbr, I->nbr_len, d->n_depots, d->n_customers, d->theta, I->stats);
+  if (I->pi)
+    launch_layout(S(stream), d->c, d->t, n, d->n_depots, I->lm, I->keys, I->pi, I->inv, I->corder, I->cl, I->tl);
   int64_t nn[2] = {0, 0};
   he = hipMemcpyAsync(nn, I->stats, sizeof nn, hipMemcpyDeviceToHost, S(stream));
   if (he == hipSuccess) he = hipStreamSynchronize(S(stream));
@@ -508,6 +543,7 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
     UnitDesc& u = B->h_units[k];
     u.c = I->d.c; u.t = I->d.t; u.q = I->d.q; u.s = I->d.s; u.e = I->d.e; u.l = I->d.l;
     u.nbr = I->nbr; u.nbr_len = I->nbr_len; u.attr = I->attr;
+    u.cl = I->cl; u.tl = I->tl ? I->tl : I->cl; u.pi = I->pi; u.corder = I->corder;
     u.nd = z.nd; u.nc = z.nc; u.n = z.n; u.theta = z.theta;
     u.Q = I->d.Q; u.NV = I->d.NV; u.Dmax = I->d.Dmax;
     u.w_tw = I->d.w_tw; u.w_load = I->d.w_load; u.w_dur = I->d.w_dur;

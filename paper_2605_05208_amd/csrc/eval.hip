@@ -189,23 +189,38 @@ __device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
 
 // --------------------------------------------------------------------------- pair kinds
 
+// Unit and local tile of this block. The blocks of one XCD take a contiguous range of
+// tiles. When every unit has the same number of tiles (per_unit > 0), tile t is local
+// tile t / n_units of unit t % n_units: an XCD then serves the same customers of
+// every unit, whose matrix rows stay in its L2.
+__device__ __forceinline__ void tile_of_block(const int32_t* __restrict__ tile_off, int n_units, int per_unit, int& ui,
+                                              int& lt) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (per_unit > 0) {
+    ui = tile % n_units;
+    lt = tile / n_units;
+  } else {
+    ui = unit_of_tile(tile_off, n_units, tile);
+    lt = tile - tile_off[ui];
+  }
+}
+
 // KM != 0 fixes the kind mask at compile time (one lean kernel per family);
 // KM == 0 takes it from the argument. A tile is kTileSize items; a block of TPB
 // threads covers it with kTileSize / TPB items per thread (the tile shape the
 // autotuner picks; results do not depend on it).
 template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
 __global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__ units,
-                                                   const int32_t* __restrict__ tile_off, int n_units,
+                                                   const int32_t* __restrict__ tile_off, int n_units, int per_unit,
                                                    uint32_t kind_arg, DenseOut dense) {
   constexpr int IPT = kTileSize / TPB;
   const uint32_t kind_mask = KM ? KM : kind_arg;
   __shared__ int s_q[kTileSize];
   __shared__ int s_nq;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int ui = unit_of_tile(tile_off, n_units, tile);
+  int ui, lt;
+  tile_of_block(tile_off, n_units, per_unit, ui, lt);
   const UnitDesc& U = units[ui];
   if (!U.ctl->active) return;
-  const int lt = tile - tile_off[ui];
   // Filtered units evaluate their candidate lists (kc entries per customer);
   // the tiles beyond that smaller item space have nothing to do.
   const bool filt = U.ctl->fmode == 1;
@@ -226,10 +241,13 @@ __global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__
   const uint32_t inter_kinds = kind_mask & ~(1u << TWOOPT);
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
-    const int item = lt * kTileSize + r * TPB + threadIdx.x;
-    if (item < U.nc * th) {
-      const int i = item / th;
-      const int k = item - i * th;
+    // tiles walk the customers in layout order (neighbouring customers share cache lines)
+    const int pos = lt * kTileSize + r * TPB + threadIdx.x;
+    if (pos < U.nc * th) {
+      const int ri = pos / th;
+      const int k = pos - ri * th;
+      const int i = U.corder ? U.corder[ri] : ri;
+      const int item = i * th + k;
       const int v = lists[item];
       if ((filt || k < U.nbr_len[i]) && v >= 0) {
         const int u = U.nd + i;
@@ -275,14 +293,13 @@ __global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__
 
 template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
 __global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__ units,
-                                                   const int32_t* __restrict__ tile_off, int n_units, int which,
-                                                   DenseOut dense) {
+                                                   const int32_t* __restrict__ tile_off, int n_units, int per_unit,
+                                                   int which, DenseOut dense) {
   constexpr int IPT = kTileSize / TPB;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int ui = unit_of_tile(tile_off, n_units, tile);
+  int ui, lt;
+  tile_of_block(tile_off, n_units, per_unit, ui, lt);
   const UnitDesc& U = units[ui];
   if (!U.ctl->active) return;
-  const int lt = tile - tile_off[ui];
   // Depot-Replace items cover the alive routes only; the tiles beyond them have
   // nothing to do (the selection reads as many tiles as the items need).
   const int n_drep = which == 1 ? U.ctl->n_slots_alive * U.nd : 0;
@@ -302,9 +319,9 @@ __global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__
   if (which == 0) {
     // Depot-Insert: one item per (customer u, depot d); cut after u when s(u) is a customer.
     if (item < U.nc * U.nd) {
-      const int i = item / U.nd;
-      const int d = item - i * U.nd;
-      const int u = U.nd + i;
+      const int ri = item / U.nd;
+      const int d = item - ri * U.nd;
+      const int u = U.nd + (U.corder ? U.corder[ri] : ri);
       const RouteCtx A = route_ctx(U, cur, U.rt[u]);
       const int pu = U.pos[u];
       if (pu < A.L) {
@@ -369,7 +386,7 @@ constexpr uint32_t k2optKinds = 1u << TWOOPT;
 template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
 static void launch_pairs(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) {
   hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, SM, AR, KM, TPB>), dim3(L.tiles[0]), dim3(TPB), 0, L.stream, L.units,
-                     L.tile_off[0], L.n_units, kinds, D);
+                     L.tile_off[0], L.n_units, L.per_unit[0], kinds, D);
 }
 
 template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
@@ -387,7 +404,7 @@ static void launch_class_t(const LaunchCtx& L, uint32_t fam_mask, int cls, const
   const int w = cls - 1;
   if (!(fam_mask >> (FAM_DINS + w) & 1) || L.tiles[1 + w] <= 0) return;
   hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, SM, AR, TPB>), dim3(L.tiles[1 + w]), dim3(TPB), 0, L.stream, L.units,
-                     L.tile_off[1 + w], L.n_units, w, D);
+                     L.tile_off[1 + w], L.n_units, L.per_unit[1 + w], w, D);
 }
 
 template <int SM, class AR, int TPB>

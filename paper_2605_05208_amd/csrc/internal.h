@@ -86,6 +86,9 @@ struct UnitDesc {
   // instance
   const int32_t *c, *t, *q, *s, *e, *l;
   const int32_t *nbr, *nbr_len;
+  // locality layout (null when off): c and t reordered so that nearby nodes have nearby
+  // indices (cl[pi[a] * n + pi[b]] = c(a, b)), and the customers in that order
+  const int32_t *cl, *tl, *pi, *corder;
   const int4* attr;  // per node {q, s, e, l}
   int32_t nd, nc, n, theta;
   int32_t Q, NV, Dmax, w_tw, w_load, w_dur;
@@ -182,10 +185,13 @@ __device__ __forceinline__ int32_t seg_tw(const SegNT&) { return 0; }
 __device__ __forceinline__ int32_t seg_tw(const SegTW& s) { return s.TW; }
 
 __device__ __forceinline__ int32_t arc_c(const UnitDesc& U, int a, int b) {
+  if (U.pi) return U.cl[(int64_t)U.pi[a] * U.n + U.pi[b]];
   return U.c[(int64_t)a * U.n + b];
 }
 __device__ __forceinline__ int32_t arc_t(const UnitDesc& U, int a, int b) {
-  return U.t_is_c ? U.c[(int64_t)a * U.n + b] : U.t[(int64_t)a * U.n + b];
+  if (U.t_is_c) return arc_c(U, a, b);
+  if (U.pi) return U.tl[(int64_t)U.pi[a] * U.n + U.pi[b]];
+  return U.t[(int64_t)a * U.n + b];
 }
 
 // Penalised cost of a complete route from its total segment (fixed-weight Eq. A.1 terms).

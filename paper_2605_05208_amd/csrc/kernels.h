@@ -25,6 +25,7 @@ struct LaunchCtx {
   // item classes: 0 pairs, 1 depot-insert, 2 depot-replace, 3 route slots, 4 one block per unit
   const int32_t* tile_off[4];  // device arrays [n_units + 1]
   int tiles[4];
+  int per_unit[4];             // tiles of each unit when all units have the same count, else 0
   int32_t* active_count;       // device int
 };
 
@@ -101,6 +102,10 @@ void launch_inst_stats_final(hipStream_t s, const int64_t* partial, int nblocks,
 // Packs q, s, e, l into one int4 per node.
 void launch_node_attr(hipStream_t s, const int32_t* q, const int32_t* sv, const int32_t* e, const int32_t* l, int n,
                       int4* attr);
+// Locality layout of an instance: landmarks (lm[6]), node keys, rank pi[x], its inverse,
+// customers in layout order, and the reordered copies of c (and of t when tl != null).
+void launch_layout(hipStream_t s, const int32_t* c, const int32_t* t, int n, int nd, int64_t* lm, uint64_t* keys,
+                   int32_t* pi, int32_t* inv, int32_t* corder, int32_t* cl, int32_t* tl);
 // Sum of c(u, first list entry) over customers with a list, and their count (out[0..1]).
 void launch_nn_sum(hipStream_t s, const int32_t* c, const int32_t* nbr, const int32_t* nbr_len, int nd, int nc,
                    int theta, int64_t* out);

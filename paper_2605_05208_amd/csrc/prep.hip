@@ -10,6 +10,8 @@
 //   compared exactly as eta*den with Gamma = num/den; ties go to the lower id.
 //   One 256-thread block per customer streams the row in chunks of 256 and
 //   merges each chunk into a running sorted list with an LDS bitonic sort.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace mdvrp {
@@ -232,6 +234,142 @@ __global__ __launch_bounds__(1024) void k_nn_sum(const int32_t* __restrict__ c, 
 void launch_nn_sum(hipStream_t s, const int32_t* c, const int32_t* nbr, const int32_t* nbr_len, int nd, int nc,
                    int theta, int64_t* out) {
   hipLaunchKernelGGL(k_nn_sum, dim3(1), dim3(1024), 0, s, c, nbr, nbr_len, nd, nc, theta, out);
+}
+
+}  // namespace mdvrp
+
+namespace mdvrp {
+
+// ---------------------------------------------------------------------------- locality layout
+//
+// Evaluations read c(x, y) for nodes x, y that are close to each other (a customer, its
+// route neighbours and its granular list). In the caller's numbering such reads land
+// on unrelated cache lines of a large matrix. A copy of c (and t) in an order that
+// keeps nearby nodes at nearby indices turns them into reads of a narrow band, shared
+// by the anchors of one tile. The order is derived from c alone: three far-apart
+// landmarks give each node three distances, whose interleaved (Morton) code is sorted.
+
+constexpr int kLayoutBlock = 1024;
+
+// argmax over x of f(x), ties to the lower x; one block.
+template <class F>
+__device__ int block_argmax(int n, F f, int64_t* best_val) {
+  __shared__ int64_t sv[kLayoutBlock / 64];
+  __shared__ int si[kLayoutBlock / 64];
+  int64_t bv = -1;
+  int bi = INT32_MAX;
+  for (int x = threadIdx.x; x < n; x += kLayoutBlock) {
+    const int64_t v = f(x);
+    if (v > bv || (v == bv && x < bi)) { bv = v; bi = x; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t v2 = __shfl_xor(bv, off);
+    const int i2 = __shfl_xor(bi, off);
+    if (v2 > bv || (v2 == bv && i2 < bi)) { bv = v2; bi = i2; }
+  }
+  __syncthreads();
+  if (lane_id() == 0) { sv[threadIdx.x >> 6] = bv; si[threadIdx.x >> 6] = bi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kLayoutBlock / 64; ++w)
+      if (sv[w] > sv[0] || (sv[w] == sv[0] && si[w] < si[0])) { sv[0] = sv[w]; si[0] = si[w]; }
+  }
+  __syncthreads();
+  if (best_val) *best_val = sv[0];
+  return si[0];
+}
+
+// out: landmarks A, B, C and the largest distance from each.
+__global__ __launch_bounds__(kLayoutBlock) void k_landmarks(const int32_t* __restrict__ c, int n, int64_t* out) {
+  const int64_t N = n;
+  int64_t mA, mB, mC;
+  const int A = block_argmax(n, [&](int x) -> int64_t { return c[x]; }, nullptr);  // farthest from node 0
+  const int B = block_argmax(n, [&](int x) -> int64_t { return c[A * N + x]; }, &mA);
+  const int C = block_argmax(
+      n, [&](int x) -> int64_t { return imin(c[A * N + x], c[B * N + x]); }, nullptr);
+  block_argmax(n, [&](int x) -> int64_t { return c[B * N + x]; }, &mB);
+  block_argmax(n, [&](int x) -> int64_t { return c[C * N + x]; }, &mC);
+  if (threadIdx.x == 0) {
+    out[0] = A; out[1] = B; out[2] = C;
+    out[3] = mA > 0 ? mA : 1; out[4] = mB > 0 ? mB : 1; out[5] = mC > 0 ? mC : 1;
+  }
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// key[x] = Morton code of the node's three landmark distances (10 bits each) << 16 | x.
+__global__ void k_layout_keys(const int32_t* __restrict__ c, int n, const int64_t* __restrict__ lm,
+                              uint64_t* __restrict__ key) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const int64_t N = n;
+  uint32_t q[3];
+  for (int j = 0; j < 3; ++j) q[j] = (uint32_t)((int64_t)c[lm[j] * N + x] * 1023 / lm[3 + j]);
+  const uint32_t m = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+  key[x] = ((uint64_t)m << 16) | (uint32_t)x;
+}
+
+// pi[x] = rank of key[x] (keys are distinct); inv[pi[x]] = x.
+__global__ __launch_bounds__(256) void k_layout_rank(const uint64_t* __restrict__ key, int n, int32_t* __restrict__ pi,
+                                                     int32_t* __restrict__ inv) {
+  __shared__ uint64_t sk[256];
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const uint64_t kx = x < n ? key[x] : ~0ull;
+  int rank = 0;
+  for (int base = 0; base < n; base += 256) {
+    __syncthreads();
+    sk[threadIdx.x] = base + threadIdx.x < n ? key[base + threadIdx.x] : ~0ull;
+    __syncthreads();
+    const int m = imin(256, n - base);
+    for (int j = 0; j < m; ++j) rank += sk[j] < kx;
+  }
+  if (x < n) {
+    pi[x] = rank;
+    inv[rank] = x;
+  }
+}
+
+// dst[r][s] = src[inv[r]][inv[s]]: rows written contiguously.
+__global__ void k_layout_permute(const int32_t* __restrict__ src, int n, const int32_t* __restrict__ inv,
+                                 int32_t* __restrict__ dst) {
+  const int r = blockIdx.y;
+  const int64_t N = n;
+  const int32_t* row = src + inv[r] * N;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) dst[r * N + s] = row[inv[s]];
+}
+
+// corder[k] = customer index (node - nd) of the k-th customer in layout order. One block.
+__global__ __launch_bounds__(kLayoutBlock) void k_layout_customers(const int32_t* __restrict__ inv, int n, int nd,
+                                                                   int32_t* __restrict__ corder) {
+  __shared__ int sh[2 * (kLayoutBlock / 64) + 1];
+  int carry = 0;
+  for (int base = 0; base < n; base += kLayoutBlock) {
+    const int r = base + threadIdx.x;
+    const int x = r < n ? inv[r] : -1;
+    const int is_c = x >= nd ? 1 : 0;
+    int tot;
+    const int ex = block_scan_excl<kLayoutBlock>(is_c, sh, &tot);
+    if (is_c) corder[carry + ex] = x - nd;
+    carry += tot;
+  }
+}
+
+void launch_layout(hipStream_t s, const int32_t* c, const int32_t* t, int n, int nd, int64_t* lm, uint64_t* keys,
+                   int32_t* pi, int32_t* inv, int32_t* corder, int32_t* cl, int32_t* tl) {
+  hipLaunchKernelGGL(k_landmarks, dim3(1), dim3(kLayoutBlock), 0, s, c, n, lm);
+  hipLaunchKernelGGL(k_layout_keys, dim3((n + 255) / 256), dim3(256), 0, s, c, n, (const int64_t*)lm, keys);
+  hipLaunchKernelGGL(k_layout_rank, dim3((n + 255) / 256), dim3(256), 0, s, (const uint64_t*)keys, n, pi, inv);
+  const dim3 grid((unsigned)std::min(8, (n + 255) / 256), (unsigned)n);
+  hipLaunchKernelGGL(k_layout_permute, grid, dim3(256), 0, s, c, n, (const int32_t*)inv, cl);
+  if (tl) hipLaunchKernelGGL(k_layout_permute, grid, dim3(256), 0, s, t, n, (const int32_t*)inv, tl);
+  hipLaunchKernelGGL(k_layout_customers, dim3(1), dim3(kLayoutBlock), 0, s, (const int32_t*)inv, n, nd, corder);
 }
 
 }  // namespace mdvrp

@@ -22,6 +22,7 @@ EVAL_DENSE, EVAL_FILTERED = 1, 2
 LS_PASSES, LS_UNION = 0, 1
 FILTER_NONE, FILTER_LISTS, FILTER_MLP = 0, 1, 2
 RESCORE_STEP, RESCORE_PASS = 0, 1
+LAYOUT_AUTO, LAYOUT_GIVEN, LAYOUT_ORDERED = 0, 1, 2
 MLP_PARAMS = 74497
 PAIR_FAMILIES = FAM_RELOCATE | FAM_SWAP | FAM_2OPT_STAR | FAM_2OPT
 
@@ -38,7 +39,8 @@ class InstanceDesc(C.Structure):
                 ("e", C.c_void_p), ("l", C.c_void_p),
                 ("Q", C.c_int32), ("NV", C.c_int32), ("Dmax", C.c_int32),
                 ("open_routes", C.c_int32), ("has_tw", C.c_int32), ("theta", C.c_int32),
-                ("w_tw", C.c_int32), ("w_load", C.c_int32), ("w_dur", C.c_int32), ("w_depot", C.c_int32)]
+                ("w_tw", C.c_int32), ("w_load", C.c_int32), ("w_dur", C.c_int32), ("w_depot", C.c_int32),
+                ("layout", C.c_int32)]
 
 
 class LsOptions(C.Structure):
@@ -175,7 +177,7 @@ def desc_from_host(inst) -> InstanceDesc:
     keep = [np.ascontiguousarray(x, dtype=np.int32) for x in (inst.c, inst.t, inst.q, inst.s, inst.e, inst.l)]
     d = InstanceDesc(inst.n_depots, inst.n_customers, *[k.ctypes.data for k in keep],
                      inst.Q, inst.NV, inst.Dmax, inst.open_routes, inst.has_tw, inst.theta,
-                     inst.w_tw, inst.w_load, inst.w_dur, inst.w_depot)
+                     inst.w_tw, inst.w_load, inst.w_dur, inst.w_depot, LAYOUT_AUTO)
     d._keep = keep
     return d
 
@@ -183,16 +185,17 @@ def desc_from_host(inst) -> InstanceDesc:
 class Instance:
     """Device-resident instance (c, t, node arrays) plus its preprocessing."""
 
-    def __init__(self, inst):
+    def __init__(self, inst, layout=None):
         torch = _torch()
         self.inst = inst
+        layout = LAYOUT_AUTO if layout is None else layout
         self.c = _dev_i32(inst.c)
         self.t = self.c if inst.t is inst.c else _dev_i32(inst.t)
         self.q, self.s, self.e, self.l = (_dev_i32(x) for x in (inst.q, inst.s, inst.e, inst.l))
         self.desc = InstanceDesc(inst.n_depots, inst.n_customers, self.c.data_ptr(), self.t.data_ptr(),
                                  self.q.data_ptr(), self.s.data_ptr(), self.e.data_ptr(), self.l.data_ptr(),
                                  inst.Q, inst.NV, inst.Dmax, inst.open_routes, inst.has_tw, inst.theta,
-                                 inst.w_tw, inst.w_load, inst.w_dur, inst.w_depot)
+                                 inst.w_tw, inst.w_load, inst.w_dur, inst.w_depot, layout)
         nbytes = C.c_size_t(0)
         check(lib().mdvrp_instance_workspace_query(C.byref(self.desc), C.byref(nbytes)))
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")

@@ -163,3 +163,32 @@ def test_autotune_on_config2_keeps_results_and_counters():
     assert np.array_equal(B.state()[:, 1], before), "autotuning changed the evaluation counters"
     assert _ls_fingerprint(B, flat, seed=1, poll_every=4) == ref
     assert _ls_fingerprint(B, flat, seed=1, poll_every=4, graph=True) == ref
+
+
+# ----------------------------------------------------------------------------- matrix layout
+
+@pytest.mark.parametrize("which", ["tiny_nt", "tiny_tw_open", "config2"])
+def test_ordered_layout_gives_identical_results(which):
+    """The locality-ordered copy of the matrices changes where the kernels read, never what."""
+    if which == "config2":
+        insts = [gen.config2()]
+        groups = [[gen.start_solution(insts[0], insts[0].seed * 1000 + j) for j in range(4)]]
+    else:
+        tw, o = (0, 0) if which == "tiny_nt" else (1, 1)
+        insts = [gen.tiny(74_000 + k, has_tw=tw, open_routes=o, nc=30 + 11 * k) for k in range(3)]
+        groups = [[gen.start_solution(I, I.seed * 1000 + j) for j in range(2)] for I in insts]
+    flat = [s for g in groups for s in g]
+    unit_inst = [k for k, g in enumerate(groups) for _ in g]
+    res = {}
+    for layout in (mdvrp.LAYOUT_GIVEN, mdvrp.LAYOUT_ORDERED):
+        dev = [mdvrp.Instance(I, layout=layout) for I in insts]
+        B = mdvrp.Batch(dev, unit_inst)
+        B.load(flat)
+        cap = sum(I.n_customers * I.theta * 14 + 2 * I.n_customers * I.n_depots for I in insts) * 2 + 1024
+        d = B.eval_neighbourhood(ALL_FAMILIES, dense_cap=cap)
+        d = d[np.lexsort((d["id"], d["unit"]))]
+        res[layout] = (d, _ls_fingerprint(B, flat, seed=4), B.features())
+    (d0, f0, x0), (d1, f1, x1) = res[mdvrp.LAYOUT_GIVEN], res[mdvrp.LAYOUT_ORDERED]
+    assert np.array_equal(d0["id"], d1["id"]) and np.array_equal(d0["dF"], d1["dF"])
+    assert f0 == f1
+    assert np.array_equal(x0, x1)
