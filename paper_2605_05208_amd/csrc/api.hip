@@ -116,6 +116,10 @@ struct mdvrp_batch {
   int n_cust = 0;                   // sum over units of n_customers
   int kc = 0;                       // filtered list length (0 = no filter attached)
   int32_t* d_cust_off = nullptr;    // [n_units + 1] customer offsets (filter workspace)
+  int32_t* d_tile_off_f = nullptr;  // [n_units + 1] filtered pair tiles (filter workspace)
+  std::vector<int32_t> h_tile_off_f;
+  int32_t* d_tile_off_r = nullptr;  // [n_units + 1] Depot-Replace compact grid (batch workspace)
+  std::vector<int32_t> h_tile_off_r;
   FilterQueue stale{};              // stale-customer queue of the re-ranking (filter workspace)
   // captured passes of the local search, keyed by everything the launch sequence depends on
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
@@ -153,6 +157,20 @@ struct mdvrp_batch {
       L.per_unit[k] = per;
     }
     L.active_count = d_active;
+    auto per = [&](const std::vector<int32_t>& off) {
+      if (off.size() != (size_t)n_units + 1 || n_units < 2 || !layout_all) return 0;
+      const int p = off[1] - off[0];
+      for (int u = 0; u < n_units; ++u)
+        if (off[u + 1] - off[u] != p) return 0;
+      return p;
+    };
+    L.tile_off_f = d_tile_off_f;
+    L.tiles_f = h_tile_off_f.empty() ? 0 : h_tile_off_f.back();
+    L.per_unit_f = per(h_tile_off_f);
+    L.tile_off_r = d_tile_off_r;
+    L.tiles_r = h_tile_off_r.empty() ? 0 : h_tile_off_r.back();
+    L.per_unit_r = per(h_tile_off_r);
+    L.compact = 0;
     return L;
   }
 };
@@ -488,6 +506,7 @@ void carve_batch(Carve& cv, const mdvrp_instance* const* insts, const int32_t* u
   UnitDesc* du = cv.take<UnitDesc>(n_units);
   int32_t* to[4];
   for (int k = 0; k < 4; ++k) to[k] = cv.take<int32_t>(n_units + 1);
+  int32_t* tor = cv.take<int32_t>(n_units + 1);
   int32_t* act = cv.take<int32_t>(1);
   int32_t* nb = cv.take<int32_t>(n_units);
   int32_t* rb = cv.take<int32_t>(n_units);
@@ -495,6 +514,7 @@ void carve_batch(Carve& cv, const mdvrp_instance* const* insts, const int32_t* u
   if (B) {
     B->d_units = du;
     for (int k = 0; k < 4; ++k) B->d_tile_off[k] = to[k];
+    B->d_tile_off_r = tor;
     B->d_active = act;
     B->d_node_base = nb;
     B->d_route_base = rb;
@@ -535,6 +555,7 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
   Carve cv(ws);
   carve_batch(cv, insts, unit_inst, n_units, B);
   for (int k = 0; k < 4; ++k) B->h_tile_off[k].assign(1, 0);
+  B->h_tile_off_r.assign(1, 0);
   std::vector<int32_t> nbase(n_units), rbase(n_units);
   int32_t nacc = 0, racc = 0;
   for (int k = 0; k < n_units; ++k) {
@@ -561,6 +582,10 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
     B->n_cust += z.nc;
     for (int f = 0; f < 4; ++f) u.frcp[f] = I->frcp[f];
     for (int c = 0; c < 4; ++c) B->h_tile_off[c].push_back(B->h_tile_off[c].back() + z.tiles[c]);
+    // Depot-Replace blocks for the routes a solution is expected to hold (a block loops
+    // over more tiles when there are more routes)
+    const int64_t rt = (I->route_est * z.nd + kTileItems - 1) / kTileItems;
+    B->h_tile_off_r.push_back(B->h_tile_off_r.back() + (int32_t)std::max<int64_t>(1, std::min<int64_t>(rt, z.tiles[2])));
     nbase[k] = nacc;
     rbase[k] = racc;
     nacc += z.nc;
@@ -570,6 +595,9 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
   hipError_t he = hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * n_units, hipMemcpyHostToDevice, s);
   for (int c = 0; c < 4 && he == hipSuccess; ++c)
     he = hipMemcpyAsync(B->d_tile_off[c], B->h_tile_off[c].data(), sizeof(int32_t) * (n_units + 1),
+                        hipMemcpyHostToDevice, s);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(B->d_tile_off_r, B->h_tile_off_r.data(), sizeof(int32_t) * (n_units + 1),
                         hipMemcpyHostToDevice, s);
   if (he == hipSuccess) {
     int dev = 0, khz = 0;
@@ -791,7 +819,8 @@ extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, u
   if (flags & ~(MDVRP_EVAL_DENSE | MDVRP_EVAL_FILTERED)) return fail(MDVRP_EINVAL, "unknown flags");
   if ((flags & MDVRP_EVAL_FILTERED) && B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
   static_assert(sizeof(mdvrp_dense_rec) == sizeof(DenseRec), "dense record layout");
-  const LaunchCtx L = B->ctx(stream);
+  LaunchCtx L = B->ctx(stream);
+  L.compact = (flags & MDVRP_EVAL_FILTERED) ? 1 : 0;
   step_begin(L, (flags & MDVRP_EVAL_FILTERED) ? 1 : 0, 0);
   DenseOut D{(DenseRec*)dense, dense_count, dense_cap};
   const uint32_t cls = eval_classes(L, fam);
@@ -925,7 +954,8 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     HIP_TRY(hipStreamWaitEvent(B->own, B->ev_in, 0));
     st = B->own;
   }
-  const LaunchCtx L = B->ctx(st);
+  LaunchCtx L = B->ctx(st);
+  L.compact = o->filter != MDVRP_FILTER_NONE;
   step_begin(L, o->filter != MDVRP_FILTER_NONE ? 1 : 0, o->filter == MDVRP_FILTER_MLP ? 1 : 0);
   int32_t active = B->n_units;
   for (int64_t p = 0; o->max_passes == 0 || p < o->max_passes; ++p) {
@@ -1244,9 +1274,11 @@ mdvrp_status check_filter_k(const mdvrp_batch* B, int32_t k) {
 }
 
 void carve_filter(Carve& cv, const mdvrp_batch* B, int32_t k, std::vector<int32_t*>* lists, int32_t** cust_off,
-                  FilterQueue* stale) {
+                  FilterQueue* stale, int32_t** tile_off_f = nullptr) {
   int32_t* co = cv.take<int32_t>(B->n_units + 1);
   if (cust_off) *cust_off = co;
+  int32_t* tf = cv.take<int32_t>(B->n_units + 1);
+  if (tile_off_f) *tile_off_f = tf;
   FilterQueue q{};
   q.lcache = cv.take<float>(B->n_anchors);
   q.queue = cv.take<int32_t>(B->n_anchors);
@@ -1285,9 +1317,10 @@ extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws,
   Carve cv(ws);
   std::vector<int32_t*> lists;
   int32_t* co = nullptr;
+  int32_t* tf = nullptr;
   FilterQueue fq{};
-  carve_filter(cv, B, k, &lists, &co, &fq);
-  std::vector<int32_t> h_co(B->n_units + 1, 0);
+  carve_filter(cv, B, k, &lists, &co, &fq, &tf);
+  std::vector<int32_t> h_co(B->n_units + 1, 0), h_tf(B->n_units + 1, 0);
   std::vector<int64_t> h_ao(B->n_units + 1, 0);
   for (int u = 0; u < B->n_units; ++u) h_ao[u + 1] = h_ao[u] + (int64_t)B->h_units[u].nc * B->h_units[u].theta;
   for (int u = 0; u < B->n_units; ++u) {
@@ -1296,9 +1329,11 @@ extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws,
     U.kc = k;
     U.ftiles = (int32_t)(((int64_t)U.nc * k + kTileItems - 1) / kTileItems);
     h_co[u + 1] = h_co[u] + U.nc;
+    h_tf[u + 1] = h_tf[u] + U.ftiles;
   }
   hipStream_t s = S(stream);
   HIP_TRY(hipMemcpyAsync(co, h_co.data(), sizeof(int32_t) * (B->n_units + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(tf, h_tf.data(), sizeof(int32_t) * (B->n_units + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync((void*)fq.anchor_off, h_ao.data(), sizeof(int64_t) * (B->n_units + 1), hipMemcpyHostToDevice,
                          s));
   HIP_TRY(hipMemsetAsync(fq.cmark, 0, B->n_cust, s));
@@ -1306,6 +1341,8 @@ extern "C" mdvrp_status mdvrp_filter_attach(mdvrp_batch* B, int32_t k, void* ws,
   B->drop_graphs();  // captured passes refer to the previous filter state
   B->kc = k;
   B->d_cust_off = co;
+  B->d_tile_off_f = tf;
+  B->h_tile_off_f = h_tf;
   B->stale = fq;
   // start from the heuristic lists so that a filtered evaluation is always defined
   launch_eta_lists(B->ctx(stream), co, B->n_cust);

@@ -11,6 +11,8 @@
 //     3.2.5), reduced per resource set inside the item, appended to the
 //     unit's candidate list with one atomic per wavefront;
 //   * the number of evaluated moves.
+#include <type_traits>
+
 #include "eval_common.h"
 #include "kernels.h"
 
@@ -205,26 +207,14 @@ __device__ __forceinline__ void tile_of_block(const int32_t* __restrict__ tile_o
   }
 }
 
-// KM != 0 fixes the kind mask at compile time (one lean kernel per family);
-// KM == 0 takes it from the argument. A tile is kTileSize items; a block of TPB
-// threads covers it with kTileSize / TPB items per thread (the tile shape the
-// autotuner picks; results do not depend on it).
-template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
-__global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__ units,
-                                                   const int32_t* __restrict__ tile_off, int n_units, int per_unit,
-                                                   uint32_t kind_arg, DenseOut dense) {
+// One tile of pair anchors of unit ui (local tile lt of its item space: the filtered
+// lists when the unit is in filtered mode, else the granular lists).
+template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
+__device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bool filt, uint32_t kind_mask,
+                                           const DenseOut& dense) {
   constexpr int IPT = kTileSize / TPB;
-  const uint32_t kind_mask = KM ? KM : kind_arg;
   __shared__ int s_q[kTileSize];
   __shared__ int s_nq;
-  int ui, lt;
-  tile_of_block(tile_off, n_units, per_unit, ui, lt);
-  const UnitDesc& U = units[ui];
-  if (!U.ctl->active) return;
-  // Filtered units evaluate their candidate lists (kc entries per customer);
-  // the tiles beyond that smaller item space have nothing to do.
-  const bool filt = U.ctl->fmode == 1;
-  if (filt && lt >= U.ftiles) return;
   const int th = filt ? U.kc : U.theta;
   const int32_t* lists = filt ? U.fcand : U.nbr;
   const int cur = U.ctl->cur;
@@ -289,21 +279,63 @@ __global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__
   item_flush<TPB>(U, U.tile_base[0] + lt, o);
 }
 
-// --------------------------------------------------------------------------- depot operators
 
-template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
-__global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__ units,
+// KM != 0 fixes the kind mask at compile time (one lean kernel per family);
+// KM == 0 takes it from the argument. A tile is kTileSize items; a block of TPB
+// threads covers it with kTileSize / TPB items per thread (the tile shape the
+// autotuner picks; results do not depend on it). One block per tile of the
+// granular lists.
+template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
+__global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__ units,
                                                    const int32_t* __restrict__ tile_off, int n_units, int per_unit,
-                                                   int which, DenseOut dense) {
-  constexpr int IPT = kTileSize / TPB;
+                                                   uint32_t kind_arg, DenseOut dense) {
+  const uint32_t kind_mask = KM ? KM : kind_arg;
   int ui, lt;
   tile_of_block(tile_off, n_units, per_unit, ui, lt);
   const UnitDesc& U = units[ui];
   if (!U.ctl->active) return;
-  // Depot-Replace items cover the alive routes only; the tiles beyond them have
-  // nothing to do (the selection reads as many tiles as the items need).
-  const int n_drep = which == 1 ? U.ctl->n_slots_alive * U.nd : 0;
-  if (which == 1 && lt * kTileSize >= n_drep) return;
+  // A unit in filtered mode has ftiles tiles: they are spread evenly over its full tile
+  // range (every XCD gets its share); the other blocks have nothing to do.
+  const bool filt = U.ctl->fmode == 1;
+  if (filt) {
+    const int64_t full = U.tile_base[1] - U.tile_base[0];
+    const int f = (int)((int64_t)lt * U.ftiles / full);
+    if (lt > 0 && f == (int)((int64_t)(lt - 1) * U.ftiles / full)) return;
+    lt = f;
+  }
+  pairs_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, filt, kind_mask, dense);
+}
+
+// The same evaluation on a compact grid of as many blocks per unit as its filtered
+// lists have tiles (searches with a filter): a block of a unit in filtered mode
+// takes one tile, a block of a unit evaluating its full lists loops over every
+// blocks-per-unit-th tile.
+template <class SEG, bool TW, bool OPEN, uint32_t KM, int TPB>
+__global__ __launch_bounds__(TPB) void k_eval_pairs_compact(const UnitDesc* __restrict__ units,
+                                                           const int32_t* __restrict__ grid_off, int n_units,
+                                                           int per_unit, uint32_t kind_arg) {
+  const uint32_t kind_mask = KM ? KM : kind_arg;
+  int ui, g;
+  tile_of_block(grid_off, n_units, per_unit, ui, g);
+  const UnitDesc& U = units[ui];
+  if (!U.ctl->active) return;
+  const bool filt = U.ctl->fmode == 1;
+  const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
+  const int T = filt ? U.ftiles : U.tile_base[1] - U.tile_base[0];
+  for (int lt = g; lt < T; lt += G) {
+    __syncthreads();
+    pairs_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, filt, kind_mask, DenseOut{});
+  }
+}
+
+// --------------------------------------------------------------------------- depot operators
+
+// One tile of depot-operator items of unit ui: (customer, depot) pairs for
+// Depot-Insert (which = 0), (alive route, depot) pairs for Depot-Replace (which = 1).
+template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
+__device__ __forceinline__ void depot_tile(const UnitDesc& U, int ui, int lt, int which, int n_drep,
+                                           const DenseOut& dense) {
+  constexpr int IPT = kTileSize / TPB;
   const int cur = U.ctl->cur;
   const SEG* fw = (const SEG*)U.fw[cur];
   const SEG* bw = (const SEG*)U.bw[cur];
@@ -359,6 +391,41 @@ __global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__
   item_flush<TPB>(U, U.tile_base[1 + which] + lt, o);
 }
 
+
+// One block per tile of the class's full item space.
+template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
+__global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__ units,
+                                                   const int32_t* __restrict__ tile_off, int n_units, int per_unit,
+                                                   int which, DenseOut dense) {
+  int ui, lt;
+  tile_of_block(tile_off, n_units, per_unit, ui, lt);
+  const UnitDesc& U = units[ui];
+  if (!U.ctl->active) return;
+  // Depot-Replace items cover the alive routes only; the tiles beyond them have
+  // nothing to do (the selection reads as many tiles as the items need).
+  const int n_drep = which == 1 ? U.ctl->n_slots_alive * U.nd : 0;
+  if (which == 1 && lt * kTileSize >= n_drep) return;
+  depot_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, which, n_drep, dense);
+}
+
+// Depot-Replace on a compact grid sized for the routes a solution is expected to hold;
+// each block loops over every blocks-per-unit-th tile of the alive routes.
+template <class SEG, bool TW, bool OPEN, int TPB>
+__global__ __launch_bounds__(TPB) void k_eval_drep_compact(const UnitDesc* __restrict__ units,
+                                                          const int32_t* __restrict__ grid_off, int n_units,
+                                                          int per_unit) {
+  int ui, g;
+  tile_of_block(grid_off, n_units, per_unit, ui, g);
+  const UnitDesc& U = units[ui];
+  if (!U.ctl->active) return;
+  const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
+  const int n_drep = U.ctl->n_slots_alive * U.nd;
+  for (int lt = g; lt * kTileSize < n_drep; lt += G) {
+    __syncthreads();
+    depot_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, 1, n_drep, DenseOut{});
+  }
+}
+
 // --------------------------------------------------------------------------- launchers
 
 static uint32_t pair_kinds(uint32_t fam_mask, int has_tw) {
@@ -385,6 +452,13 @@ constexpr uint32_t k2optKinds = 1u << TWOOPT;
 
 template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
 static void launch_pairs(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) {
+  if constexpr (SM == 0 && std::is_same<AR, ArcPlain>::value) {
+    if (L.compact && L.tiles_f > 0) {
+      hipLaunchKernelGGL((k_eval_pairs_compact<SEG, TW, OPEN, KM, TPB>), dim3(L.tiles_f), dim3(TPB), 0, L.stream,
+                         L.units, L.tile_off_f, L.n_units, L.per_unit_f, kinds);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, SM, AR, KM, TPB>), dim3(L.tiles[0]), dim3(TPB), 0, L.stream, L.units,
                      L.tile_off[0], L.n_units, L.per_unit[0], kinds, D);
 }
@@ -403,6 +477,13 @@ static void launch_class_t(const LaunchCtx& L, uint32_t fam_mask, int cls, const
   }
   const int w = cls - 1;
   if (!(fam_mask >> (FAM_DINS + w) & 1) || L.tiles[1 + w] <= 0) return;
+  if constexpr (SM == 0 && std::is_same<AR, ArcPlain>::value) {
+    if (w == 1 && L.tiles_r > 0) {
+      hipLaunchKernelGGL((k_eval_drep_compact<SEG, TW, OPEN, TPB>), dim3(L.tiles_r), dim3(TPB), 0, L.stream, L.units,
+                         L.tile_off_r, L.n_units, L.per_unit_r);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, SM, AR, TPB>), dim3(L.tiles[1 + w]), dim3(TPB), 0, L.stream, L.units,
                      L.tile_off[1 + w], L.n_units, L.per_unit[1 + w], w, D);
 }

@@ -26,6 +26,14 @@ struct LaunchCtx {
   const int32_t* tile_off[4];  // device arrays [n_units + 1]
   int tiles[4];
   int per_unit[4];             // tiles of each unit when all units have the same count, else 0
+  // compact grids: pair evaluation of a search with a filter (blocks per unit = filtered
+  // tiles; used when compact is set), and Depot-Replace (blocks per unit for the
+  // expected routes); tiles_* = 0 when absent
+  const int32_t* tile_off_f;
+  int tiles_f, per_unit_f;
+  const int32_t* tile_off_r;
+  int tiles_r, per_unit_r;
+  int compact;
   int32_t* active_count;       // device int
 };
 
