@@ -97,7 +97,7 @@ typedef struct {
  * pointers taken as host pointers; c and t are not read). Pure CPU; usable
  * without a GPU. Checks: n_depots >= 1, n_customers >= 1, N <= 65535,
  * Q > 0, NV >= 0, 1 <= theta <= 128, weights >= 0, q >= 0, s >= 0, e <= l,
- * depots q = s = 0. */
+ * depots q = s = 0 (EINVAL); total demand < 2^30 (ERANGE). */
 mdvrp_status mdvrp_validate_instance_host(const mdvrp_instance_desc* desc);
 
 /* Device workspace needed by mdvrp_instance_create. */
@@ -241,7 +241,11 @@ typedef struct {
   int32_t mode;        /* MDVRP_LS_PASSES or MDVRP_LS_UNION */
   int32_t leader_only; /* 1 = single-move steps (the paper's ETGA-S) */
   int32_t max_passes;  /* search depth delta; 0 = until a local optimum */
-  int32_t poll_every;  /* passes between host convergence checks (>= 1) */
+  int32_t poll_every;  /* passes between host convergence checks (>= 1). The host reads the
+                          count of active units of one interval while the next interval
+                          runs (pinned host memory owned by the batch), so up to
+                          2 * poll_every - 1 passes may follow the last unit's convergence;
+                          they change nothing (inactive units skip every kernel) */
   uint64_t seed;       /* family order of pass p: Fisher-Yates with SplitMix64(seed ^ p) */
   int32_t filter;      /* MDVRP_FILTER_*; a filter needs mdvrp_filter_attach first */
   int32_t rescore;     /* when MDVRP_FILTER_MLP re-ranks stale lists: MDVRP_RESCORE_STEP, or
@@ -287,8 +291,8 @@ mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* batch, const mdvrp_ls_op
 #define MDVRP_PROF_EVAL_PAIRS 0
 #define MDVRP_PROF_EVAL_DEPOT_INSERT 1
 #define MDVRP_PROF_EVAL_DEPOT_REPLACE 2
-#define MDVRP_PROF_SELECT 3
-#define MDVRP_PROF_APPLY 4
+#define MDVRP_PROF_SELECT 3 /* in the local search: selection and apply, one fused kernel per step */
+#define MDVRP_PROF_APPLY 4  /* mdvrp_apply_moves */
 #define MDVRP_PROF_FILTER_SCORE 5
 
 /* Turn per-launch timing on (class_mask != 0) or off for a batch. Every launch
@@ -298,7 +302,14 @@ mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* batch, const mdvrp_ls_op
  * they are folded into totals. Resets the totals. */
 mdvrp_status mdvrp_profile_enable(mdvrp_batch* batch, uint32_t class_mask, int32_t max_launches);
 
-/* Per-class totals since enabling: launches[8] and elapsed milliseconds ms[8]
+/* Time only every n-th launch of each class (every >= 1; 1 = all, the default).
+ * Each timed launch adds two event records to the stream, which delay the
+ * next launch by a few microseconds; sampling keeps that cost small while the
+ * sampled launches still give the average duration of the class. Kept across
+ * mdvrp_profile_enable calls. Errors: EINVAL. */
+mdvrp_status mdvrp_profile_sampling(mdvrp_batch* batch, int32_t every);
+
+/* Per-class totals since enabling: launches[8] (timed launches) and elapsed milliseconds ms[8]
  * (HOST arrays, indexed by MDVRP_PROF_*). Waits for pending events. */
 mdvrp_status mdvrp_profile_read(mdvrp_batch* batch, int64_t* launches, double* ms);
 

@@ -90,11 +90,13 @@ struct Profiler {
   std::vector<hipEvent_t> ev;
   std::vector<int> cls;  // kernel class of pending event pair k
   int used = 0;
+  int every = 1;            // time every n-th launch of a class
+  int64_t seen[8] = {0};    // launches of each class since enabling (timed or not)
   int64_t launches[8] = {0};
   double ms[8] = {0};
   void reset() {
     used = 0;
-    for (int k = 0; k < 8; ++k) { launches[k] = 0; ms[k] = 0; }
+    for (int k = 0; k < 8; ++k) { launches[k] = 0; ms[k] = 0; seen[k] = 0; }
   }
 };
 
@@ -125,6 +127,10 @@ struct mdvrp_batch {
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   hipStream_t own = nullptr;        // capture stream used when the caller passes the null stream
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // convergence poll of the search: active-unit counts of two poll intervals in pinned
+  // host memory, each with the event that marks its copy
+  int32_t* h_poll = nullptr;
+  hipEvent_t ev_poll[2] = {nullptr, nullptr};
   double clock_khz = 0;             // device wall-clock rate
   int shape[6] = {0, 0, 0, 0, 0, 0};  // tile shape of each family's evaluation (autotuner)
   // tile shape of an evaluation of fam_mask: the tuned one of a single family, else the default
@@ -237,11 +243,15 @@ static mdvrp_status check_scalars(const mdvrp_instance_desc* d) {
 static mdvrp_status check_node_arrays(const mdvrp_instance_desc* d, const int32_t* q, const int32_t* s,
                                       const int32_t* e, const int32_t* l) {
   const int n = d->n_depots + d->n_customers;
+  int64_t q_total = 0;
   for (int x = 0; x < n; ++x) {
     if (q[x] < 0 || s[x] < 0) return fail(MDVRP_EINVAL, "node %d: negative demand or service", x);
+    q_total += q[x];
     if (e[x] > l[x]) return fail(MDVRP_EINVAL, "node %d: e > l", x);
     if (x < d->n_depots && (q[x] != 0 || s[x] != 0)) return fail(MDVRP_EINVAL, "depot %d: q and s must be 0", x);
   }
+  // route loads (and the load deltas of a move) stay int32-safe
+  if (q_total >= (1ll << 30)) return fail(MDVRP_ERANGE, "total demand %lld >= 2^30", (long long)q_total);
   return MDVRP_OK;
 }
 
@@ -629,6 +639,9 @@ extern "C" void mdvrp_batch_destroy(mdvrp_batch* B) {
   B->drop_graphs();
   if (B->ev_in) (void)hipEventDestroy(B->ev_in);
   if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  for (hipEvent_t e : B->ev_poll)
+    if (e) (void)hipEventDestroy(e);
+  if (B->h_poll) (void)hipHostFree(B->h_poll);
   if (B->own) (void)hipStreamDestroy(B->own);
   delete B;
 }
@@ -665,6 +678,12 @@ static mdvrp_status profile_flush(Profiler& P) {
   return MDVRP_OK;
 }
 
+extern "C" mdvrp_status mdvrp_profile_sampling(mdvrp_batch* B, int32_t every) {
+  if (!B || every < 1) return fail(MDVRP_EINVAL, "bad argument");
+  B->prof.every = every;
+  return MDVRP_OK;
+}
+
 extern "C" mdvrp_status mdvrp_profile_read(mdvrp_batch* B, int64_t* launches, double* ms) {
   if (!B || !launches || !ms) return fail(MDVRP_EINVAL, "null argument");
   mdvrp_status s = profile_flush(B->prof);
@@ -679,6 +698,7 @@ template <class F>
 void timed(mdvrp_batch* B, hipStream_t s, int cls, F&& launch) {
   Profiler& P = B->prof;
   if (!P.on || !(P.mask >> cls & 1)) { launch(); return; }
+  if (P.seen[cls]++ % P.every != 0) { launch(); return; }
   if (P.used * 2 + 2 > (int)P.ev.size()) profile_flush(P);
   if (P.used * 2 + 2 > (int)P.ev.size()) { launch(); return; }
   const int k = P.used++;
@@ -921,8 +941,7 @@ void launch_pass(mdvrp_batch* B, const LaunchCtx& L, const mdvrp_ls_options* o, 
           [&] { launch_rank(L, B->d_cust_off, B->n_cust, o->mlp->d, B->stale, 0); });
     for (int c = 0; c < 3; ++c)
       if (cls >> c & 1) run(c, [&] { launch_eval_class(L, mask, c, nullptr, B->shape_for(mask)); });
-    run(3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0, score ? 1 : 0); });
-    run(4, [&] { launch_rebuild(L); });
+    run(3, [&] { launch_select(L, mask, o->leader_only ? 1 : 0, score ? 1 : 0, /*apply=*/true); });
   }
   launch_pass_end(L);
 }
@@ -957,7 +976,15 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   LaunchCtx L = B->ctx(st);
   L.compact = o->filter != MDVRP_FILTER_NONE;
   step_begin(L, o->filter != MDVRP_FILTER_NONE ? 1 : 0, o->filter == MDVRP_FILTER_MLP ? 1 : 0);
-  int32_t active = B->n_units;
+  if (!B->h_poll) {
+    HIP_TRY(hipHostMalloc((void**)&B->h_poll, 2 * sizeof(int32_t), hipHostMallocDefault));
+    for (hipEvent_t& e : B->ev_poll) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // Pipelined convergence check: at the end of poll interval c the active-unit count is
+  // copied to host slot c % 2; the host then waits for interval c - 1's copy, which the
+  // GPU finished before starting interval c, so the queue never drains. Passes that run
+  // after the last unit converged are no-ops (every kernel skips inactive units).
+  int64_t chunk = 0;
   for (int64_t p = 0; o->max_passes == 0 || p < o->max_passes; ++p) {
     int32_t fam[6];
     const int nf = o->mode == MDVRP_LS_PASSES ? mdvrp_family_order(B->has_tw, o->seed, p, fam) : 1;
@@ -984,9 +1011,14 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     }
     HIP_TRY(hipGetLastError());
     if ((p + 1) % poll == 0) {
-      HIP_TRY(hipMemcpyAsync(&active, B->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      if (active == 0) break;
+      const int slot = (int)(chunk & 1);
+      HIP_TRY(hipMemcpyAsync(&B->h_poll[slot], B->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipEventRecord(B->ev_poll[slot], st));
+      if (chunk > 0) {
+        HIP_TRY(hipEventSynchronize(B->ev_poll[slot ^ 1]));
+        if (B->h_poll[slot ^ 1] == 0) break;
+      }
+      ++chunk;
     }
   }
   HIP_TRY(hipStreamSynchronize(st));

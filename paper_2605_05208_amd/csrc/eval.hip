@@ -229,29 +229,29 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
   __syncthreads();
   const uint32_t intra_kinds = kind_mask & ~(1u << X2);
   const uint32_t inter_kinds = kind_mask & ~(1u << TWOOPT);
-#pragma unroll
+#pragma unroll 1
   for (int r = 0; r < IPT; ++r) {
     // tiles walk the customers in layout order (neighbouring customers share cache lines)
     const int pos = lt * kTileSize + r * TPB + threadIdx.x;
     if (pos < U.nc * th) {
       const int ri = pos / th;
       const int k = pos - ri * th;
-      const int i = U.corder ? U.corder[ri] : ri;
+      const int i = U.corder ? ld(U.corder, ri) : ri;
       const int item = i * th + k;
-      const int v = lists[item];
-      if ((filt || k < U.nbr_len[i]) && v >= 0) {
+      const int v = ld(lists, item);
+      if ((filt || k < ld(U.nbr_len, i)) && v >= 0) {
         const int u = U.nd + i;
-        const int sa = U.rt[u], sb = U.rt[v];
+        const int sa = ld(U.rt, u), sb = ld(U.rt, v);
         if (sa != sb) {
           if (inter_kinds) {
             if constexpr (SM == 2) sk.item = item;
-            const int4 ma = U.r_meta[cur][sa], mb = U.r_meta[cur][sb];
+            const int4 ma = ld(U.r_meta[cur], sa), mb = ld(U.r_meta[cur], sb);
             InterCtx x;
             x.u = u; x.v = v; x.slotA = sa; x.slotB = sb;
             x.LA = ma.y; x.LB = mb.y;
             x.sA = ma.z; x.sB = mb.z;
             x.eA = ma.w; x.eB = mb.w;
-            x.pu = U.pos[u]; x.pv = U.pos[v];
+            x.pu = ld(U.pos, u); x.pv = ld(U.pos, v);
             eval_inter<SEG, TW, OPEN>(U, fw, bw, ma.x, mb.x, x, inter_kinds, ar, sk);
           }
         } else if (intra_kinds) {
@@ -269,10 +269,10 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
     if (e < nq) {
       const int it = s_q[e];
       const int i = it / th;
-      const int u = U.nd + i, v = lists[it];
+      const int u = U.nd + i, v = ld(lists, it);
       if constexpr (SM == 2) sk.item = it;
-      const RouteCtx A = route_ctx(U, cur, U.rt[u]);
-      eval_intra<SEG, TW, OPEN>(U, fw, bw, A, u, v, U.pos[u], U.pos[v], intra_kinds, ar, sk);
+      const RouteCtx A = route_ctx(U, cur, ld(U.rt, u));
+      eval_intra<SEG, TW, OPEN>(U, fw, bw, A, u, v, ld(U.pos, u), ld(U.pos, v), intra_kinds, ar, sk);
     }
     cand_flush(U, o);
   }
@@ -345,7 +345,7 @@ __device__ __forceinline__ void depot_tile(const UnitDesc& U, int ui, int lt, in
   AR ar;
   if constexpr (sizeof(AR) > 1) ar.bits = U.foot;
   MoveEval m;
-#pragma unroll
+#pragma unroll 1
   for (int r = 0; r < IPT; ++r) {
   const int item = lt * kTileSize + r * TPB + threadIdx.x;
   if (which == 0) {
@@ -353,9 +353,9 @@ __device__ __forceinline__ void depot_tile(const UnitDesc& U, int ui, int lt, in
     if (item < U.nc * U.nd) {
       const int ri = item / U.nd;
       const int d = item - ri * U.nd;
-      const int u = U.nd + (U.corder ? U.corder[ri] : ri);
-      const RouteCtx A = route_ctx(U, cur, U.rt[u]);
-      const int pu = U.pos[u];
+      const int u = U.nd + (U.corder ? ld(U.corder, ri) : ri);
+      const RouteCtx A = route_ctx(U, cur, ld(U.rt, u));
+      const int pu = ld(U.pos, u);
       if (pu < A.L) {
         eval_dins<SEG, TW, OPEN>(U, fw, bw, A, pu, d, ar, m);
         take(U, sk, m, make_id(DINS, 0, u, d));
@@ -364,8 +364,8 @@ __device__ __forceinline__ void depot_tile(const UnitDesc& U, int ui, int lt, in
   } else if (item < n_drep) {
     // Depot-Replace: one item per (alive route, depot), the best surviving case.
     const int d = item % U.nd;
-    const RouteCtx A = route_ctx(U, cur, U.slot_list[item / U.nd]);
-    const int u = fw[A.off + 1].node;
+    const RouteCtx A = route_ctx(U, cur, ld(U.slot_list, item / U.nd));
+    const int u = ld(fw, A.off + 1).node;
     bool have = false;
     MoveEval best;
     int bcase = 0;

@@ -15,8 +15,8 @@ __device__ __forceinline__ SEG seg_at(const SEG* a, int64_t i) {
   return a[i];
 }
 
-__device__ __forceinline__ int node_at(const SegNT* fw, int64_t i) { return fw[i].node; }
-__device__ __forceinline__ int node_at(const SegTW* fw, int64_t i) { return fw[i].node; }
+__device__ __forceinline__ int node_at(const SegNT* fw, int64_t i) { return ld(fw, i).node; }
+__device__ __forceinline__ int node_at(const SegTW* fw, int64_t i) { return ld(fw, i).node; }
 
 // Middle range [from, to] of route cx (1 <= from < to <= L) as one segment.
 // Without time windows the prefix sums are invertible; with time windows the
@@ -28,9 +28,9 @@ __device__ __forceinline__ SEG mid_range(const UnitDesc& U, const SEG* fw, const
 template <>
 __device__ __forceinline__ SegNT mid_range<SegNT, false>(const UnitDesc& U, const SegNT* fw, const RouteCtx& cx,
                                                         int from, int to, int rev) {
-  const SegNT a = fw[cx.off + from];
-  const SegNT b = fw[cx.off + to];
-  const SegNT p = fw[cx.off + from - 1];
+  const SegNT a = ld(fw, cx.off + from);
+  const SegNT b = ld(fw, cx.off + to);
+  const SegNT p = ld(fw, cx.off + from - 1);
   SegNT r;
   r.C = b.C - a.C;
   r.Q = b.Q - p.Q;
@@ -43,10 +43,10 @@ template <>
 __device__ __forceinline__ SegTW mid_range<SegTW, true>(const UnitDesc& U, const SegTW* fw, const RouteCtx& cx,
                                                        int from, int to, int rev) {
   (void)rev;  // reversal only exists without time windows
-  SegTW prev = fw[cx.off + from];
+  SegTW prev = ld(fw, cx.off + from);
   SegTW acc = node_seg<SegTW>(U, prev.node);
   for (int k = from + 1; k <= to; ++k) {
-    const SegTW cur = fw[cx.off + k];
+    const SegTW cur = ld(fw, cx.off + k);
     acc = cat(acc, cur.C - prev.C, prev.aux, node_seg<SegTW>(U, cur.node));
     prev = cur;
   }
@@ -79,9 +79,9 @@ __device__ SEG eval_route(const UnitDesc& U, const SEG* fw, const SEG* bw, const
     const RouteCtx& c0 = rc[p0.src];
     if (!p0.rev && p0.from == 1 && start == c0.start) {
       if (np == 1 && p0.to == c0.L && end == c0.end) {
-        return fw[c0.off + (end >= 0 ? c0.L + 1 : c0.L)];
+        return ld(fw, c0.off + (end >= 0 ? c0.L + 1 : c0.L));
       }
-      acc = fw[c0.off + p0.to];
+      acc = ld(fw, c0.off + p0.to);
       last = acc.node;
       k = 1;
     } else {
@@ -97,7 +97,7 @@ __device__ SEG eval_route(const UnitDesc& U, const SEG* fw, const SEG* bw, const
     const int32_t cab = arc_c(U, last, first);
     const int32_t tab = TW ? arc_t(U, last, first) : (U.t_is_c ? cab : arc_t(U, last, first));
     if (k == np - 1 && !p.rev && p.to == cx.L && end == cx.end) {
-      return cat(acc, cab, tab, bw[cx.off + p.from]);
+      return cat(acc, cab, tab, ld(bw, cx.off + p.from));
     }
     if (p.from == p.to) {
       acc = cat(acc, cab, tab, node_seg<SEG>(U, first));
@@ -127,7 +127,6 @@ struct MoveEval {
 template <class SEG, bool TW, class AR = ArcPlain>
 __device__ __forceinline__ void eval_recipe(const UnitDesc& U, const SEG* fw, const SEG* bw, const RouteCtx* rc,
                                             const Recipe& R, MoveEval& o, const AR& ar = AR()) {
-  int64_t dc = 0;
   int32_t dD = 0, dTW = 0, dLX = 0, dDX = 0, dCL = 0;
   int32_t dep[4], dd[4];
   int nd = 0;
@@ -138,8 +137,7 @@ __device__ __forceinline__ void eval_recipe(const UnitDesc& U, const SEG* fw, co
   };
   for (int k = 0; k < R.nold; ++k) {
     const RouteCtx& c = rc[k];
-    const int4 tot = U.r_tot[c.slot];
-    dc -= U.r_cost[c.slot];
+    const int4 tot = ld(U.r_tot, c.slot);
     dD -= tot.x;
     dTW -= tot.w;
     dLX -= imax(tot.y - U.Q, 0);
@@ -151,7 +149,6 @@ __device__ __forceinline__ void eval_recipe(const UnitDesc& U, const SEG* fw, co
     if (R.np[w] == 0) continue;  // an emptied route is deleted
     const SEG s = eval_route<SEG, TW, AR>(U, fw, bw, rc, R.st[w], R.en[w], R.pc[w], R.np[w], ar);
     const RouteTerms t = route_terms(U, s);
-    dc += t.cost;
     dD += t.C;
     dTW += t.TW;
     dLX += t.LX;
@@ -165,7 +162,7 @@ __device__ __forceinline__ void eval_recipe(const UnitDesc& U, const SEG* fw, co
   for (int k = 0; k < R.nold; ++k) o.res[nres++] = rc[k].slot;
   for (int z = 0; z < nd; ++z) {
     if (dd[z] == 0) continue;
-    const int32_t n0 = U.ndep[dep[z]];
+    const int32_t n0 = ld(U.ndep, dep[z]);
     dFX += imax(n0 + dd[z] - U.NV, 0) - imax(n0 - U.NV, 0);
     if (nres < 3) o.res[nres] = U.R + dep[z];
     ++nres;
@@ -175,7 +172,7 @@ __device__ __forceinline__ void eval_recipe(const UnitDesc& U, const SEG* fw, co
   o.dLX = dLX;
   o.dDX = dDX;
   o.dV4 = dCL + dFX;
-  o.dF = dc + U.w_depot * (int64_t)(dCL + dFX);
+  o.dF = delta_F(U, dD, dTW, dLX, dDX, dCL + dFX);
 }
 
 __device__ __forceinline__ bool follower(const MoveEval& m) {
@@ -183,7 +180,7 @@ __device__ __forceinline__ bool follower(const MoveEval& m) {
 }
 
 __device__ __forceinline__ RouteCtx route_ctx(const UnitDesc& U, int cur, int slot) {
-  const int4 m = U.r_meta[cur][slot];
+  const int4 m = ld(U.r_meta[cur], slot);
   RouteCtx c;
   c.slot = slot;
   c.off = m.x;

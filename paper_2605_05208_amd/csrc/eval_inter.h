@@ -66,26 +66,25 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
   const bool sym = !TW;
   const int pu = x.pu, pv = x.pv, LA = x.LA;
   // ---------------------------------------------------------------- loads
-  const SEG fa0 = fw[offA + pu];       // prefix to u
-  const SEG fa1 = fw[offA + pu - 1];   // prefix to p(u)
+  const SEG fa0 = ld(fw, offA + pu);       // prefix to u
+  const SEG fa1 = ld(fw, offA + pu - 1);   // prefix to p(u)
   const bool hasPPu = pu >= 2;
-  const SEG fa2 = fw[offA + (hasPPu ? pu - 2 : pu - 1)];  // prefix to pp(u)
+  const SEG fa2 = ld(fw, offA + (hasPPu ? pu - 2 : pu - 1));  // prefix to pp(u)
   const bool hasSA1 = OPEN ? (pu + 1 <= LA) : true;          // suffix from s(u) exists
-  const SEG ba1 = bw[offA + (hasSA1 ? pu + 1 : pu)];
+  const SEG ba1 = ld(bw, offA + (hasSA1 ? pu + 1 : pu));
   const bool hasSu = pu + 1 <= LA;                           // s(u) is a customer
   const bool hasSA2 = OPEN ? (pu + 2 <= LA) : (pu + 2 <= LA + 1);
-  const SEG ba2 = bw[offA + (sym && hasSA2 ? pu + 2 : pu)];
-  const SEG fb1 = fw[offB + pv - 1];   // prefix to p(v)
+  const SEG ba2 = ld(bw, offA + (sym && hasSA2 ? pu + 2 : pu));
+  const SEG fb1 = ld(fw, offB + pv - 1);   // prefix to p(v)
   const bool hasPv = pv >= 2, hasPPv = pv >= 3;
-  const SEG fb2 = fw[offB + (hasPv ? pv - 2 : pv - 1)];    // prefix to pp(v)
-  const SEG fb3 = fw[offB + (hasPPv ? pv - 3 : pv - 1)];   // prefix to ppp(v)
-  const SEG bb0 = bw[offB + pv];       // suffix from v
+  const SEG fb2 = ld(fw, offB + (hasPv ? pv - 2 : pv - 1));    // prefix to pp(v)
+  const SEG fb3 = ld(fw, offB + (hasPPv ? pv - 3 : pv - 1));   // prefix to ppp(v)
+  const SEG bb0 = ld(bw, offB + pv);       // suffix from v
   const int u = x.u, v = x.v;
   const int p_u = fa1.node, pp_u = fa2.node, s_u = hasSA1 ? ba1.node : -1, ss_u = hasSA2 ? ba2.node : -1;
   const int p_v = fb1.node, pp_v = fb2.node, ppp_v = fb3.node;
   // old route terms
-  const int4 totA = U.r_tot[x.slotA], totB = U.r_tot[x.slotB];
-  const int64_t costAB = U.r_cost[x.slotA] + U.r_cost[x.slotB];
+  const int4 totA = ld(U.r_tot, x.slotA), totB = ld(U.r_tot, x.slotB);
   const int32_t lxAB = imax(totA.y - U.Q, 0) + imax(totB.y - U.Q, 0);
   const int32_t dxAB = U.Dmax >= 0 ? imax(totA.z - U.Dmax, 0) + imax(totB.z - U.Dmax, 0) : 0;
   const int32_t clAB = (x.eA >= 0 && x.sA != x.eA) + (x.eB >= 0 && x.sB != x.eB);
@@ -124,19 +123,18 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
   // move delta: new A' (may be empty), new B' (may be empty), end depots of the new routes
   auto finish = [&](uint64_t id, bool aEmpty, const SEG& Ap, int eAp, bool bEmpty, const SEG& Bp, int eBp) {
     MoveEval m;
-    int64_t dc = -costAB;
     int32_t dD = -(totA.x + totB.x), dTW = -(totA.w + totB.w), dLX = -lxAB, dDX = -dxAB, dCL = -clAB;
     int dep = -1;
     if (!aEmpty) {
       const RouteTerms t = route_terms(U, Ap);
-      dc += t.cost; dD += t.C; dTW += t.TW; dLX += t.LX; dDX += t.DX;
+      dD += t.C; dTW += t.TW; dLX += t.LX; dDX += t.DX;
       dCL += (eAp >= 0 && x.sA != eAp);
     } else {
       dep = x.sA;
     }
     if (!bEmpty) {
       const RouteTerms t = route_terms(U, Bp);
-      dc += t.cost; dD += t.C; dTW += t.TW; dLX += t.LX; dDX += t.DX;
+      dD += t.C; dTW += t.TW; dLX += t.LX; dDX += t.DX;
       dCL += (eBp >= 0 && x.sB != eBp);
     } else {
       dep = x.sB;
@@ -146,12 +144,12 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
     m.res[1] = x.slotB;
     m.res[2] = -1;
     if (dep >= 0) {
-      const int32_t n0 = U.ndep[dep];
+      const int32_t n0 = ld(U.ndep, dep);
       dFX = imax(n0 - 1 - U.NV, 0) - imax(n0 - U.NV, 0);
       m.res[2] = U.R + dep;
     }
     m.dD = dD; m.dTW = dTW; m.dLX = dLX; m.dDX = dDX; m.dV4 = dCL + dFX;
-    m.dF = dc + U.w_depot * (int64_t)(dCL + dFX);
+    m.dF = delta_F(U, dD, dTW, dLX, dDX, dCL + dFX);
     take(U, o, m, id);
   };
   // A' = prefix + [block] + suffix (suffix may be absent on open routes)

@@ -54,7 +54,7 @@ __device__ __forceinline__ IntraShape shape_swp(int xa, int xb, int xrev, int ya
 template <class SEG, bool TW, bool OPEN, class AR>
 __device__ __forceinline__ SEG eval_shape(const UnitDesc& U, const SEG* fw, const SEG* bw, const RouteCtx& A,
                                           const IntraShape& s, const AR& ar) {
-  SEG acc = fw[A.off + s.x];
+  SEG acc = ld(fw, A.off + s.x);
   int last = acc.node;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -73,7 +73,7 @@ __device__ __forceinline__ SEG eval_shape(const UnitDesc& U, const SEG* fw, cons
   }
   const bool hasS = OPEN ? (s.y <= A.L) : true;
   if (hasS) {
-    const SEG suf = bw[A.off + s.y];
+    const SEG suf = ld(bw, A.off + s.y);
     ar.mark(U, last, suf.node);
     const int32_t c = arc_c(U, last, suf.node);
     const int32_t t = U.t_is_c ? c : arc_t(U, last, suf.node);
@@ -85,14 +85,14 @@ __device__ __forceinline__ SEG eval_shape(const UnitDesc& U, const SEG* fw, cons
 // Delta of replacing route A by A' with the same depots (intra-route moves).
 template <class SEG>
 __device__ __forceinline__ void intra_delta(const UnitDesc& U, const RouteCtx& A, const SEG& Ap, MoveEval& m) {
-  const int4 tot = U.r_tot[A.slot];
+  const int4 tot = ld(U.r_tot, A.slot);
   const RouteTerms t = route_terms(U, Ap);
-  m.dF = t.cost - U.r_cost[A.slot];
   m.dD = t.C - tot.x;
   m.dTW = t.TW - tot.w;
   m.dLX = t.LX - imax(tot.y - U.Q, 0);
   m.dDX = t.DX - (U.Dmax >= 0 ? imax(tot.z - U.Dmax, 0) : 0);
   m.dV4 = 0;
+  m.dF = delta_F(U, m.dD, m.dTW, m.dLX, m.dDX, 0);
   m.res[0] = A.slot;
   m.res[1] = -1;
   m.res[2] = -1;
@@ -163,20 +163,19 @@ __device__ __forceinline__ void eval_intra(const UnitDesc& U, const SEG* fw, con
 template <class SEG>
 __device__ __forceinline__ void depot_delta(const UnitDesc& U, const RouteCtx& A, int n_new, const SEG& R1, int s1,
                                             int e1, const SEG& R2, int s2, int e2, int dm, int dp, MoveEval& m) {
-  const int4 tot = U.r_tot[A.slot];
-  int64_t dc = -U.r_cost[A.slot];
+  const int4 tot = ld(U.r_tot, A.slot);
   int32_t dD = -tot.x, dTW = -tot.w;
   int32_t dLX = -imax(tot.y - U.Q, 0);
   int32_t dDX = -(U.Dmax >= 0 ? imax(tot.z - U.Dmax, 0) : 0);
   int32_t dCL = -(A.end >= 0 && A.start != A.end);
   {
     const RouteTerms t = route_terms(U, R1);
-    dc += t.cost; dD += t.C; dTW += t.TW; dLX += t.LX; dDX += t.DX;
+    dD += t.C; dTW += t.TW; dLX += t.LX; dDX += t.DX;
     dCL += (e1 >= 0 && s1 != e1);
   }
   if (n_new == 2) {
     const RouteTerms t = route_terms(U, R2);
-    dc += t.cost; dD += t.C; dTW += t.TW; dLX += t.LX; dDX += t.DX;
+    dD += t.C; dTW += t.TW; dLX += t.LX; dDX += t.DX;
     dCL += (e2 >= 0 && s2 != e2);
   }
   int32_t dFX = 0;
@@ -185,31 +184,31 @@ __device__ __forceinline__ void depot_delta(const UnitDesc& U, const RouteCtx& A
   m.res[2] = -1;
   int nres = 1;
   if (dm >= 0) {
-    const int32_t n0 = U.ndep[dm];
+    const int32_t n0 = ld(U.ndep, dm);
     dFX += imax(n0 - 1 - U.NV, 0) - imax(n0 - U.NV, 0);
     m.res[nres++] = U.R + dm;
   }
   if (dp >= 0) {
-    const int32_t n0 = U.ndep[dp];
+    const int32_t n0 = ld(U.ndep, dp);
     dFX += imax(n0 + 1 - U.NV, 0) - imax(n0 - U.NV, 0);
     m.res[nres++] = U.R + dp;
   }
   m.dD = dD; m.dTW = dTW; m.dLX = dLX; m.dDX = dDX; m.dV4 = dCL + dFX;
-  m.dF = dc + U.w_depot * (int64_t)(dCL + dFX);
+  m.dF = delta_F(U, dD, dTW, dLX, dDX, dCL + dFX);
 }
 
 // Depot-Insert (Fig. 1a): cut after position pu of A, insert depot d between the parts.
 template <class SEG, bool TW, bool OPEN, class AR>
 __device__ __forceinline__ void eval_dins(const UnitDesc& U, const SEG* fw, const SEG* bw, const RouteCtx& A, int pu,
                                           int d, const AR& ar, MoveEval& m) {
-  const SEG pre = fw[A.off + pu];
+  const SEG pre = ld(fw, A.off + pu);
   SEG R1 = pre;
   if (!OPEN) {
     ar.mark(U, pre.node, d);
     const int32_t c = arc_c(U, pre.node, d);
     R1 = cat(pre, c, U.t_is_c ? c : arc_t(U, pre.node, d), node_seg<SEG>(U, d));
   }
-  const SEG suf = bw[A.off + pu + 1];
+  const SEG suf = ld(bw, A.off + pu + 1);
   ar.mark(U, d, suf.node);
   const int32_t c2 = arc_c(U, d, suf.node);
   const SEG R2 = cat(node_seg<SEG>(U, d), c2, U.t_is_c ? c2 : arc_t(U, d, suf.node), suf);
@@ -224,18 +223,18 @@ __device__ __forceinline__ void eval_drep(const UnitDesc& U, const SEG* fw, cons
   const int ne = (cs == 1 || cs == 2) ? d : A.end;
   SEG R;
   if (cs == 0) {
-    const SEG suf = bw[A.off + 1];
+    const SEG suf = ld(bw, A.off + 1);
     ar.mark(U, d, suf.node);
     const int32_t c = arc_c(U, d, suf.node);
     R = cat(node_seg<SEG>(U, d), c, U.t_is_c ? c : arc_t(U, d, suf.node), suf);
   } else {
-    const SEG pre = fw[A.off + A.L];
+    const SEG pre = ld(fw, A.off + A.L);
     SEG body;
     int first;
     if (cs == 1) {
       body = pre;
     } else {
-      first = fw[A.off + 1].node;
+      first = ld(fw, A.off + 1).node;
       const SEG core = A.L == 1 ? node_seg<SEG>(U, first) : mid_range<SEG, TW>(U, fw, A, 1, A.L, 0);
       ar.mark(U, d, first);
       const int32_t c = arc_c(U, d, first);

@@ -166,32 +166,52 @@ __device__ __forceinline__ SegTW cat(const SegTW& a, int32_t cab, int32_t tab, c
   return r;
 }
 
+// Loads of the hot per-unit and per-instance arrays: global address space and a 32-bit
+// byte offset from a wave-uniform base, so each is one global load with an SGPR base
+// and no 64-bit address arithmetic. Every such array is far below 4 GiB (segment
+// buffers, route tables, lists, node attributes); the matrices use ld_mat.
+#define MDVRP_GLOBAL __attribute__((address_space(1)))
+// (The host pass only type-checks device code and cannot copy vector types out of
+// address space 1, hence the plain form there.)
+template <class T>
+__device__ __forceinline__ T ld(const T* base, uint32_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const MDVRP_GLOBAL T*)((const MDVRP_GLOBAL char*)base + i * (uint32_t)sizeof(T));
+#else
+  return base[i];
+#endif
+}
+// Matrix entry a * n + b (< 2^32 for n <= 65535; the byte offset may exceed 32 bits).
+__device__ __forceinline__ int32_t ld_mat(const int32_t* m, uint32_t n, int a, int b) {
+  return ((const MDVRP_GLOBAL int32_t*)m)[(uint32_t)a * n + (uint32_t)b];
+}
+
 template <class SEG> __device__ __forceinline__ SEG node_seg(const UnitDesc& U, int x);
 template <> __device__ __forceinline__ SegNT node_seg<SegNT>(const UnitDesc& U, int x) {
-  const int4 a = U.attr[x];
+  const int4 a = ld(U.attr, x);
   SegNT r;
   r.C = 0; r.Q = a.x; r.D = a.y; r.node = x;
   return r;
 }
 template <> __device__ __forceinline__ SegTW node_seg<SegTW>(const UnitDesc& U, int x) {
-  const int4 a = U.attr[x];
+  const int4 a = ld(U.attr, x);
   SegTW r;
   r.C = 0; r.Q = a.x; r.D = a.y; r.TW = 0; r.E = a.z; r.L = a.w; r.node = x; r.aux = 0;
   return r;
 }
-__device__ __forceinline__ int32_t service(const UnitDesc& U, int x) { return U.attr[x].y; }
+__device__ __forceinline__ int32_t service(const UnitDesc& U, int x) { return ld(U.attr, x).y; }
 
 __device__ __forceinline__ int32_t seg_tw(const SegNT&) { return 0; }
 __device__ __forceinline__ int32_t seg_tw(const SegTW& s) { return s.TW; }
 
 __device__ __forceinline__ int32_t arc_c(const UnitDesc& U, int a, int b) {
-  if (U.pi) return U.cl[(int64_t)U.pi[a] * U.n + U.pi[b]];
-  return U.c[(int64_t)a * U.n + b];
+  if (U.pi) return ld_mat(U.cl, U.n, ld(U.pi, a), ld(U.pi, b));
+  return ld_mat(U.c, U.n, a, b);
 }
 __device__ __forceinline__ int32_t arc_t(const UnitDesc& U, int a, int b) {
   if (U.t_is_c) return arc_c(U, a, b);
-  if (U.pi) return U.tl[(int64_t)U.pi[a] * U.n + U.pi[b]];
-  return U.t[(int64_t)a * U.n + b];
+  if (U.pi) return ld_mat(U.tl, U.n, ld(U.pi, a), ld(U.pi, b));
+  return ld_mat(U.t, U.n, a, b);
 }
 
 // Penalised cost of a complete route from its total segment (fixed-weight Eq. A.1 terms).
@@ -208,6 +228,16 @@ __device__ __forceinline__ RouteTerms route_terms(const UnitDesc& U, const SEG& 
   r.DX = U.Dmax >= 0 ? imax(s.D - U.Dmax, 0) : 0;
   r.cost = (int64_t)r.C + (int64_t)U.w_tw * r.TW + (int64_t)U.w_load * r.LX + (int64_t)U.w_dur * r.DX;
   return r;
+}
+
+// dF of a move from the int32 deltas of its cost terms. The fixed-weight Eq. A.1 is
+// linear in distance, time warp, load and duration excess and the depot term, so the
+// difference of the route costs equals this combination exactly; the evaluators need
+// no 64-bit per-route costs. (Every route term stays below 2^30, so the deltas fit int32.)
+__device__ __forceinline__ int64_t delta_F(const UnitDesc& U, int32_t dC, int32_t dTW, int32_t dLX, int32_t dDX,
+                                           int32_t dV4) {
+  return (int64_t)dC + (int64_t)U.w_tw * dTW + (int64_t)U.w_load * dLX + (int64_t)U.w_dur * dDX +
+         U.w_depot * (int64_t)dV4;
 }
 
 // ---------------------------------------------------------------------------- move recipes

@@ -50,7 +50,8 @@ void launch_eval_footprint(const LaunchCtx& L, uint32_t fam_mask, int cls);
 // Item classes an evaluation of fam_mask fills (bit 0 pairs, 1 depot-insert, 2 depot-replace).
 uint32_t eval_classes(const LaunchCtx& L, uint32_t fam_mask);
 // scored = the filtered lists were re-scored before this step's evaluation.
-void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only, int scored = 0);
+// apply = true: the selection kernel also rebuilds the new routes (the local search's fused step)
+void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only, int scored = 0, bool apply = false);
 void launch_rebuild(const LaunchCtx& L);
 void launch_pass_begin(const LaunchCtx& L);
 void launch_pass_end(const LaunchCtx& L);

@@ -12,9 +12,11 @@
 //
 // One 1024-thread workgroup per unit. After selection the same workgroup
 // turns each selected move into per-slot piece lists (the recipe of the
-// evaluation) and lays out the rebuilt solution's offsets.
-#include "eval_common.h"
+// evaluation) and lays out the rebuilt solution's offsets. In the local
+// search it then rebuilds the new routes itself (one wavefront per route),
+// which saves the separate apply launch and its round trips per step.
 #include "kernels.h"
+#include "rebuild.h"
 
 namespace mdvrp {
 
@@ -34,6 +36,95 @@ __device__ __forceinline__ void reset_min(uint64_t* p) {
 }
 
 __device__ __forceinline__ int64_t unpack_dD(uint64_t key) { return (int64_t)(key >> 38) - (1ll << 25); }
+
+// Units whose resources (route slots + depots) fit kLdsRes and whose candidates fit
+// kCandPerThread per thread run the follower rounds out of LDS and registers; the
+// others use the global-memory version (same rounds, same result).
+constexpr int kLdsRes = 4096;
+constexpr int kCandPerThread = 4;
+
+struct SelLds {
+  uint64_t rmin[kLdsRes];  // per resource: minimum key of the live candidates touching it
+  uint8_t taken[kLdsRes];  // per resource: taken by a selected move of this step
+};
+
+__device__ __forceinline__ bool lds_taken(const SelLds& S, const int4& r) {
+  return (r.x >= 0 && S.taken[r.x]) || (r.y >= 0 && S.taken[r.y]) || (r.z >= 0 && S.taken[r.z]);
+}
+
+// Locally dominant rounds with the candidates held in registers (thread t holds
+// candidates t, t + kSelBlock, ...) and the per-resource minima in LDS.
+__device__ void followers_lds(const UnitDesc& U, SelLds& S, int n_cand, uint64_t lead_id, int* s_nsel, int* s_alive) {
+  const int tid = threadIdx.x;
+  uint64_t ck[kCandPerThread], ci[kCandPerThread];
+  int4 cr[kCandPerThread];
+  int st[kCandPerThread];  // 0 dead, 1 live, 2 selected this round
+#pragma unroll
+  for (int j = 0; j < kCandPerThread; ++j) {
+    const int c = tid + j * kSelBlock;
+    st[j] = 0;
+    if (c < n_cand) {
+      ck[j] = U.cand_key[c];
+      ci[j] = U.cand_id[c];
+      cr[j] = U.cand_res[c];
+      st[j] = (ci[j] != lead_id && !lds_taken(S, cr[j])) ? 1 : 0;
+    }
+  }
+  for (int round = 0;; ++round) {
+#pragma unroll
+    for (int j = 0; j < kCandPerThread; ++j) {
+      if (st[j] != 1) continue;
+      const int4 r = cr[j];
+      if (r.x >= 0) atomicMin((unsigned long long*)&S.rmin[r.x], (unsigned long long)ck[j]);
+      if (r.y >= 0) atomicMin((unsigned long long*)&S.rmin[r.y], (unsigned long long)ck[j]);
+      if (r.z >= 0) atomicMin((unsigned long long*)&S.rmin[r.z], (unsigned long long)ck[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kCandPerThread; ++j) {
+      if (st[j] != 1) continue;
+      const int4 r = cr[j];
+      const uint64_t k = ck[j];
+      if ((r.x < 0 || S.rmin[r.x] == k) && (r.y < 0 || S.rmin[r.y] == k) && (r.z < 0 || S.rmin[r.z] == k)) {
+        st[j] = 2;
+        const int s = atomicAdd(s_nsel, 1);
+        U.sel_id[s] = ci[j];
+        U.sel_dF[s] = unpack_dD(k);
+      }
+    }
+    if (tid == 0) *s_alive = 0;
+    __syncthreads();
+    // the selected moves take their resources (no live move reads taken[] until the sync)
+#pragma unroll
+    for (int j = 0; j < kCandPerThread; ++j) {
+      if (st[j] != 2) continue;
+      const int4 r = cr[j];
+      if (r.x >= 0) S.taken[r.x] = 1;
+      if (r.y >= 0) S.taken[r.y] = 1;
+      if (r.z >= 0) S.taken[r.z] = 1;
+      st[j] = 0;
+    }
+    __syncthreads();
+    int alive = 0;
+#pragma unroll
+    for (int j = 0; j < kCandPerThread; ++j) {
+      if (st[j] != 1) continue;
+      const int4 r = cr[j];
+      if (lds_taken(S, r)) { st[j] = 0; continue; }
+      if (r.x >= 0) S.rmin[r.x] = ~0ull;
+      if (r.y >= 0) S.rmin[r.y] = ~0ull;
+      if (r.z >= 0) S.rmin[r.z] = ~0ull;
+      ++alive;
+    }
+    if (alive) atomicAdd(s_alive, alive);
+    __syncthreads();
+    if (*s_alive == 0) break;
+    if (round > n_cand + 1) {  // every round takes the smallest live move
+      if (tid == 0) atomicOr(&U.ctl->err, 16);
+      break;
+    }
+  }
+}
 
 // Move s of the selection: per new route the pieces of the old routes it is made of
 // (with the old routes' absolute offsets, so the rebuild can read them wherever the
@@ -82,7 +173,7 @@ __device__ void plan_move(const UnitDesc& U, int cur, uint64_t id, int64_t dF, i
   atomicAdd((unsigned long long*)&U.ctl->F, (unsigned long long)dF);
 }
 
-template <bool OPEN>
+template <class SEG, bool TW, bool OPEN, bool APPLY>
 __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __restrict__ units, uint32_t cls_mask,
                                                            int leader_only, int scored) {
   const UnitDesc& U = units[blockIdx.x];
@@ -92,6 +183,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   __shared__ int shT[kSelWaves];
   __shared__ int sh[2 * kSelWaves + 1];
   __shared__ int s_nsel, s_alive, s_epoch, s_leader_tile, s_ndins, s_nbuild, s_alive_changed;
+  __shared__ SelLds S;
   if (!ctl->active) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int cur = ctl->cur;
@@ -148,17 +240,31 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   const MoveRec lead = U.wg_best[s_leader_tile];
   const int n_cand = imin(ctl->n_cand, U.cand_cap);
 
+  const int n_res = U.R + U.nd;
+  const bool lds = !leader_only && n_res <= kLdsRes && n_cand <= kSelBlock * kCandPerThread;
+  if (lds) {
+    for (int i = tid; i < n_res; i += kSelBlock) {
+      S.rmin[i] = ~0ull;
+      S.taken[i] = 0;
+    }
+    __syncthreads();
+  }
   if (tid == 0) {
     U.sel_id[0] = lead.id;
     U.sel_dF[0] = lead.dF;
     s_nsel = 1;
     for (int k = 0; k < 3; ++k)
-      if (lead.res[k] >= 0) U.taken[lead.res[k]] = epoch;
+      if (lead.res[k] >= 0) {
+        if (lds) S.taken[lead.res[k]] = 1;
+        else U.taken[lead.res[k]] = epoch;
+      }
   }
   __syncthreads();
 
   // ---- followers: locally dominant rounds
-  if (!leader_only) {
+  if (lds) {
+    followers_lds(U, S, n_cand, lead.id, &s_nsel, &s_alive);
+  } else if (!leader_only) {
     for (int c = tid; c < n_cand; c += kSelBlock) {
       const int4 r = U.cand_res[c];
       bool live = U.cand_id[c] != lead.id;
@@ -350,16 +456,30 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     ctl->pass_applied = 1;
     ctl->n_cand = 0;
   }
+  if constexpr (APPLY) {
+    __syncthreads();
+    rebuild_items<SEG, TW, OPEN>(U, ctl, wave, kSelWaves);
+  }
 }
 
-void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only, int scored) {
+template <class SEG, bool TW, bool OPEN, bool APPLY>
+static void select_t(const LaunchCtx& L, uint32_t cls, int leader_only, int scored) {
+  hipLaunchKernelGGL((k_select_plan<SEG, TW, OPEN, APPLY>), dim3(L.n_units), dim3(kSelBlock), 0, L.stream, L.units,
+                     cls, leader_only, scored);
+}
+
+void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only, int scored, bool apply) {
   const uint32_t cls = eval_classes(L, fam_mask);
-  if (L.open)
-    hipLaunchKernelGGL(k_select_plan<true>, dim3(L.n_units), dim3(kSelBlock), 0, L.stream, L.units, cls,
-                       leader_only, scored);
-  else
-    hipLaunchKernelGGL(k_select_plan<false>, dim3(L.n_units), dim3(kSelBlock), 0, L.stream, L.units, cls,
-                       leader_only, scored);
+  if (!apply) {
+    if (L.open) select_t<SegNT, false, true, false>(L, cls, leader_only, scored);
+    else select_t<SegNT, false, false, false>(L, cls, leader_only, scored);
+  } else if (L.has_tw) {
+    if (L.open) select_t<SegTW, true, true, true>(L, cls, leader_only, scored);
+    else select_t<SegTW, true, false, true>(L, cls, leader_only, scored);
+  } else {
+    if (L.open) select_t<SegNT, false, true, true>(L, cls, leader_only, scored);
+    else select_t<SegNT, false, false, true>(L, cls, leader_only, scored);
+  }
 }
 
 }  // namespace mdvrp

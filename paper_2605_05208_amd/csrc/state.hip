@@ -1,98 +1,14 @@
 // state.hip -- solution state: load, per-step rebuild, pass bookkeeping, cost, export.
 //
-// A route is (re)built by one wavefront: lanes own positions, the forward
-// segments (start depot .. position) come from an inclusive wave scan of the
-// concatenation operator and the backward segments (position .. end depot)
-// from a reverse scan, 64 positions per chunk with a carried segment between
-// chunks. Routes untouched by the step's moves are copied (coalesced) to
-// their new offsets in the other buffer.
-#include "eval_common.h"
+// Routes are built by one wavefront each (rebuild.h); this file launches the
+// per-step rebuild on its own grid (the apply call) and loads solutions.
 #include "kernels.h"
+#include "rebuild.h"
 
 namespace mdvrp {
 
 constexpr int kRebuildBlock = 256;
 constexpr int kUnitBlock = 1024;
-
-template <class SEG> __device__ __forceinline__ void set_aux(SEG& s, int32_t v);
-template <> __device__ __forceinline__ void set_aux<SegNT>(SegNT&, int32_t) {}
-template <> __device__ __forceinline__ void set_aux<SegTW>(SegTW& s, int32_t v) { s.aux = v; }
-
-// Build positions 0..P-1 of one route at flat offset `off` of buffer `dst`.
-// nodeAt(p) returns the customer at position p (1..L).
-template <class SEG, bool TW, bool OPEN, class NodeFn>
-__device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int L, int start, int end, NodeFn nodeAt) {
-  const int lane = lane_id();
-  const int P = OPEN ? L + 1 : L + 2;
-  const int64_t off = U.r_off[dst][slot];
-  SEG* fw = (SEG*)U.fw[dst];
-  SEG* bw = (SEG*)U.bw[dst];
-  auto node = [&](int p) -> int {
-    if (p == 0) return start;
-    if (p == L + 1) return end;
-    return nodeAt(p);
-  };
-  // forward scan
-  SEG carry;
-  int32_t carry_c = 0, carry_t = 0;
-  for (int base = 0; base < P; base += 64) {
-    const int p = base + lane;
-    const bool valid = p < P;
-    const int x = valid ? node(p) : start;
-    const int xn = (p + 1 < P) ? node(p + 1) : -1;
-    const int32_t oc = xn >= 0 ? arc_c(U, x, xn) : 0;
-    const int32_t ot = xn >= 0 ? arc_t(U, x, xn) : 0;
-    SEG seg = node_seg<SEG>(U, x);
-    set_aux(seg, ot);
-    for (int o = 1; o < 64; o <<= 1) {
-      const SEG l = shfl_up_seg(seg, o);
-      const int32_t lc = __shfl_up(oc, o);
-      const int32_t lt = __shfl_up(ot, o);
-      if (lane >= o) seg = cat(l, lc, lt, seg);
-    }
-    if (base > 0) seg = cat(carry, carry_c, carry_t, seg);
-    if (valid) {
-      fw[off + p] = seg;
-      if (p >= 1 && p <= L) {
-        U.rt[x] = slot;
-        U.pos[x] = p;
-      }
-      if (p == P - 1) {
-        const RouteTerms t = route_terms(U, seg);
-        U.r_tot[slot] = make_int4(seg.C, seg.Q, seg.D, seg_tw(seg));
-        U.r_cost[slot] = t.cost;
-      }
-    }
-    const int lv = imin(63, P - 1 - base);
-    carry = shfl_seg(seg, lv);
-    carry_c = __shfl(oc, lv);
-    carry_t = __shfl(ot, lv);
-  }
-  // backward scan
-  const int last_base = ((P - 1) / 64) * 64;
-  for (int base = last_base; base >= 0; base -= 64) {
-    const int p = base + lane;
-    const bool valid = p < P;
-    const int x = valid ? node(p) : start;
-    const int xp = (valid && p >= 1) ? node(p - 1) : -1;
-    const int32_t ic = xp >= 0 ? arc_c(U, xp, x) : 0;
-    const int32_t it = xp >= 0 ? arc_t(U, xp, x) : 0;
-    SEG seg = node_seg<SEG>(U, x);
-    for (int o = 1; o < 64; o <<= 1) {
-      const SEG r = shfl_down_seg(seg, o);
-      const int32_t rc = __shfl_down(ic, o);
-      const int32_t rt = __shfl_down(it, o);
-      if (lane + o < 64 && p + o < P) seg = cat(seg, rc, rt, r);
-    }
-    if (base != last_base) seg = cat(seg, carry_c, carry_t, carry);
-    seg.node = x;
-    set_aux(seg, 0);
-    if (valid) bw[off + p] = seg;
-    carry = shfl_seg(seg, 0);
-    carry_c = __shfl(ic, 0);
-    carry_t = __shfl(it, 0);
-  }
-}
 
 // --------------------------------------------------------------------------- per-step rebuild
 
@@ -107,53 +23,7 @@ __global__ __launch_bounds__(kRebuildBlock) void k_rebuild(const UnitDesc* __res
   const int lt = tile - tile_off[ui];
   const int ntiles = tile_off[ui + 1] - tile_off[ui];
   const int waves_per_block = kRebuildBlock / 64;
-  const int w0 = lt * waves_per_block + (threadIdx.x >> 6);
-  const int stride = ntiles * waves_per_block;
-  // mode 0: the step's new routes were given fresh space at the end of the current
-  // buffer; only they are built. mode 1: full relayout into the other buffer (the
-  // current one after the flip): untouched routes are copied, new ones built.
-  const bool in_place = ctl->rebuild_mode == 0;
-  const int dst = ctl->cur, src = in_place ? dst : dst ^ 1;
-  const int epoch = ctl->epoch;
-  const int n_items = in_place ? ctl->n_build : ctl->n_slots_alive;
-  const SEG* fws = (const SEG*)U.fw[src];
-  const SEG* bws = (const SEG*)U.bw[src];
-  SEG* fwd = (SEG*)U.fw[dst];
-  SEG* bwd = (SEG*)U.bw[dst];
-  const int lane = lane_id();
-  for (int k = w0; k < n_items; k += stride) {
-    const int slot = in_place ? U.build_list[k] : U.slot_list[k];
-    const int L = U.r_len[slot];
-    if (!in_place && U.dirty[slot] != epoch) {
-      const int P = OPEN ? L + 1 : L + 2;
-      const int64_t so = U.r_off[src][slot], d0 = U.r_off[dst][slot];
-      for (int p = lane; p < P; p += 64) {
-        fwd[d0 + p] = fws[so + p];
-        bwd[d0 + p] = bws[so + p];
-      }
-      continue;
-    }
-    const int np = U.plan_n[slot];
-    int4 pc[kMaxPieces];
-    int po[kMaxPieces];
-    for (int j = 0; j < np; ++j) {
-      pc[j] = U.plan_pc[(int64_t)slot * kMaxPieces + j];
-      po[j] = pc[j].x;
-    }
-    auto nodeAt = [&](int p) -> int {
-      int q = p;
-      for (int j = 0; j < np; ++j) {
-        const int len = pc[j].z - pc[j].y + 1;
-        if (q <= len) {
-          const int at = pc[j].w ? pc[j].z - (q - 1) : pc[j].y + (q - 1);
-          return fws[po[j] + at].node;
-        }
-        q -= len;
-      }
-      return -1;
-    };
-    build_route_wave<SEG, TW, OPEN>(U, dst, slot, L, U.r_start[slot], OPEN ? -1 : U.r_end[slot], nodeAt);
-  }
+  rebuild_items<SEG, TW, OPEN>(U, ctl, lt * waves_per_block + (threadIdx.x >> 6), ntiles * waves_per_block);
 }
 
 // --------------------------------------------------------------------------- load

@@ -69,7 +69,7 @@ EXPORTED = [
     "mdvrp_validate_solutions_host", "mdvrp_solutions_load", "mdvrp_solutions_export", "mdvrp_batch_cost",
     "mdvrp_batch_state", "mdvrp_eval_neighbourhood", "mdvrp_select_multimove", "mdvrp_apply_moves",
     "mdvrp_local_search_to_optimum", "mdvrp_status_string", "mdvrp_last_error", "mdvrp_family_order",
-    "mdvrp_profile_enable", "mdvrp_profile_read", "mdvrp_eval_footprint",
+    "mdvrp_profile_enable", "mdvrp_profile_sampling", "mdvrp_profile_read", "mdvrp_eval_footprint",
     "mdvrp_mlp_workspace_query", "mdvrp_mlp_create", "mdvrp_mlp_params", "mdvrp_mlp_sync", "mdvrp_mlp_destroy",
     "mdvrp_mlp_act_bytes", "mdvrp_mlp_forward", "mdvrp_mlp_backward", "mdvrp_mlp_bce", "mdvrp_adam_step",
     "mdvrp_mlp_train_step", "mdvrp_filter_workspace_query", "mdvrp_filter_attach", "mdvrp_filter_anchor_count",
@@ -107,6 +107,7 @@ def lib():
             "mdvrp_local_search_to_optimum": [p, p, p, p],
             "mdvrp_family_order": [i32, u64, i64, p],
             "mdvrp_profile_enable": [p, u32, i32],
+            "mdvrp_profile_sampling": [p, i32],
             "mdvrp_profile_read": [p, p, p],
             "mdvrp_eval_footprint": [p, u32, p, i64, p],
             "mdvrp_mlp_workspace_query": [p],
@@ -306,6 +307,10 @@ class Batch:
     def profile_enable(self, class_mask=0x1F, max_launches=1 << 16):
         """Time the kernel classes in class_mask (bit k = PROF_CLASSES[k]); 0 turns timing off."""
         check(lib().mdvrp_profile_enable(self.handle, class_mask, max_launches))
+
+    def profile_sampling(self, every: int):
+        """Time only every n-th launch of each class (1 = all)."""
+        check(lib().mdvrp_profile_sampling(self.handle, int(every)))
 
     def profile_read(self):
         n = np.zeros(8, np.int64)

@@ -64,6 +64,9 @@ def test_validate_instance_host(L):
     assert mdvrp.validate_instance_host(gen.Instance(**{**I.__dict__, "q": q})) == mdvrp.EINVAL
     q = I.q.copy(); q[-1] = -1
     assert mdvrp.validate_instance_host(gen.Instance(**{**I.__dict__, "q": q})) == mdvrp.EINVAL
+    # route loads and load deltas are int32: the total demand must stay below 2^30
+    q = I.q.copy(); q[I.n_depots:] = (1 << 30) // (len(q) - I.n_depots) + 1
+    assert mdvrp.validate_instance_host(gen.Instance(**{**I.__dict__, "q": q})) == mdvrp.ERANGE
 
 
 def test_validate_solutions_host(L):
