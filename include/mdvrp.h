@@ -19,6 +19,12 @@
  *  - Calls are ordered on the caller's HIP stream (passed as void*, a
  *    hipStream_t; NULL = the default stream). Calls that return host values
  *    synchronise that stream.
+ *  - Call order on a batch: every call that reads or changes its solutions
+ *    returns ESTATE before the first successful mdvrp_solutions_load;
+ *    mdvrp_select_multimove needs the latest mdvrp_eval_neighbourhood of the
+ *    current solutions to be of the same family mask, and mdvrp_apply_moves a
+ *    selection made since the last change of the solutions. These checks run
+ *    on the host.
  *  - A handle is not thread-safe.
  *  - All numbers are int32 fixed point; sums and objective values are int64.
  *    Every result is bit-exact and deterministic.

@@ -131,6 +131,12 @@ struct mdvrp_batch {
   // host memory, each with the event that marks its copy
   int32_t* h_poll = nullptr;
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
+  // call order: the device state is defined only after a load; a selection needs an
+  // evaluation of the same families on the current state, an apply needs a selection
+  bool loaded = false;
+  uint32_t eval_fam = 0;  // families of the latest evaluation of the current state (0 = none)
+  bool planned = false;
+  void state_changed() { eval_fam = 0; planned = false; }
   double clock_khz = 0;             // device wall-clock rate
   int shape[6] = {0, 0, 0, 0, 0, 0};  // tile shape of each family's evaluation (autotuner)
   // tile shape of an evaluation of fam_mask: the tuned one of a single family, else the default
@@ -709,6 +715,10 @@ void timed(mdvrp_batch* B, hipStream_t s, int cls, F&& launch) {
 }
 }  // namespace
 
+static mdvrp_status need_loaded(const mdvrp_batch* B) {
+  return B->loaded ? MDVRP_OK : fail(MDVRP_ESTATE, "no solutions loaded in this batch");
+}
+
 extern "C" mdvrp_status mdvrp_validate_solutions_host(const mdvrp_instance_desc* descs, int32_t n_inst,
                                                       const int32_t* unit_inst, int32_t n_units, const int32_t* nodes,
                                                       const int32_t* offs, const int32_t* starts, const int32_t* ends,
@@ -769,15 +779,19 @@ extern "C" mdvrp_status mdvrp_solutions_load(mdvrp_batch* B, const int32_t* node
                                                   B->n_units, hn.data(), ho.data(), hs.data(), he_.data(), hu.data());
   if (st) return st;
   const LaunchCtx L = B->ctx(stream);
+  B->loaded = false;
+  B->state_changed();
   launch_load(L, nodes, offs, starts, ends, uro);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
+  B->loaded = true;
   return MDVRP_OK;
 }
 
 extern "C" mdvrp_status mdvrp_solutions_export(const mdvrp_batch* B, int32_t* nodes, int32_t* offs, int32_t* starts,
                                                int32_t* ends, int32_t* counts, void* stream) {
   if (!B || !nodes || !offs || !starts || !ends || !counts) return fail(MDVRP_EINVAL, "null argument");
+  if (mdvrp_status e = need_loaded(B)) return e;
   const LaunchCtx L = B->ctx(stream);
   launch_export(L, nodes, offs, starts, ends, counts, B->d_node_base, B->d_route_base);
   HIP_TRY(hipGetLastError());
@@ -786,6 +800,7 @@ extern "C" mdvrp_status mdvrp_solutions_export(const mdvrp_batch* B, int32_t* no
 
 extern "C" mdvrp_status mdvrp_batch_cost(mdvrp_batch* B, int64_t* F, int64_t* terms, void* stream) {
   if (!B || !F) return fail(MDVRP_EINVAL, "null argument");
+  if (mdvrp_status e = need_loaded(B)) return e;
   launch_cost(B->ctx(stream), F, terms);
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
@@ -839,6 +854,7 @@ extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, u
   if (flags & ~(MDVRP_EVAL_DENSE | MDVRP_EVAL_FILTERED)) return fail(MDVRP_EINVAL, "unknown flags");
   if ((flags & MDVRP_EVAL_FILTERED) && B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
   static_assert(sizeof(mdvrp_dense_rec) == sizeof(DenseRec), "dense record layout");
+  if (mdvrp_status e = need_loaded(B)) return e;
   LaunchCtx L = B->ctx(stream);
   L.compact = (flags & MDVRP_EVAL_FILTERED) ? 1 : 0;
   step_begin(L, (flags & MDVRP_EVAL_FILTERED) ? 1 : 0, 0);
@@ -851,6 +867,8 @@ extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, u
                           (flags & MDVRP_EVAL_DENSE) ? 0 : B->shape_for(fam));
       });
   HIP_TRY(hipGetLastError());
+  B->planned = false;
+  B->eval_fam = fam;
   return MDVRP_OK;
 }
 
@@ -864,6 +882,8 @@ extern "C" mdvrp_status mdvrp_eval_footprint(mdvrp_batch* B, uint32_t fam, uint3
     base[k + 1] = base[k] + (n * n + 31) / 32;
   }
   if (words < base.back()) return fail(MDVRP_ENOSPC, "footprint bitmap needs %lld words", (long long)base.back());
+  if (mdvrp_status e = need_loaded(B)) return e;
+  B->state_changed();
   hipStream_t s = S(stream);
   std::vector<UnitDesc> u = B->h_units;
   for (int k = 0; k < B->n_units; ++k) u[k].foot = bitmap + base[B->unit_inst[k]];
@@ -884,7 +904,12 @@ extern "C" mdvrp_status mdvrp_select_multimove(mdvrp_batch* B, uint32_t fam, int
                                                int64_t* sel_dF, int32_t* sel_count, int32_t sel_cap, void* stream) {
   if (!B) return fail(MDVRP_EINVAL, "null batch");
   if (sel_ids && (!sel_dF || !sel_count || sel_cap < 1)) return fail(MDVRP_EINVAL, "selection output incomplete");
+  if (mdvrp_status e = need_loaded(B)) return e;
   const LaunchCtx L = B->ctx(stream);
+  if (fam == 0 || fam != B->eval_fam)
+    return fail(MDVRP_ESTATE, "select: the latest evaluation of the current solutions was not of these families");
+  B->eval_fam = 0;
+  B->planned = true;
   timed(B, L.stream, 3, [&] { launch_select(L, fam, leader_only ? 1 : 0); });
   if (sel_ids) launch_sel_export(L, sel_ids, sel_dF, sel_count, sel_cap);
   HIP_TRY(hipGetLastError());
@@ -893,7 +918,9 @@ extern "C" mdvrp_status mdvrp_select_multimove(mdvrp_batch* B, uint32_t fam, int
 
 extern "C" mdvrp_status mdvrp_apply_moves(mdvrp_batch* B, void* stream) {
   if (!B) return fail(MDVRP_EINVAL, "null batch");
+  if (!B->planned) return fail(MDVRP_ESTATE, "apply: no selection to apply");
   const LaunchCtx L = B->ctx(stream);
+  B->state_changed();
   timed(B, L.stream, 4, [&] { launch_rebuild(L); });
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
@@ -958,6 +985,8 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   if (o->filter == MDVRP_FILTER_MLP && !o->mlp) return fail(MDVRP_EINVAL, "the MLP filter needs a network");
   if (o->rescore < 0) return fail(MDVRP_EINVAL, "rescore must be >= 0");
   if (o->graph != 0 && o->graph != 1) return fail(MDVRP_EINVAL, "graph must be 0 or 1");
+  if (mdvrp_status e = need_loaded(B)) return e;
+  B->state_changed();
   const int poll = std::max(1, o->poll_every);
   // A pass captured as a graph needs a capturable stream: the null stream is
   // replaced by the batch's own stream, ordered after and before the caller's work.
@@ -1061,6 +1090,8 @@ extern "C" mdvrp_status mdvrp_autotune(mdvrp_batch* B, uint32_t fam_mask, int32_
                                        void* stream) {
   if (!B || reps < 1) return fail(MDVRP_EINVAL, "bad argument");
   if (fam_mask & ~MDVRP_FAM_ALL) return fail(MDVRP_EINVAL, "unknown family bits");
+  if (mdvrp_status e = need_loaded(B)) return e;
+  B->state_changed();
   const LaunchCtx L = B->ctx(stream);
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -1391,6 +1422,7 @@ extern "C" mdvrp_status mdvrp_filter_anchor_count(const mdvrp_batch* B, int64_t*
 
 extern "C" mdvrp_status mdvrp_filter_features(mdvrp_batch* B, uint16_t* feats, void* stream) {
   if (!B || !feats) return fail(MDVRP_EINVAL, "null argument");
+  if (mdvrp_status e = need_loaded(B)) return e;
   launch_features(B->ctx(stream), feats);
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
@@ -1399,6 +1431,8 @@ extern "C" mdvrp_status mdvrp_filter_features(mdvrp_batch* B, uint16_t* feats, v
 extern "C" mdvrp_status mdvrp_filter_labels(mdvrp_batch* B, uint32_t fam, uint8_t* labels, void* stream) {
   if (!B || !labels) return fail(MDVRP_EINVAL, "null argument");
   if (fam & ~MDVRP_FAM_ALL) return fail(MDVRP_EINVAL, "unknown family bits");
+  if (mdvrp_status e = need_loaded(B)) return e;
+  B->state_changed();
   const LaunchCtx L = B->ctx(stream);
   step_begin(L, 0, 0);
   DenseOut D;
@@ -1412,6 +1446,7 @@ extern "C" mdvrp_status mdvrp_filter_labels(mdvrp_batch* B, uint32_t fam, uint8_
 extern "C" mdvrp_status mdvrp_filter_score_topk(mdvrp_batch* B, const mdvrp_mlp* M, float* logits, void* stream) {
   if (!B || !M) return fail(MDVRP_EINVAL, "null argument");
   if (B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
+  if (mdvrp_status e = need_loaded(B)) return e;
   const LaunchCtx L = B->ctx(stream);
   timed(B, L.stream, MDVRP_PROF_FILTER_SCORE, [&] { launch_rank(L, B->d_cust_off, B->n_cust, M->d, B->stale, 1); });
   if (logits)

@@ -244,3 +244,36 @@ def test_reload_and_rerun_is_deterministic():
     assert e1 == e2
     assert [s["F"] for s in st1] == [s["F"] for s in st2]
     assert [s["passes"] for s in st1] == [s["passes"] for s in st2]
+
+
+def test_call_order_is_checked_on_the_host():
+    """Calls on a batch without loaded solutions, a selection without an evaluation of
+    its families, and an apply without a selection are refused before any launch."""
+    inst = gen.tiny(75_001, nc=20)
+    dev = mdvrp.Instance(inst)
+    B = mdvrp.Batch([dev], [0, 0])
+
+    def status(f):
+        try:
+            f()
+        except mdvrp.MdvrpError as e:
+            return e.status
+        return mdvrp.OK
+
+    assert status(lambda: B.autotune(reps=1)) == mdvrp.ESTATE
+    assert status(lambda: B.eval_neighbourhood(ALL_FAMILIES)) == mdvrp.ESTATE
+    assert status(lambda: B.local_search_to_optimum()) == mdvrp.ESTATE
+    assert status(lambda: B.export()) == mdvrp.ESTATE
+    sols = [gen.start_solution(inst, inst.seed * 1000 + k) for k in range(2)]
+    B.load(sols)
+    assert status(lambda: B.select_multimove(ALL_FAMILIES)) == mdvrp.ESTATE
+    assert status(lambda: B.apply_moves()) == mdvrp.ESTATE
+    B.eval_neighbourhood(1)
+    assert status(lambda: B.select_multimove(2)) == mdvrp.ESTATE  # family 2 not evaluated
+    B.select_multimove(1)
+    B.apply_moves()
+    assert status(lambda: B.apply_moves()) == mdvrp.ESTATE  # the plan was applied
+    assert status(lambda: B.select_multimove(1)) == mdvrp.ESTATE  # solutions changed since
+    ref = Ref(inst)
+    exp, _, _, _ = ref.step(sols[0], 1, 0)
+    assert canonical(B.export()[0].routes) == canonical(exp.routes)
