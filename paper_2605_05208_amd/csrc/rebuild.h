@@ -18,10 +18,10 @@ template <> __device__ __forceinline__ void set_aux<SegTW>(SegTW& s, int32_t v) 
 // Build positions 0..P-1 of one route at flat offset `off` of buffer `dst`.
 // nodeAt(p) returns the customer at position p (1..L).
 template <class SEG, bool TW, bool OPEN, class NodeFn>
-__device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int L, int start, int end, NodeFn nodeAt) {
+__device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t off, int L, int start, int end,
+                                 NodeFn nodeAt) {
   const int lane = lane_id();
   const int P = OPEN ? L + 1 : L + 2;
-  const int64_t off = U.r_off[dst][slot];
   SEG* fw = (SEG*)U.fw[dst];
   SEG* bw = (SEG*)U.bw[dst];
   auto node = [&](int p) -> int {
@@ -119,6 +119,7 @@ __device__ void rebuild_items(const UnitDesc& U, const UnitCtl* ctl, int w0, int
       continue;
     }
     const int np = U.plan_n[slot];
+    if (np < 0) continue;  // recipe held in LDS by the fused step, which builds this route
     int4 pc[kMaxPieces];
     int po[kMaxPieces];
     for (int j = 0; j < np; ++j) {
@@ -137,8 +138,40 @@ __device__ void rebuild_items(const UnitDesc& U, const UnitCtl* ctl, int w0, int
       }
       return -1;
     };
-    build_route_wave<SEG, TW, OPEN>(U, dst, slot, L, U.r_start[slot], OPEN ? -1 : U.r_end[slot], nodeAt);
+    build_route_wave<SEG, TW, OPEN>(U, dst, slot, U.r_off[dst][slot], L, U.r_start[slot], OPEN ? -1 : U.r_end[slot],
+                                    nodeAt);
   }
+}
+
+// A new route of the step whose recipe is held in LDS (the fused select-and-apply
+// step): its pieces {old absolute offset, from, to, rev} and where it goes.
+struct RouteRec {
+  int32_t slot, len, start, end;
+  int32_t np, off, pad0, pad1;
+  int4 pc[kMaxPieces];
+};
+
+// Build one recorded route (len > 0) at rec.off of buffer dst, reading its customers
+// from the pieces of the old routes in buffer src.
+template <class SEG, bool TW, bool OPEN>
+__device__ void build_recorded_route(const UnitDesc& U, const RouteRec& rec, int src, int dst) {
+  const SEG* fws = (const SEG*)U.fw[src];
+  const int np = rec.np;
+  int4 pc[kMaxPieces];
+  for (int j = 0; j < np; ++j) pc[j] = rec.pc[j];
+  auto nodeAt = [&](int p) -> int {
+    int q = p;
+    for (int j = 0; j < np; ++j) {
+      const int len = pc[j].z - pc[j].y + 1;
+      if (q <= len) {
+        const int at = pc[j].w ? pc[j].z - (q - 1) : pc[j].y + (q - 1);
+        return ld(fws, pc[j].x + at).node;
+      }
+      q -= len;
+    }
+    return -1;
+  };
+  build_route_wave<SEG, TW, OPEN>(U, dst, rec.slot, rec.off, rec.len, rec.start, OPEN ? -1 : rec.end, nodeAt);
 }
 
 }  // namespace mdvrp

@@ -52,9 +52,46 @@ __device__ __forceinline__ bool lds_taken(const SelLds& S, const int4& r) {
   return (r.x >= 0 && S.taken[r.x]) || (r.y >= 0 && S.taken[r.y]) || (r.z >= 0 && S.taken[r.z]);
 }
 
+// Per-step data the selection keeps in LDS: the selected moves (the first kPlanLds;
+// further ones go to the unit's global arrays), the objective delta, and in the fused
+// step the recipes of the new routes of the first kPlanLds moves.
+constexpr int kPlanLds = 256;
+
+struct PlanLds {
+  uint64_t id[kPlanLds];
+  int64_t dF[kPlanLds];
+  int32_t size[kPlanLds];  // positions the move's new routes take, then their exclusive offset
+  unsigned long long F;
+  RouteRec rr[2 * kPlanLds];  // fused step: new route w of move s is rr[2 s + w] (len < 0 = none)
+};
+
+template <bool APPLY>
+struct SelView {
+  const UnitDesc& U;
+  PlanLds& P;
+  __device__ bool in_lds(int s) const { return APPLY && s < kPlanLds; }
+  __device__ void put(int s, uint64_t id, int64_t dF) const {
+    if (in_lds(s)) { P.id[s] = id; P.dF[s] = dF; }
+    else { U.sel_id[s] = id; U.sel_dF[s] = dF; }
+  }
+  __device__ uint64_t id(int s) const { return in_lds(s) ? P.id[s] : U.sel_id[s]; }
+  __device__ int64_t dF(int s) const { return in_lds(s) ? P.dF[s] : U.sel_dF[s]; }
+  __device__ int size(int s) const { return in_lds(s) ? P.size[s] : U.sel_size[s]; }
+  __device__ void set_size(int s, int v) const {
+    if (in_lds(s)) P.size[s] = v;
+    else U.sel_size[s] = v;
+  }
+  // vehicle counts stay in global memory: an LDS copy reached through this view's
+  // generic pointer would be updated with flat atomics, which gave wrong counts
+  __device__ void dep_add(int d, int by) const { atomicAdd(&U.ndep[d], by); }
+};
+
 // Locally dominant rounds with the candidates held in registers (thread t holds
 // candidates t, t + kSelBlock, ...) and the per-resource minima in LDS.
-__device__ void followers_lds(const UnitDesc& U, SelLds& S, int n_cand, uint64_t lead_id, int* s_nsel, int* s_alive) {
+template <bool APPLY>
+__device__ void followers_lds(const SelView<APPLY>& V, SelLds& S, int n_cand, uint64_t lead_id, int* s_nsel,
+                              int* s_alive) {
+  const UnitDesc& U = V.U;
   const int tid = threadIdx.x;
   uint64_t ck[kCandPerThread], ci[kCandPerThread];
   int4 cr[kCandPerThread];
@@ -87,9 +124,7 @@ __device__ void followers_lds(const UnitDesc& U, SelLds& S, int n_cand, uint64_t
       const uint64_t k = ck[j];
       if ((r.x < 0 || S.rmin[r.x] == k) && (r.y < 0 || S.rmin[r.y] == k) && (r.z < 0 || S.rmin[r.z] == k)) {
         st[j] = 2;
-        const int s = atomicAdd(s_nsel, 1);
-        U.sel_id[s] = ci[j];
-        U.sel_dF[s] = unpack_dD(k);
+        V.put(atomicAdd(s_nsel, 1), ci[j], unpack_dD(k));
       }
     }
     if (tid == 0) *s_alive = 0;
@@ -128,49 +163,63 @@ __device__ void followers_lds(const UnitDesc& U, SelLds& S, int n_cand, uint64_t
 
 // Move s of the selection: per new route the pieces of the old routes it is made of
 // (with the old routes' absolute offsets, so the rebuild can read them wherever the
-// new routes go), its length, depots and slot; the positions the new routes take.
-template <bool OPEN>
-__device__ void plan_move(const UnitDesc& U, int cur, uint64_t id, int64_t dF, int fresh_slot, int epoch, int s) {
+// new routes go), its length, depots and slot. The recipe goes to LDS (fused step,
+// s < kPlanLds) or to the unit's plan arrays; the route table entries are updated.
+template <bool OPEN, bool APPLY>
+__device__ void plan_move(const SelView<APPLY>& V, int cur, uint64_t id, int64_t dF, int fresh_slot, int epoch, int s) {
+  const UnitDesc& U = V.U;
   const int kind = (int)(id >> 56), var = (int)((id >> 48) & 0xff);
   const int a = (int)((id >> 24) & 0xffffff), b = (int)(id & 0xffffff);
   RouteCtx rc[2];
   Recipe R;
-  rc[0] = route_ctx(U, cur, U.rt[a]);
+  rc[0] = route_ctx(U, cur, ld(U.rt, a));
   if (kind <= TWOOPT) {
-    rc[1] = route_ctx(U, cur, U.rt[b]);
-    build_pair(kind, var, rc[0], U.pos[a], rc[1], U.pos[b], rc[0].slot == rc[1].slot, /*sym=*/true, R);
+    rc[1] = route_ctx(U, cur, ld(U.rt, b));
+    build_pair(kind, var, rc[0], ld(U.pos, a), rc[1], ld(U.pos, b), rc[0].slot == rc[1].slot, /*sym=*/true, R);
   } else if (kind == DINS) {
-    build_dins(rc[0], U.pos[a], b, OPEN, R);
+    build_dins(rc[0], ld(U.pos, a), b, OPEN, R);
   } else {
     build_drep(rc[0], b, var, R);
   }
-  for (int k = 0; k < R.nold; ++k) atomicSub(&U.ndep[rc[k].start], 1);
+  for (int k = 0; k < R.nold; ++k) V.dep_add(rc[k].start, -1);
+  const bool rec = V.in_lds(s);
   int size = 0;
-  U.sel_slot[2 * s + 1] = -1;
+  if (rec) V.P.rr[2 * s + 1].len = -1;
+  else U.sel_slot[2 * s + 1] = -1;
   for (int w = 0; w < R.nnew; ++w) {
     const int slot = (R.fresh && w == 1) ? fresh_slot : rc[w].slot;
     int len = 0;
-    for (int k = 0; k < R.np[w]; ++k) {
-      const Piece& p = R.pc[w][k];
-      U.plan_pc[(int64_t)slot * kMaxPieces + k] = make_int4(rc[p.src].off, p.from, p.to, p.rev);
-      len += p.to - p.from + 1;
+    for (int k = 0; k < R.np[w]; ++k) len += R.pc[w][k].to - R.pc[w][k].from + 1;
+    if (rec) {
+      RouteRec& r = V.P.rr[2 * s + w];
+      r.slot = slot; r.len = len; r.start = R.st[w]; r.end = R.en[w]; r.np = R.np[w];
+      for (int k = 0; k < R.np[w]; ++k) {
+        const Piece& p = R.pc[w][k];
+        r.pc[k] = make_int4(rc[p.src].off, p.from, p.to, p.rev);
+      }
+      U.plan_n[slot] = -1;  // a relayout in this step leaves this route to the recorded build
+    } else {
+      for (int k = 0; k < R.np[w]; ++k) {
+        const Piece& p = R.pc[w][k];
+        U.plan_pc[(int64_t)slot * kMaxPieces + k] = make_int4(rc[p.src].off, p.from, p.to, p.rev);
+      }
+      U.plan_n[slot] = R.np[w];
+      U.plan_se[2 * slot] = R.st[w];
+      U.plan_se[2 * slot + 1] = R.en[w];
+      U.sel_slot[2 * s + w] = slot;
     }
-    U.plan_n[slot] = R.np[w];
-    U.plan_se[2 * slot] = R.st[w];
-    U.plan_se[2 * slot + 1] = R.en[w];
     U.dirty[slot] = epoch;
     U.r_len[slot] = len;
     if (len > 0) {
       U.r_start[slot] = R.st[w];
       U.r_end[slot] = R.en[w];
       size += len + 2;
-      atomicAdd(&U.ndep[R.st[w]], 1);
+      V.dep_add(R.st[w], +1);
     }
-    U.sel_slot[2 * s + w] = slot;
     if (len > U.len_guard) atomicOr(&U.ctl->err, 4);
   }
-  U.sel_size[s] = size;
-  atomicAdd((unsigned long long*)&U.ctl->F, (unsigned long long)dF);
+  V.set_size(s, size);
+  atomicAdd(&V.P.F, (unsigned long long)dF);
 }
 
 template <class SEG, bool TW, bool OPEN, bool APPLY>
@@ -184,9 +233,11 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   __shared__ int sh[2 * kSelWaves + 1];
   __shared__ int s_nsel, s_alive, s_epoch, s_leader_tile, s_ndins, s_nbuild, s_alive_changed;
   __shared__ SelLds S;
+  __shared__ PlanLds P;
   if (!ctl->active) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int cur = ctl->cur;
+  const SelView<APPLY> V{U, P};
 
   // ---- leader: minimum (dF, id) over the block bests of the evaluated item classes
   int64_t bf = kNoMove;
@@ -221,6 +272,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     s_ndins = 0;
     s_nbuild = 0;
     s_alive_changed = 0;
+    P.F = 0;
     ctl->steps += 1;
     // the lists scored before this step's evaluation reflect every route up to this epoch
     if (scored && ctl->fmode == 1) ctl->scored_epoch = ctl->epoch;
@@ -250,8 +302,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     __syncthreads();
   }
   if (tid == 0) {
-    U.sel_id[0] = lead.id;
-    U.sel_dF[0] = lead.dF;
+    V.put(0, lead.id, lead.dF);
     s_nsel = 1;
     for (int k = 0; k < 3; ++k)
       if (lead.res[k] >= 0) {
@@ -263,7 +314,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
 
   // ---- followers: locally dominant rounds
   if (lds) {
-    followers_lds(U, S, n_cand, lead.id, &s_nsel, &s_alive);
+    followers_lds(V, S, n_cand, lead.id, &s_nsel, &s_alive);
   } else if (!leader_only) {
     for (int c = tid; c < n_cand; c += kSelBlock) {
       const int4 r = U.cand_res[c];
@@ -296,9 +347,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
                          (r.z < 0 || ld_min(&U.resmin[r.z]) == k);
         if (dom) {
           U.cand_alive[c] = 2;
-          const int s = atomicAdd(&s_nsel, 1);
-          U.sel_id[s] = U.cand_id[c];
-          U.sel_dF[s] = unpack_dD(k);
+          V.put(atomicAdd(&s_nsel, 1), U.cand_id[c], unpack_dD(k));
           if (r.x >= 0) U.taken[r.x] = epoch;
           if (r.y >= 0) U.taken[r.y] = epoch;
           if (r.z >= 0) U.taken[r.z] = epoch;
@@ -338,7 +387,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
 
   // ---- plan: free slots for Depot-Insert routes, taken in key order
   for (int s = tid; s < n_sel; s += kSelBlock)
-    if ((U.sel_id[s] >> 56) == DINS) atomicAdd(&s_ndins, 1);
+    if ((V.id(s) >> 56) == DINS) atomicAdd(&s_ndins, 1);
   __syncthreads();
   const int n_dins = s_ndins;
   // free slot list (slots empty before this step) into resmin's storage as int32
@@ -357,18 +406,18 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   }
   __syncthreads();
   for (int s = tid; s < n_sel; s += kSelBlock) {
-    const uint64_t id = U.sel_id[s];
-    const int64_t dF = U.sel_dF[s];
+    const uint64_t id = V.id(s);
+    const int64_t dF = V.dF(s);
     int fresh = -1;
     if ((id >> 56) == DINS) {
       int rank = 0;
       for (int z = 0; z < n_sel; ++z) {
-        const uint64_t iz = U.sel_id[z];
-        if ((iz >> 56) == DINS && key_less(U.sel_dF[z], iz, dF, id)) ++rank;
+        const uint64_t iz = V.id(z);
+        if ((iz >> 56) == DINS && key_less(V.dF(z), iz, dF, id)) ++rank;
       }
       fresh = rank < n_dins ? free_list[rank] : 0;
     }
-    plan_move<OPEN>(U, cur, id, dF, fresh, epoch, s);
+    plan_move<OPEN, APPLY>(V, cur, id, dF, fresh, epoch, s);
   }
   __syncthreads();
 
@@ -378,32 +427,41 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   int total = 0;
   for (int base = 0; base < n_sel; base += kSelBlock) {
     const int k = base + tid;
-    const int sz = k < n_sel ? U.sel_size[k] : 0;
+    const int sz = k < n_sel ? V.size(k) : 0;
     int tot;
     const int ex = block_scan(sz, sh, &tot);
-    if (k < n_sel) U.sel_size[k] = total + ex;  // exclusive offset of move k's routes
+    if (k < n_sel) V.set_size(k, total + ex);  // exclusive offset of move k's routes
     total += tot;
   }
   __syncthreads();
   const int top = ctl->arena_top;
-  if ((int64_t)top + total <= U.cap) {
+  const bool in_place = (int64_t)top + total <= U.cap;
+  if (in_place) {
     for (int k = tid; k < n_sel; k += kSelBlock) {
-      int at = top + U.sel_size[k];
+      int at = top + V.size(k);
       for (int w = 0; w < 2; ++w) {
-        const int slot = U.sel_slot[2 * k + w];
-        if (slot < 0) continue;
-        const int len = U.r_len[slot];
+        int slot, len, st, en;
+        if (V.in_lds(k)) {
+          RouteRec& r = P.rr[2 * k + w];
+          if (r.len < 0) continue;
+          slot = r.slot; len = r.len; st = r.start; en = r.end;
+          r.off = at;
+        } else {
+          slot = U.sel_slot[2 * k + w];
+          if (slot < 0) continue;
+          len = U.r_len[slot]; st = U.r_start[slot]; en = U.r_end[slot];
+        }
         if (len > 0) {
           U.r_off[cur][slot] = at;
-          U.r_meta[cur][slot] = make_int4(at, len, U.r_start[slot], U.r_end[slot]);
-          U.build_list[atomicAdd(&s_nbuild, 1)] = slot;
+          U.r_meta[cur][slot] = make_int4(at, len, st, en);
+          if (!V.in_lds(k)) U.build_list[atomicAdd(&s_nbuild, 1)] = slot;
           at += len + 2;
         } else {
           U.r_meta[cur][slot] = make_int4(0, 0, -1, -1);
           s_alive_changed = 1;
         }
       }
-      if ((U.sel_id[k] >> 56) == DINS) s_alive_changed = 1;  // a route in a slot that was empty
+      if ((V.id(k) >> 56) == DINS) s_alive_changed = 1;  // a route in a slot that was empty
     }
     __syncthreads();
     if (s_alive_changed) {
@@ -451,6 +509,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     }
   }
   if (tid == 0) {
+    ctl->F += (int64_t)P.F;
     ctl->n_sel = n_sel;
     ctl->moves_applied += n_sel;
     ctl->pass_applied = 1;
@@ -458,6 +517,17 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   }
   if constexpr (APPLY) {
     __syncthreads();
+    // the recorded routes (one wavefront each), then whatever the unit's plan arrays
+    // hold: copies of untouched routes in a relayout, routes of moves beyond kPlanLds
+    const int n_rec = 2 * imin(n_sel, kPlanLds);
+    const int src = cur;  // the old routes live in the buffer that was current before this step
+    const int dst = in_place ? cur : cur ^ 1;
+    for (int r = wave; r < n_rec; r += kSelWaves) {
+      RouteRec rec = P.rr[r];
+      if (rec.len <= 0) continue;
+      if (!in_place) rec.off = U.r_off[dst][rec.slot];
+      build_recorded_route<SEG, TW, OPEN>(U, rec, src, dst);
+    }
     rebuild_items<SEG, TW, OPEN>(U, ctl, wave, kSelWaves);
   }
 }

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kRebuildBlock) void k_load_routes(const UnitDesc* _
     const int base = offs[g];
     const int L = offs[g + 1] - base;
     auto nodeAt = [&](int p) -> int { return nodes[base + p - 1]; };
-    build_route_wave<SEG, TW, OPEN>(U, 0, slot, L, U.r_start[slot], OPEN ? -1 : U.r_end[slot], nodeAt);
+    build_route_wave<SEG, TW, OPEN>(U, 0, slot, U.r_off[0][slot], L, U.r_start[slot], OPEN ? -1 : U.r_end[slot], nodeAt);
   }
 }
 
