@@ -16,7 +16,10 @@ template <> __device__ __forceinline__ void set_aux<SegNT>(SegNT&, int32_t) {}
 template <> __device__ __forceinline__ void set_aux<SegTW>(SegTW& s, int32_t v) { s.aux = v; }
 
 // Build positions 0..P-1 of one route at flat offset `off` of buffer `dst`.
-// nodeAt(p) returns the customer at position p (1..L).
+// nodeAt(p) returns the customer at position p (1..L). Each lane reads its own node
+// once per chunk and gets its neighbours' by shuffles; a route of at most 64
+// positions (one chunk) reuses the forward pass's nodes, arcs and node segments in
+// the backward pass.
 template <class SEG, bool TW, bool OPEN, class NodeFn>
 __device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t off, int L, int start, int end,
                                  NodeFn nodeAt) {
@@ -29,6 +32,10 @@ __device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t o
     if (p == L + 1) return end;
     return nodeAt(p);
   };
+  const bool one_chunk = P <= 64;
+  int x1 = start;       // one chunk: this lane's node,
+  int32_t c1 = 0, t1 = 0;  // the arc to the next position,
+  SEG n1;               // and its node segment
   // forward scan
   SEG carry;
   int32_t carry_c = 0, carry_t = 0;
@@ -36,10 +43,14 @@ __device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t o
     const int p = base + lane;
     const bool valid = p < P;
     const int x = valid ? node(p) : start;
-    const int xn = (p + 1 < P) ? node(p + 1) : -1;
+    int xn = __shfl_down(x, 1);
+    if (lane == 63) xn = p + 1 < P ? node(p + 1) : -1;
+    if (p + 1 >= P) xn = -1;
     const int32_t oc = xn >= 0 ? arc_c(U, x, xn) : 0;
     const int32_t ot = xn >= 0 ? arc_t(U, x, xn) : 0;
-    SEG seg = node_seg<SEG>(U, x);
+    const SEG nseg = node_seg<SEG>(U, x);
+    if (one_chunk) { x1 = x; c1 = oc; t1 = ot; n1 = nseg; }
+    SEG seg = nseg;
     set_aux(seg, ot);
     for (int o = 1; o < 64; o <<= 1) {
       const SEG l = shfl_up_seg(seg, o);
@@ -70,11 +81,25 @@ __device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t o
   for (int base = last_base; base >= 0; base -= 64) {
     const int p = base + lane;
     const bool valid = p < P;
-    const int x = valid ? node(p) : start;
-    const int xp = (valid && p >= 1) ? node(p - 1) : -1;
-    const int32_t ic = xp >= 0 ? arc_c(U, xp, x) : 0;
-    const int32_t it = xp >= 0 ? arc_t(U, xp, x) : 0;
-    SEG seg = node_seg<SEG>(U, x);
+    int x;
+    int32_t ic, it;
+    SEG seg;
+    if (one_chunk) {
+      // the arc into position p is the forward arc out of position p - 1
+      x = x1;
+      ic = __shfl_up(c1, 1);
+      it = __shfl_up(t1, 1);
+      if (lane == 0) { ic = 0; it = 0; }
+      seg = n1;
+    } else {
+      x = valid ? node(p) : start;
+      int xp = __shfl_up(x, 1);
+      if (lane == 0) xp = p >= 1 ? node(p - 1) : -1;
+      if (!valid) xp = -1;
+      ic = xp >= 0 ? arc_c(U, xp, x) : 0;
+      it = xp >= 0 ? arc_t(U, xp, x) : 0;
+      seg = node_seg<SEG>(U, x);
+    }
     for (int o = 1; o < 64; o <<= 1) {
       const SEG r = shfl_down_seg(seg, o);
       const int32_t rc = __shfl_down(ic, o);
@@ -89,6 +114,27 @@ __device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t o
     carry_c = __shfl(ic, 0);
     carry_t = __shfl(it, 0);
   }
+}
+
+// Customer at position p (1..L) of a route made of up to kMaxPieces pieces
+// {old absolute offset, from, to, rev} of the old routes in fws (unrolled over the
+// pieces so that they stay in registers).
+template <class SEG>
+__device__ __forceinline__ int piece_node(const SEG* fws, const int4 (&pc)[kMaxPieces], int np, int p) {
+  int q = p, at = -1, base = 0;
+#pragma unroll
+  for (int j = 0; j < kMaxPieces; ++j) {
+    if (j < np && at < 0) {
+      const int len = pc[j].z - pc[j].y + 1;
+      if (q <= len) {
+        at = pc[j].w ? pc[j].z - (q - 1) : pc[j].y + (q - 1);
+        base = pc[j].x;
+      } else {
+        q -= len;
+      }
+    }
+  }
+  return at < 0 ? -1 : ld(fws, base + at).node;
 }
 
 // Rebuild work of one step, spread over waves w0, w0 + stride, ...
@@ -121,23 +167,10 @@ __device__ void rebuild_items(const UnitDesc& U, const UnitCtl* ctl, int w0, int
     const int np = U.plan_n[slot];
     if (np < 0) continue;  // recipe held in LDS by the fused step, which builds this route
     int4 pc[kMaxPieces];
-    int po[kMaxPieces];
-    for (int j = 0; j < np; ++j) {
-      pc[j] = U.plan_pc[(int64_t)slot * kMaxPieces + j];
-      po[j] = pc[j].x;
-    }
-    auto nodeAt = [&](int p) -> int {
-      int q = p;
-      for (int j = 0; j < np; ++j) {
-        const int len = pc[j].z - pc[j].y + 1;
-        if (q <= len) {
-          const int at = pc[j].w ? pc[j].z - (q - 1) : pc[j].y + (q - 1);
-          return fws[po[j] + at].node;
-        }
-        q -= len;
-      }
-      return -1;
-    };
+#pragma unroll
+    for (int j = 0; j < kMaxPieces; ++j)
+      pc[j] = j < np ? U.plan_pc[(int64_t)slot * kMaxPieces + j] : make_int4(0, 0, -1, 0);
+    auto nodeAt = [&](int p) -> int { return piece_node(fws, pc, np, p); };
     build_route_wave<SEG, TW, OPEN>(U, dst, slot, U.r_off[dst][slot], L, U.r_start[slot], OPEN ? -1 : U.r_end[slot],
                                     nodeAt);
   }
@@ -158,19 +191,9 @@ __device__ void build_recorded_route(const UnitDesc& U, const RouteRec& rec, int
   const SEG* fws = (const SEG*)U.fw[src];
   const int np = rec.np;
   int4 pc[kMaxPieces];
-  for (int j = 0; j < np; ++j) pc[j] = rec.pc[j];
-  auto nodeAt = [&](int p) -> int {
-    int q = p;
-    for (int j = 0; j < np; ++j) {
-      const int len = pc[j].z - pc[j].y + 1;
-      if (q <= len) {
-        const int at = pc[j].w ? pc[j].z - (q - 1) : pc[j].y + (q - 1);
-        return ld(fws, pc[j].x + at).node;
-      }
-      q -= len;
-    }
-    return -1;
-  };
+#pragma unroll
+  for (int j = 0; j < kMaxPieces; ++j) pc[j] = j < np ? rec.pc[j] : make_int4(0, 0, -1, 0);
+  auto nodeAt = [&](int p) -> int { return piece_node(fws, pc, np, p); };
   build_route_wave<SEG, TW, OPEN>(U, dst, rec.slot, rec.off, rec.len, rec.start, OPEN ? -1 : rec.end, nodeAt);
 }
 
