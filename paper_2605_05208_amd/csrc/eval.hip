@@ -118,7 +118,7 @@ __device__ __forceinline__ void cand_put(const UnitDesc& U, int at, uint64_t k, 
 }
 
 // Append this wave's follower candidates with one atomic per wavefront.
-__device__ void cand_flush(const UnitDesc& U, ItemOut& o) {
+__device__ __forceinline__ void cand_flush(const UnitDesc& U, ItemOut& o) {
   const int lane = lane_id();
   const int n = (o.k0 != ~0ull) + (o.k1 != ~0ull) + (o.k2 != ~0ull);
   int incl = n;
@@ -140,7 +140,7 @@ __device__ void cand_flush(const UnitDesc& U, ItemOut& o) {
 
 // Block-level epilogue: candidate append, leader reduction, evaluated count.
 template <int TPB>
-__device__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
+__device__ __forceinline__ void item_flush(const UnitDesc& U, int wg_slot, ItemOut& o) {
   __shared__ int64_t sF[TPB / 64];
   __shared__ uint64_t sI[TPB / 64];
   __shared__ int sLane[TPB / 64];

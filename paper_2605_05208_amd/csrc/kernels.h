@@ -34,6 +34,7 @@ struct LaunchCtx {
   const int32_t* tile_off_r;
   int tiles_r, per_unit_r;
   int compact;
+  int max_nd;                  // largest depot count over the batch's instances
   int32_t* active_count;       // device int
 };
 

@@ -21,7 +21,7 @@ template <> __device__ __forceinline__ void set_aux<SegTW>(SegTW& s, int32_t v) 
 // positions (one chunk) reuses the forward pass's nodes, arcs and node segments in
 // the backward pass.
 template <class SEG, bool TW, bool OPEN, class NodeFn>
-__device__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t off, int L, int start, int end,
+__device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t off, int L, int start, int end,
                                  NodeFn nodeAt) {
   const int lane = lane_id();
   const int P = OPEN ? L + 1 : L + 2;
@@ -142,7 +142,7 @@ __device__ __forceinline__ int piece_node(const SEG* fws, const int4 (&pc)[kMaxP
 // buffer; only they are built. mode 1: full relayout into the other buffer (the
 // current one after the flip): untouched routes are copied, new ones built.
 template <class SEG, bool TW, bool OPEN>
-__device__ void rebuild_items(const UnitDesc& U, const UnitCtl* ctl, int w0, int stride) {
+__device__ __forceinline__ void rebuild_items(const UnitDesc& U, const UnitCtl* ctl, int w0, int stride) {
   const bool in_place = ctl->rebuild_mode == 0;
   const int dst = ctl->cur, src = in_place ? dst : dst ^ 1;
   const int epoch = ctl->epoch;
@@ -187,7 +187,7 @@ struct RouteRec {
 // Build one recorded route (len > 0) at rec.off of buffer dst, reading its customers
 // from the pieces of the old routes in buffer src.
 template <class SEG, bool TW, bool OPEN>
-__device__ void build_recorded_route(const UnitDesc& U, const RouteRec& rec, int src, int dst) {
+__device__ __forceinline__ void build_recorded_route(const UnitDesc& U, const RouteRec& rec, int src, int dst) {
   const SEG* fws = (const SEG*)U.fw[src];
   const int np = rec.np;
   int4 pc[kMaxPieces];

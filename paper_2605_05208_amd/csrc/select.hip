@@ -56,40 +56,50 @@ __device__ __forceinline__ bool lds_taken(const SelLds& S, const int4& r) {
 // further ones go to the unit's global arrays), the objective delta, and in the fused
 // step the recipes of the new routes of the first kPlanLds moves.
 constexpr int kPlanLds = 256;
+constexpr int kDepLds = 256;  // depot counts kept in LDS during the step when nd <= kDepLds
 
 struct PlanLds {
   uint64_t id[kPlanLds];
   int64_t dF[kPlanLds];
   int32_t size[kPlanLds];  // positions the move's new routes take, then their exclusive offset
+  int32_t ndep[kDepLds];   // vehicle counts per depot (DEPL kernels)
   unsigned long long F;
   RouteRec rr[2 * kPlanLds];  // fused step: new route w of move s is rr[2 s + w] (len < 0 = none)
 };
 
-template <bool APPLY>
+template <bool APPLY, bool DEPL>
 struct SelView {
   const UnitDesc& U;
   PlanLds& P;
-  __device__ bool in_lds(int s) const { return APPLY && s < kPlanLds; }
-  __device__ void put(int s, uint64_t id, int64_t dF) const {
+  __device__ __forceinline__ bool in_lds(int s) const { return APPLY && s < kPlanLds; }
+  __device__ __forceinline__ void put(int s, uint64_t id, int64_t dF) const {
     if (in_lds(s)) { P.id[s] = id; P.dF[s] = dF; }
     else { U.sel_id[s] = id; U.sel_dF[s] = dF; }
   }
-  __device__ uint64_t id(int s) const { return in_lds(s) ? P.id[s] : U.sel_id[s]; }
-  __device__ int64_t dF(int s) const { return in_lds(s) ? P.dF[s] : U.sel_dF[s]; }
-  __device__ int size(int s) const { return in_lds(s) ? P.size[s] : U.sel_size[s]; }
-  __device__ void set_size(int s, int v) const {
+  __device__ __forceinline__ uint64_t id(int s) const { return in_lds(s) ? P.id[s] : U.sel_id[s]; }
+  __device__ __forceinline__ int64_t dF(int s) const { return in_lds(s) ? P.dF[s] : U.sel_dF[s]; }
+  __device__ __forceinline__ int size(int s) const { return in_lds(s) ? P.size[s] : U.sel_size[s]; }
+  __device__ __forceinline__ void set_size(int s, int v) const {
     if (in_lds(s)) P.size[s] = v;
     else U.sel_size[s] = v;
   }
-  // vehicle counts stay in global memory: an LDS copy reached through this view's
-  // generic pointer would be updated with flat atomics, which gave wrong counts
-  __device__ void dep_add(int d, int by) const { atomicAdd(&U.ndep[d], by); }
+  // DEPL (chosen per launch, so that no code path mixes the two address spaces): the
+  // counts live in LDS for the step and are updated with LDS atomics through an
+  // explicit LDS pointer; otherwise with device atomics on the unit's array
+  __device__ __forceinline__ void dep_add(int d, int by) const {
+    if constexpr (DEPL) {
+      __attribute__((address_space(3))) int32_t* p = (__attribute__((address_space(3))) int32_t*)&P.ndep[d];
+      __hip_atomic_fetch_add(p, by, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      atomicAdd(&U.ndep[d], by);
+    }
+  }
 };
 
 // Locally dominant rounds with the candidates held in registers (thread t holds
 // candidates t, t + kSelBlock, ...) and the per-resource minima in LDS.
-template <bool APPLY>
-__device__ void followers_lds(const SelView<APPLY>& V, SelLds& S, int n_cand, uint64_t lead_id, int* s_nsel,
+template <bool APPLY, bool DEPL>
+__device__ __forceinline__ void followers_lds(const SelView<APPLY, DEPL>& V, SelLds& S, int n_cand, uint64_t lead_id, int* s_nsel,
                               int* s_alive) {
   const UnitDesc& U = V.U;
   const int tid = threadIdx.x;
@@ -165,8 +175,8 @@ __device__ void followers_lds(const SelView<APPLY>& V, SelLds& S, int n_cand, ui
 // (with the old routes' absolute offsets, so the rebuild can read them wherever the
 // new routes go), its length, depots and slot. The recipe goes to LDS (fused step,
 // s < kPlanLds) or to the unit's plan arrays; the route table entries are updated.
-template <bool OPEN, bool APPLY>
-__device__ void plan_move(const SelView<APPLY>& V, int cur, uint64_t id, int64_t dF, int fresh_slot, int epoch, int s) {
+template <bool OPEN, bool APPLY, bool DEPL>
+__device__ __forceinline__ void plan_move(const SelView<APPLY, DEPL>& V, int cur, uint64_t id, int64_t dF, int fresh_slot, int epoch, int s) {
   const UnitDesc& U = V.U;
   const int kind = (int)(id >> 56), var = (int)((id >> 48) & 0xff);
   const int a = (int)((id >> 24) & 0xffffff), b = (int)(id & 0xffffff);
@@ -222,7 +232,7 @@ __device__ void plan_move(const SelView<APPLY>& V, int cur, uint64_t id, int64_t
   atomicAdd(&V.P.F, (unsigned long long)dF);
 }
 
-template <class SEG, bool TW, bool OPEN, bool APPLY>
+template <class SEG, bool TW, bool OPEN, bool APPLY, bool DEPL>
 __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __restrict__ units, uint32_t cls_mask,
                                                            int leader_only, int scored) {
   const UnitDesc& U = units[blockIdx.x];
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   if (!ctl->active) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int cur = ctl->cur;
-  const SelView<APPLY> V{U, P};
+  const SelView<APPLY, DEPL> V{U, P};
 
   // ---- leader: minimum (dF, id) over the block bests of the evaluated item classes
   int64_t bf = kNoMove;
@@ -291,6 +301,8 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   const int epoch = s_epoch;
   const MoveRec lead = U.wg_best[s_leader_tile];
   const int n_cand = imin(ctl->n_cand, U.cand_cap);
+  if constexpr (DEPL)
+    for (int d = tid; d < U.nd; d += kSelBlock) P.ndep[d] = U.ndep[d];
 
   const int n_res = U.R + U.nd;
   const bool lds = !leader_only && n_res <= kLdsRes && n_cand <= kSelBlock * kCandPerThread;
@@ -417,9 +429,11 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
       }
       fresh = rank < n_dins ? free_list[rank] : 0;
     }
-    plan_move<OPEN, APPLY>(V, cur, id, dF, fresh, epoch, s);
+    plan_move<OPEN, APPLY, DEPL>(V, cur, id, dF, fresh, epoch, s);
   }
   __syncthreads();
+  if constexpr (DEPL)
+    for (int d = tid; d < U.nd; d += kSelBlock) U.ndep[d] = P.ndep[d];
 
   // ---- where the new routes go: appended at the end of the current buffer when they
   // fit (the other routes stay where they are), else a relayout of every route into
@@ -534,8 +548,12 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
 
 template <class SEG, bool TW, bool OPEN, bool APPLY>
 static void select_t(const LaunchCtx& L, uint32_t cls, int leader_only, int scored) {
-  hipLaunchKernelGGL((k_select_plan<SEG, TW, OPEN, APPLY>), dim3(L.n_units), dim3(kSelBlock), 0, L.stream, L.units,
-                     cls, leader_only, scored);
+  if (L.max_nd <= kDepLds)
+    hipLaunchKernelGGL((k_select_plan<SEG, TW, OPEN, APPLY, true>), dim3(L.n_units), dim3(kSelBlock), 0, L.stream,
+                       L.units, cls, leader_only, scored);
+  else
+    hipLaunchKernelGGL((k_select_plan<SEG, TW, OPEN, APPLY, false>), dim3(L.n_units), dim3(kSelBlock), 0, L.stream,
+                       L.units, cls, leader_only, scored);
 }
 
 void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only, int scored, bool apply) {
