@@ -133,7 +133,7 @@ def ls_run(B, sols, **kw):
     if kw.pop("eta", False):
         B.eta_lists()
     torch.cuda.synchronize()
-    B.profile_enable(0x3F)
+    B.profile_enable(1 << 5)  # HIP events around the re-ranking launches only (every 4th pass)
     t0 = time.perf_counter()
     st = B.local_search_to_optimum(seed=1, poll_every=4, **kw)
     torch.cuda.synchronize()

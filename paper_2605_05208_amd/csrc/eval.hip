@@ -31,7 +31,9 @@ struct ItemOut {
   uint64_t k0, k1, k2;
   uint64_t i0, i1, i2;
   int4 r0, r1, r2;
-  int64_t evaluated;
+  int32_t evaluated;  // moves evaluated by this thread in this launch
+  int32_t err;        // error bits, posted once by the block epilogue (no store inside the
+                      // evaluation, so repeated matrix and segment loads can be merged)
 };
 
 __device__ __forceinline__ void item_init(ItemOut& o) {
@@ -40,6 +42,7 @@ __device__ __forceinline__ void item_init(ItemOut& o) {
   o.b_dD = 0; o.b_elig = 0; o.b_res0 = o.b_res1 = o.b_res2 = -1;
   o.k0 = o.k1 = o.k2 = ~0ull;
   o.evaluated = 0;
+  o.err = 0;
 }
 
 __device__ __forceinline__ bool same_res(const int4& r, const MoveEval& m) {
@@ -65,7 +68,7 @@ __device__ __forceinline__ void item_take(const UnitDesc& U, ItemOut& o, const M
     } else if (o.k2 == ~0ull || same_res(o.r2, m)) {
       if (key < o.k2) { o.k2 = key; o.i2 = id; o.r2 = r; }
     } else {
-      atomicOr(&U.ctl->err, 8);
+      o.err |= 8;
     }
   }
 }
@@ -148,6 +151,7 @@ __device__ __forceinline__ void item_flush(const UnitDesc& U, int wg_slot, ItemO
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
   cand_flush(U, o);
+  if (o.err) atomicOr(&U.ctl->err, o.err);
   if (threadIdx.x == 0) sEval = 0;
   int64_t f = o.bF;
   uint64_t id = o.bid;

@@ -270,12 +270,17 @@ struct Recipe {
 
 __device__ __forceinline__ void rc_add(Recipe& R, int w, int src, int from, int to, int rev) {
   if (from > to) return;
-  Piece& p = R.pc[w][R.np[w]++];
+  Piece p;
   p.src = (int8_t)src;
   p.rev = (int8_t)rev;
   p.pad = 0;
   p.from = from;
   p.to = to;
+  // stores at static indices only, so that a recipe can live in registers
+  const int k = R.np[w]++;
+#pragma unroll
+  for (int j = 0; j < kMaxPieces; ++j)
+    if (j == k) R.pc[w][j] = p;
 }
 
 // Relocate: block [xa, xb] of A (placed reversed when xrev) goes in front of position pv of B.

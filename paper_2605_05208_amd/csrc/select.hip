@@ -191,27 +191,39 @@ __device__ __forceinline__ void plan_move(const SelView<APPLY, DEPL>& V, int cur
   } else {
     build_drep(rc[0], b, var, R);
   }
-  for (int k = 0; k < R.nold; ++k) V.dep_add(rc[k].start, -1);
+  // (loops over routes and pieces are unrolled with static indices: the recipe and the
+  // route contexts stay in registers)
+  V.dep_add(rc[0].start, -1);
+  if (R.nold > 1) V.dep_add(rc[1].start, -1);
   const bool rec = V.in_lds(s);
   int size = 0;
   if (rec) V.P.rr[2 * s + 1].len = -1;
   else U.sel_slot[2 * s + 1] = -1;
-  for (int w = 0; w < R.nnew; ++w) {
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    if (w >= R.nnew) break;
     const int slot = (R.fresh && w == 1) ? fresh_slot : rc[w].slot;
+    const int np = R.np[w];
     int len = 0;
-    for (int k = 0; k < R.np[w]; ++k) len += R.pc[w][k].to - R.pc[w][k].from + 1;
+#pragma unroll
+    for (int k = 0; k < kMaxPieces; ++k)
+      if (k < np) len += R.pc[w][k].to - R.pc[w][k].from + 1;
     if (rec) {
       RouteRec& r = V.P.rr[2 * s + w];
-      r.slot = slot; r.len = len; r.start = R.st[w]; r.end = R.en[w]; r.np = R.np[w];
-      for (int k = 0; k < R.np[w]; ++k) {
+      r.slot = slot; r.len = len; r.start = R.st[w]; r.end = R.en[w]; r.np = np;
+#pragma unroll
+      for (int k = 0; k < kMaxPieces; ++k) {
+        if (k >= np) break;
         const Piece& p = R.pc[w][k];
-        r.pc[k] = make_int4(rc[p.src].off, p.from, p.to, p.rev);
+        r.pc[k] = make_int4(p.src ? rc[1].off : rc[0].off, p.from, p.to, p.rev);
       }
       U.plan_n[slot] = -1;  // a relayout in this step leaves this route to the recorded build
     } else {
-      for (int k = 0; k < R.np[w]; ++k) {
+#pragma unroll
+      for (int k = 0; k < kMaxPieces; ++k) {
+        if (k >= np) break;
         const Piece& p = R.pc[w][k];
-        U.plan_pc[(int64_t)slot * kMaxPieces + k] = make_int4(rc[p.src].off, p.from, p.to, p.rev);
+        U.plan_pc[(int64_t)slot * kMaxPieces + k] = make_int4(p.src ? rc[1].off : rc[0].off, p.from, p.to, p.rev);
       }
       U.plan_n[slot] = R.np[w];
       U.plan_se[2 * slot] = R.st[w];
