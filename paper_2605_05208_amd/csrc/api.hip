@@ -470,6 +470,7 @@ void carve_unit(Carve& cv, const mdvrp_instance* I, int has_tw, UnitDesc* U) {
   UnitDesc u{};
   u.rt = cv.take<int32_t>(z.n);
   u.pos = cv.take<int32_t>(z.n);
+  u.apos = cv.take<int32_t>(z.n);
   u.r_len = cv.take<int32_t>(z.R);
   u.r_start = cv.take<int32_t>(z.R);
   u.r_end = cv.take<int32_t>(z.R);

@@ -255,7 +255,8 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
             x.LA = ma.y; x.LB = mb.y;
             x.sA = ma.z; x.sB = mb.z;
             x.eA = ma.w; x.eB = mb.w;
-            x.pu = ld(U.pos, u); x.pv = ld(U.pos, v);
+            x.au = ld(U.apos, u); x.av = ld(U.apos, v);
+            x.pu = x.au - ma.x; x.pv = x.av - mb.x;
             eval_inter<SEG, TW, OPEN>(U, fw, bw, ma.x, mb.x, x, inter_kinds, ar, sk);
           }
         } else if (intra_kinds) {

@@ -58,6 +58,7 @@ __device__ __forceinline__ int32_t next_t(const UnitDesc& U, const SegNT& a, con
 struct InterCtx {
   int u, v;
   int slotA, slotB, LA, LB, sA, sB, eA, eB, pu, pv;
+  int au, av;  // absolute positions of u and v in the current buffer
 };
 
 template <class SEG, bool TW, bool OPEN, class AR, class OUT>
@@ -66,20 +67,31 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
   const bool sym = !TW;
   const int pu = x.pu, pv = x.pv, LA = x.LA;
   // ---------------------------------------------------------------- loads
-  const SEG fa0 = ld(fw, offA + pu);       // prefix to u
-  const SEG fa1 = ld(fw, offA + pu - 1);   // prefix to p(u)
+  // Addressed by absolute position, so they do not wait for the route table; the
+  // neighbours that may not exist are loaded at clamped in-buffer positions and
+  // replaced below by the segment the position rules choose.
+  (void)offA; (void)offB;
+  const int au = x.au, av = x.av, last = U.cap - 1;
+  const SEG fa0 = ld(fw, au);                  // prefix to u
+  const SEG fa1 = ld(fw, au - 1);              // prefix to p(u)
+  const SEG fa2l = ld(fw, imax(au - 2, 0));
+  const SEG bau = ld(bw, au);                  // suffix from u
+  const SEG ba1l = ld(bw, imin(au + 1, last));
+  const SEG ba2l = sym ? ld(bw, imin(au + 2, last)) : bau;
+  const SEG fb1 = ld(fw, av - 1);              // prefix to p(v)
+  const SEG fb2l = ld(fw, imax(av - 2, 0));
+  const SEG fb3l = ld(fw, imax(av - 3, 0));
+  const SEG bb0 = ld(bw, av);                  // suffix from v
   const bool hasPPu = pu >= 2;
-  const SEG fa2 = ld(fw, offA + (hasPPu ? pu - 2 : pu - 1));  // prefix to pp(u)
+  const SEG fa2 = hasPPu ? fa2l : fa1;         // prefix to pp(u)
   const bool hasSA1 = OPEN ? (pu + 1 <= LA) : true;          // suffix from s(u) exists
-  const SEG ba1 = ld(bw, offA + (hasSA1 ? pu + 1 : pu));
+  const SEG ba1 = hasSA1 ? ba1l : bau;
   const bool hasSu = pu + 1 <= LA;                           // s(u) is a customer
   const bool hasSA2 = OPEN ? (pu + 2 <= LA) : (pu + 2 <= LA + 1);
-  const SEG ba2 = ld(bw, offA + (sym && hasSA2 ? pu + 2 : pu));
-  const SEG fb1 = ld(fw, offB + pv - 1);   // prefix to p(v)
+  const SEG ba2 = (sym && hasSA2) ? ba2l : bau;
   const bool hasPv = pv >= 2, hasPPv = pv >= 3;
-  const SEG fb2 = ld(fw, offB + (hasPv ? pv - 2 : pv - 1));    // prefix to pp(v)
-  const SEG fb3 = ld(fw, offB + (hasPPv ? pv - 3 : pv - 1));   // prefix to ppp(v)
-  const SEG bb0 = ld(bw, offB + pv);       // suffix from v
+  const SEG fb2 = hasPv ? fb2l : fb1;          // prefix to pp(v)
+  const SEG fb3 = hasPPv ? fb3l : fb1;         // prefix to ppp(v)
   const int u = x.u, v = x.v;
   const int p_u = fa1.node, pp_u = fa2.node, s_u = hasSA1 ? ba1.node : -1, ss_u = hasSA2 ? ba2.node : -1;
   const int p_v = fb1.node, pp_v = fb2.node, ppp_v = fb3.node;

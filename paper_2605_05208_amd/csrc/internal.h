@@ -96,6 +96,7 @@ struct UnitDesc {
   int32_t R, cap, t_is_c, pad0;
   // solution state
   int32_t *rt, *pos;
+  int32_t* apos;  // absolute position of each customer in the current buffer (route offset + pos)
   int32_t *r_len, *r_start, *r_end;
   int32_t *r_off[2];
   int4* r_meta[2];  // per buffer and slot {offset, length, start depot, end depot}

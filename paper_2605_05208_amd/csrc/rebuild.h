@@ -64,6 +64,7 @@ __device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int
       if (p >= 1 && p <= L) {
         U.rt[x] = slot;
         U.pos[x] = p;
+        U.apos[x] = (int32_t)(off + p);
       }
       if (p == P - 1) {
         const RouteTerms t = route_terms(U, seg);
@@ -159,8 +160,10 @@ __device__ __forceinline__ void rebuild_items(const UnitDesc& U, const UnitCtl* 
       const int P = OPEN ? L + 1 : L + 2;
       const int64_t so = U.r_off[src][slot], d0 = U.r_off[dst][slot];
       for (int p = lane; p < P; p += 64) {
-        fwd[d0 + p] = fws[so + p];
+        const SEG f = fws[so + p];
+        fwd[d0 + p] = f;
         bwd[d0 + p] = bws[so + p];
+        if (p >= 1 && p <= L) U.apos[f.node] = (int32_t)(d0 + p);
       }
       continue;
     }
