@@ -182,9 +182,12 @@ __device__ __forceinline__ T ld(const T* base, uint32_t i) {
   return base[i];
 #endif
 }
-// Matrix entry a * n + b (< 2^32 for n <= 65535; the byte offset may exceed 32 bits).
+// Matrix entry a * n + b: a 24-bit multiply-add (a, n < 2^16); a 32-bit byte offset from
+// the (uniform) matrix base while n * n * 4 < 2^32, else a 64-bit address.
 __device__ __forceinline__ int32_t ld_mat(const int32_t* m, uint32_t n, int a, int b) {
-  return ((const MDVRP_GLOBAL int32_t*)m)[(uint32_t)a * n + (uint32_t)b];
+  const uint32_t i = __umul24((uint32_t)a, n) + (uint32_t)b;
+  if (n <= 32767u) return ld(m, i);
+  return ((const MDVRP_GLOBAL int32_t*)m)[i];
 }
 
 template <class SEG> __device__ __forceinline__ SEG node_seg(const UnitDesc& U, int x);
