@@ -194,11 +194,11 @@ def test_ordered_layout_gives_identical_results(which):
     assert np.array_equal(x0, x1)
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_results_do_not_depend_on_the_poll_interval(graph):
+@pytest.mark.parametrize("graph,open_r", [(False, 0), (True, 1)])
+def test_results_do_not_depend_on_the_poll_interval(graph, open_r):
     """The host reads the active-unit count of one poll interval while the next one
     runs; the extra passes after convergence must change nothing."""
-    insts = [gen.tiny(76_000 + k, has_tw=1, open_routes=k % 2, nc=35 + 8 * k) for k in range(2)]
+    insts = [gen.tiny(76_000 + k, has_tw=1, open_routes=open_r, nc=35 + 8 * k) for k in range(2)]
     groups = [[gen.start_solution(I, I.seed * 1000 + j) for j in range(2)] for I in insts]
     dev, B, flat = make_batch(insts, groups)
     ref = None
