@@ -494,7 +494,6 @@ void carve_unit(Carve& cv, const mdvrp_instance* I, int has_tw, UnitDesc* U) {
   u.taken = cv.take<int32_t>(z.R + z.nd);
   u.dirty = cv.take<int32_t>(z.R);
   u.plan_n = cv.take<int32_t>(z.R);
-  u.plan_se = cv.take<int32_t>(2 * (size_t)z.R);
   u.plan_pc = cv.take<int4>((size_t)z.R * kMaxPieces);
   u.slot_list = cv.take<int32_t>(z.R);
   u.sel_size = cv.take<int32_t>(z.R + 1);

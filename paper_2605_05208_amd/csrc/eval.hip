@@ -18,8 +18,6 @@
 
 namespace mdvrp {
 
-constexpr int kEvalBlock = kTileSize;
-
 // Per-thread results. Follower candidates are reduced per resource set; an
 // item has at most three distinct sets: {A, B} (or {A}), {A, B, depot of A},
 // {A, B, depot of B}. Slot z holds the best (packed) key of set z.
@@ -523,14 +521,9 @@ void launch_eval_class(const LaunchCtx& L, uint32_t fam_mask, int cls, const Den
   }
 }
 
-void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense) {
-  for (int c = 0; c < 3; ++c) launch_eval_class(L, fam_mask, c, dense);
-}
-
 void launch_eval_footprint(const LaunchCtx& L, uint32_t fam_mask, int cls) {
   launch_class<0, ArcFoot, kTileSize>(L, fam_mask, cls, DenseOut{});
 }
 
-int eval_block_size() { return kEvalBlock; }
 
 }  // namespace mdvrp

@@ -116,7 +116,6 @@ struct UnitDesc {
   int32_t* taken;     // [R + nd] epoch tags
   int32_t* dirty;     // [R] epoch tags
   int32_t* plan_n;    // [R] number of pieces of a rebuilt route (0 = deleted)
-  int32_t* plan_se;   // [2R] start, end depot of a rebuilt route
   int4* plan_pc;      // [R * kMaxPieces] {old offset of the source route, from, to, rev}
   int32_t* slot_list; // [R] alive slots in increasing order
   int32_t* sel_size;  // [R + 1] per selected move: positions its new routes take (then their offsets)

@@ -38,8 +38,6 @@ struct LaunchCtx {
   int32_t* active_count;       // device int
 };
 
-int eval_block_size();
-void launch_eval(const LaunchCtx& L, uint32_t fam_mask, const DenseOut* dense);
 // One item class: 0 pair kinds, 1 depot-insert, 2 depot-replace (no launch when it has no work).
 // shape: tile shape index (threads per block = tile_shape_threads(shape)); dense, label and
 // footprint launches always use shape 0.

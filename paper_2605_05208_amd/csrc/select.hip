@@ -226,8 +226,6 @@ __device__ __forceinline__ void plan_move(const SelView<APPLY, DEPL>& V, int cur
         U.plan_pc[(int64_t)slot * kMaxPieces + k] = make_int4(p.src ? rc[1].off : rc[0].off, p.from, p.to, p.rev);
       }
       U.plan_n[slot] = R.np[w];
-      U.plan_se[2 * slot] = R.st[w];
-      U.plan_se[2 * slot + 1] = R.en[w];
       U.sel_slot[2 * s + w] = slot;
     }
     U.dirty[slot] = epoch;
