@@ -480,6 +480,7 @@ void carve_unit(Carve& cv, const mdvrp_instance* I, int has_tw, UnitDesc* U) {
   u.r_meta[1] = cv.take<int4>(z.R);
   u.r_tot = cv.take<int4>(z.R);
   u.r_cost = cv.take<int64_t>(z.R);
+  u.r_core = has_tw ? cv.take<SegTW>(z.R) : nullptr;
   for (int b = 0; b < 2; ++b) {
     u.fw[b] = cv.take<char>(seg * z.cap);
     u.bw[b] = cv.take<char>(seg * z.cap);

@@ -235,7 +235,13 @@ __device__ __forceinline__ void eval_drep(const UnitDesc& U, const SEG* fw, cons
       body = pre;
     } else {
       first = ld(fw, A.off + 1).node;
-      const SEG core = A.L == 1 ? node_seg<SEG>(U, first) : mid_range<SEG, TW>(U, fw, A, 1, A.L, 0);
+      SEG core;
+      if constexpr (TW) {
+        core = A.L <= kCoreMaxL ? ld(U.r_core, A.slot)
+                                : (A.L == 1 ? node_seg<SEG>(U, first) : mid_range<SEG, TW>(U, fw, A, 1, A.L, 0));
+      } else {
+        core = A.L == 1 ? node_seg<SEG>(U, first) : mid_range<SEG, TW>(U, fw, A, 1, A.L, 0);
+      }
       ar.mark(U, d, first);
       const int32_t c = arc_c(U, d, first);
       body = cat(node_seg<SEG>(U, d), c, U.t_is_c ? c : arc_t(U, d, first), core);

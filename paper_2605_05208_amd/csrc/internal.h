@@ -21,6 +21,9 @@
 namespace mdvrp {
 
 constexpr int kMaxPieces = 5;
+// Time-window routes of at most kCoreMaxL customers keep the segment of their customers
+// (positions 1..L, no depots), which Depot-Replace needs for a new pair of depots.
+constexpr int kCoreMaxL = 62;
 constexpr int kTileSize = 256;  // items per evaluation tile (one block, one leader record)
 constexpr int kPairKindSlots = 14;  // kind/variant slots of one (u, v) anchor
 constexpr int64_t kNoMove = INT64_MAX;
@@ -102,6 +105,7 @@ struct UnitDesc {
   int4* r_meta[2];  // per buffer and slot {offset, length, start depot, end depot}
   int4* r_tot;      // {C, Q, D, TW} of every route
   int64_t* r_cost;  // penalised route cost
+  SegTW* r_core;    // time windows: segment of customers 1..L (routes with L <= kCoreMaxL)
   void* fw[2];
   void* bw[2];
   int32_t* ndep;

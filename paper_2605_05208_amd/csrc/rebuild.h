@@ -77,6 +77,20 @@ __device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int
     carry_c = __shfl(oc, lv);
     carry_t = __shfl(ot, lv);
   }
+  // time windows, one chunk: the segment of the customers alone (an inclusive scan that
+  // starts at position 1), kept for Depot-Replace
+  if constexpr (TW) {
+    if (one_chunk && L >= 1 && L <= kCoreMaxL) {
+      SEG seg = n1;
+      for (int o = 1; o < 64; o <<= 1) {
+        const SEG l = shfl_up_seg(seg, o);
+        const int32_t lc = __shfl_up(c1, o);
+        const int32_t lt = __shfl_up(t1, o);
+        if (lane - o >= 1) seg = cat(l, lc, lt, seg);
+      }
+      if (lane == L) U.r_core[slot] = seg;
+    }
+  }
   // backward scan
   const int last_base = ((P - 1) / 64) * 64;
   for (int base = last_base; base >= 0; base -= 64) {
