@@ -53,8 +53,9 @@ __device__ __forceinline__ bool lds_taken(const SelLds& S, const int4& r) {
 }
 
 // Per-step data the selection keeps in LDS: the selected moves (the first kPlanLds;
-// further ones go to the unit's global arrays), the objective delta, and in the fused
-// step the recipes of the new routes of the first kPlanLds moves.
+// further ones go to the unit's global arrays), the objective delta, the vehicle
+// counts per depot (kernels launched with DEPL), and in the fused step the recipes
+// of the new routes of the first kPlanLds moves.
 constexpr int kPlanLds = 256;
 constexpr int kDepLds = 256;  // depot counts kept in LDS during the step when nd <= kDepLds
 
