@@ -277,3 +277,27 @@ def test_call_order_is_checked_on_the_host():
     ref = Ref(inst)
     exp, _, _, _ = ref.step(sols[0], 1, 0)
     assert canonical(B.export()[0].routes) == canonical(exp.routes)
+
+
+def test_depot_operator_worked_example_on_the_gpu():
+    """The hand-computed Depot-Insert / Depot-Replace example of tests/golden
+    (Section 3.2.2, Fig. 1) through the library's dense evaluation."""
+    import json
+    import os
+
+    import test_oracle_golden as G
+    case = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")))["depot_moves"][0]
+    inst = G._instance(case)
+    dev = mdvrp.Instance(inst)
+    B = mdvrp.Batch([dev], [0])
+    B.load([G._routes(case)])
+    got = B.eval_neighbourhood((1 << 4) | (1 << 5), dense_cap=64)
+    names = ["REL1", "REL2", "SWP11", "SWP21", "SWP12", "SWP22", "X2", "2OPT", "DINS", "DREP"]
+    rec = {}
+    for m in got:
+        i = int(m["id"])
+        rec[(names[i >> 56], (i >> 48) & 0xFF, (i >> 24) & 0xFFFFFF, i & 0xFFFFFF)] = m
+    want = {(w["kind"], w["variant"], w["a"], w["b"]): w for w in case["moves"]}
+    assert set(rec) == set(want)
+    for key, w in want.items():
+        assert (int(rec[key]["dF"]), int(rec[key]["dD"]), int(rec[key]["dV4"])) == (w["dF"], w["dD"], w["dV4"]), key

@@ -1,0 +1,78 @@
+"""Worked examples of the paper's definitions, stored as text fixtures in
+tests/golden/hand_cases.json (each with its citation), checked against the CPU
+oracle. No GPU."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import KIND_NAMES, Ref
+from paper_2605_05208_amd import gen
+from paper_2605_05208_amd.gen import Instance, Solution
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")))
+
+
+def _instance(case, **kw):
+    xy = np.asarray(case["xy"], np.int64)
+    n = len(xy)
+    d = xy[:, None, :] - xy[None, :, :]
+    c = np.floor(np.sqrt((d * d).sum(-1)) * 10 + 0.5).astype(np.int32)
+    z = np.zeros(n, np.int32)
+    nd = case["n_depots"]
+    args = dict(n_depots=nd, n_customers=n - nd, c=c, t=c, q=np.asarray(case["q"], np.int32), s=z, e=z,
+                l=np.full(n, gen.BIG_HORIZON, np.int32), Q=case["Q"], NV=case.get("NV", 4), Dmax=-1,
+                open_routes=0, has_tw=0, theta=n - nd - 1, w_tw=0, w_load=case.get("w_load", 10), w_dur=0,
+                w_depot=-1)
+    args.update(kw)
+    return Instance(**args)
+
+
+def _routes(case):
+    return Solution([(a, list(xs), b) for a, xs, b in case["routes"]])
+
+
+@pytest.mark.parametrize("case", GOLDEN["cost"], ids=lambda c: c["note"][:30])
+def test_cost_worked_example(case):
+    F, terms = Ref(_instance(case)).cost(_routes(case))
+    assert terms.tolist() == case["terms"]
+    assert F == case["F"]
+
+
+@pytest.mark.parametrize("case", GOLDEN["time_warp"], ids=lambda c: c["note"][:30])
+def test_time_warp_worked_example(case):
+    """One open route from depot 0 through the windowed nodes; F with w_tw = 1
+    reads off the time warp, with w_dur = 1 and Dmax = 0 the duration."""
+    win, travel = case["windows"], case["travel"]
+    n = len(win)
+    c = np.zeros((n, n), np.int32)
+    for k, tk in enumerate(travel):
+        c[k, k + 1] = c[k + 1, k] = tk
+    e = np.array([a for a, _ in win], np.int32)
+    l = np.array([b for _, b in win], np.int32)
+    base = dict(n_depots=1, n_customers=n - 1, c=c, t=c, q=np.zeros(n, np.int32), s=np.zeros(n, np.int32),
+                e=e, l=l, Q=10, NV=9, Dmax=0, open_routes=1, has_tw=1, theta=1, w_load=0, w_depot=0)
+    sol = Solution([(0, list(range(1, n)), -1)])
+    _, t_tw = Ref(Instance(**base, w_tw=1, w_dur=0)).cost(sol)
+    _, t_dur = Ref(Instance(**base, w_tw=0, w_dur=1)).cost(sol)
+    assert int(t_tw[1]) == case["TW"]
+    assert int(t_dur[3]) == case["D"]
+
+
+@pytest.mark.parametrize("case", GOLDEN["depot_moves"], ids=lambda c: c["cite"][:20])
+def test_depot_operator_worked_example(case):
+    inst = _instance(case)
+    ref = Ref(inst)
+    sol = _routes(case)
+    assert ref.cost(sol)[0] == case["F"]
+    moves = ref.eval(sol, (1 << 4) | (1 << 5))
+    got = {}
+    for m in moves:
+        i = int(m["id"])
+        got[(KIND_NAMES[i >> 56], (i >> 48) & 0xFF, (i >> 24) & 0xFFFFFF, i & 0xFFFFFF)] = m
+    want = {(w["kind"], w["variant"], w["a"], w["b"]): w for w in case["moves"]}
+    assert set(got) == set(want), (sorted(got), sorted(want))
+    for key, w in want.items():
+        m = got[key]
+        assert (int(m["dF"]), int(m["dD"]), int(m["dV4"])) == (w["dF"], w["dD"], w["dV4"]), key

@@ -28,48 +28,7 @@ def _inst(xy, q, Q, nd, scale=10, has_tw=0, e=None, l=None, s=None, w_load=10, D
                     theta=theta or (n - nd - 1), w_tw=w_tw, w_load=w_load, w_dur=w_dur, w_depot=-1)
 
 
-# ----------------------------------------------------------------------------- hand cases
-
-def test_hand_cost_example():
-    """Depot (0,0), customers (3,4) and (6,8), scale 10: arcs 50, 50, 100 -> D = 200.
-    q = 5 and 7 with Q = 10 overloads by 2; w_load = 10 -> F = 220 (Eq. 1, Eq. A.1)."""
-    I = _inst([(0, 0), (3, 4), (6, 8)], [0, 5, 7], 10, 1)
-    F, terms = Ref(I).cost(Solution([(0, [1, 2], 0)]))
-    assert terms.tolist() == [200, 0, 2, 0, 0, 0]
-    assert F == 220
-
-
-def _tw_route_cost(nodes_ew, travel):
-    """One route start -> ... -> end with windows; returns (TW, D) through the oracle.
-
-    The instance is built so that F reads off the route's time warp (w_tw = 1)
-    and duration (w_dur = 1 with Dmax = 0)."""
-    n = len(nodes_ew)
-    c = np.zeros((n, n), np.int32)
-    for k, tk in enumerate(travel):
-        c[k, k + 1] = c[k + 1, k] = tk
-    e = np.array([a for a, _ in nodes_ew], np.int32)
-    l = np.array([b for _, b in nodes_ew], np.int32)
-    # node 0 is the depot; the last node plays an open route's last customer
-    I = Instance(n_depots=1, n_customers=n - 1, c=c, t=c, q=np.zeros(n, np.int32), s=np.zeros(n, np.int32),
-                 e=e, l=l, Q=10, NV=9, Dmax=0, open_routes=1, has_tw=1, theta=1, w_tw=1, w_load=0,
-                 w_dur=0, w_depot=0)
-    _, terms = Ref(I).cost(Solution([(0, list(range(1, n)), -1)]))
-    I2 = Instance(**{**I.__dict__, "w_tw": 0, "w_dur": 1})
-    _, terms2 = Ref(I2).cost(Solution([(0, list(range(1, n)), -1)]))
-    return int(terms[1]), int(terms2[3])
-
-
-@pytest.mark.parametrize("case,expect", [
-    # (W1) a[0,10] -> b[100,200], t = 10: wait 80 -> D = 90, no warp
-    (([(0, 10), (100, 200)], [10]), (0, 90)),
-    # (W2) a[0,10] -> b[0,5], t = 10: arrive 10 > 5 -> warp 5, D = 10
-    (([(0, 10), (0, 5)], [10]), (5, 10)),
-    # (W3) a[0,100] -> b[50,50] -> c[0,55], t = 10, 10: depart 40, arrive c at 60 -> warp 5, D = 20
-    (([(0, 100), (50, 50), (0, 55)], [10, 10]), (5, 20)),
-])
-def test_time_warp_hand_cases(case, expect):
-    assert _tw_route_cost(*case) == expect
+# (hand-computed worked examples: tests/golden/hand_cases.json, test_oracle_golden.py)
 
 
 # ----------------------------------------------------------------------------- time warp vs enumeration
