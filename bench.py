@@ -13,8 +13,9 @@ CPU oracle timed on a bounded sample of the same workload.
 
 The `filter` object compares, on the 20-depot / 10000-customer MDVRPTW
 instance with 16 solutions, the local search over the full granular lists
-with the searches over 8-entry lists ranked by the trained network and by the
-eta order: GPU time, and the gap of the local-optimum cost per seed. The
+with the searches over 4-entry lists ranked by the trained network (stale lists
+re-ranked every 32 passes) and by the eta order: GPU time, and the gap of the
+local-optimum cost per seed. The
 network is trained first, on the GPU, from logs of full-list searches of the
 1000-customer instance and of uneven instances (not timed in the comparison).
 """
@@ -133,7 +134,7 @@ def ls_run(B, sols, **kw):
     if kw.pop("eta", False):
         B.eta_lists()
     torch.cuda.synchronize()
-    B.profile_enable(1 << 5)  # HIP events around the re-ranking launches only (every 4th pass)
+    B.profile_enable(1 << 5)  # HIP events around the re-ranking launches only
     t0 = time.perf_counter()
     st = B.local_search_to_optimum(seed=1, poll_every=4, **kw)
     torch.cuda.synchronize()
@@ -144,7 +145,7 @@ def ls_run(B, sols, **kw):
     return dt, st, prof
 
 
-def filter_study(n_sol=16, k=8, epochs=6, rescore=4):
+def filter_study(n_sol=16, k=4, epochs=6, rescore=32):
     """Full vs filtered local search on the 20 x 10000 MDVRPTW instance."""
     import torch
 
@@ -181,6 +182,7 @@ def filter_study(n_sol=16, k=8, epochs=6, rescore=4):
                k=k, rescore_every_passes=rescore, full_ms=round(full_dt * 1e3, 1), full_F_mean=float(full_F.mean()),
                tile_threads_per_family=shapes,
                full_evaluated=int(sum(s["evaluated"] for s in runs["full"][2])),
+               full_passes_max=int(max(s["passes"] for s in runs["full"][2])),
                train=dict(samples=int(x.shape[0]), positives=int(y.sum().item()), snapshots=snaps,
                           log_s=round(t_log, 2), train_s=round(t_train, 2), epochs=epochs,
                           loss_first=round(losses[0], 4), loss_last=round(losses[-1], 4)))
@@ -190,6 +192,7 @@ def filter_study(n_sol=16, k=8, epochs=6, rescore=4):
         out[name] = dict(ms=round(dt * 1e3, 1), speedup=round(full_dt / dt, 3), gap_mean=float(gap.mean()),
                          gap_max=float(gap.max()), F_mean=float(F.mean()),
                          evaluated=int(sum(s["evaluated"] for s in st)),
+                         passes_max=int(max(s["passes"] for s in st)),
                          fallback_passes_max=int(max(s["fallback_passes"] for s in st)),
                          score_ms=round(prof["filter_score"][1], 1))
     return out
