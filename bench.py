@@ -312,6 +312,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes (no autotuning)")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB copy (counter reference)")
     ap.add_argument("--mlp-probe", action="store_true", help="only time the filter's scoring and training kernels")
+    ap.add_argument("--filter-only", action="store_true", help="only run the learned-filter comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the local search of a population is data parallel over "
@@ -326,6 +327,9 @@ def main():
         return 0
     if args.mlp_probe:
         print(json.dumps(mlp_probe()), flush=True)
+        return 0
+    if args.filter_only:
+        print(json.dumps(filter_study()), flush=True)
         return 0
 
     from paper_2605_05208_amd import mdvrp
