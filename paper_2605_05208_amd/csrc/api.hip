@@ -65,6 +65,7 @@ struct mdvrp_instance {
   int32_t* nbr = nullptr;
   int32_t* nbr_len = nullptr;
   int4* attr = nullptr;
+  int4* dep_arc = nullptr;  // depot-arc table (null beyond kDepArcMaxDepots depots)
   int64_t* partial = nullptr;
   int64_t* stats = nullptr;
   int nblocks = 0;
@@ -278,18 +279,24 @@ static bool uses_layout(const mdvrp_instance_desc* d) {
   return n * n * 4 > ((int64_t)64 << 20);
 }
 
+// Instances with at most this many depots keep a depot-arc table (16 bytes per
+// customer and depot) for the depot operators; larger ones read the matrices.
+constexpr int kDepArcMaxDepots = 64;
+
 static void carve_instance(Carve& cv, const mdvrp_instance_desc* d, mdvrp_instance* I) {
   const int n = d->n_depots + d->n_customers;
   const int nb = inst_stats_blocks(n);
   int32_t* nbr = cv.take<int32_t>((size_t)d->n_customers * d->theta);
   int32_t* nbl = cv.take<int32_t>(d->n_customers);
   int4* attr = cv.take<int4>(n);
+  int4* dep_arc = d->n_depots <= kDepArcMaxDepots ? cv.take<int4>((size_t)d->n_customers * d->n_depots) : nullptr;
   int64_t* part = cv.take<int64_t>((size_t)nb * 8);
   int64_t* st = cv.take<int64_t>(8);
   if (I) {
     I->nbr = nbr;
     I->nbr_len = nbl;
     I->attr = attr;
+    I->dep_arc = dep_arc;
     I->partial = part;
     I->stats = st;
     I->nblocks = nb;
@@ -355,6 +362,7 @@ extern "C" mdvrp_status mdvrp_instance_create(const mdvrp_instance_desc* d, void
   Carve cv(ws);
   carve_instance(cv, d, I);
   launch_node_attr(S(stream), d->q, d->s, d->e, d->l, n, I->attr);
+  if (I->dep_arc) launch_depot_arcs(S(stream), d->c, d->t, d->n_depots, d->n_customers, I->dep_arc);
   launch_inst_stats(S(stream), d->c, d->t, n, I->partial, I->nblocks);
   launch_inst_stats_final(S(stream), I->partial, I->nblocks, I->stats);
   int64_t h[8];
@@ -582,7 +590,7 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
     const UnitSizes z = unit_sizes(I);
     UnitDesc& u = B->h_units[k];
     u.c = I->d.c; u.t = I->d.t; u.q = I->d.q; u.s = I->d.s; u.e = I->d.e; u.l = I->d.l;
-    u.nbr = I->nbr; u.nbr_len = I->nbr_len; u.attr = I->attr;
+    u.nbr = I->nbr; u.nbr_len = I->nbr_len; u.attr = I->attr; u.dep_arc = I->dep_arc;
     u.cl = I->cl; u.tl = I->tl ? I->tl : I->cl; u.pi = I->pi; u.corder = I->corder;
     u.nd = z.nd; u.nc = z.nc; u.n = z.n; u.theta = z.theta;
     u.Q = I->d.Q; u.NV = I->d.NV; u.Dmax = I->d.Dmax;

@@ -205,13 +205,13 @@ __device__ __forceinline__ void eval_dins(const UnitDesc& U, const SEG* fw, cons
   SEG R1 = pre;
   if (!OPEN) {
     ar.mark(U, pre.node, d);
-    const int32_t c = arc_c(U, pre.node, d);
-    R1 = cat(pre, c, U.t_is_c ? c : arc_t(U, pre.node, d), node_seg<SEG>(U, d));
+    const int4 a = dep_arcs(U, pre.node, d);
+    R1 = cat(pre, a.z, a.w, node_seg<SEG>(U, d));
   }
   const SEG suf = ld(bw, A.off + pu + 1);
   ar.mark(U, d, suf.node);
-  const int32_t c2 = arc_c(U, d, suf.node);
-  const SEG R2 = cat(node_seg<SEG>(U, d), c2, U.t_is_c ? c2 : arc_t(U, d, suf.node), suf);
+  const int4 a2 = dep_arcs(U, suf.node, d);
+  const SEG R2 = cat(node_seg<SEG>(U, d), a2.x, a2.y, suf);
   depot_delta(U, A, 2, R1, A.start, OPEN ? -1 : d, R2, d, A.end, -1, d, m);
 }
 
@@ -225,8 +225,8 @@ __device__ __forceinline__ void eval_drep(const UnitDesc& U, const SEG* fw, cons
   if (cs == 0) {
     const SEG suf = ld(bw, A.off + 1);
     ar.mark(U, d, suf.node);
-    const int32_t c = arc_c(U, d, suf.node);
-    R = cat(node_seg<SEG>(U, d), c, U.t_is_c ? c : arc_t(U, d, suf.node), suf);
+    const int4 a = dep_arcs(U, suf.node, d);
+    R = cat(node_seg<SEG>(U, d), a.x, a.y, suf);
   } else {
     const SEG pre = ld(fw, A.off + A.L);
     SEG body;
@@ -243,12 +243,12 @@ __device__ __forceinline__ void eval_drep(const UnitDesc& U, const SEG* fw, cons
         core = A.L == 1 ? node_seg<SEG>(U, first) : mid_range<SEG, TW>(U, fw, A, 1, A.L, 0);
       }
       ar.mark(U, d, first);
-      const int32_t c = arc_c(U, d, first);
-      body = cat(node_seg<SEG>(U, d), c, U.t_is_c ? c : arc_t(U, d, first), core);
+      const int4 a = dep_arcs(U, first, d);
+      body = cat(node_seg<SEG>(U, d), a.x, a.y, core);
     }
     ar.mark(U, pre.node, d);
-    const int32_t c = arc_c(U, pre.node, d);
-    R = cat(body, c, U.t_is_c ? c : arc_t(U, pre.node, d), node_seg<SEG>(U, d));
+    const int4 a = dep_arcs(U, pre.node, d);
+    R = cat(body, a.z, a.w, node_seg<SEG>(U, d));
   }
   const bool moves_start = cs != 1;
   depot_delta(U, A, 1, R, ns, ne, R, 0, 0, moves_start ? A.start : -1, moves_start ? d : -1, m);

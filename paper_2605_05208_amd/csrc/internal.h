@@ -93,6 +93,7 @@ struct UnitDesc {
   // indices (cl[pi[a] * n + pi[b]] = c(a, b)), and the customers in that order
   const int32_t *cl, *tl, *pi, *corder;
   const int4* attr;  // per node {q, s, e, l}
+  const int4* dep_arc;  // per (customer, depot) {c(d,x), t(d,x), c(x,d), t(x,d)} at [(x - nd) * nd + d], or null
   int32_t nd, nc, n, theta;
   int32_t Q, NV, Dmax, w_tw, w_load, w_dur;
   int64_t w_depot;
@@ -219,6 +220,15 @@ __device__ __forceinline__ int32_t arc_t(const UnitDesc& U, int a, int b) {
   if (U.t_is_c) return arc_c(U, a, b);
   if (U.pi) return ld_mat(U.tl, U.n, ld(U.pi, a), ld(U.pi, b));
   return ld_mat(U.t, U.n, a, b);
+}
+
+// The arcs between customer x and depot d, {c(d,x), t(d,x), c(x,d), t(x,d)}: one
+// 16-byte load from the instance's depot-arc table (contiguous over d for a given x),
+// or the matrices when the instance has no table.
+__device__ __forceinline__ int4 dep_arcs(const UnitDesc& U, int x, int d) {
+  if (U.dep_arc) return ld(U.dep_arc, (uint32_t)((x - U.nd) * U.nd + d));
+  const int32_t ci = arc_c(U, d, x), co = arc_c(U, x, d);
+  return make_int4(ci, U.t_is_c ? ci : arc_t(U, d, x), co, U.t_is_c ? co : arc_t(U, x, d));
 }
 
 // Penalised cost of a complete route from its total segment (fixed-weight Eq. A.1 terms).

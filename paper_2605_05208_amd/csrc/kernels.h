@@ -110,6 +110,8 @@ void launch_inst_stats_final(hipStream_t s, const int64_t* partial, int nblocks,
 // Packs q, s, e, l into one int4 per node.
 void launch_node_attr(hipStream_t s, const int32_t* q, const int32_t* sv, const int32_t* e, const int32_t* l, int n,
                       int4* attr);
+// Depot-arc table of an instance: {c(d,x), t(d,x), c(x,d), t(x,d)} at [(x - nd) * nd + d].
+void launch_depot_arcs(hipStream_t s, const int32_t* c, const int32_t* t, int nd, int nc, int4* out);
 // Locality layout of an instance: landmarks (lm[6]), node keys, rank pi[x], its inverse,
 // customers in layout order, and the reordered copies of c (and of t when tl != null).
 void launch_layout(hipStream_t s, const int32_t* c, const int32_t* t, int n, int nd, int64_t* lm, uint64_t* keys,

@@ -196,6 +196,23 @@ void launch_node_attr(hipStream_t s, const int32_t* q, const int32_t* sv, const 
   hipLaunchKernelGGL(k_node_attr, dim3((n + 255) / 256), dim3(256), 0, s, q, sv, e, l, n, attr);
 }
 
+// Depot-arc table: out[(x - nd) * nd + d] = {c(d,x), t(d,x), c(x,d), t(x,d)} for every
+// customer x and depot d (original node ids); one thread per entry, d fastest.
+__global__ void k_depot_arcs(const int32_t* __restrict__ c, const int32_t* __restrict__ t, int nd, int nc,
+                             int4* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nc * nd) return;
+  const int64_t n = (int64_t)nd + nc;
+  const int x = nd + (int)(i / nd), d = (int)(i % nd);
+  out[i] = make_int4(c[d * n + x], t[d * n + x], c[x * n + d], t[x * n + d]);
+}
+
+void launch_depot_arcs(hipStream_t s, const int32_t* c, const int32_t* t, int nd, int nc, int4* out) {
+  const int64_t m = (int64_t)nc * nd;
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_depot_arcs, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, c, t, nd, nc, out);
+}
+
 void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* sv, const int32_t* ev,
                       const int32_t* lv, int nd, int nc, int theta, int has_tw, int64_t gnum, int64_t gden,
                       int32_t* nbr, int32_t* nbr_len) {

@@ -97,3 +97,16 @@ def test_batch_mixing_edge_cases_with_ordinary_units():
     log("mixed edge batch")
     _dense_compare(insts, sols, ALL_FAMILIES, "mixed edge batch")
     _ls_compare(insts, sols, 0, 13, tag="mixed edge batch")
+
+
+@pytest.mark.parametrize("tw,open_r", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_many_depots(tw, open_r):
+    """64 depots (the depot operators read the instance's depot-arc table) and 65 (they
+    read the matrices), in one batch."""
+    insts = [gen.tiny(88_100 + 10 * nd + 2 * tw + open_r, has_tw=tw, open_routes=open_r, nd=nd, nc=8)
+             for nd in (64, 65)]
+    sols = [[gen.random_solution(i, 3), gen.start_solution(i, 4)] for i in insts]
+    log("many depots", tw, open_r)
+    for fam in [ALL_FAMILIES, 16, 32]:
+        _dense_compare(insts, sols, fam, f"many depots tw={tw} open={open_r} fam {fam}")
+    _ls_compare(insts, sols, 0, 17, tag=f"many depots tw={tw} open={open_r}")
