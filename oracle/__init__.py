@@ -88,6 +88,9 @@ def lib():
         L.ref_topk.argtypes = [p, p, C.c_int32, C.c_int32, p, C.c_int32, p]
         L.ref_bf16.argtypes = [C.c_float]
         L.ref_bf16.restype = C.c_uint16
+        L.ref_route_terms.argtypes = [p, C.c_int32, p, C.c_int32, C.c_int32, p]
+        L.ref_splitmix64.argtypes = [p]
+        L.ref_splitmix64.restype = C.c_uint64
         L.ref_family_order.argtypes = [C.c_int32, C.c_uint64, C.c_int64, p]
         L.ref_family_order.restype = C.c_int32
         _lib = L
@@ -130,6 +133,13 @@ class Ref:
             assert rc == 0
             self._nbr = (nbr, ln)
         return self._nbr
+
+    def route_terms(self, start, xs, end):
+        """(distance, load, duration, time warp) of one route walked node by node."""
+        xs = np.ascontiguousarray(xs if len(xs) else [0], np.int32)
+        out = np.zeros(4, np.int64)
+        lib().ref_route_terms(self.dref, int(start), _ptr(xs), len(xs), int(end), _ptr(out))
+        return tuple(int(x) for x in out)
 
     def cost(self, sol):
         nodes, offs, st, en = sol.flat()
@@ -283,3 +293,9 @@ def family_order(has_tw: int, seed: int, p: int):
     fam = np.zeros(6, np.int32)
     n = lib().ref_family_order(has_tw, seed, p, _ptr(fam))
     return [int(x) for x in fam[:n]]
+
+
+def splitmix64(state: int, n: int):
+    """The first n outputs of SplitMix64 started from state."""
+    st = np.array([state], np.uint64)
+    return [int(lib().ref_splitmix64(_ptr(st))) for _ in range(n)]

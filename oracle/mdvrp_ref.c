@@ -158,6 +158,12 @@ static rterm route_terms(const ref_instance* I, int start, const int32_t* xs, in
   return o;
 }
 
+int ref_route_terms(const ref_instance* I, int32_t start, const int32_t* xs, int32_t L, int32_t end, int64_t out[4]) {
+  rterm t = route_terms(I, start, xs, L, end);
+  out[0] = t.dist; out[1] = t.load; out[2] = t.dur; out[3] = t.tw;
+  return 0;
+}
+
 static int64_t lx_of(const ref_instance* I, rterm t) { return mx(t.load - I->Q, 0); }
 static int64_t dx_of(const ref_instance* I, rterm t) { return I->Dmax >= 0 ? mx(t.dur - I->Dmax, 0) : 0; }
 static int64_t cost_of(const ref_instance* I, rterm t) {
@@ -720,7 +726,9 @@ int ref_step(const ref_instance* I, const int32_t* nbr, const int32_t* nbr_len, 
 
 /* SplitMix64 (Steele, Lea and Flood, 2014): state += golden gamma, then two
  * xor-shift-multiply rounds and a final xor-shift. */
-static uint64_t splitmix64(uint64_t* s) {
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): advance the state by the golden
+ * gamma, then mix with two xor-shift-multiply rounds and a final xor-shift. */
+uint64_t ref_splitmix64(uint64_t* s) {
   uint64_t z = (*s += 0x9E3779B97F4A7C15ull);
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
@@ -738,7 +746,7 @@ int ref_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam) 
   fam[n++] = REF_FAM_DREP;
   uint64_t st = seed ^ (uint64_t)pass;
   for (int i = n - 1; i >= 1; --i) {
-    int j = (int)(splitmix64(&st) % (uint64_t)(i + 1));
+    int j = (int)(ref_splitmix64(&st) % (uint64_t)(i + 1));
     int tmp = fam[i]; fam[i] = fam[j]; fam[j] = tmp;
   }
   return n;

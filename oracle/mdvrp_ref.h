@@ -67,6 +67,12 @@ int ref_neighbours(const ref_instance* I, int32_t* nbr, int32_t* nbr_len);
 int ref_cost(const ref_instance* I, int32_t n_routes, const int32_t* nodes, const int32_t* offs,
              const int32_t* start, const int32_t* end, int64_t* F, int64_t terms[6]);
 
+/* Terms of one route walked node by node (start depot, customers xs[0..L-1],
+ * end depot or -1 when open): out[0] distance, out[1] load, out[2] duration
+ * and out[3] time warp by the left fold of Vidal's concatenation (Section 3.2.2,
+ * Appendix A; without time windows duration = travel + service, warp 0). */
+int ref_route_terms(const ref_instance* I, int32_t start, const int32_t* xs, int32_t L, int32_t end, int64_t out[4]);
+
 /* Every evaluated move of the families in fam_mask (dense list). */
 int ref_eval(const ref_instance* I, const int32_t* nbr, const int32_t* nbr_len,
              int32_t n_routes, const int32_t* nodes, const int32_t* offs,
@@ -135,6 +141,9 @@ int ref_adam(float* params, float* m, float* v, const float* grads, int32_t n, f
 /* k largest scores per customer (ties -> lower customer id), -1 padding */
 int ref_topk(const int32_t* nbr, const int32_t* nbr_len, int32_t n_customers, int32_t theta, const float* score,
              int32_t k, int32_t* out);
+
+/* One output of SplitMix64 (Steele, Lea and Flood 2014); advances *state. */
+uint64_t ref_splitmix64(uint64_t* state);
 
 /* Family order of pass p: Fisher-Yates driven by SplitMix64 seeded with seed ^ p. */
 int ref_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam_out);

@@ -45,34 +45,12 @@ float ref_bf16_to_f32(uint16_t h) {
 
 typedef struct { int64_t load, dur, tw; } rfacts;
 
-/* load, duration and time warp of a route by a left fold (same definitions as the evaluator) */
+/* load, duration and time warp of a route: the evaluator's own route walk (one fold of
+ * Vidal's concatenation for the whole oracle, pinned against departure-time enumeration) */
 static rfacts route_facts(const ref_instance* I, int start, const int32_t* xs, int L, int end) {
-  rfacts o = {0, 0, 0};
-  int64_t D = I->s[start], TW = 0, E = I->e[start], Lt = I->l[start];
-  int prev = start;
-  for (int k = 0; k <= L; ++k) {
-    int x;
-    if (k < L) x = xs[k];
-    else if (end >= 0) x = end;
-    else break;
-    if (k < L) o.load += I->q[x];
-    const int64_t tab = tt(I, prev, x);
-    if (I->has_tw) {
-      const int64_t delta = D - TW + tab;
-      const int64_t wait = I->e[x] - delta - Lt > 0 ? I->e[x] - delta - Lt : 0;
-      const int64_t warp = E + delta - I->l[x] > 0 ? E + delta - I->l[x] : 0;
-      const int64_t nD = D + I->s[x] + tab + wait;
-      const int64_t nTW = TW + warp;
-      const int64_t nE = (I->e[x] - delta > E ? I->e[x] - delta : E) - wait;
-      const int64_t nL = (I->l[x] - delta < Lt ? I->l[x] - delta : Lt) + warp;
-      D = nD; TW = nTW; E = nE; Lt = nL;
-    } else {
-      D += tab + I->s[x];
-    }
-    prev = x;
-  }
-  o.dur = D;
-  o.tw = I->has_tw ? TW : 0;
+  int64_t t[4];
+  ref_route_terms(I, start, xs, L, end, t);
+  rfacts o = {t[1], t[2], t[3]};
   return o;
 }
 

@@ -290,6 +290,25 @@ def tiny(seed: int, has_tw: int = 0, open_routes: int = 0, nd: int | None = None
                     name=f"tiny-{seed}", seed=seed, coords=xy, **w)
 
 
+def with_separate_times(inst: Instance, seed: int, c_jitter: int = 3, t_extra: int = 6) -> Instance:
+    """A copy of a time-window instance whose distance matrix c is made asymmetric
+    (each off-diagonal entry raised by U{0..c_jitter-1}) and whose travel times are a
+    separate, asymmetric matrix t = c + U{0..t_extra-1} per arc; the diagonals stay 0.
+    The distance-time ratio Gamma of the granular lists is then not 1."""
+    assert inst.has_tw, "asymmetric matrices need time windows"
+    rng = np.random.default_rng(seed)
+    n = inst.N
+    c = inst.c.astype(np.int64) + rng.integers(0, c_jitter, (n, n))
+    t = c + rng.integers(0, t_extra, (n, n))
+    np.fill_diagonal(c, 0)
+    np.fill_diagonal(t, 0)
+    out = Instance(**{**inst.__dict__})
+    out.c = np.ascontiguousarray(c, np.int32)
+    out.t = np.ascontiguousarray(t, np.int32)
+    out.name = inst.name + "-ct"
+    return out
+
+
 # ----------------------------------------------------------------------------- start solutions
 
 def start_solution(inst: Instance, sol_seed: int) -> Solution:

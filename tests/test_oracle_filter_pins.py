@@ -167,7 +167,7 @@ def test_features_hand_example():
     def S(iv, r):
         return f32_of_bits(bf16_bits(float(np.float32(iv) * r)))
 
-    c01, c12, c20, c03, c13, c23 = 50, 50, 100, 50, 32, 58
+    c01, c12, c20, c03, c13, c23 = 50, 50, 100, 50, 32, 67
     assert c[0, 1] == c01 and c[1, 2] == c12 and c[2, 0] == c20 and c[0, 3] == c03 and c[1, 3] == c13
     ints = {0: c13, 1: c01, 2: c12, 3: c[0, 2], 4: c03, 5: c[0, 1],
             6: c[0, 2] - c01 - c12 + c[0, 1] + c13 - c03,
@@ -182,3 +182,19 @@ def test_features_hand_example():
     assert vals[23] == 0.0 and vals[24] == 1.0 and vals[25] == 0.0 and vals[26] == 0.0
     assert vals[27] == S(2, np.float32(1 / 32)) and vals[28] == S(1, np.float32(1 / 32))
     assert vals[29] == S(1, np.float32(1) / np.float32(2)) and vals[30] == 1.0 and vals[31] == 0.0
+
+
+def test_adam_second_step_by_hand():
+    """Two Adam steps on one parameter (beta 0.9 / 0.999, eps 1e-8, lr 0.1), gradients 0.5 then
+    -0.25. Step 1: m = 0.05, v = 2.5e-4, m^ = 0.5, v^ = 0.25, theta = 1 - 0.1 * 0.5 / 0.5 = 0.9.
+    Step 2: m = 0.9 * 0.05 - 0.1 * 0.25 = 0.02, v = 0.999 * 2.5e-4 + 0.001 * 0.0625 = 3.1225e-4,
+    m^ = 0.02 / 0.19, v^ = 3.1225e-4 / 0.001999, theta = 0.9 - 0.1 * m^ / sqrt(v^) = 0.8733663.
+    (Swapped betas would give 0.8679139; no bias correction 0.7868.)"""
+    P = np.ones(1, np.float32)
+    m = np.zeros(1, np.float32)
+    v = np.zeros(1, np.float32)
+    oracle.adam(P, m, v, np.array([0.5], np.float32), 0.1, 1)
+    assert abs(float(P[0]) - 0.9) <= 1e-6
+    oracle.adam(P, m, v, np.array([-0.25], np.float32), 0.1, 2)
+    assert abs(float(m[0]) - 0.02) <= 1e-8 and abs(float(v[0]) - 3.1225e-4) <= 1e-10
+    assert abs(float(P[0]) - 0.8733663) <= 1e-6

@@ -76,3 +76,63 @@ def test_depot_operator_worked_example(case):
     for key, w in want.items():
         m = got[key]
         assert (int(m["dF"]), int(m["dD"]), int(m["dV4"])) == (w["dF"], w["dD"], w["dV4"]), key
+
+
+def _ff_instance(case):
+    n = len(case["q"])
+    return Instance(n_depots=case["n_depots"], n_customers=n - case["n_depots"],
+                    c=np.asarray(case["c"], np.int32), t=np.asarray(case["t"], np.int32),
+                    q=np.asarray(case["q"], np.int32), s=np.asarray(case["s"], np.int32),
+                    e=np.asarray(case["e"], np.int32), l=np.asarray(case["l"], np.int32), Q=case["Q"], NV=4,
+                    Dmax=case["Dmax"], open_routes=0, has_tw=1, theta=case["theta"], w_tw=1, w_load=1, w_dur=1,
+                    w_depot=-1)
+
+
+def _bf16_value(iv, rcp):
+    """bf16 (nearest even) of fp32(iv) * fp32 rcp, as a float: the filter's scaling rule."""
+    import struct
+    x = np.float32(np.float32(iv) * np.float32(rcp))
+    u = struct.unpack("<I", struct.pack("<f", float(x)))[0]
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return struct.unpack("<f", struct.pack("<I", u << 16))[0]
+
+
+@pytest.mark.parametrize("case", GOLDEN["filter_features"], ids=lambda c: c["cite"][:20])
+def test_filter_features_time_windows_worked_example(case):
+    """Time-window features (13..22) of hand-computed anchors, with travel times t != c,
+    service times and a duration limit; also the route facts and lists they rest on."""
+    import struct
+    inst = _ff_instance(case)
+    ref = Ref(inst)
+    st = ref.stats()
+    assert (st["gamma_num"], st["gamma_den"]) == tuple(case["gamma"])
+    nbr, ln = ref.neighbours()
+    th = inst.theta
+    for i, want in enumerate(case["lists"]):
+        assert list(nbr[i * th:i * th + ln[i]]) == want, i
+    sol = _routes(case)
+    for rf in case["route_facts"]:
+        a, xs, b = case["routes"][rf["route"]]
+        dist, load, dur, tw = ref.route_terms(a, xs, b)
+        assert (tw, dur) == (rf["tw"], rf["dur"]), rf["note"]
+    fx = ref.features(sol)
+    sc = case["scales"]
+    rcp = [np.float32(1) / np.float32(sc["dist"]), np.float32(1) / np.float32(sc["load"]),
+           np.float32(1) / np.float32(sc["time"]), np.float32(1) / np.float32(sc["depots"])]
+    routes = case["routes"]
+    for an in case["anchors"]:
+        u, k, ints = an["u"], an["k"], an["ints"]
+        row = fx[(u - inst.n_depots) * th + k]
+        got = [struct.unpack("<f", struct.pack("<I", int(b) << 16))[0] for b in row]
+        LA = next(len(xs) for _, xs, _ in routes if u in xs)
+        LB = next(len(xs) for _, xs, _ in routes if an["v"] in xs)
+        scale = [rcp[0]] * 9 + [rcp[1]] * 4 + [rcp[2]] * 10 + [1, 1, rcp[3], rcp[3], 1 / 32, 1 / 32,
+                                                                 np.float32(1) / np.float32(LA),
+                                                                 np.float32(1) / np.float32(LB),
+                                                                 np.float32(1) / np.float32(th)]
+        for f in range(32):
+            assert got[f] == _bf16_value(ints[f], scale[f]), (u, f, got[f], ints[f])
+    # customer 3 has no list: its rows are zero, as is the missing second entry of 1 and 2
+    for i in range(inst.n_customers):
+        for kk in range(ln[i], th):
+            assert not fx[i * th + kk].any()

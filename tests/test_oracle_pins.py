@@ -339,3 +339,72 @@ def test_config1_optimum_has_closed_routes():
         assert a == b
     F, terms = ref.cost(out[0])
     assert terms[4] == 0 and terms[5] == 0
+
+
+def test_splitmix64_published_outputs():
+    """The generator behind the family order of a pass is SplitMix64 (Steele, Lea and Flood,
+    OOPSLA 2014): its published outputs for seed 1234567 and the first output for seed 0."""
+    from oracle import splitmix64
+    assert splitmix64(1234567, 5) == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                                      4593380528125082431, 16408922859458223821]
+    assert splitmix64(0, 1) == [0xE220A8397B1DCDAF]
+
+
+def test_family_order_is_fisher_yates_over_splitmix64():
+    """Fisher-Yates from the last position down, j = next output mod (i + 1), state seed ^ pass."""
+    from oracle import splitmix64
+    for has_tw in (0, 1):
+        for seed, p in ((0, 0), (12345, 7), (2 ** 63 + 5, 1)):
+            fam = [0, 1, 2, 4, 5] if has_tw else [0, 1, 2, 3, 4, 5]
+            outs = splitmix64((seed ^ p) & (2 ** 64 - 1), len(fam) - 1)
+            for step, i in enumerate(range(len(fam) - 1, 0, -1)):
+                j = outs[step] % (i + 1)
+                fam[i], fam[j] = fam[j], fam[i]
+            assert family_order(has_tw, seed, p) == fam
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_separate_asymmetric_times_lists_and_gamma(seed):
+    """Asymmetric c with a separate, asymmetric t (Gamma != 1): Gamma equals the reduced
+    fraction of the sums over all ordered pairs, and the eta lists (Eq. 3, exact fractions in
+    the brute force) and Theta agree."""
+    from fractions import Fraction
+    I = gen.with_separate_times(gen.tiny(60_000 + seed, has_tw=1, theta=[None, 3, 2][seed % 3]), seed)
+    n = I.N
+    off = ~np.eye(n, dtype=bool)
+    g = Fraction(int(I.c[off].sum()), int(I.t[off].sum()))
+    st = Ref(I).stats()
+    assert g != 1
+    assert (st["gamma_num"], st["gamma_den"]) == (g.numerator, g.denominator)
+    assert st["Theta"] == T0.theta_norm(I)
+    nbr, ln = Ref(I).neighbours()
+    py = T0.neighbour_lists(I)
+    for u in range(I.n_depots, I.N):
+        k = u - I.n_depots
+        assert list(nbr[k * I.theta:k * I.theta + ln[k]]) == py[u]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_separate_times_route_terms_and_move_deltas(seed):
+    """With t != c (asymmetric), every route's time warp and duration equal departure-time
+    enumeration over t, its distance walks c, and every move's dF equals F(m(S)) - F(S)."""
+    I = gen.with_separate_times(gen.tiny(70_000 + seed, has_tw=1, open_routes=int(seed % 4 == 1)), seed)
+    ref = Ref(I)
+    nbr, ln = ref.neighbours()
+    nbrs = {u: list(nbr[(u - I.n_depots) * I.theta:(u - I.n_depots) * I.theta + ln[u - I.n_depots]])
+            for u in range(I.n_depots, I.N)}
+    sol = gen.random_solution(I, seed)
+    routes = [(a, list(xs), -1 if I.open_routes else b) for (a, xs, b) in sol.routes]
+    for (a, xs, b) in routes:
+        dist, load, dur, tw = ref.route_terms(a, xs, b)
+        seq = [a] + xs + ([b] if b >= 0 else [])
+        assert dist == sum(int(I.c[seq[k], seq[k + 1]]) for k in range(len(seq) - 1))
+        assert (tw, dur) == T0.tw_dur(I, a, xs, b)
+    F0, _ = T0.F_terms(I, routes)
+    assert ref.cost(sol)[0] == F0
+    moves = ref.eval(sol, ALL_FAMILIES)
+    py = T0.all_neighbours(I, routes, ALL_FAMILIES, nbrs)
+    got = {int(m["id"]): m for m in moves}
+    assert {k for k in got if (k >> 56) != 9} == set(py)
+    for mid, nb in py.items():
+        assert int(got[mid]["dF"]) == T0.F_terms(I, nb)[0] - F0, hex(mid)
