@@ -26,8 +26,11 @@
  *    selection made since the last change of the solutions. These checks run
  *    on the host.
  *  - A handle is not thread-safe.
- *  - All numbers are int32 fixed point; sums and objective values are int64.
- *    Every result is bit-exact and deterministic.
+ *  - The routing arithmetic is int32 fixed point with int64 sums and objective
+ *    values: every result is exact and deterministic. The learned filter
+ *    computes in bf16 / fp32; every sum over samples runs in a fixed order, so
+ *    its results are deterministic too. The one unspecified order is that of
+ *    the rows of an improving-move list (mdvrp_moves).
  */
 #ifndef MDVRP_H
 #define MDVRP_H
@@ -157,8 +160,10 @@ mdvrp_status mdvrp_validate_solutions_host(const mdvrp_instance_desc* descs, int
  * unit_route_offsets[k] .. unit_route_offsets[k+1]-1 (n_units+1 entries);
  * route r visits route_nodes[route_offsets[r] .. route_offsets[r+1]-1]
  * between depots route_start[r] and route_end[r] (ignored when open).
- * The arrays are copied to the host and validated first (EINVAL), then the
- * route-major segment state is built on the device. Synchronises. */
+ * The arrays are copied to the host and validated first (EINVAL); a route
+ * longer than the instance's int32-safe length (mdvrp_instance_info [7]) is
+ * refused with ERANGE before any launch; then the route-major segment state is
+ * built on the device. Synchronises. */
 mdvrp_status mdvrp_solutions_load(mdvrp_batch* batch, const int32_t* route_nodes, const int32_t* route_offsets,
                                   const int32_t* route_start, const int32_t* route_end,
                                   const int32_t* unit_route_offsets, int32_t n_routes_total,
@@ -188,6 +193,53 @@ mdvrp_status mdvrp_batch_state(const mdvrp_batch* batch, int64_t* out_host);
 
 /* ------------------------------------------------------------------------- hot path */
 
+/* Compacted list of improving moves (dF < 0), structure of arrays. Every array
+ * is a DEVICE array owned by the caller with room for cap rows; count is a
+ * DEVICE counter that the evaluation sets to the number of improving moves it
+ * found (which may exceed cap: rows beyond cap are not written). Row order is
+ * unspecified (it depends on scheduling); the set of rows is deterministic. */
+typedef struct {
+  int64_t* dF;              /* penalised cost delta (Eq. A.1 with fixed weights), < 0 */
+  int64_t* dD;              /* distance delta */
+  uint64_t* id;             /* kind<<56 | variant<<48 | a<<24 | b */
+  uint8_t* kind;            /* MDVRP_KIND_* (= id >> 56) */
+  uint8_t* variant;         /* (id >> 48) & 0xff: orientation of 2-node blocks, Depot-Replace case */
+  uint8_t* changed;         /* penalty terms the move changes: bit 0 time warp, 1 load excess,
+                               2 duration excess, 3 closure + fleet excess (V4) */
+  int32_t* unit;            /* unit (solution) of the move */
+  int32_t* a;               /* pair kinds: u; Depot-Insert: u (cut after u); Depot-Replace: first customer */
+  int32_t* b;               /* pair kinds: v; depot moves: the depot */
+  int32_t* res;             /* [cap][3] resources: route slot r, n_customers + d for depot d's
+                               vehicle count, -1 none (the conflict sets of Section 3.2.5) */
+  int64_t cap;
+  unsigned long long* count;
+} mdvrp_moves;
+
+/* Evaluate, in parallel, the penalised delta of every move of the families in
+ * family_mask for every active unit (Sections 3.2.1-3.2.4: Eq. A.1 deltas of
+ * Relocate, Swap, 2-opt*, 2-opt and the depot operators of Fig. 1 over the
+ * granular neighbourhood of Eq. 3). The per-unit leader candidate and follower
+ * candidates stay in the batch for mdvrp_select_multimove.
+ *   cand, k: optional candidate lists (DEVICE int32, cand[unit][i][k] for
+ *     customer n_depots + i of the unit's instance, units in batch order; -1
+ *     pads a list). When given, pair moves are anchored on (u, v) for the
+ *     entries v of u's list instead of the granular list N(u); the depot
+ *     operators are unchanged. 1 <= k <= theta of every instance; entries must
+ *     be customers other than u, without repeats in one list (checked on the
+ *     host: EINVAL). cand = NULL: the granular lists, or with
+ *     MDVRP_EVAL_FILTERED the lists of the attached filter.
+ *   moves (nullable): receives every improving move (mdvrp_moves). When
+ *     *moves->count exceeds moves->cap the call returns ENOSPC after the
+ *     evaluation; *moves->count then holds the required capacity and the
+ *     selection state is still valid.
+ *   n_evaluated (DEVICE int64[n_units], nullable): moves evaluated per unit
+ *     (every tuple that passes its preconditions).
+ * Families without moves in an instance (2-opt with time windows) are
+ * ignored. Synchronises the stream when cand or moves is given. */
+#define MDVRP_EVAL_FILTERED 0x2u
+mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* batch, uint32_t family_mask, const int32_t* cand, int32_t k,
+                                      mdvrp_moves* moves, uint32_t flags, int64_t* n_evaluated, void* stream);
+
 /* One dense record per evaluated move (debug output). */
 typedef struct {
   int64_t dF, dD, dTW, dLX, dDX, dV4; /* deltas of F, distance, time warp, load excess,
@@ -197,23 +249,12 @@ typedef struct {
   int32_t res[3];                     /* route slot r, or n_customers + depot, or -1 */
 } mdvrp_dense_rec;
 
-#define MDVRP_EVAL_DENSE 0x1u
-/* Pair families evaluate the filtered candidate lists of an attached filter
- * (mdvrp_filter_attach) instead of the granular lists. */
-#define MDVRP_EVAL_FILTERED 0x2u
-
-/* Evaluate, in parallel, the penalised delta of every move of the families in
- * family_mask for every active unit (paper Sections 3.2.1-3.2.4: Eq. A.1
- * deltas over the granular neighbourhood). The result (per-unit leader
- * candidate and follower candidates) stays in the batch for
- * mdvrp_select_multimove. With MDVRP_EVAL_DENSE every evaluated move is
- * also written to dense (DEVICE array of dense_cap records; *dense_count, a
- * DEVICE counter the caller zeroes, receives the total, which may exceed
- * dense_cap). Families without moves in an instance (2-opt with time
- * windows) are ignored. */
-mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* batch, uint32_t family_mask, uint32_t flags,
-                                      mdvrp_dense_rec* dense, int64_t dense_cap,
-                                      unsigned long long* dense_count, void* stream);
+/* Debug form of mdvrp_eval_neighbourhood: the same evaluation (with flags
+ * MDVRP_EVAL_FILTERED as there), writing every evaluated move, improving or
+ * not, to dense (DEVICE array of dense_cap records); *dense_count, a DEVICE
+ * counter the caller zeroes, receives the total, which may exceed dense_cap. */
+mdvrp_status mdvrp_eval_dense(mdvrp_batch* batch, uint32_t family_mask, uint32_t flags, mdvrp_dense_rec* dense,
+                              int64_t dense_cap, unsigned long long* dense_count, void* stream);
 
 /* Leader-follower selection (Section 3.2.5) over the last evaluation: the
  * leader is the move with the smallest (dF, id) and is taken when dF < 0;
@@ -227,9 +268,11 @@ mdvrp_status mdvrp_select_multimove(mdvrp_batch* batch, uint32_t family_mask, in
                                     uint64_t* sel_ids, int64_t* sel_dF, int32_t* sel_count, int32_t sel_cap,
                                     void* stream);
 
-/* Apply the selected moves of every unit (they are route-disjoint, so the
- * order does not matter), delete emptied routes and rebuild the segment
- * state of the changed routes. */
+/* Apply the selected moves of every unit: the update of the current solution
+ * by the accepted move set of Algorithm 2 (the leader and its followers of
+ * Section 3.2.5). The moves are route-disjoint, so the order does not matter;
+ * emptied routes are deleted and the segment state of the changed routes is
+ * rebuilt. */
 mdvrp_status mdvrp_apply_moves(mdvrp_batch* batch, void* stream);
 
 #define MDVRP_LS_PASSES 0 /* Algorithm 2: per pass, every family in a seeded random order */
@@ -327,7 +370,11 @@ mdvrp_status mdvrp_profile_read(mdvrp_batch* batch, int64_t* launches, double* m
  * bitmap: zeroed DEVICE array; instance k of the batch (order of the
  * instance list given at creation) owns words [sum_{j<k} W_j, ...) with
  * W_j = ceil(N_j*N_j / 32). bitmap_words must cover all instances.
- * The results of the evaluation itself are discarded. Synchronises. */
+ * Arcs between a customer and a depot that Depot-Insert and Depot-Replace read
+ * from the instance's depot-arc table (instances with at most 64 depots) are
+ * not matrix reads and are not marked; the table is 16 bytes per (customer,
+ * depot) pair. The results of the evaluation itself are discarded.
+ * Synchronises. */
 mdvrp_status mdvrp_eval_footprint(mdvrp_batch* batch, uint32_t family_mask, uint32_t* bitmap, int64_t bitmap_words,
                                   void* stream);
 

@@ -789,6 +789,14 @@ extern "C" mdvrp_status mdvrp_solutions_load(mdvrp_batch* B, const int32_t* node
   mdvrp_status st = mdvrp_validate_solutions_host(descs.data(), (int32_t)descs.size(), B->unit_inst.data(),
                                                   B->n_units, hn.data(), ho.data(), hs.data(), he_.data(), hu.data());
   if (st) return st;
+  // the segment arithmetic is int32: a route longer than the instance's guard could overflow
+  for (int k = 0; k < B->n_units; ++k) {
+    const int64_t guard = B->inst[B->unit_inst[k]]->len_guard;
+    for (int r = hu[k]; r < hu[k + 1]; ++r)
+      if (ho[r + 1] - ho[r] > guard)
+        return fail(MDVRP_ERANGE, "unit %d route %d: %d customers, beyond the int32-safe length %lld", k, r - hu[k],
+                    ho[r + 1] - ho[r], (long long)guard);
+  }
   const LaunchCtx L = B->ctx(stream);
   B->loaded = false;
   B->state_changed();
@@ -855,32 +863,117 @@ static void step_begin(const LaunchCtx& L, int fmode, int rescore) {
                      rescore);
 }
 
-extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, uint32_t flags,
-                                                 mdvrp_dense_rec* dense, int64_t dense_cap,
-                                                 unsigned long long* dense_count, void* stream) {
+namespace {
+
+// Host check of caller candidate lists (copied to the host): entries are customers of
+// the unit's instance other than the anchor, or -1; no entry repeats within a list.
+mdvrp_status check_cand_lists(const mdvrp_batch* B, const int32_t* cand, int32_t k, hipStream_t s) {
+  int64_t total = 0;
+  for (const UnitDesc& u : B->h_units) {
+    if (k > u.theta) return fail(MDVRP_EINVAL, "candidate lists of %d entries exceed theta = %d", k, u.theta);
+    total += (int64_t)u.nc * k;
+  }
+  std::vector<int32_t> h(std::max<int64_t>(total, 1));
+  HIP_TRY(hipMemcpyAsync(h.data(), cand, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int64_t at = 0;
+  std::vector<int32_t> seen;
+  for (int ui = 0; ui < B->n_units; ++ui) {
+    const UnitDesc& u = B->h_units[ui];
+    seen.assign(u.n, -1);
+    for (int i = 0; i < u.nc; ++i, at += k)
+      for (int j = 0; j < k; ++j) {
+        const int v = h[at + j];
+        if (v == -1) continue;
+        if (v < u.nd || v >= u.n || v == u.nd + i)
+          return fail(MDVRP_EINVAL, "unit %d customer %d: list entry %d is not another customer", ui, u.nd + i, v);
+        if (seen[v] == i) return fail(MDVRP_EINVAL, "unit %d customer %d: entry %d repeats", ui, u.nd + i, v);
+        seen[v] = i;
+      }
+  }
+  return MDVRP_OK;
+}
+
+// Shared body of mdvrp_eval_neighbourhood and mdvrp_eval_dense.
+mdvrp_status eval_impl(mdvrp_batch* B, uint32_t fam, const int32_t* cand, int32_t k, const mdvrp_moves* moves,
+                       uint32_t flags, mdvrp_dense_rec* dense, int64_t dense_cap, unsigned long long* dense_count,
+                       int64_t* n_evaluated, void* stream) {
   if (!B) return fail(MDVRP_EINVAL, "null batch");
   if (fam & ~MDVRP_FAM_ALL) return fail(MDVRP_EINVAL, "unknown family bits");
-  if ((flags & MDVRP_EVAL_DENSE) && (!dense || !dense_count || dense_cap < 0))
-    return fail(MDVRP_EINVAL, "dense output needs a buffer and a counter");
-  if (flags & ~(MDVRP_EVAL_DENSE | MDVRP_EVAL_FILTERED)) return fail(MDVRP_EINVAL, "unknown flags");
+  if (flags & ~MDVRP_EVAL_FILTERED) return fail(MDVRP_EINVAL, "unknown flags");
+  if (cand && (flags & MDVRP_EVAL_FILTERED)) return fail(MDVRP_EINVAL, "caller lists and the filter's lists together");
+  if (cand && k < 1) return fail(MDVRP_EINVAL, "candidate lists need k >= 1");
   if ((flags & MDVRP_EVAL_FILTERED) && B->kc == 0) return fail(MDVRP_ESTATE, "no filter attached");
+  if (moves && (!moves->count || moves->cap < 0 || (moves->cap > 0 && (!moves->dF || !moves->dD || !moves->id ||
+                !moves->kind || !moves->variant || !moves->changed || !moves->unit || !moves->a || !moves->b ||
+                !moves->res))))
+    return fail(MDVRP_EINVAL, "incomplete move list");
   static_assert(sizeof(mdvrp_dense_rec) == sizeof(DenseRec), "dense record layout");
   if (mdvrp_status e = need_loaded(B)) return e;
+  hipStream_t s = S(stream);
+  if (cand) {
+    if (mdvrp_status e = check_cand_lists(B, cand, k, s)) return e;
+    // point every unit at its slice of the caller's lists for this evaluation
+    std::vector<UnitDesc> u = B->h_units;
+    int64_t off = 0;
+    for (UnitDesc& x : u) {
+      x.fcand = const_cast<int32_t*>(cand) + off * k;
+      x.kc = k;
+      x.ftiles = (int32_t)(((int64_t)x.nc * k + kTileItems - 1) / kTileItems);
+      off += x.nc;
+    }
+    HIP_TRY(hipMemcpyAsync(B->d_units, u.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (moves) HIP_TRY(hipMemsetAsync(moves->count, 0, sizeof(unsigned long long), s));
   LaunchCtx L = B->ctx(stream);
+  const bool filt = cand || (flags & MDVRP_EVAL_FILTERED);
   L.compact = (flags & MDVRP_EVAL_FILTERED) ? 1 : 0;
-  step_begin(L, (flags & MDVRP_EVAL_FILTERED) ? 1 : 0, 0);
-  DenseOut D{(DenseRec*)dense, dense_count, dense_cap};
+  step_begin(L, filt ? 1 : 0, 0);
+  DenseOut D{};
+  D.rec = (DenseRec*)dense;
+  D.count = dense_count;
+  D.cap = dense_cap;
+  if (moves) {
+    D.ml.dF = moves->dF; D.ml.dD = moves->dD; D.ml.id = moves->id; D.ml.kind = moves->kind;
+    D.ml.variant = moves->variant; D.ml.changed = moves->changed; D.ml.unit = moves->unit;
+    D.ml.a = moves->a; D.ml.b = moves->b; D.ml.res = moves->res; D.ml.cap = moves->cap; D.ml.count = moves->count;
+  }
+  const bool sink = dense || moves;
   const uint32_t cls = eval_classes(L, fam);
   for (int c = 0; c < 3; ++c)
     if (cls >> c & 1)
-      timed(B, L.stream, c, [&] {
-        launch_eval_class(L, fam, c, (flags & MDVRP_EVAL_DENSE) ? &D : nullptr,
-                          (flags & MDVRP_EVAL_DENSE) ? 0 : B->shape_for(fam));
-      });
+      timed(B, L.stream, c, [&] { launch_eval_class(L, fam, c, sink ? &D : nullptr, sink ? 0 : B->shape_for(fam)); });
   HIP_TRY(hipGetLastError());
+  if (n_evaluated) launch_evaluated_export(L, n_evaluated);
   B->planned = false;
   B->eval_fam = fam;
+  if (cand) {
+    HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (moves) {
+    unsigned long long n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, moves->count, sizeof n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((int64_t)n > moves->cap)
+      return fail(MDVRP_ENOSPC, "the move list needs %llu rows (capacity %lld)", n, (long long)moves->cap);
+  }
   return MDVRP_OK;
+}
+
+}  // namespace
+
+extern "C" mdvrp_status mdvrp_eval_neighbourhood(mdvrp_batch* B, uint32_t fam, const int32_t* cand, int32_t k,
+                                                 mdvrp_moves* moves, uint32_t flags, int64_t* n_evaluated,
+                                                 void* stream) {
+  return eval_impl(B, fam, cand, k, moves, flags, nullptr, 0, nullptr, n_evaluated, stream);
+}
+
+extern "C" mdvrp_status mdvrp_eval_dense(mdvrp_batch* B, uint32_t fam, uint32_t flags, mdvrp_dense_rec* dense,
+                                         int64_t dense_cap, unsigned long long* dense_count, void* stream) {
+  if (!dense || !dense_count || dense_cap < 0) return fail(MDVRP_EINVAL, "dense output needs a buffer and a counter");
+  return eval_impl(B, fam, nullptr, 0, nullptr, flags, dense, dense_cap, dense_count, nullptr, stream);
 }
 
 extern "C" mdvrp_status mdvrp_eval_footprint(mdvrp_batch* B, uint32_t fam, uint32_t* bitmap, int64_t words,
@@ -1175,17 +1268,18 @@ void carve_mlp(Carve& cv, MlpDev* M) {
   m.w2f = cv.take<char>(16 * 8 * 64 * 16);
   m.w2h = cv.take<uint16_t>(256 * 256);
   m.w3b = cv.take<float>(256);
-  m.scratch = cv.take<float>(4);
+  m.scratch = cv.take<float>(2 + kBceBlocks);
   if (M) *M = m;
 }
 
 struct ActBufs {
   uint16_t *h1, *h2, *G2, *G1;
   float* dz;
+  float* part;  // partial sums of the backward pass
 };
 
 // Activation workspace of n samples: h1, h2 (rows padded for the forward tiles), the
-// two backward gradients, and dlogits.
+// two backward gradients, dlogits, and the backward pass's partial sums.
 void carve_act(Carve& cv, int n, ActBufs* A) {
   const int pad = mlp_row_pad();
   const size_t rows = ((size_t)std::max(n, 1) + pad - 1) / pad * pad;
@@ -1195,6 +1289,7 @@ void carve_act(Carve& cv, int n, ActBufs* A) {
   a.G2 = cv.take<uint16_t>(rows * 256);
   a.G1 = cv.take<uint16_t>(rows * 256);
   a.dz = cv.take<float>(rows);
+  a.part = cv.take<float>(mlp_grad_part_floats(n));
   if (A) *A = a;
 }
 
@@ -1293,8 +1388,7 @@ extern "C" mdvrp_status mdvrp_mlp_backward(const mdvrp_mlp* M, const uint16_t* x
   ActBufs A{};
   mdvrp_status st = check_act(n, act_ws, act_bytes, &A);
   if (st) return st;
-  launch_mlp_zero(S(stream), grads, mlp_param_count());
-  launch_mlp_backward(S(stream), M->d, x, n, dlogits, A.h1, A.h2, grads, A.G2, A.G1);
+  launch_mlp_backward(S(stream), M->d, x, n, dlogits, A.h1, A.h2, grads, A.G2, A.G1, A.part);
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
 }
@@ -1302,7 +1396,7 @@ extern "C" mdvrp_status mdvrp_mlp_backward(const mdvrp_mlp* M, const uint16_t* x
 extern "C" mdvrp_status mdvrp_mlp_bce(mdvrp_mlp* M, const float* logits, const float* labels, const float* weights,
                                       int32_t n, float* dlogits, float* loss, void* stream) {
   if (!M || n < 0 || (n > 0 && (!logits || !labels || !dlogits))) return fail(MDVRP_EINVAL, "bad argument");
-  launch_bce(S(stream), logits, labels, weights, n, M->d.scratch, dlogits, loss);
+  launch_bce(S(stream), logits, labels, weights, n, M->d.scratch, bce_blocks(n, kBceBlocks), dlogits, loss);
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
 }
@@ -1326,9 +1420,8 @@ extern "C" mdvrp_status mdvrp_mlp_train_step(mdvrp_mlp* M, const uint16_t* x, co
   if (st) return st;
   hipStream_t s = S(stream);
   launch_mlp_forward(s, M->d, x, n, logits, A.h1, A.h2);
-  launch_bce(s, logits, labels, weights, n, M->d.scratch, A.dz, loss);
-  launch_mlp_zero(s, grads, mlp_param_count());
-  launch_mlp_backward(s, M->d, x, n, A.dz, A.h1, A.h2, grads, A.G2, A.G1);
+  launch_bce(s, logits, labels, weights, n, M->d.scratch, bce_blocks(n, kBceBlocks), A.dz, loss);
+  launch_mlp_backward(s, M->d, x, n, A.dz, A.h1, A.h2, grads, A.G2, A.G1, A.part);
   launch_adam(s, M->d, grads, lr, step);
   launch_mlp_pack(s, M->d);
   HIP_TRY(hipGetLastError());

@@ -81,9 +81,29 @@ __device__ __forceinline__ void dense_put(const DenseOut& D, int unit, const Mov
   D.rec[k] = r;
 }
 
+// Append an improving move to the compacted list (one atomic per wavefront: the
+// compiler aggregates the same-address increments of the active lanes).
+__device__ __forceinline__ void move_put(const MoveList& M, int unit, const MoveEval& m, uint64_t id) {
+  const unsigned long long k = atomicAdd(M.count, 1ull);
+  if ((int64_t)k >= M.cap) return;
+  M.dF[k] = m.dF;
+  M.dD[k] = m.dD;
+  M.id[k] = id;
+  M.kind[k] = (uint8_t)(id >> 56);
+  M.variant[k] = (uint8_t)(id >> 48);
+  M.changed[k] = (uint8_t)((m.dTW != 0) | (m.dLX != 0) << 1 | (m.dDX != 0) << 2 | (m.dV4 != 0) << 3);
+  M.unit[k] = unit;
+  M.a[k] = (int32_t)((id >> 24) & 0xffffff);
+  M.b[k] = (int32_t)(id & 0xffffff);
+  M.res[3 * k] = m.res[0];
+  M.res[3 * k + 1] = m.res[1];
+  M.res[3 * k + 2] = m.res[2];
+}
+
 // Result sink of the evaluators: leader/follower bookkeeping plus, by mode SM,
-// nothing (0), the dense record of every evaluated move (1), or the anchor's
-// improving flag (2: label[item] = 1 when some move of the anchor has dF < 0).
+// nothing (0), the dense record of every evaluated move and / or the list of the
+// improving ones (1), or the anchor's improving flag (2: label[item] = 1 when some
+// move of the anchor has dF < 0).
 template <int SM>
 struct Sink {
   ItemOut* o;
@@ -95,7 +115,10 @@ struct Sink {
 template <int SM>
 __device__ __forceinline__ void take(const UnitDesc& U, Sink<SM>& s, const MoveEval& m, uint64_t id) {
   item_take(U, *s.o, m, id);
-  if constexpr (SM == 1) dense_put(s.d, s.unit, m, id);
+  if constexpr (SM == 1) {
+    if (s.d.rec) dense_put(s.d, s.unit, m, id);
+    if (s.d.ml.count && m.dF < 0) move_put(s.d.ml, s.unit, m, id);
+  }
   if constexpr (SM == 2) {
     if (m.dF < 0) s.d.label[U.item_base + s.item] = 1;
   }

@@ -204,12 +204,12 @@ __device__ __forceinline__ void eval_dins(const UnitDesc& U, const SEG* fw, cons
   const SEG pre = ld(fw, A.off + pu);
   SEG R1 = pre;
   if (!OPEN) {
-    ar.mark(U, pre.node, d);
+    if (!U.dep_arc) ar.mark(U, pre.node, d);
     const int4 a = dep_arcs(U, pre.node, d);
     R1 = cat(pre, a.z, a.w, node_seg<SEG>(U, d));
   }
   const SEG suf = ld(bw, A.off + pu + 1);
-  ar.mark(U, d, suf.node);
+  if (!U.dep_arc) ar.mark(U, d, suf.node);
   const int4 a2 = dep_arcs(U, suf.node, d);
   const SEG R2 = cat(node_seg<SEG>(U, d), a2.x, a2.y, suf);
   depot_delta(U, A, 2, R1, A.start, OPEN ? -1 : d, R2, d, A.end, -1, d, m);
@@ -224,7 +224,7 @@ __device__ __forceinline__ void eval_drep(const UnitDesc& U, const SEG* fw, cons
   SEG R;
   if (cs == 0) {
     const SEG suf = ld(bw, A.off + 1);
-    ar.mark(U, d, suf.node);
+    if (!U.dep_arc) ar.mark(U, d, suf.node);
     const int4 a = dep_arcs(U, suf.node, d);
     R = cat(node_seg<SEG>(U, d), a.x, a.y, suf);
   } else {
@@ -242,11 +242,11 @@ __device__ __forceinline__ void eval_drep(const UnitDesc& U, const SEG* fw, cons
       } else {
         core = A.L == 1 ? node_seg<SEG>(U, first) : mid_range<SEG, TW>(U, fw, A, 1, A.L, 0);
       }
-      ar.mark(U, d, first);
+      if (!U.dep_arc) ar.mark(U, d, first);
       const int4 a = dep_arcs(U, first, d);
       body = cat(node_seg<SEG>(U, d), a.x, a.y, core);
     }
-    ar.mark(U, pre.node, d);
+    if (!U.dep_arc) ar.mark(U, pre.node, d);
     const int4 a = dep_arcs(U, pre.node, d);
     R = cat(body, a.z, a.w, node_seg<SEG>(U, d));
   }

@@ -7,13 +7,31 @@
 
 namespace mdvrp {
 
-// Optional outputs of an evaluation: every evaluated move (rec/count/cap), or
-// per-anchor improving flags (label, pair kinds only, full lists).
+// Compacted improving-move list (structure of arrays, caller-owned device arrays).
+struct MoveList {
+  int64_t* dF = nullptr;
+  int64_t* dD = nullptr;
+  uint64_t* id = nullptr;
+  uint8_t* kind = nullptr;
+  uint8_t* variant = nullptr;
+  uint8_t* changed = nullptr;
+  int32_t* unit = nullptr;
+  int32_t* a = nullptr;
+  int32_t* b = nullptr;
+  int32_t* res = nullptr;  // [cap][3]
+  int64_t cap = 0;
+  unsigned long long* count = nullptr;  // null: no list
+};
+
+// Optional outputs of an evaluation: every evaluated move (rec/count/cap), the
+// improving moves (ml), or per-anchor improving flags (label, pair kinds only,
+// full lists).
 struct DenseOut {
   DenseRec* rec = nullptr;
   unsigned long long* count = nullptr;
   int64_t cap = 0;
   uint8_t* label = nullptr;
+  MoveList ml;
 };
 
 // Everything a launch needs about a batch.
@@ -59,6 +77,8 @@ void launch_export(const LaunchCtx& L, int32_t* nodes, int32_t* offs, int32_t* s
                    int32_t* counts, const int32_t* node_base, const int32_t* route_base);
 void launch_load(const LaunchCtx& L, const int32_t* nodes, const int32_t* offs, const int32_t* starts,
                  const int32_t* ends, const int32_t* unit_route_off);
+// Moves evaluated by every unit in the latest evaluation (out[n_units]).
+void launch_evaluated_export(const LaunchCtx& L, int64_t* out);
 void launch_sel_export(const LaunchCtx& L, uint64_t* ids, int64_t* dF, int32_t* counts, int32_t cap_per_unit);
 constexpr int kStateWords = 12;  // per-unit counters exported by launch_state_export
 void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][kStateWords] */);
@@ -66,7 +86,8 @@ void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][kStateWor
 // ---- learned move filter
 // Device buffers of one network: fp32 master parameters, Adam moments, and the
 // bf16 operand copies the kernels read (W1 / W2 in MFMA fragment order, W2
-// row-major, w3 rounded and widened back to fp32); scratch holds two floats.
+// row-major, w3 rounded and widened back to fp32); scratch holds the loss kernel's weight
+// sum and per-block partials (2 + kBceBlocks floats).
 struct MlpDev {
   float *P, *m, *v;
   void *w1f, *w2f;
@@ -74,6 +95,7 @@ struct MlpDev {
   float* w3b;
   float* scratch;
 };
+constexpr int kBceBlocks = 1024;  // loss-kernel blocks of a network's own scratch
 int mlp_param_count();
 int mlp_row_pad();  // activation buffers hold n rounded up to a multiple of this
 void launch_mlp_pack(hipStream_t s, const MlpDev& M);
@@ -97,10 +119,15 @@ void launch_rank(const LaunchCtx& L, const int32_t* cust_off, int n_cust, const 
 void launch_eta_lists(const LaunchCtx& L, const int32_t* cust_off, int n_tasks);
 void launch_mlp_forward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, float* logits, uint16_t* h1,
                         uint16_t* h2);
-void launch_bce(hipStream_t s, const float* z, const float* y, const float* w, int n, float* wsum, float* dz,
-                float* loss);
+// Blocks of the loss kernel for n samples (at most max_blocks; one partial sum each).
+int bce_blocks(int n, int max_blocks);
+// scratch: [0] weight sum, [1] unused, [2 .. 2 + nb) per-block loss partials; nb = bce_blocks(n, ...).
+void launch_bce(hipStream_t s, const float* z, const float* y, const float* w, int n, float* scratch, int nb,
+                float* dz, float* loss);
+// Floats of partial sums the backward pass of n samples needs.
+size_t mlp_grad_part_floats(int n);
 void launch_mlp_backward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, const float* dz, const uint16_t* h1,
-                         const uint16_t* h2, float* g, uint16_t* G2, uint16_t* G1);
+                         const uint16_t* h2, float* g, uint16_t* G2, uint16_t* G1, float* part);
 void launch_adam(hipStream_t s, const MlpDev& M, const float* g, float lr, int step);
 
 // instance preprocessing

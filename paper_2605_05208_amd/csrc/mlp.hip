@@ -514,8 +514,9 @@ int mlp_row_pad() { return 16 * kFwdT; }
 
 // ---------------------------------------------------------------------------- loss and backward
 
-// wsum = sum of weights (n when weights is null); zeroes the loss accumulator. One block.
-__global__ void k_bce_prep(const float* __restrict__ w, int n, float* __restrict__ wsum, float* __restrict__ loss) {
+// wsum = sum of weights (n when weights is null). One block; the order of the sums is
+// fixed by the block shape, so the result does not vary between runs.
+__global__ void k_bce_prep(const float* __restrict__ w, int n, float* __restrict__ wsum) {
   __shared__ float sh[16];
   float s = 0.f;
   for (int p = threadIdx.x; p < n; p += blockDim.x) s += w ? w[p] : 1.f;
@@ -526,26 +527,45 @@ __global__ void k_bce_prep(const float* __restrict__ w, int n, float* __restrict
     float t = 0.f;
     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
     *wsum = t;
-    if (loss) *loss = 0.f;
   }
 }
 
-// Weighted mean BCE with logits: dz_p = w_p (sigmoid(z_p) - y_p) / sum w, loss += w_p l_p / sum w.
-__global__ void k_bce(const float* __restrict__ z, const float* __restrict__ y, const float* __restrict__ w, int n,
-                      const float* __restrict__ wsum, float* __restrict__ dz, float* __restrict__ loss) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// Weighted mean BCE with logits: dz_p = w_p (sigmoid(z_p) - y_p) / sum w, and the block's
+// share of the loss sum_p w_p l_p / sum w in part[blockIdx.x] (grid-stride over samples;
+// 256 threads per block).
+__global__ __launch_bounds__(256) void k_bce(const float* __restrict__ z, const float* __restrict__ y,
+                                             const float* __restrict__ w, int n, const float* __restrict__ wsum,
+                                             float* __restrict__ dz, float* __restrict__ part) {
+  __shared__ float sh[4];
   const float ws = *wsum;
   const float inv = ws > 0.f ? 1.f / ws : 0.f;
   float l = 0.f;
-  if (p < n) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
     const float wp = w ? w[p] : 1.f;
     const float zp = z[p];
     const float sg = 1.f / (1.f + expf(-zp));
     dz[p] = wp * (sg - y[p]) * inv;
-    l = wp * ((zp > 0.f ? zp : 0.f) - zp * y[p] + log1pf(expf(-fabsf(zp)))) * inv;
+    l += wp * ((zp > 0.f ? zp : 0.f) - zp * y[p] + log1pf(expf(-fabsf(zp)))) * inv;
   }
   for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
-  if (lane_id() == 0 && loss) atomicAdd(loss, l);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// loss = sum of the nb block partials in a fixed order (one block of 1024 threads).
+__global__ __launch_bounds__(1024) void k_bce_final(const float* __restrict__ part, int nb, float* __restrict__ loss) {
+  __shared__ float sh[16];
+  float s = 0.f;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+    *loss = t;
+  }
 }
 
 __global__ void k_zero(float* __restrict__ g, int n) {
@@ -553,10 +573,13 @@ __global__ void k_zero(float* __restrict__ g, int n) {
   if (i < n) g[i] = 0.f;
 }
 
-// Output layer: g[w3] += sum_p dz_p h2_p, g[b3] += sum dz, g[b2] += sum_p G2_p and
+// Output layer, block share: part[blockIdx.x][0..255] = sum_p G2_p (the b2 gradient),
+// [256..511] = sum_p dz_p h2_p (w3), [512] = sum_p dz_p (b3), over the block's samples;
 // G2[p][o] = dz_p w3[o] [h2[p][o] > 0] rounded to bf16 (the layer-2 output gradient).
+// Rows of kOutPart floats follow the parameter order b2, w3, b3.
+constexpr int kOutPart = 2 * kH + 1;
 __global__ __launch_bounds__(256) void k_back_out(const float* __restrict__ dz, const uint16_t* __restrict__ h2,
-                                                  const float* __restrict__ w3b, int n, float* __restrict__ g,
+                                                  const float* __restrict__ w3b, int n, float* __restrict__ part,
                                                   uint16_t* __restrict__ G2) {
   const int o = threadIdx.x;
   float aw = 0.f, ab2 = 0.f, ab3 = 0.f;
@@ -569,9 +592,10 @@ __global__ __launch_bounds__(256) void k_back_out(const float* __restrict__ dz, 
     ab2 += gv;
     G2[(int64_t)p * kH + o] = f2bf(gv);
   }
-  atomicAdd(&g[P_W3 + o], aw);
-  atomicAdd(&g[P_B2 + o], ab2);
-  if (o == 0) atomicAdd(&g[P_B3], ab3);
+  float* row = part + (int64_t)blockIdx.x * kOutPart;
+  row[o] = ab2;
+  row[kH + o] = aw;
+  if (o == 0) row[2 * kH] = ab3;
 }
 
 // G1 = (G2 W2) masked by [h1 > 0], rounded to bf16; one wave per 16 x 16 output tile.
@@ -608,20 +632,21 @@ __global__ __launch_bounds__(256) void k_back_hidden(const uint16_t* __restrict_
   }
 }
 
-// g[off + o] += sum_p G[p][o] over bf16 rows of 256.
-__global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ G, int n, float* __restrict__ g, int off) {
+// Block share of the column sums of bf16 rows of 256: part[blockIdx.x][o] = sum_p G[p][o].
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ G, int n, float* __restrict__ part) {
   const int o = threadIdx.x;
   float acc = 0.f;
   for (int p = blockIdx.x; p < n; p += gridDim.x) acc += bf2f(G[(int64_t)p * kH + o]);
-  atomicAdd(&g[off + o], acc);
+  part[(int64_t)blockIdx.x * kH + o] = acc;
 }
 
 constexpr int kSplitK = 1024;  // samples per wave in the weight-gradient products
 
-// Weight gradient C[M][N] += sum_p L[p][m] R[p][n] over the samples (both bf16, row-major
-// with row lengths M and N), split over the samples; one wave per (16 x 16 tile, chunk).
+// Weight gradient of one chunk of kSplitK samples: part[ch][M][N] = sum_p L[p][m] R[p][n]
+// over the chunk's samples (both bf16, row-major with row lengths M and N); one wave per
+// (16 x 16 tile, chunk).
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ Lm, int M, const uint16_t* __restrict__ Rm,
-                                               int N, int n, float* __restrict__ C) {
+                                               int N, int n, float* __restrict__ part) {
   const int wave = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4;
   const int tm = M / 16, tn = N / 16, chunks = (n + kSplitK - 1) / kSplitK;
   for (int t = blockIdx.x * 4 + wave; t < tm * tn * chunks; t += gridDim.x * 4) {
@@ -639,9 +664,20 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ Lm, 
       }
       acc = mfma(a, b, acc);
     }
+    float* C = part + (int64_t)ch * M * N;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) atomicAdd(&C[((tile / tn) * 16 + 4 * g + r) * N + nn], acc[r]);
+    for (int r = 0; r < 4; ++r) C[((tile / tn) * 16 + 4 * g + r) * N + nn] = acc[r];
   }
+}
+
+// out[j] = sum over r = 0, 1, .., rows - 1 of part[r][j] (the same order every run).
+__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ part, int rows, int width,
+                                                     float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= width) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += part[(int64_t)r * width + j];
+  out[j] = s;
 }
 
 // Adam on the fp32 master parameters (bias-corrected moments).
@@ -724,30 +760,54 @@ void launch_mlp_forward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n
                      (const bf16x8*)M.w2f, (const float*)M.P, (const float*)M.w3b, logits, h1, h2);
 }
 
-void launch_bce(hipStream_t s, const float* z, const float* y, const float* w, int n, float* wsum, float* dz,
-                float* loss) {
-  hipLaunchKernelGGL(k_bce_prep, dim3(1), dim3(1024), 0, s, w, n, wsum, loss);
-  if (n > 0) hipLaunchKernelGGL(k_bce, dim3((n + 255) / 256), dim3(256), 0, s, z, y, w, n, wsum, dz, loss);
+int bce_blocks(int n, int max_blocks) { return grid_for(n, 256, max_blocks); }
+
+void launch_bce(hipStream_t s, const float* z, const float* y, const float* w, int n, float* scratch, int nb,
+                float* dz, float* loss) {
+  hipLaunchKernelGGL(k_bce_prep, dim3(1), dim3(1024), 0, s, w, n, scratch);
+  if (n > 0) hipLaunchKernelGGL(k_bce, dim3(nb), dim3(256), 0, s, z, y, w, n, (const float*)scratch, dz, scratch + 2);
+  if (loss) hipLaunchKernelGGL(k_bce_final, dim3(1), dim3(1024), 0, s, (const float*)scratch + 2, n > 0 ? nb : 0, loss);
 }
 
-// Gradient of sum_p dz_p logit_p accumulated into g (the caller zeroes g); h1, h2 from
-// the forward pass; G2, G1 scratch of [n][256] bf16 each.
+size_t mlp_grad_part_floats(int n) {
+  const int64_t rows = grid_for(n, 1, 1024), chunks = (std::max(n, 1) + kSplitK - 1) / kSplitK;
+  return (size_t)(rows * kOutPart + rows * kH + chunks * (int64_t)kH * (kH + kF));
+}
+
+// Gradient of sum_p dz_p logit_p written to g (every parameter); h1, h2 from the forward
+// pass; G2, G1 scratch of [n][256] bf16 each; part: mlp_grad_part_floats(n) floats of
+// per-block and per-chunk partial sums, reduced in a fixed order (the gradient does not
+// vary between runs).
 void launch_mlp_backward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, const float* dz, const uint16_t* h1,
-                         const uint16_t* h2, float* g, uint16_t* G2, uint16_t* G1) {
-  if (n <= 0) return;
+                         const uint16_t* h2, float* g, uint16_t* G2, uint16_t* G1, float* part) {
+  if (n <= 0) {
+    launch_mlp_zero(s, g, P_N);
+    return;
+  }
   const int rows = grid_for(n, 1, 1024);
-  hipLaunchKernelGGL(k_back_out, dim3(rows), dim3(kH), 0, s, dz, h2, (const float*)M.w3b, n, g, G2);
   const int chunks = (n + kSplitK - 1) / kSplitK;
+  float* p_out = part;
+  float* p_b1 = p_out + (int64_t)rows * kOutPart;
+  float* p_w2 = p_b1 + (int64_t)rows * kH;
+  float* p_w1 = p_w2 + (int64_t)chunks * kH * kH;
+  hipLaunchKernelGGL(k_back_out, dim3(rows), dim3(kH), 0, s, dz, h2, (const float*)M.w3b, n, p_out, G2);
+  hipLaunchKernelGGL(k_reduce_rows, dim3((kOutPart + 255) / 256), dim3(256), 0, s, (const float*)p_out, rows,
+                     kOutPart, g + P_B2);
   // dW2[o2][o1] = sum_p G2[p][o2] h1[p][o1]
   hipLaunchKernelGGL(k_wgrad, dim3(grid_for((int64_t)(kH / 16) * (kH / 16) * chunks, 4, 4096)), dim3(256), 0, s,
-                     (const uint16_t*)G2, kH, h1, kH, n, g + P_W2);
+                     (const uint16_t*)G2, kH, h1, kH, n, p_w2);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(kH * kH / 256), dim3(256), 0, s, (const float*)p_w2, chunks, kH * kH,
+                     g + P_W2);
   const int64_t tiles = (int64_t)(n + 15) / 16 * (kH / 16);
   hipLaunchKernelGGL(k_back_hidden, dim3(grid_for(tiles, 4, 4096)), dim3(256), 0, s, (const uint16_t*)G2,
                      (const uint16_t*)M.w2h, h1, n, G1);
-  hipLaunchKernelGGL(k_colsum, dim3(rows), dim3(kH), 0, s, (const uint16_t*)G1, n, g, P_B1);
+  hipLaunchKernelGGL(k_colsum, dim3(rows), dim3(kH), 0, s, (const uint16_t*)G1, n, p_b1);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(256), 0, s, (const float*)p_b1, rows, kH, g + P_B1);
   // dW1[o1][i] = sum_p G1[p][o1] x[p][i]
   hipLaunchKernelGGL(k_wgrad, dim3(grid_for((int64_t)(kH / 16) * (kF / 16) * chunks, 4, 4096)), dim3(256), 0, s,
-                     (const uint16_t*)G1, kH, x, kF, n, g + P_W1);
+                     (const uint16_t*)G1, kH, x, kF, n, p_w1);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(kH * kF / 256), dim3(256), 0, s, (const float*)p_w1, chunks, kH * kF,
+                     g + P_W1);
 }
 
 void launch_adam(hipStream_t s, const MlpDev& M, const float* g, float lr, int step) {

@@ -294,6 +294,14 @@ void launch_export(const LaunchCtx& L, int32_t* nodes, int32_t* offs, int32_t* s
     else hipLaunchKernelGGL((k_export<SegNT, false>), dim3(L.n_units), dim3(kUnitBlock), 0, L.stream, L.units, nodes, offs, starts, ends, counts, node_base, route_base);
   }
 }
+__global__ static void k_evaluated_export(const UnitDesc* units, int n_units, int64_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_units) out[i] = units[i].ctl->last_eval;
+}
+void launch_evaluated_export(const LaunchCtx& L, int64_t* out) {
+  hipLaunchKernelGGL(k_evaluated_export, dim3((L.n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units,
+                     out);
+}
 void launch_sel_export(const LaunchCtx& L, uint64_t* ids, int64_t* dF, int32_t* counts, int32_t cap) {
   hipLaunchKernelGGL(k_sel_export, dim3(L.n_units), dim3(256), 0, L.stream, L.units, L.n_units, ids, dF, counts, cap);
 }

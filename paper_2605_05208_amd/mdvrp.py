@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmdvrp.so")
 OK, EINVAL, ERANGE, ENOSPC, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 FAM_RELOCATE, FAM_SWAP, FAM_2OPT_STAR, FAM_2OPT, FAM_DEPOT_INSERT, FAM_DEPOT_REPLACE = 1, 2, 4, 8, 16, 32
 FAM_ALL = 0x3F
-EVAL_DENSE, EVAL_FILTERED = 1, 2
+EVAL_FILTERED = 2
 LS_PASSES, LS_UNION = 0, 1
 FILTER_NONE, FILTER_LISTS, FILTER_MLP = 0, 1, 2
 RESCORE_STEP, RESCORE_PASS = 0, 1
@@ -41,6 +41,18 @@ class InstanceDesc(C.Structure):
                 ("open_routes", C.c_int32), ("has_tw", C.c_int32), ("theta", C.c_int32),
                 ("w_tw", C.c_int32), ("w_load", C.c_int32), ("w_dur", C.c_int32), ("w_depot", C.c_int32),
                 ("layout", C.c_int32)]
+
+
+class Moves(C.Structure):
+    """mdvrp_moves: device arrays of the improving-move list."""
+    _fields_ = [("dF", C.c_void_p), ("dD", C.c_void_p), ("id", C.c_void_p), ("kind", C.c_void_p),
+                ("variant", C.c_void_p), ("changed", C.c_void_p), ("unit", C.c_void_p), ("a", C.c_void_p),
+                ("b", C.c_void_p), ("res", C.c_void_p), ("cap", C.c_int64), ("count", C.c_void_p)]
+
+
+MOVE_FIELDS = [("dF", np.int64), ("dD", np.int64), ("id", np.uint64), ("kind", np.uint8), ("variant", np.uint8),
+               ("changed", np.uint8), ("unit", np.int32), ("a", np.int32), ("b", np.int32), ("res", np.int32, (3,))]
+MOVE_DTYPE = np.dtype(MOVE_FIELDS)
 
 
 class LsOptions(C.Structure):
@@ -67,7 +79,8 @@ EXPORTED = [
     "mdvrp_instance_info", "mdvrp_instance_copy_lists", "mdvrp_instance_destroy",
     "mdvrp_batch_workspace_query", "mdvrp_batch_create", "mdvrp_batch_destroy",
     "mdvrp_validate_solutions_host", "mdvrp_solutions_load", "mdvrp_solutions_export", "mdvrp_batch_cost",
-    "mdvrp_batch_state", "mdvrp_eval_neighbourhood", "mdvrp_select_multimove", "mdvrp_apply_moves",
+    "mdvrp_batch_state", "mdvrp_eval_neighbourhood", "mdvrp_eval_dense", "mdvrp_select_multimove",
+    "mdvrp_apply_moves",
     "mdvrp_local_search_to_optimum", "mdvrp_status_string", "mdvrp_last_error", "mdvrp_family_order",
     "mdvrp_profile_enable", "mdvrp_profile_sampling", "mdvrp_profile_read", "mdvrp_eval_footprint",
     "mdvrp_mlp_workspace_query", "mdvrp_mlp_create", "mdvrp_mlp_params", "mdvrp_mlp_sync", "mdvrp_mlp_destroy",
@@ -101,7 +114,8 @@ def lib():
             "mdvrp_solutions_export": [p, p, p, p, p, p, p],
             "mdvrp_batch_cost": [p, p, p, p],
             "mdvrp_batch_state": [p, p],
-            "mdvrp_eval_neighbourhood": [p, u32, u32, p, i64, p, p],
+            "mdvrp_eval_neighbourhood": [p, u32, p, i32, p, u32, p, p],
+            "mdvrp_eval_dense": [p, u32, u32, p, i64, p, p],
             "mdvrp_select_multimove": [p, u32, i32, p, p, p, i32, p],
             "mdvrp_apply_moves": [p, p],
             "mdvrp_local_search_to_optimum": [p, p, p, p],
@@ -319,21 +333,57 @@ class Batch:
         return {name: (int(n[k]), float(ms[k])) for k, name in enumerate(PROF_CLASSES)}
 
     # ------------------------------------------------------------------ hot path
-    def eval_neighbourhood(self, fam_mask=FAM_ALL, dense_cap=0, filtered=False):
+    def eval_neighbourhood(self, fam_mask=FAM_ALL, dense_cap=0, filtered=False, cand=None, moves_cap=0,
+                           want_evaluated=False):
+        """Evaluate the families of fam_mask. dense_cap > 0: every evaluated move as a
+        DENSE_DTYPE array (mdvrp_eval_dense). Otherwise mdvrp_eval_neighbourhood with,
+        optionally, caller candidate lists cand (int32 [n_customers of the batch, k], units
+        in batch order), the improving-move list (moves_cap rows; MOVE_DTYPE array) and the
+        per-unit evaluated counts. Returns (moves or None, evaluated or None) then."""
         torch = _torch()
         fl = EVAL_FILTERED if filtered else 0
         if dense_cap:
             rec = torch.empty(dense_cap * DENSE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
             cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-            check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, EVAL_DENSE | fl, _dptr(rec), dense_cap,
-                                                 _dptr(cnt), _stream()))
+            check(lib().mdvrp_eval_dense(self.handle, fam_mask, fl, _dptr(rec), dense_cap, _dptr(cnt), _stream()))
             torch.cuda.synchronize()
             n = int(cnt.item())
             if n > dense_cap:
                 raise MdvrpError(ENOSPC, f"dense table needs {n} records")
             return np.frombuffer(rec[:n * DENSE_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=DENSE_DTYPE)
-        check(lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, fl, None, 0, None, _stream()))
-        return None
+        cand_t, k = None, 0
+        if cand is not None:
+            cand_np = np.ascontiguousarray(cand, dtype=np.int32)
+            k = int(cand_np.shape[1])
+            cand_t = torch.from_numpy(cand_np.ravel()).to("cuda")
+        mv, arrs = None, None
+        if moves_cap:
+            cap = int(moves_cap)
+            arrs = {name: torch.empty(cap * (3 if name == "res" else 1),
+                                      dtype={np.int64: torch.int64, np.uint64: torch.int64, np.uint8: torch.uint8,
+                                             np.int32: torch.int32}[dt], device="cuda")
+                    for name, dt, *_ in MOVE_FIELDS}
+            arrs["count"] = torch.zeros(1, dtype=torch.int64, device="cuda")
+            mv = Moves(*[arrs[name].data_ptr() for name, *_ in MOVE_FIELDS], cap, arrs["count"].data_ptr())
+        ev = torch.empty(self.n_units, dtype=torch.int64, device="cuda") if want_evaluated else None
+        st = lib().mdvrp_eval_neighbourhood(self.handle, fam_mask, _dptr(cand_t) if cand_t is not None else None, k,
+                                            C.byref(mv) if mv is not None else None, fl,
+                                            _dptr(ev) if ev is not None else None, _stream())
+        if st == ENOSPC and arrs is not None:
+            raise MdvrpError(ENOSPC, f"move list needs {int(arrs['count'].item())} rows")
+        check(st)
+        out = None
+        if arrs is not None:
+            torch.cuda.synchronize()
+            n = int(arrs["count"].item())
+            out = np.zeros(n, MOVE_DTYPE)
+            for name, dt, *shape in MOVE_FIELDS:
+                a = arrs[name].cpu().numpy()
+                if dt == np.uint64:
+                    a = a.view(np.uint64)
+                out[name] = a[:3 * n].reshape(n, 3) if name == "res" else a[:n]
+        evn = ev.cpu().numpy() if ev is not None else None
+        return out, evn
 
     def eval_footprint(self, fam_mask=FAM_ALL):
         """Distinct matrix entries (c/t) the evaluation of fam_mask reads, per instance."""
