@@ -250,7 +250,12 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
   Sink<SM> sk{&o, dense, ui, 0};
   AR ar;
   if constexpr (sizeof(AR) > 1) ar.bits = U.foot;
-  if (threadIdx.x == 0) s_nq = 0;
+  if (threadIdx.x == 0) {
+    s_nq = 0;
+    // the selection scans the block bests of the tiles this evaluation covered; the lists
+    // (and so their tile count) may be a caller's, valid for this evaluation only
+    if (filt && lt == 0) U.ctl->ftiles_eval = U.ftiles;
+  }
   __syncthreads();
   const uint32_t intra_kinds = kind_mask & ~(1u << X2);
   const uint32_t inter_kinds = kind_mask & ~(1u << TWOOPT);

@@ -74,7 +74,7 @@ struct UnitCtl {
   int32_t arena_top;     // first free position of the current buffer (rebuilt routes are appended)
   int32_t rebuild_mode;  // latest step: 0 = rebuilt routes appended in place, 1 = full relayout
   int32_t n_build;       // routes to build in place (mode 0)
-  int32_t pad_ctl;
+  int32_t ftiles_eval;   // pair tiles the latest evaluation in filtered mode covered (its lists' tiles)
   int64_t F;             // running objective (sum of applied deltas)
   int64_t evaluated;
   int64_t passes, steps, moves_applied;

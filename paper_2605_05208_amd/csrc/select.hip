@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     // a filtered unit's pair tiles cover its candidate lists only; Depot-Replace tiles
     // cover the alive routes only
     int t_end = U.tile_base[c + 1];
-    if (c == 0 && ctl->fmode == 1) t_end = U.tile_base[0] + U.ftiles;
+    if (c == 0 && ctl->fmode == 1) t_end = U.tile_base[0] + ctl->ftiles_eval;
     if (c == 2) t_end = imin(t_end, U.tile_base[2] + (ctl->n_slots_alive * U.nd + kTileSize - 1) / kTileSize);
     for (int t = U.tile_base[c] + tid; t < t_end; t += kSelBlock) {
       const int64_t f = U.wg_best[t].dF;

@@ -88,6 +88,7 @@ __global__ __launch_bounds__(kUnitBlock) void k_load_table(const UnitDesc* __res
     ctl->last_eval = 0;
     ctl->fallbacks = 0;
     ctl->fmode = 0;
+    ctl->ftiles_eval = 0;
     ctl->scored_epoch = -1;
     ctl->arena_top = carry;
     ctl->rebuild_mode = 1;
