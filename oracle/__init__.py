@@ -52,12 +52,13 @@ assert MOVE_DTYPE.itemsize == C.sizeof(RefMove)
 
 class RefLsOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("leader_only", C.c_int32), ("max_passes", C.c_int32),
-                ("pad", C.c_int32), ("seed", C.c_uint64)]
+                ("penalty_adapt", C.c_int32), ("seed", C.c_uint64),
+                ("w_min", C.c_int32 * 4), ("w_max", C.c_int32 * 4)]
 
 
 class RefLsStats(C.Structure):
     _fields_ = [("passes", C.c_int64), ("steps", C.c_int64), ("moves_applied", C.c_int64),
-                ("evaluated", C.c_int64), ("F", C.c_int64)]
+                ("evaluated", C.c_int64), ("F", C.c_int64), ("w_final", C.c_int64 * 4)]
 
 
 _lib = None
@@ -93,8 +94,17 @@ def lib():
         L.ref_splitmix64.restype = C.c_uint64
         L.ref_family_order.argtypes = [C.c_int32, C.c_uint64, C.c_int64, p]
         L.ref_family_order.restype = C.c_int32
+        L.ref_set_threads.argtypes = [C.c_int32]
+        L.ref_get_threads.restype = C.c_int32
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's solution-parallel local search; returns the previous count."""
+    old = int(lib().ref_get_threads())
+    lib().ref_set_threads(int(n))
+    return old
 
 
 def _ptr(a: np.ndarray):
@@ -213,7 +223,9 @@ class Ref:
         return Solution([(int(o_st[r]), [int(x) for x in o_nodes[o_offs[r]:o_offs[r + 1]]], int(o_en[r]))
                          for r in range(nr)])
 
-    def local_search(self, sols, mode=0, seed=0, max_passes=0, leader_only=0):
+    def local_search(self, sols, mode=0, seed=0, max_passes=0, leader_only=0, adapt=None):
+        """adapt = (w_min, w_max), each 4 weights (time window, load, duration, depot): dynamic
+        penalty coefficients (Section 3.2.1) within those bounds; None = fixed weights."""
         from paper_2605_05208_amd.gen import batch_flat, solutions_from_flat
         nbr, ln = self.neighbours()
         nodes, offs, st, en, so = batch_flat(sols)
@@ -226,12 +238,16 @@ class Ref:
         o_so = np.zeros(n + 1, np.int32)
         stats = (RefLsStats * n)()
         opt = RefLsOptions(mode, leader_only, max_passes, 0, seed)
+        if adapt is not None:
+            opt.penalty_adapt = 1
+            opt.w_min = (C.c_int32 * 4)(*[int(x) for x in adapt[0]])
+            opt.w_max = (C.c_int32 * 4)(*[int(x) for x in adapt[1]])
         lib().ref_local_search(self.dref, _ptr(nbr), _ptr(ln), n, _ptr(nodes), _ptr(offs), _ptr(st), _ptr(en),
                                _ptr(so), C.byref(opt), _ptr(o_nodes), _ptr(o_offs), _ptr(o_st), _ptr(o_en),
                                _ptr(o_so), stats)
         out = solutions_from_flat(o_nodes, o_offs, o_st, o_en, o_so)
-        st_list = [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F)
-                   for s in stats]
+        st_list = [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F,
+                        w_final=[int(x) for x in s.w_final]) for s in stats]
         return out, st_list
 
 

@@ -8,6 +8,7 @@
  */
 #include "mdvrp_ref.h"
 
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -752,9 +753,50 @@ int ref_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam) 
   return n;
 }
 
-static void ls_one(const ref_instance* I, const int32_t* nbr, const int32_t* nbr_len, rsol* S,
+/* Terms of Eq. A.1 of a solution, every route walked node by node:
+ * t = {D, TW, LX, DX, CL, FX}. */
+static void sol_terms(const ref_instance* I, const rsol* S, int64_t t[6]) {
+  int64_t* cnt = (int64_t*)calloc((size_t)I->n_depots, sizeof(int64_t));
+  for (int k = 0; k < 6; ++k) t[k] = 0;
+  for (int r = 0; r < S->nr; ++r) {
+    const rroute* R = &S->r[r];
+    rterm x = route_terms(I, R->start, R->x, R->len, R->end);
+    t[0] += x.dist; t[1] += x.tw; t[2] += lx_of(I, x); t[3] += dx_of(I, x);
+    if (R->end >= 0 && R->start != R->end) t[4] += 1;
+    cnt[R->start] += 1;
+  }
+  for (int d = 0; d < I->n_depots; ++d) t[5] += mx(cnt[d] - I->NV, 0);
+  free(cnt);
+}
+
+/* Dynamic penalty coefficients (Section 3.2.1; kappa = 0.5 in Table 1), integer form.
+ * After an accepted step each coefficient is updated on its own: lambda / kappa (twice
+ * the weight, at most w_max) when the current solution violates the constraint of its
+ * term, lambda * kappa (half the weight, rounded down, at least w_min) when it does not.
+ * Terms: V1 time warp, V2 load excess, V3 duration excess, V4 closure + fleet excess. */
+static void adapt_weights(ref_instance* J, int64_t* wdep, const rsol* S, const ref_ls_options* opt) {
+  int64_t t[6];
+  sol_terms(J, S, t);
+  const int viol[4] = {t[1] > 0, t[2] > 0, t[3] > 0, t[4] + t[5] > 0};
+  int64_t w[4] = {J->w_tw, J->w_load, J->w_dur, *wdep};
+  for (int i = 0; i < 4; ++i) {
+    int64_t x = viol[i] ? 2 * w[i] : w[i] / 2;
+    w[i] = mx(mn(x, opt->w_max[i]), opt->w_min[i]);
+  }
+  J->w_tw = (int32_t)w[0];
+  J->w_load = (int32_t)w[1];
+  J->w_dur = (int32_t)w[2];
+  *wdep = w[3];
+  J->w_depot = (int32_t)w[3];
+}
+
+static void ls_one(const ref_instance* I0, const int32_t* nbr, const int32_t* nbr_len, rsol* S,
                    const ref_ls_options* opt, int64_t wdep, ref_ls_stats* st) {
   memset(st, 0, sizeof(*st));
+  /* the weights of this search (they change only with penalty_adapt) */
+  ref_instance Jw = *I0;
+  Jw.w_depot = (int32_t)wdep;
+  ref_instance* I = &Jw;
   ref_move* sel = NULL;
   int64_t selcap = 0;
   const uint32_t all = (1u << 6) - 1;
@@ -778,12 +820,21 @@ static void ls_one(const ref_instance* I, const int32_t* nbr, const int32_t* nbr
       st->steps += 1;
       if (M.n + 1 > selcap) { selcap = M.n + 1; sel = (ref_move*)realloc(sel, sizeof(ref_move) * (size_t)selcap); }
       int64_t ns = select_moves(M.v, M.n, opt->leader_only, sel);
-      if (ns) { apply_moves(I, S, sel, ns); applied = 1; st->moves_applied += ns; }
+      if (ns) {
+        apply_moves(I, S, sel, ns);
+        applied = 1;
+        st->moves_applied += ns;
+        if (opt->penalty_adapt) adapt_weights(I, &wdep, S, opt);
+      }
       free(M.v);
     }
     if (!applied) break;
   }
   free(sel);
+  st->w_final[0] = I->w_tw;
+  st->w_final[1] = I->w_load;
+  st->w_final[2] = I->w_dur;
+  st->w_final[3] = wdep;
 }
 
 int ref_local_search(const ref_instance* I, const int32_t* nbr, const int32_t* nbr_len, int32_t n_sol,
@@ -809,7 +860,12 @@ int ref_local_search(const ref_instance* I, const int32_t* nbr, const int32_t* n
     int32_t* ts = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nr + 1));
     int32_t* te = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nr + 1));
     sol_store(&S[k], NULL, tn, to, ts, te, 0);
-    ref_cost(I, nr, tn, to, ts, te, &stats[k].F, terms);
+    ref_instance Jw = *I; /* F under the weights the search ended with */
+    Jw.w_tw = (int32_t)stats[k].w_final[0];
+    Jw.w_load = (int32_t)stats[k].w_final[1];
+    Jw.w_dur = (int32_t)stats[k].w_final[2];
+    Jw.w_depot = (int32_t)stats[k].w_final[3];
+    ref_cost(&Jw, nr, tn, to, ts, te, &stats[k].F, terms);
     free(tn); free(to); free(ts); free(te);
   }
   /* serial write-back in solution order */
@@ -844,3 +900,8 @@ int ref_apply_ids(const ref_instance* I, int32_t n_routes, const int32_t* nodes,
   sol_free(&S);
   return 0;
 }
+
+/* Threads of the solution-parallel loop of ref_local_search (timing of the oracle
+ * at one thread and at all host cores; the results do not depend on it). */
+void ref_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }
+int32_t ref_get_threads(void) { return (int32_t)omp_get_max_threads(); }

@@ -98,13 +98,19 @@ int ref_apply_ids(const ref_instance* I, int32_t n_routes, const int32_t* nodes,
 typedef struct {
   int32_t mode;        /* 0 = passes over a permutation of families, 1 = union */
   int32_t leader_only; /* 1 = apply the leader alone */
-  int32_t max_passes;  /* 0 = until a local optimum */
-  int32_t pad;
+  int32_t max_passes;  /* 0 = until a local optimum (the depth delta of Algorithm 2 otherwise) */
+  int32_t penalty_adapt; /* 1 = dynamic penalty coefficients (Section 3.2.1), see w_min/w_max */
   uint64_t seed;
+  /* Bounds of the adapted weights, order time window, load, duration, depot
+   * (lambda_1..lambda_4): after every step that applied moves, each weight is
+   * doubled (divided by kappa = 1/2) when the new solution violates its constraint
+   * and halved, rounding down, otherwise, then clamped to [w_min, w_max]. */
+  int32_t w_min[4], w_max[4];
 } ref_ls_options;
 
 typedef struct {
-  int64_t passes, steps, moves_applied, evaluated, F;
+  int64_t passes, steps, moves_applied, evaluated, F; /* F under the final weights */
+  int64_t w_final[4];                                 /* weights at the end (tw, load, dur, depot) */
 } ref_ls_stats;
 
 /* Local search to a local optimum for each of n_sol solutions (OpenMP over
@@ -147,6 +153,10 @@ uint64_t ref_splitmix64(uint64_t* state);
 
 /* Family order of pass p: Fisher-Yates driven by SplitMix64 seeded with seed ^ p. */
 int ref_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam_out);
+
+/* OpenMP threads of the solution-parallel local search (timing only). */
+void ref_set_threads(int32_t n);
+int32_t ref_get_threads(void);
 
 #ifdef __cplusplus
 }

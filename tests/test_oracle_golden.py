@@ -136,3 +136,24 @@ def test_filter_features_time_windows_worked_example(case):
     for i in range(inst.n_customers):
         for kk in range(ln[i], th):
             assert not fx[i * th + kk].any()
+
+
+@pytest.mark.parametrize("case", GOLDEN["penalty_adapt"], ids=lambda c: c["note"][:30])
+def test_dynamic_penalty_worked_example(case):
+    """Dynamic penalty coefficients (Section 3.2.1, kappa = 0.5 of Table 1): final weights and
+    objective of a local search whose one accepted step is computed by hand."""
+    c = np.asarray(case["c"], np.int32)
+    n = len(c)
+    z = np.zeros(n, np.int32)
+    inst = Instance(n_depots=case["n_depots"], n_customers=n - case["n_depots"], c=c, t=c,
+                    q=np.asarray(case["q"], np.int32), s=z, e=z, l=np.full(n, gen.BIG_HORIZON, np.int32),
+                    Q=case["Q"], NV=case["NV"], Dmax=-1, open_routes=0, has_tw=0, theta=n - 2,
+                    **case["weights"])
+    sol = _routes(case)
+    for seed in range(4):  # the family order does not matter here
+        out, st = Ref(inst).local_search([sol], seed=seed, adapt=(case["w_min"], case["w_max"]))
+        assert st[0]["w_final"] == case["w_final"]
+        assert st[0]["F"] == case["F"]
+        assert len(out[0].routes) == 1 and sorted(out[0].routes[0][1]) == [1, 2]
+        _, terms = Ref(inst).cost(out[0])
+        assert int(terms[0]) == case["D"]

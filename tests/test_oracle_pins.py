@@ -408,3 +408,64 @@ def test_separate_times_route_terms_and_move_deltas(seed):
     assert {k for k in got if (k >> 56) != 9} == set(py)
     for mid, nb in py.items():
         assert int(got[mid]["dF"]) == T0.F_terms(I, nb)[0] - F0, hex(mid)
+
+
+def _weights(inst):
+    wd = inst.w_depot if inst.w_depot >= 0 else Ref(inst).stats()["w_depot"]
+    return [inst.w_tw, inst.w_load, inst.w_dur, wd]
+
+
+@pytest.mark.parametrize("seed,has_tw,open_r", [(61, 0, 0), (62, 1, 0), (63, 1, 1)])
+def test_dynamic_penalty_with_fixed_bounds_is_the_fixed_weight_search(seed, has_tw, open_r):
+    """With w_min = w_max = the instance's weights the adapted weights cannot move: the
+    search must be the fixed-weight search (pinned above) step for step."""
+    inst = gen.tiny(seed, has_tw=has_tw, open_routes=open_r, nc=9, Dmax=600 if has_tw else -1)
+    inst.w_tw, inst.w_dur = (7, 3) if has_tw else (0, 0)
+    sols = [gen.random_solution(inst, seed * 10 + k) for k in range(3)]
+    w = _weights(inst)
+    ref = Ref(inst)
+    a, sa = ref.local_search(sols, seed=5, adapt=(w, w))
+    b, sb = ref.local_search(sols, seed=5)
+    for k in range(len(sols)):
+        assert canonical(a[k].routes) == canonical(b[k].routes)
+        for key in ("F", "passes", "steps", "moves_applied", "evaluated"):
+            assert sa[k][key] == sb[k][key], key
+        assert sa[k]["w_final"] == w
+
+
+@pytest.mark.parametrize("seed,has_tw,open_r", [(71, 0, 0), (72, 1, 0), (73, 1, 1), (74, 0, 1)])
+def test_dynamic_penalty_search_step_by_step(seed, has_tw, open_r):
+    """The adapted search against its definition run step by step from the pinned single
+    step (Algorithm 2 with the coefficient update of Section 3.2.1 after every accepted
+    step): each step evaluates with the current weights; after a step that applied moves a
+    weight doubles when the recomputed solution violates its term and halves otherwise,
+    within [w_min, w_max]; a pass that applies nothing ends the search; depth limit 12."""
+    import dataclasses
+    inst = gen.tiny(seed, has_tw=has_tw, open_routes=open_r, nc=10, Dmax=500 if has_tw else -1)
+    inst.w_tw, inst.w_dur, inst.w_load, inst.w_depot = (12, 6, 9, 40) if has_tw else (0, 0, 9, 40)
+    w_min, w_max = [1, 2, 1, 5], [400, 300, 200, 900]
+    sol = gen.random_solution(inst, seed)
+    out, st = Ref(inst).local_search([sol], seed=3, max_passes=12, adapt=(w_min, w_max))
+    w = _weights(inst)
+    cur, steps, moves, evaluated = sol, 0, 0, 0
+    for p in range(12):
+        applied = False
+        for fam in family_order(has_tw, 3, p):
+            J = dataclasses.replace(inst, w_tw=w[0], w_load=w[1], w_dur=w[2], w_depot=w[3])
+            nxt, ids, _, n_eval = Ref(J).step(cur, 1 << fam)
+            steps += 1
+            evaluated += n_eval
+            if len(ids):
+                applied = True
+                moves += len(ids)
+                cur = nxt
+                _, t = Ref(J).cost(cur)
+                viol = [t[1] > 0, t[2] > 0, t[3] > 0, t[4] + t[5] > 0]
+                w = [min(max(2 * x if v else x // 2, lo), hi) for x, v, lo, hi in zip(w, viol, w_min, w_max)]
+        if not applied:
+            break
+    assert canonical(out[0].routes) == canonical(cur.routes)
+    assert st[0]["w_final"] == w
+    assert (st[0]["steps"], st[0]["moves_applied"], st[0]["evaluated"]) == (steps, moves, evaluated)
+    J = dataclasses.replace(inst, w_tw=w[0], w_load=w[1], w_dur=w[2], w_depot=w[3])
+    assert st[0]["F"] == Ref(J).cost(cur)[0]
