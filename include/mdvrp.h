@@ -461,6 +461,20 @@ mdvrp_status mdvrp_mlp_train_step(mdvrp_mlp* mlp, const uint16_t* x, const float
                                   int32_t n, float lr, int32_t step, float* grads, float* logits, float* loss,
                                   void* act_ws, size_t act_bytes, void* stream);
 
+/* mdvrp_mlp_train_step without the activation workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid allocation). It runs the same kernels; the
+ * activations, hidden-layer gradients and partial sums live in a static device
+ * array of 16 MiB inside the library (one per GPU, held until the process ends),
+ * so the call allocates nothing. n is at most MDVRP_TRAIN_STATIC_MAX_N (EINVAL
+ * beyond). Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or threads) race and must be serialised by the caller.
+ * Results equal those of mdvrp_mlp_train_step on the same arguments. */
+#define MDVRP_TRAIN_STATIC_MAX_N 4096
+mdvrp_status mdvrp_mlp_train_step_static(mdvrp_mlp* mlp, const uint16_t* x, const float* labels,
+                                         const float* weights, int32_t n, float lr, int32_t step, float* grads,
+                                         float* logits, float* loss, void* stream);
+
 /* Candidate lists of k entries per customer for every unit of a batch
  * (1 <= k <= theta of every instance); attaching sets them to the first k
  * entries of the granular lists. */

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -1418,6 +1419,70 @@ extern "C" mdvrp_status mdvrp_mlp_train_step(mdvrp_mlp* M, const uint16_t* x, co
   ActBufs A{};
   mdvrp_status st = check_act(n, act_ws, act_bytes, &A);
   if (st) return st;
+  hipStream_t s = S(stream);
+  launch_mlp_forward(s, M->d, x, n, logits, A.h1, A.h2);
+  launch_bce(s, logits, labels, weights, n, M->d.scratch, bce_blocks(n, kBceBlocks), A.dz, loss);
+  launch_mlp_backward(s, M->d, x, n, A.dz, A.h1, A.h2, grads, A.G2, A.G1, A.part);
+  launch_adam(s, M->d, grads, lr, step);
+  launch_mlp_pack(s, M->d);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+// ---------------------------------------------------------------------------- allocation-free training step
+//
+// mdvrp_mlp_train_step_static keeps the activations, gradients of the hidden layers
+// and the backward pass's partial sums -- the act_ws of mdvrp_mlp_train_step -- in
+// this file-scope device array. Each GPU the library runs on holds its own copy until
+// the process ends. On the host the array's name is only a stand-in symbol: every
+// host use goes through the device address hipGetSymbolAddress returns for the
+// current device, looked up once per device on the entry point's first call there.
+constexpr int kStaticTrainMaxN = MDVRP_TRAIN_STATIC_MAX_N;
+constexpr size_t kStaticTrainBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticTrainBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+mdvrp_status static_scratch(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MDVRP_EDEVICE, "device %d beyond the static scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MDVRP_EDEVICE, "no device address for the static scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MDVRP_OK;
+}
+
+}  // namespace
+
+extern "C" mdvrp_status mdvrp_mlp_train_step_static(mdvrp_mlp* M, const uint16_t* x, const float* labels,
+                                                    const float* weights, int32_t n, float lr, int32_t step,
+                                                    float* grads, float* logits, float* loss, void* stream) {
+  if (!M || !x || !labels || !grads || !logits || n < 1 || step < 1 || !(lr >= 0.f))
+    return fail(MDVRP_EINVAL, "bad argument");
+  if (n > kStaticTrainMaxN)
+    return fail(MDVRP_EINVAL, "mdvrp_mlp_train_step_static takes at most %d samples per call (got %d)",
+                kStaticTrainMaxN, n);
+  Carve need(nullptr);
+  carve_act(need, n, nullptr);
+  if (need.off + 256 > kStaticTrainBytes)
+    return fail(MDVRP_ESTATE, "static scratch of %zu bytes is below the %zu bytes of %d samples", kStaticTrainBytes,
+                need.off + 256, n);
+  void* ws = nullptr;
+  mdvrp_status st = static_scratch(&ws);
+  if (st) return st;
+  ActBufs A{};
+  Carve cv(ws);
+  carve_act(cv, n, &A);
   hipStream_t s = S(stream);
   launch_mlp_forward(s, M->d, x, n, logits, A.h1, A.h2);
   launch_bce(s, logits, labels, weights, n, M->d.scratch, bce_blocks(n, kBceBlocks), A.dz, loss);

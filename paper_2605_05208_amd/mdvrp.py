@@ -24,6 +24,7 @@ FILTER_NONE, FILTER_LISTS, FILTER_MLP = 0, 1, 2
 RESCORE_STEP, RESCORE_PASS = 0, 1
 LAYOUT_AUTO, LAYOUT_GIVEN, LAYOUT_ORDERED = 0, 1, 2
 MLP_PARAMS = 74497
+TRAIN_STATIC_MAX_N = 4096  # samples per call of the allocation-free training step
 PAIR_FAMILIES = FAM_RELOCATE | FAM_SWAP | FAM_2OPT_STAR | FAM_2OPT
 
 
@@ -85,7 +86,8 @@ EXPORTED = [
     "mdvrp_profile_enable", "mdvrp_profile_sampling", "mdvrp_profile_read", "mdvrp_eval_footprint",
     "mdvrp_mlp_workspace_query", "mdvrp_mlp_create", "mdvrp_mlp_params", "mdvrp_mlp_sync", "mdvrp_mlp_destroy",
     "mdvrp_mlp_act_bytes", "mdvrp_mlp_forward", "mdvrp_mlp_backward", "mdvrp_mlp_bce", "mdvrp_adam_step",
-    "mdvrp_mlp_train_step", "mdvrp_filter_workspace_query", "mdvrp_filter_attach", "mdvrp_filter_anchor_count",
+    "mdvrp_mlp_train_step", "mdvrp_mlp_train_step_static", "mdvrp_filter_workspace_query", "mdvrp_filter_attach",
+    "mdvrp_filter_anchor_count",
     "mdvrp_filter_features", "mdvrp_filter_labels", "mdvrp_filter_score_topk", "mdvrp_filter_eta_lists",
     "mdvrp_filter_export", "mdvrp_autotune", "mdvrp_set_tile_shapes",
 ]
@@ -134,6 +136,7 @@ def lib():
             "mdvrp_mlp_bce": [p, p, p, p, i32, p, p, p],
             "mdvrp_adam_step": [p, p, C.c_float, i32, p],
             "mdvrp_mlp_train_step": [p, p, p, p, i32, C.c_float, i32, p, p, p, p, sz, p],
+            "mdvrp_mlp_train_step_static": [p, p, p, p, i32, C.c_float, i32, p, p, p, p],
             "mdvrp_filter_workspace_query": [p, i32, p],
             "mdvrp_filter_attach": [p, i32, p, sz, p],
             "mdvrp_filter_anchor_count": [p, p],
@@ -595,6 +598,18 @@ class Mlp:
         check(lib().mdvrp_mlp_train_step(self.handle, _dptr(x), _dptr(y), _dptr(w) if w is not None else None, n,
                                          float(lr), int(step), _dptr(g), _dptr(z), _dptr(loss), _dptr(a), ab,
                                          _stream()))
+        return z, loss, g
+
+    def train_step_static(self, x, y, w, lr, step):
+        """train_step through the allocation-free entry point (n <= TRAIN_STATIC_MAX_N)."""
+        torch = _torch()
+        n = x.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        check(lib().mdvrp_mlp_train_step_static(self.handle, _dptr(x), _dptr(y), _dptr(w) if w is not None else None,
+                                                n, float(lr), int(step), _dptr(g), _dptr(z), _dptr(loss),
+                                                _stream()))
         return z, loss, g
 
 
