@@ -13,7 +13,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmdvrp_ref.so")
-SOURCES = ["mdvrp_ref.c", "mlp_ref.c"]
+SOURCES = ["mdvrp_ref.c", "mlp_ref.c", "pop_ref.c", "repair_ref.c", "dcrex_ref.c"]
 
 FAM_REL, FAM_SWP, FAM_X2, FAM_2OPT, FAM_DINS, FAM_DREP = range(6)
 ALL_FAMILIES = (1 << 6) - 1
@@ -94,6 +94,17 @@ def lib():
         L.ref_splitmix64.restype = C.c_uint64
         L.ref_family_order.argtypes = [C.c_int32, C.c_uint64, C.c_int64, p]
         L.ref_family_order.restype = C.c_int32
+        L.ref_population_distance.argtypes = [C.c_void_p, C.c_int32] + [p] * 8
+        L.ref_population_reduce.argtypes = [C.c_int32, p, p, C.c_int32, C.c_double, C.c_int32, p, p, p, p]
+        L.ref_repair.argtypes = [p, C.c_int32, p, p, p, p, C.c_int32, C.c_uint64] + [p] * 8
+        L.ref_dcrex_counts.argtypes = [C.c_int32] + [p] * 5 + [C.c_int32] + [p] * 8
+        L.ref_ucb_select.argtypes = [C.c_int32, p, p]
+        L.ref_ucb_select.restype = C.c_int32
+        L.ref_ucb_update.argtypes = [C.c_int32, p, p, C.c_int32, C.c_double, C.c_double]
+        L.ref_ucb_ln.argtypes = [C.c_double]
+        L.ref_ucb_ln.restype = C.c_double
+        L.ref_ucb_sqrt.argtypes = [C.c_double]
+        L.ref_ucb_sqrt.restype = C.c_double
         L.ref_set_threads.argtypes = [C.c_int32]
         L.ref_get_threads.restype = C.c_int32
         _lib = L
@@ -242,14 +253,57 @@ class Ref:
             opt.penalty_adapt = 1
             opt.w_min = (C.c_int32 * 4)(*[int(x) for x in adapt[0]])
             opt.w_max = (C.c_int32 * 4)(*[int(x) for x in adapt[1]])
-        lib().ref_local_search(self.dref, _ptr(nbr), _ptr(ln), n, _ptr(nodes), _ptr(offs), _ptr(st), _ptr(en),
-                               _ptr(so), C.byref(opt), _ptr(o_nodes), _ptr(o_offs), _ptr(o_st), _ptr(o_en),
-                               _ptr(o_so), stats)
+        rc = lib().ref_local_search(self.dref, _ptr(nbr), _ptr(ln), n, _ptr(nodes), _ptr(offs), _ptr(st),
+                                    _ptr(en), _ptr(so), C.byref(opt), _ptr(o_nodes), _ptr(o_offs), _ptr(o_st),
+                                    _ptr(o_en), _ptr(o_so), stats)
+        if rc != 0:
+            raise ValueError(f"oracle local search refused its options ({rc})")
         out = solutions_from_flat(o_nodes, o_offs, o_st, o_en, o_so)
         st_list = [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F,
                         w_final=[int(x) for x in s.w_final]) for s in stats]
         return out, st_list
 
+
+    def population_distance(self, sols):
+        """Eq. 7 between every pair of solutions: (dist [n][n] fp64, common arcs [n][n], |E| [n])."""
+        from paper_2605_05208_amd.gen import batch_flat
+        nodes, offs, st, en, so = batch_flat(sols)
+        n = len(sols)
+        dist = np.zeros((n, n), np.float64)
+        common = np.zeros((n, n), np.int64)
+        ne = np.zeros(n, np.int64)
+        rc = lib().ref_population_distance(self.dref, n, _ptr(nodes), _ptr(offs), _ptr(st), _ptr(en), _ptr(so),
+                                           _ptr(dist), _ptr(common), _ptr(ne))
+        assert rc == 0, rc
+        return dist, common, ne
+
+    def repair(self, sol, op, seed=0):
+        """Insert the customers missing from sol with operator op (0 FBI, 1 IBI, 2 FRI, 3 IRI,
+        4 RI): (complete solution, insertion order, positions evaluated)."""
+        from paper_2605_05208_amd.gen import Solution
+        nc = self.inst.n_customers
+        if sol.routes:
+            nodes, offs, st, en = sol.flat()
+        else:
+            nodes, offs, st, en = (np.zeros(1, np.int32), np.zeros(1, np.int32), np.zeros(1, np.int32),
+                                   np.zeros(1, np.int32))
+        nr = len(sol.routes)
+        o_nr = np.zeros(1, np.int32)
+        o_nodes = np.zeros(nc + 1, np.int32)
+        o_offs = np.zeros(nc + 2, np.int32)
+        o_st = np.zeros(nc + 1, np.int32)
+        o_en = np.zeros(nc + 1, np.int32)
+        order = np.zeros(nc + 1, np.int32)
+        n_order = np.zeros(1, np.int32)
+        n_eval = np.zeros(1, np.int64)
+        rc = lib().ref_repair(self.dref, nr, _ptr(nodes), _ptr(offs), _ptr(st), _ptr(en), int(op), int(seed),
+                              _ptr(o_nr), _ptr(o_nodes), _ptr(o_offs), _ptr(o_st), _ptr(o_en), _ptr(order),
+                              _ptr(n_order), _ptr(n_eval))
+        assert rc == 0, rc
+        m = int(o_nr[0])
+        out = Solution([(int(o_st[r]), [int(v) for v in o_nodes[o_offs[r]:o_offs[r + 1]]], int(o_en[r]))
+                        for r in range(m)])
+        return out, [int(v) for v in order[:int(n_order[0])]], int(n_eval[0])
 
     def features(self, sol):
         nbr, ln = self.neighbours()
@@ -261,6 +315,91 @@ class Ref:
 
 
 N_PARAMS = 74497
+
+
+def population_reduce(dist, f, mu, xi=0.7, n_close=5):
+    """Reduce a population to mu solutions by chi (Eq. 5-6): (keep [n], removal order,
+    chi over all n, population distance over all n)."""
+    dist = np.ascontiguousarray(dist, np.float64)
+    f = np.ascontiguousarray(f, np.int64)
+    n = len(f)
+    keep = np.zeros(n, np.int32)
+    order = np.zeros(max(n - mu, 1), np.int32)
+    chi = np.zeros(n, np.float64)
+    dpop = np.zeros(n, np.float64)
+    rc = lib().ref_population_reduce(n, _ptr(dist), _ptr(f), int(mu), float(xi), int(n_close), _ptr(keep),
+                                     _ptr(order), _ptr(chi), _ptr(dpop))
+    assert rc == 0, rc
+    return keep, order[:max(n - mu, 0)], chi, dpop
+
+
+def _flat_routes(routes):
+    nodes, offs, st, en = [], [0], [], []
+    for a, xs, b in routes:
+        nodes.extend(xs)
+        offs.append(len(nodes))
+        st.append(a)
+        en.append(b)
+    z = lambda v: np.asarray(v if len(v) else [0], np.int32)  # noqa: E731
+    return z(nodes), np.asarray(offs, np.int32), z(st), z(en)
+
+
+def dcrex_counts(offspring, intro, parent):
+    """Route-pair counts of the crossover (Algorithm 3): offspring and parent are lists of
+    (start, customers, end) routes (the offspring may hold a customer twice), intro the
+    offspring routes introduced from parents. Returns EI, NR, NM, NC as [ns][np] arrays."""
+    ns, np_ = len(offspring), len(parent)
+    sn, so, ss, se = _flat_routes(offspring)
+    pn, po, ps, pe = _flat_routes(parent)
+    it = np.ascontiguousarray(intro if len(intro) else [0], np.int32)
+    out = [np.zeros((max(ns, 1), max(np_, 1)), np.int32) for _ in range(4)]
+    lib().ref_dcrex_counts(ns, _ptr(sn), _ptr(so), _ptr(ss), _ptr(se), _ptr(it), np_, _ptr(pn), _ptr(po),
+                           _ptr(ps), _ptr(pe), *[_ptr(o) for o in out])
+    return [o[:ns, :np_] for o in out]
+
+
+def dcrex_score(ei, nr, nm, nc):
+    """Score of a route pair (Algorithm 3): lower is better."""
+    return -(ei - nr - nm - 10 * nc)
+
+
+def dcrex_dsigma(ei, nr, nm):
+    """Diversity increase of an exchange (Algorithm 3)."""
+    return ei + nr + nm
+
+
+def dcrex_pick(ei, nr, nm, nc, seed):
+    """Algorithm 3's choice: among the min(5, #pairs) pairs of lowest (score, i, j), the one
+    at index SplitMix64(seed) mod their number: (i, j, diversity increase, candidates)."""
+    ns, np_ = ei.shape
+    if ns * np_ == 0:
+        return [-1, -1, 0, 0]
+    score = dcrex_score(ei.astype(np.int64), nr, nm, nc)
+    flat = np.arange(ns * np_)
+    order = np.lexsort((flat, score.ravel()))  # score ascending, then i * np + j
+    cnt = min(5, ns * np_)
+    t = int(order[splitmix64(seed, 1)[0] % cnt])
+    i, j = divmod(t, np_)
+    return [i, j, int(dcrex_dsigma(ei[i, j], nr[i, j], nm[i, j])), cnt]
+
+
+def ucb_select(R, N):
+    R = np.ascontiguousarray(R, np.float64)
+    N = np.ascontiguousarray(N, np.float64)
+    return int(lib().ref_ucb_select(len(R), _ptr(R), _ptr(N)))
+
+
+def ucb_update(R, N, arm, reward, gamma=0.99):
+    """In place on float64 arrays R, N."""
+    lib().ref_ucb_update(len(R), _ptr(R), _ptr(N), int(arm), float(reward), float(gamma))
+
+
+def ucb_ln(x):
+    return float(lib().ref_ucb_ln(float(x)))
+
+
+def ucb_sqrt(x):
+    return float(lib().ref_ucb_sqrt(float(x)))
 
 
 def mlp_forward(params, x, round_act=1):

@@ -842,6 +842,8 @@ int ref_local_search(const ref_instance* I, const int32_t* nbr, const int32_t* n
                      const int32_t* sol_offs, const ref_ls_options* opt, int32_t* o_nodes,
                      int32_t* o_offs, int32_t* o_start, int32_t* o_end, int32_t* o_sol_offs,
                      ref_ls_stats* stats) {
+  /* with moving weights a search need not reach a fixed point: it runs to a depth */
+  if (opt->penalty_adapt && opt->max_passes <= 0) return -1;
   rsol* S = (rsol*)calloc((size_t)(n_sol > 0 ? n_sol : 1), sizeof(rsol));
   int64_t ist[4];
   ref_instance_stats(I, ist);

@@ -17,7 +17,9 @@
  *     the two depot operators Depot-Insert / Depot-Replace (Section 3.2.2,
  *     Fig. 1), restricted to granular lists (Section 3.2.3, Eq. 3);
  *   - the leader-follower multi-move selection (Section 3.2.5);
- *   - the local search loop (Algorithm 2).
+ *   - the local search loop (Algorithm 2), optionally with the dynamic
+ *     penalty coefficients of Section 3.2.1;
+ *   - the population measures of Section 3.4 (Eq. 5-7; pop_ref.c).
  * Every move is evaluated by rebuilding the changed routes as explicit node
  * lists and recomputing their cost from scratch.
  *
@@ -99,7 +101,9 @@ typedef struct {
   int32_t mode;        /* 0 = passes over a permutation of families, 1 = union */
   int32_t leader_only; /* 1 = apply the leader alone */
   int32_t max_passes;  /* 0 = until a local optimum (the depth delta of Algorithm 2 otherwise) */
-  int32_t penalty_adapt; /* 1 = dynamic penalty coefficients (Section 3.2.1), see w_min/w_max */
+  int32_t penalty_adapt; /* 1 = dynamic penalty coefficients (Section 3.2.1), see w_min/w_max;
+                            needs max_passes > 0 (the search depth of Algorithm 2): with moving
+                            weights a search can revisit solutions forever */
   uint64_t seed;
   /* Bounds of the adapted weights, order time window, load, duration, depot
    * (lambda_1..lambda_4): after every step that applied moves, each weight is
@@ -153,6 +157,80 @@ uint64_t ref_splitmix64(uint64_t* state);
 
 /* Family order of pass p: Fisher-Yates driven by SplitMix64 seeded with seed ^ p. */
 int ref_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam_out);
+
+/* ---- population measures (pop_ref.c; Section 3.4) ---- */
+
+/* Distance between every pair of n_sol solutions (batch layout of
+ * ref_local_search), Eq. 7: dist[i*n_sol + j] = 100 * (1 - |E_i & E_j| /
+ * max(|E_i|, |E_j|)), with E the set of directed arcs of a solution's routes
+ * (departure depot to first customer, consecutive customers, last customer to
+ * arrival depot unless the route is open). common[i*n_sol + j] = |E_i & E_j|
+ * and n_edges[i] = |E_i| (both nullable). */
+int ref_population_distance(const ref_instance* I, int32_t n_sol, const int32_t* nodes, const int32_t* offs,
+                            const int32_t* start, const int32_t* end, const int32_t* sol_offs, double* dist,
+                            int64_t* common, int64_t* n_edges);
+
+/* Reduction of a population of n solutions to mu (Section 3.4): while more than
+ * mu remain, chi (Eq. 5, with the population distance of Eq. 6 over the n_close
+ * nearest other solutions, fewer when fewer remain) is computed over the
+ * remaining ones and the one of lowest chi leaves (ties: higher index).
+ * Rank_f: objective f ascending; Rank_D: population distance descending (ties in
+ * either: lower index first), both from 1. keep[i] = 1 for the survivors,
+ * order[0 .. n-mu) the removal order, chi_first / dpop_first (nullable) the
+ * scores and population distances over all n solutions. */
+int ref_population_reduce(int32_t n, const double* dist, const int64_t* f, int32_t mu, double xi, int32_t n_close,
+                          int32_t* keep, int32_t* order, double* chi_first, double* dpop_first);
+
+/* ---- repair insertion (repair_ref.c; Section 3.3, after Algorithm 3) ---- */
+
+/* Insert every customer missing from the partial solution (routes as in ref_cost;
+ * each customer at most once, routes non-empty) with operator op: 0 FBI, 1 IBI,
+ * 2 FRI, 3 IRI, 4 RI. A position is "after the k-th customer of a route" (k = 0:
+ * after the departure depot, k = L: before the arrival depot or at the end of an
+ * open route); its cost is the change of that route's Eq. A.1 cost; it is
+ * feasible when it adds no time warp, load excess or duration excess. Positions
+ * tie by their predecessor customer (or N + the first customer for k = 0).
+ * FBI / IBI take the customers in ascending id order, each to its cheapest
+ * (feasible) position; FRI / IRI repeatedly take the customer of largest regret
+ * (second cheapest minus cheapest admissible cost; fewer than two admissible
+ * positions count as the largest regret; ties to the lower id) to its cheapest
+ * position. FBI / FRI open a new route (d, x, d) -- (d, x) when open -- at the
+ * depot of least cost change, fleet term included (ties: lower depot), when x
+ * has no feasible position; IBI / IRI only when the solution has no route. RI
+ * takes the customers in ascending id order and inserts x into route
+ * r1 mod M after customer r2 mod (L + 1), routes numbered by their first
+ * customer ascending, (r1, r2) the first two outputs of SplitMix64 seeded with
+ * seed ^ x. Output routes are ordered by their first customer (capacity:
+ * n_customers routes); order[0 .. n_order) lists the inserted customers in
+ * insertion order; n_evaluated counts the positions evaluated. */
+int ref_repair(const ref_instance* I, int32_t n_routes, const int32_t* nodes, const int32_t* offs,
+               const int32_t* start, const int32_t* end, int32_t op, uint64_t seed, int32_t* o_nroutes,
+               int32_t* o_nodes, int32_t* o_offs, int32_t* o_start, int32_t* o_end, int32_t* order,
+               int32_t* n_order, int64_t* n_evaluated);
+
+/* ---- DCREX crossover (dcrex_ref.c; Algorithm 3, Eq. 4) ---- */
+
+/* The counts behind the score of every route pair (R_i of the offspring S',
+ * R_j of a parent P), at [i*np + j]: EI new arcs (arcs of R_j held by no route
+ * of S' other than R_i), NR missing nodes (customers of R_i that R_j does not
+ * bring and no other route of S' holds), NM redundant nodes (customers of R_j
+ * held by another route of S'), NC conflicting nodes (customers of R_j held by
+ * another route of S' introduced from a parent: intro[r] = 1). Score =
+ * -(EI - NR - NM - 10 NC); diversity increase = EI + NR + NM. */
+int ref_dcrex_counts(int32_t ns, const int32_t* s_nodes, const int32_t* s_offs, const int32_t* s_start,
+                     const int32_t* s_end, const int32_t* s_intro, int32_t np, const int32_t* p_nodes,
+                     const int32_t* p_offs, const int32_t* p_start, const int32_t* p_end, int32_t* EI, int32_t* NR,
+                     int32_t* NM, int32_t* NC);
+
+/* Discounted UCB1 (Eq. 4) over n_arms arms with discounted reward sums R and
+ * counts N: the arm of largest R/N + sqrt(2 ln(sum N) / N) (an arm with N = 0
+ * first; ties to the lower index); the update discounts every arm by gamma and
+ * adds the reward and 1 to the played one. ln and sqrt are computed by the fixed
+ * operation sequences below. */
+int32_t ref_ucb_select(int32_t n_arms, const double* R, const double* N);
+void ref_ucb_update(int32_t n_arms, double* R, double* N, int32_t arm, double reward, double gamma);
+double ref_ucb_ln(double x);
+double ref_ucb_sqrt(double x);
 
 /* OpenMP threads of the solution-parallel local search (timing only). */
 void ref_set_threads(int32_t n);

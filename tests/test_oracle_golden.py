@@ -151,7 +151,7 @@ def test_dynamic_penalty_worked_example(case):
                     **case["weights"])
     sol = _routes(case)
     for seed in range(4):  # the family order does not matter here
-        out, st = Ref(inst).local_search([sol], seed=seed, adapt=(case["w_min"], case["w_max"]))
+        out, st = Ref(inst).local_search([sol], seed=seed, max_passes=50, adapt=(case["w_min"], case["w_max"]))
         assert st[0]["w_final"] == case["w_final"]
         assert st[0]["F"] == case["F"]
         assert len(out[0].routes) == 1 and sorted(out[0].routes[0][1]) == [1, 2]

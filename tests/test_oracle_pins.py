@@ -424,13 +424,22 @@ def test_dynamic_penalty_with_fixed_bounds_is_the_fixed_weight_search(seed, has_
     sols = [gen.random_solution(inst, seed * 10 + k) for k in range(3)]
     w = _weights(inst)
     ref = Ref(inst)
-    a, sa = ref.local_search(sols, seed=5, adapt=(w, w))
+    a, sa = ref.local_search(sols, seed=5, max_passes=1000, adapt=(w, w))
     b, sb = ref.local_search(sols, seed=5)
+    assert all(s["passes"] < 1000 for s in sb)  # the depth does not cut the fixed-weight search
     for k in range(len(sols)):
         assert canonical(a[k].routes) == canonical(b[k].routes)
         for key in ("F", "passes", "steps", "moves_applied", "evaluated"):
             assert sa[k][key] == sb[k][key], key
         assert sa[k]["w_final"] == w
+
+
+def test_dynamic_penalty_needs_a_depth():
+    """With moving weights a search need not reach a fixed point: without a depth the oracle
+    refuses the options."""
+    inst = gen.tiny(81)
+    with pytest.raises(ValueError):
+        Ref(inst).local_search([gen.random_solution(inst, 1)], adapt=([1] * 4, [64] * 4))
 
 
 @pytest.mark.parametrize("seed,has_tw,open_r", [(71, 0, 0), (72, 1, 0), (73, 1, 1), (74, 0, 1)])
