@@ -163,11 +163,60 @@ mdvrp_status mdvrp_validate_solutions_host(const mdvrp_instance_desc* descs, int
  * The arrays are copied to the host and validated first (EINVAL); a route
  * longer than the instance's int32-safe length (mdvrp_instance_info [7]) is
  * refused with ERANGE before any launch; then the route-major segment state is
- * built on the device. Synchronises. */
+ * built on the device and every unit's penalty weights are reset to its
+ * instance's. Synchronises. */
 mdvrp_status mdvrp_solutions_load(mdvrp_batch* batch, const int32_t* route_nodes, const int32_t* route_offsets,
                                   const int32_t* route_start, const int32_t* route_end,
                                   const int32_t* unit_route_offsets, int32_t n_routes_total,
                                   int32_t n_nodes_total, void* stream);
+
+/* mdvrp_solutions_load for partial solutions: customers may be missing (each
+ * appears at most once; routes non-empty; EINVAL otherwise). ERANGE when a route
+ * plus every missing customer of its unit could exceed the int32-safe length.
+ * Until mdvrp_repair completes the solutions, only mdvrp_repair,
+ * mdvrp_solutions_export, mdvrp_batch_cost and mdvrp_batch_state accept the
+ * batch (ESTATE otherwise). */
+mdvrp_status mdvrp_solutions_load_partial(mdvrp_batch* batch, const int32_t* route_nodes, const int32_t* route_offsets,
+                                          const int32_t* route_start, const int32_t* route_end,
+                                          const int32_t* unit_route_offsets, int32_t n_routes_total,
+                                          int32_t n_nodes_total, void* stream);
+
+/* Insertion operators of the repair step (Section 3.3, after Algorithm 3). */
+#define MDVRP_REPAIR_FBI 0 /* feasible best insertion */
+#define MDVRP_REPAIR_IBI 1 /* infeasible best insertion */
+#define MDVRP_REPAIR_FRI 2 /* feasible regret insertion */
+#define MDVRP_REPAIR_IRI 3 /* infeasible regret insertion */
+#define MDVRP_REPAIR_RI 4  /* random insertion */
+
+/* Insert every customer missing from each unit's solution (loaded with
+ * mdvrp_solutions_load_partial) with operator op; afterwards every unit holds a
+ * complete solution. A position is "after the k-th customer of a route" (k = 0:
+ * after the departure depot; k = L: before the arrival depot, or at the end of
+ * an open route); its cost is the change of that route's Eq. A.1 cost under the
+ * unit's current weights; it is feasible when it adds no time warp, load
+ * excess or duration excess. Positions tie by their predecessor customer, or by
+ * N + the route's first customer for k = 0.
+ *   FBI / IBI: the missing customers in ascending id order, each to its
+ *     cheapest feasible (FBI) / cheapest (IBI) position.
+ *   FRI / IRI: repeatedly the customer of largest regret -- the cost of its
+ *     second cheapest admissible position minus that of its cheapest; fewer than
+ *     two admissible positions count as the largest; ties to the lower id -- to
+ *     its cheapest admissible position.
+ *   RI: in ascending id order, customer x goes into route r1 mod M after its
+ *     (r2 mod (L + 1))-th customer, routes numbered by their first customer
+ *     ascending, (r1, r2) the first two outputs of SplitMix64 seeded with
+ *     seed ^ x.
+ * FBI and FRI open a new route (d, x, d) -- (d, x) for open routes -- at the
+ * depot of least cost change, fleet term included (ties: lower depot), in the
+ * lowest empty route slot, when x has no feasible position; IBI, IRI and RI do
+ * so only when the unit has no route. order (DEVICE int32, nullable) receives
+ * the inserted customers of unit k in insertion order from entry node_base_k on
+ * (node_base_k as in mdvrp_solutions_export); n_evaluated (DEVICE int64
+ * [n_units], nullable) the insertion positions evaluated. Synchronises.
+ * Errors: EINVAL (op), ESTATE (nothing loaded), ENOSPC (a unit's position
+ * buffer is full). A batch of complete solutions is left unchanged. */
+mdvrp_status mdvrp_repair(mdvrp_batch* batch, int32_t op, uint64_t seed, int32_t* order, int64_t* n_evaluated,
+                          void* stream);
 
 /* Export the current solutions to DEVICE arrays. Unit k writes its customers to
  * route_nodes[node_base_k ..] with node_base_k = sum of n_customers of units < k,
@@ -178,16 +227,18 @@ mdvrp_status mdvrp_solutions_load(mdvrp_batch* batch, const int32_t* route_nodes
 mdvrp_status mdvrp_solutions_export(const mdvrp_batch* batch, int32_t* route_nodes, int32_t* route_offsets,
                                     int32_t* route_start, int32_t* route_end, int32_t* route_count, void* stream);
 
-/* F(S) of every unit recomputed from the current routes (Eq. A.1 with fixed
- * weights): F[k] and terms[k*6 + 0..5] = D, TW, LX, DX, CL, FX (DEVICE arrays,
- * terms nullable). */
+/* F(S) of every unit recomputed from the current routes (Eq. A.1 under the
+ * unit's current penalty weights: its instance's, unless a search with
+ * penalty_adapt changed them): F[k] and terms[k*6 + 0..5] = D, TW, LX, DX, CL,
+ * FX (DEVICE arrays, terms nullable). */
 mdvrp_status mdvrp_batch_cost(mdvrp_batch* batch, int64_t* F, int64_t* terms, void* stream);
 
-/* Host copy of per-unit counters, 12 per unit: running F, evaluated moves,
+/* Host copy of per-unit counters, 16 per unit: running F, evaluated moves,
  * passes, steps, moves applied, error bits, active flag, moves selected in
  * the latest step, full-list fallback passes of a filtered search, current
  * list mode (0 full, 1 filtered, 2 full fallback pass), device clock at the
- * start of the latest search and at the end of the unit's latest pass.
+ * start of the latest search and at the end of the unit's latest pass, and
+ * the unit's current penalty weights (time window, load, duration, depot).
  * Synchronises. */
 mdvrp_status mdvrp_batch_state(const mdvrp_batch* batch, int64_t* out_host);
 
@@ -305,7 +356,16 @@ typedef struct {
   int32_t graph;       /* 1 = each pass runs as a HIP graph, captured once per distinct launch
                           sequence (family order and options) and replayed; per-launch
                           profiling is off for captured passes */
-  int32_t pad2;
+  int32_t penalty_adapt; /* 1 = dynamic penalty coefficients (Section 3.2.1): every unit starts
+                          from its instance's weights; after each step that applied moves each of
+                          the four weights (order: time window, load, duration, depot) is doubled
+                          (divided by kappa = 1/2) when the new solution violates its term (time
+                          warp; load excess; duration excess; closure or fleet excess) and halved,
+                          rounding down (multiplied by kappa), otherwise, then clamped to
+                          [w_min, w_max]. The weights of a unit change only here. Needs
+                          max_passes > 0 (EINVAL otherwise): with moving weights a search need
+                          not reach a fixed point (the paper bounds it by its depth delta = 500) */
+  int32_t w_min[4], w_max[4]; /* bounds of the adapted weights: 0 <= w_min <= w_max <= 2^30 */
 } mdvrp_ls_options;
 
 typedef struct {
@@ -314,6 +374,8 @@ typedef struct {
   double device_ms;        /* device clock from the start of the search to the end of this
                               unit's last pass (its time to the local optimum) */
   int32_t converged, err;
+  int64_t w_final[4];      /* penalty weights at the end (time window, load, duration, depot);
+                              F is the objective under these weights */
 } mdvrp_ls_stats;
 
 /* Local search to a local optimum for every unit of the batch (Algorithm 2 with
@@ -335,6 +397,91 @@ typedef struct {
  * internal capacity overflow, EDEVICE. */
 mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* batch, const mdvrp_ls_options* opts,
                                            mdvrp_ls_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------- population (Section 3.4)
+ *
+ * A population is a list of distinct units of one batch that hold solutions of
+ * the same instance (units: HOST array of n unit indices, 1 <= n <= 1024). The
+ * edge set E of a solution is the set of directed arcs along its routes: from the
+ * departure depot to the first customer, between consecutive customers, and from
+ * the last customer to the arrival depot (none for an open route). */
+
+/* Device workspace of mdvrp_population_distance for these members. */
+mdvrp_status mdvrp_population_workspace_query(const mdvrp_batch* batch, const int32_t* units, int32_t n,
+                                              size_t* bytes);
+
+/* Distance between every pair of members' current solutions (Eq. 7):
+ * dist[i*n + j] = 100 * (1 - |E_i & E_j| / max(|E_i|, |E_j|)) in fp64 (DEVICE,
+ * n*n; the quotient, the difference and the product each rounded once, in that
+ * order); common[i*n + j] = |E_i & E_j| and n_edges[i] = |E_i| (DEVICE int64,
+ * nullable). ws: DEVICE workspace of mdvrp_population_workspace_query bytes.
+ * Errors: EINVAL (bad member list), ESTATE (no solutions loaded), ENOSPC
+ * (workspace too small). Synchronises the stream. */
+mdvrp_status mdvrp_population_distance(mdvrp_batch* batch, const int32_t* units, int32_t n, double* dist,
+                                       int64_t* common, int64_t* n_edges, void* ws, size_t ws_bytes, void* stream);
+
+/* Reduction of a population of n members to mu (Section 3.4; all arrays DEVICE):
+ * while more than mu remain, the fitness-and-distance score chi (Eq. 5) of every
+ * remaining member is computed and the member of lowest chi leaves (ties: the
+ * higher index). chi = (m - Rank_f)/m + xi * (m - Rank_D)/m over the m remaining
+ * members; Rank_f orders f[] ascending, Rank_D the population distance (Eq. 6:
+ * the mean of the n_close smallest distances to the other remaining members,
+ * summed in ascending order; fewer when fewer remain) descending; ties in either
+ * go to the lower index; ranks count from 1. dist: n*n from
+ * mdvrp_population_distance (or any symmetric matrix); f: n objective values
+ * (e.g. mdvrp_batch_cost of the members); xi >= 0 (the paper uses 0.7);
+ * 1 <= n_close <= 16 (the paper uses 5). keep[i] = 1 for the survivors; order
+ * (nullable, n - mu entries) the removal order; chi and dpop (nullable, n each)
+ * the scores and population distances over all n members. */
+mdvrp_status mdvrp_population_reduce(const double* dist, const int64_t* f, int32_t n, int32_t mu, double xi,
+                                     int32_t n_close, int32_t* keep, int32_t* order, double* chi, double* dpop,
+                                     void* stream);
+
+/* ------------------------------------------------------------------------- DCREX crossover (Algorithm 3, Eq. 4)
+ *
+ * The offspring S' of the route-exchange crossover may hold a customer in more
+ * than one route, so it is passed as plain route lists: DEVICE int32 arrays, route
+ * r = (start[r], nodes[offs[r] .. offs[r+1]-1], end[r]), end -1 for an open route;
+ * intro[r] = 1 for the routes introduced from other parents. Arcs are the directed
+ * arcs along a route, as in the population distance. */
+
+mdvrp_status mdvrp_dcrex_workspace_query(int32_t n_nodes, int32_t ns, int32_t np, int32_t p_len, size_t* bytes);
+
+/* The counts behind the score of every route pair (R_i of S', ns routes; R_j of
+ * parent P, np routes), at [i*np + j] (DEVICE int32 outputs): EI = arcs of R_j
+ * held by no route of S' other than R_i (new arcs); NR = customers of R_i that
+ * R_j does not bring and no other route of S' holds (missing); NM = customers of
+ * R_j held by another route of S' (redundant); NC = customers of R_j held by
+ * another introduced route of S' (conflicting). Algorithm 3 scores a pair by
+ * -(EI - NR - NM - 10 NC) and its exchange adds EI + NR + NM to the diversity.
+ * Node ids: depots [0, n_depots), customers [n_depots, n_nodes). The route lists
+ * are copied to the host and checked first (EINVAL: ids, offsets, flags, a customer
+ * twice in one route of S' or anywhere in P). ENOSPC when a customer occurs in more
+ * than 8 routes of S'. Synchronises. */
+mdvrp_status mdvrp_dcrex_counts(int32_t n_depots, int32_t n_nodes, int32_t ns, int32_t s_len, const int32_t* s_nodes,
+                                const int32_t* s_offs, const int32_t* s_start, const int32_t* s_end,
+                                const int32_t* s_intro, int32_t np, int32_t p_len, const int32_t* p_nodes,
+                                const int32_t* p_offs, const int32_t* p_start, const int32_t* p_end, int32_t* EI,
+                                int32_t* NR, int32_t* NM, int32_t* NC, void* ws, size_t ws_bytes, void* stream);
+
+/* Algorithm 3's choice of the exchange: among the min(5, ns*np) pairs of lowest
+ * (score, i, j), the one at index SplitMix64(seed) mod their number. out (DEVICE
+ * int32[4]) = {i, j, diversity increase EI + NR + NM, number of candidates}
+ * ({-1, -1, 0, 0} without pairs). */
+mdvrp_status mdvrp_dcrex_pick(int32_t ns, int32_t np, const int32_t* EI, const int32_t* NR, const int32_t* NM,
+                              const int32_t* NC, uint64_t seed, int32_t* out, void* stream);
+
+/* Discounted UCB1 (Eq. 4) over n_arms arms (1..1024) with discounted reward sums R
+ * and counts N (DEVICE fp64). Select: *arm (DEVICE) = an arm with N = 0 (lowest
+ * index) if any, else the arm of largest R/N + sqrt(2 ln(sum N) / N), ties to the
+ * lower index; ln and sqrt follow fixed operation sequences (a 40-term atanh
+ * series after halving into [1, 2); 8 Newton steps after scaling into [1, 4)), so
+ * that the choice is reproducible bit for bit. Update: every arm's R and N times
+ * gamma (the paper's gamma_d = 0.99), then the reward (*reward, DEVICE) and 1 added
+ * to arm *arm. The reward of the paper is 100 (f(P_m) - f(S')) / f(P_m). */
+mdvrp_status mdvrp_ucb_select(int32_t n_arms, const double* R, const double* N, int32_t* arm, void* stream);
+mdvrp_status mdvrp_ucb_update(int32_t n_arms, double* R, double* N, const int32_t* arm, const double* reward,
+                              double gamma, void* stream);
 
 /* ------------------------------------------------------------------------- profiling */
 

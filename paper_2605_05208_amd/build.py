@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdvrp.so")
-SOURCES = ["api.hip", "prep.hip", "eval.hip", "select.hip", "state.hip", "mlp.hip"]
+SOURCES = ["api.hip", "prep.hip", "eval.hip", "select.hip", "state.hip", "mlp.hip", "pop.hip", "repair.hip", "dcrex.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -136,6 +136,8 @@ struct mdvrp_batch {
   // call order: the device state is defined only after a load; a selection needs an
   // evaluation of the same families on the current state, an apply needs a selection
   bool loaded = false;
+  bool partial = false;    // loaded solutions miss customers (mdvrp_solutions_load_partial)
+  int max_missing = 0;     // most customers missing from one unit's partial solution
   uint32_t eval_fam = 0;  // families of the latest evaluation of the current state (0 = none)
   bool planned = false;
   void state_changed() { eval_fam = 0; planned = false; }
@@ -173,6 +175,8 @@ struct mdvrp_batch {
       L.per_unit[k] = per;
     }
     L.active_count = d_active;
+    L.adapt_units = nullptr;
+    L.adapt = AdaptBounds{};
     auto per = [&](const std::vector<int32_t>& off) {
       if (off.size() != (size_t)n_units + 1 || n_units < 2 || !layout_all) return 0;
       const int p = off[1] - off[0];
@@ -206,14 +210,6 @@ extern "C" const char* mdvrp_status_string(mdvrp_status s) {
 }
 
 extern "C" const char* mdvrp_last_error(void) { return g_err.c_str(); }
-
-// SplitMix64 (Steele, Lea and Flood, 2014).
-static uint64_t splitmix64_next(uint64_t* st) {
-  uint64_t z = (*st += 0x9E3779B97F4A7C15ull);
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
 
 // Algorithm 2 visits the operator families in a random order each pass.
 extern "C" int32_t mdvrp_family_order(int32_t has_tw, uint64_t seed, int64_t pass, int32_t* fam) {
@@ -488,7 +484,6 @@ void carve_unit(Carve& cv, const mdvrp_instance* I, int has_tw, UnitDesc* U) {
   u.r_meta[0] = cv.take<int4>(z.R);
   u.r_meta[1] = cv.take<int4>(z.R);
   u.r_tot = cv.take<int4>(z.R);
-  u.r_cost = cv.take<int64_t>(z.R);
   u.r_core = has_tw ? cv.take<SegTW>(z.R) : nullptr;
   for (int b = 0; b < 2; ++b) {
     u.fw[b] = cv.take<char>(seg * z.cap);
@@ -727,14 +722,36 @@ void timed(mdvrp_batch* B, hipStream_t s, int cls, F&& launch) {
 }
 }  // namespace
 
-static mdvrp_status need_loaded(const mdvrp_batch* B) {
+// Solutions loaded, possibly partial (customers missing).
+static mdvrp_status need_loaded_any(const mdvrp_batch* B) {
   return B->loaded ? MDVRP_OK : fail(MDVRP_ESTATE, "no solutions loaded in this batch");
 }
+
+// Complete solutions loaded (every customer routed): what the evaluation, selection,
+// search, filter and population calls need.
+static mdvrp_status need_loaded(const mdvrp_batch* B) {
+  if (mdvrp_status e = need_loaded_any(B)) return e;
+  return B->partial ? fail(MDVRP_ESTATE, "the batch holds partial solutions: call mdvrp_repair first") : MDVRP_OK;
+}
+
+// Checks of mdvrp_validate_solutions_host; with missing != nullptr customers may be
+// absent (partial solutions) and missing[k] receives unit k's count of them.
+static mdvrp_status validate_solutions(const mdvrp_instance_desc* descs, int32_t n_inst, const int32_t* unit_inst,
+                                       int32_t n_units, const int32_t* nodes, const int32_t* offs,
+                                       const int32_t* starts, const int32_t* ends, const int32_t* uro,
+                                       std::vector<int>* missing);
 
 extern "C" mdvrp_status mdvrp_validate_solutions_host(const mdvrp_instance_desc* descs, int32_t n_inst,
                                                       const int32_t* unit_inst, int32_t n_units, const int32_t* nodes,
                                                       const int32_t* offs, const int32_t* starts, const int32_t* ends,
                                                       const int32_t* uro) {
+  return validate_solutions(descs, n_inst, unit_inst, n_units, nodes, offs, starts, ends, uro, nullptr);
+}
+
+static mdvrp_status validate_solutions(const mdvrp_instance_desc* descs, int32_t n_inst, const int32_t* unit_inst,
+                                       int32_t n_units, const int32_t* nodes, const int32_t* offs,
+                                       const int32_t* starts, const int32_t* ends, const int32_t* uro,
+                                       std::vector<int>* missing) {
   if (!descs || !unit_inst || !nodes || !offs || !starts || !ends || !uro || n_inst < 1 || n_units < 1)
     return fail(MDVRP_EINVAL, "null argument");
   std::vector<int32_t> seen;
@@ -760,14 +777,34 @@ extern "C" mdvrp_status mdvrp_validate_solutions_host(const mdvrp_instance_desc*
         ++count;
       }
     }
-    if (count != nc) return fail(MDVRP_EINVAL, "unit %d: %d of %d customers routed", k, count, nc);
+    if (missing) (*missing)[k] = nc - count;
+    else if (count != nc) return fail(MDVRP_EINVAL, "unit %d: %d of %d customers routed", k, count, nc);
   }
   return MDVRP_OK;
 }
 
-extern "C" mdvrp_status mdvrp_solutions_load(mdvrp_batch* B, const int32_t* nodes, const int32_t* offs,
-                                             const int32_t* starts, const int32_t* ends, const int32_t* uro,
-                                             int32_t n_routes, int32_t n_nodes, void* stream) {
+// Reset every unit's penalty weights (host copy of the unit descriptors) to its
+// instance's; true when any changed, so that the device copy needs an upload.
+static bool weights_to_instance(mdvrp_batch* B) {
+  bool changed = false;
+  for (int k = 0; k < B->n_units; ++k) {
+    const mdvrp_instance* I = B->inst[B->unit_inst[k]];
+    UnitDesc& u = B->h_units[k];
+    if (u.w_tw != I->d.w_tw || u.w_load != I->d.w_load || u.w_dur != I->d.w_dur || u.w_depot != I->w_depot) {
+      u.w_tw = I->d.w_tw;
+      u.w_load = I->d.w_load;
+      u.w_dur = I->d.w_dur;
+      u.w_depot = I->w_depot;
+      changed = true;
+    }
+  }
+  return changed;
+}
+
+// Solutions of every unit from device arrays; partial = customers may be missing.
+static mdvrp_status load_solutions(mdvrp_batch* B, const int32_t* nodes, const int32_t* offs, const int32_t* starts,
+                                   const int32_t* ends, const int32_t* uro, int32_t n_routes, int32_t n_nodes,
+                                   void* stream, bool partial) {
   if (!B || !nodes || !offs || !starts || !ends || !uro) return fail(MDVRP_EINVAL, "null argument");
   if (n_routes < 0 || n_nodes < 0) return fail(MDVRP_EINVAL, "negative sizes");
   hipStream_t s = S(stream);
@@ -787,31 +824,76 @@ extern "C" mdvrp_status mdvrp_solutions_load(mdvrp_batch* B, const int32_t* node
     if (ho[r + 1] < ho[r]) return fail(MDVRP_EINVAL, "decreasing route offsets");
   std::vector<mdvrp_instance_desc> descs;
   for (const mdvrp_instance* I : B->inst) descs.push_back(I->d);
-  mdvrp_status st = mdvrp_validate_solutions_host(descs.data(), (int32_t)descs.size(), B->unit_inst.data(),
-                                                  B->n_units, hn.data(), ho.data(), hs.data(), he_.data(), hu.data());
+  std::vector<int> missing(B->n_units, 0);
+  mdvrp_status st = validate_solutions(descs.data(), (int32_t)descs.size(), B->unit_inst.data(), B->n_units,
+                                       hn.data(), ho.data(), hs.data(), he_.data(), hu.data(),
+                                       partial ? &missing : nullptr);
   if (st) return st;
   // the segment arithmetic is int32: a route longer than the instance's guard could overflow
+  // (a partial solution: not even when every missing customer joins its longest route)
+  int max_missing = 0;
   for (int k = 0; k < B->n_units; ++k) {
     const int64_t guard = B->inst[B->unit_inst[k]]->len_guard;
     for (int r = hu[k]; r < hu[k + 1]; ++r)
-      if (ho[r + 1] - ho[r] > guard)
-        return fail(MDVRP_ERANGE, "unit %d route %d: %d customers, beyond the int32-safe length %lld", k, r - hu[k],
-                    ho[r + 1] - ho[r], (long long)guard);
+      if (ho[r + 1] - ho[r] + missing[k] > guard)
+        return fail(MDVRP_ERANGE, "unit %d route %d: %d customers (and %d missing), beyond the int32-safe length %lld",
+                    k, r - hu[k], ho[r + 1] - ho[r], missing[k], (long long)guard);
+    if (missing[k] > guard) return fail(MDVRP_ERANGE, "unit %d: %d missing customers, beyond the int32-safe length",
+                                        k, missing[k]);
+    max_missing = std::max(max_missing, missing[k]);
   }
   const LaunchCtx L = B->ctx(stream);
   B->loaded = false;
   B->state_changed();
+  if (weights_to_instance(B))
+    HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, s));
   launch_load(L, nodes, offs, starts, ends, uro);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   B->loaded = true;
+  B->partial = partial && max_missing > 0;
+  B->max_missing = partial ? max_missing : 0;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_solutions_load(mdvrp_batch* B, const int32_t* nodes, const int32_t* offs,
+                                             const int32_t* starts, const int32_t* ends, const int32_t* uro,
+                                             int32_t n_routes, int32_t n_nodes, void* stream) {
+  return load_solutions(B, nodes, offs, starts, ends, uro, n_routes, n_nodes, stream, false);
+}
+
+extern "C" mdvrp_status mdvrp_solutions_load_partial(mdvrp_batch* B, const int32_t* nodes, const int32_t* offs,
+                                                     const int32_t* starts, const int32_t* ends, const int32_t* uro,
+                                                     int32_t n_routes, int32_t n_nodes, void* stream) {
+  return load_solutions(B, nodes, offs, starts, ends, uro, n_routes, n_nodes, stream, true);
+}
+
+static mdvrp_status check_unit_errors(mdvrp_batch* B, std::vector<int64_t>& st, void* stream);
+
+extern "C" mdvrp_status mdvrp_repair(mdvrp_batch* B, int32_t op, uint64_t seed, int32_t* order, int64_t* n_evaluated,
+                                     void* stream) {
+  if (!B) return fail(MDVRP_EINVAL, "null batch");
+  if (op < MDVRP_REPAIR_FBI || op > MDVRP_REPAIR_RI) return fail(MDVRP_EINVAL, "unknown insertion operator %d", op);
+  if (mdvrp_status e = need_loaded_any(B)) return e;
+  B->state_changed();
+  const LaunchCtx L = B->ctx(stream);
+  launch_ins_begin(L);
+  for (int r = 0; r < B->max_missing; ++r) launch_ins_round(L, op, seed, B->max_missing, order, B->d_node_base);
+  HIP_TRY(hipGetLastError());
+  launch_cost(L, nullptr, nullptr);
+  if (n_evaluated) launch_ins_export(L, n_evaluated);
+  std::vector<int64_t> stv;
+  mdvrp_status s = check_unit_errors(B, stv, stream);
+  if (s) return s;
+  B->partial = false;
+  B->max_missing = 0;
   return MDVRP_OK;
 }
 
 extern "C" mdvrp_status mdvrp_solutions_export(const mdvrp_batch* B, int32_t* nodes, int32_t* offs, int32_t* starts,
                                                int32_t* ends, int32_t* counts, void* stream) {
   if (!B || !nodes || !offs || !starts || !ends || !counts) return fail(MDVRP_EINVAL, "null argument");
-  if (mdvrp_status e = need_loaded(B)) return e;
+  if (mdvrp_status e = need_loaded_any(B)) return e;
   const LaunchCtx L = B->ctx(stream);
   launch_export(L, nodes, offs, starts, ends, counts, B->d_node_base, B->d_route_base);
   HIP_TRY(hipGetLastError());
@@ -820,8 +902,197 @@ extern "C" mdvrp_status mdvrp_solutions_export(const mdvrp_batch* B, int32_t* no
 
 extern "C" mdvrp_status mdvrp_batch_cost(mdvrp_batch* B, int64_t* F, int64_t* terms, void* stream) {
   if (!B || !F) return fail(MDVRP_EINVAL, "null argument");
-  if (mdvrp_status e = need_loaded(B)) return e;
+  if (mdvrp_status e = need_loaded_any(B)) return e;
   launch_cost(B->ctx(stream), F, terms);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+// ============================================================================ population (Section 3.4)
+
+namespace {
+
+// Workspace of a population call: the member list and the per-member edge keys and
+// edge counts.
+void carve_pop(Carve& cv, int n, int nc, int32_t** list, int2** keys, int64_t** n_edges) {
+  int32_t* l = cv.take<int32_t>(n);
+  int2* k = cv.take<int2>((size_t)n * nc);
+  int64_t* e = cv.take<int64_t>(n);
+  if (list) *list = l;
+  if (keys) *keys = k;
+  if (n_edges) *n_edges = e;
+}
+
+// Members: distinct units of the batch, all of one instance.
+mdvrp_status check_members(const mdvrp_batch* B, const int32_t* units, int32_t n, int* nc) {
+  if (!B || !units || n < 1 || n > kPopMaxMembers)
+    return fail(MDVRP_EINVAL, "population of %d members (1..%d)", n, kPopMaxMembers);
+  std::vector<char> seen(B->n_units, 0);
+  for (int i = 0; i < n; ++i) {
+    const int u = units[i];
+    if (u < 0 || u >= B->n_units) return fail(MDVRP_EINVAL, "member %d: unit %d out of range", i, u);
+    if (seen[u]) return fail(MDVRP_EINVAL, "member %d: unit %d listed twice", i, u);
+    seen[u] = 1;
+    if (B->unit_inst[u] != B->unit_inst[units[0]])
+      return fail(MDVRP_EINVAL, "member %d: unit %d belongs to another instance", i, u);
+  }
+  *nc = B->h_units[units[0]].nc;
+  return MDVRP_OK;
+}
+
+}  // namespace
+
+extern "C" mdvrp_status mdvrp_population_workspace_query(const mdvrp_batch* B, const int32_t* units, int32_t n,
+                                                         size_t* bytes) {
+  if (!bytes) return fail(MDVRP_EINVAL, "null bytes");
+  int nc = 0;
+  if (mdvrp_status e = check_members(B, units, n, &nc)) return e;
+  Carve cv(nullptr);
+  carve_pop(cv, n, nc, nullptr, nullptr, nullptr);
+  *bytes = cv.off + 256;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_population_distance(mdvrp_batch* B, const int32_t* units, int32_t n, double* dist,
+                                                  int64_t* common, int64_t* n_edges, void* ws, size_t ws_bytes,
+                                                  void* stream) {
+  int nc = 0;
+  if (mdvrp_status e = check_members(B, units, n, &nc)) return e;
+  if (!dist) return fail(MDVRP_EINVAL, "null dist");
+  if (mdvrp_status e = need_loaded(B)) return e;
+  Carve need(nullptr);
+  carve_pop(need, n, nc, nullptr, nullptr, nullptr);
+  if (!ws || ws_bytes < need.off + 256) return fail(MDVRP_ENOSPC, "population workspace needs %zu bytes", need.off + 256);
+  Carve cv(ws);
+  int32_t* list = nullptr;
+  int2* keys = nullptr;
+  int64_t* ne = nullptr;
+  carve_pop(cv, n, nc, &list, &keys, &ne);
+  const LaunchCtx L = B->ctx(stream);
+  HIP_TRY(hipMemcpyAsync(list, units, sizeof(int32_t) * n, hipMemcpyHostToDevice, L.stream));
+  launch_pop_distance(L, list, n, nc, keys, ne, dist, common);
+  if (n_edges) HIP_TRY(hipMemcpyAsync(n_edges, ne, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, L.stream));
+  HIP_TRY(hipGetLastError());
+  // the member list was copied from the caller's host array: wait before returning
+  HIP_TRY(hipStreamSynchronize(L.stream));
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_population_reduce(const double* dist, const int64_t* f, int32_t n, int32_t mu,
+                                                double xi, int32_t n_close, int32_t* keep, int32_t* order,
+                                                double* chi, double* dpop, void* stream) {
+  if (!dist || !f || !keep) return fail(MDVRP_EINVAL, "null argument");
+  if (n < 1 || n > kPopMaxMembers) return fail(MDVRP_EINVAL, "population of %d members (1..%d)", n, kPopMaxMembers);
+  if (mu < 1) return fail(MDVRP_EINVAL, "mu must be >= 1");
+  if (n_close < 1 || n_close > kPopMaxClose) return fail(MDVRP_EINVAL, "n_close must be 1..%d", kPopMaxClose);
+  if (!(xi >= 0.0) || !(xi <= 1e6)) return fail(MDVRP_EINVAL, "xi must be a finite value >= 0");
+  launch_pop_reduce(S(stream), dist, f, n, mu, xi, n_close, keep, order, chi, dpop);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+// ============================================================================ DCREX crossover (Algorithm 3, Eq. 4)
+
+namespace {
+
+// Host copy and checks of route lists given in device arrays: offsets from 0 to len,
+// non-decreasing; customers in [nd, n); starts depots; ends depots or -1; flags 0/1;
+// no customer twice in one route (unique_all: in the whole list).
+mdvrp_status check_routes_dev(const char* what, int nd, int n, int nr, int len, const int32_t* nodes,
+                              const int32_t* offs, const int32_t* start, const int32_t* end, const int32_t* flags,
+                              bool unique_all, hipStream_t s) {
+  if (nr < 0 || len < 0) return fail(MDVRP_EINVAL, "%s: negative sizes", what);
+  if (nr == 0) return MDVRP_OK;
+  if (!nodes || !offs || !start || !end) return fail(MDVRP_EINVAL, "%s: null array", what);
+  std::vector<int32_t> hn(std::max(len, 1)), ho(nr + 1), hs(nr), he(nr), hf(flags ? nr : 0);
+  HIP_TRY(hipMemcpyAsync(ho.data(), offs, sizeof(int32_t) * (nr + 1), hipMemcpyDeviceToHost, s));
+  if (len) HIP_TRY(hipMemcpyAsync(hn.data(), nodes, sizeof(int32_t) * len, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hs.data(), start, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(he.data(), end, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, s));
+  if (flags) HIP_TRY(hipMemcpyAsync(hf.data(), flags, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ho[0] != 0 || ho[nr] != len) return fail(MDVRP_EINVAL, "%s: offsets do not span the nodes", what);
+  std::vector<int32_t> seen(n, -1);
+  for (int r = 0; r < nr; ++r) {
+    if (ho[r + 1] < ho[r]) return fail(MDVRP_EINVAL, "%s: decreasing offsets", what);
+    if (hs[r] < 0 || hs[r] >= nd) return fail(MDVRP_EINVAL, "%s route %d: start is not a depot", what, r);
+    if (he[r] < -1 || he[r] >= nd) return fail(MDVRP_EINVAL, "%s route %d: end is neither a depot nor -1", what, r);
+    if (flags && hf[r] != 0 && hf[r] != 1) return fail(MDVRP_EINVAL, "%s route %d: flag not 0 or 1", what, r);
+    for (int p = ho[r]; p < ho[r + 1]; ++p) {
+      const int x = hn[p];
+      if (x < nd || x >= n) return fail(MDVRP_EINVAL, "%s route %d: node %d is not a customer", what, r, x);
+      if (seen[x] == r || (unique_all && seen[x] >= 0))
+        return fail(MDVRP_EINVAL, "%s: customer %d visited twice", what, x);
+      seen[x] = r;
+    }
+  }
+  return MDVRP_OK;
+}
+
+}  // namespace
+
+extern "C" mdvrp_status mdvrp_dcrex_workspace_query(int32_t n_nodes, int32_t ns, int32_t np, int32_t p_len,
+                                                    size_t* bytes) {
+  if (!bytes || n_nodes < 1 || ns < 0 || np < 0 || p_len < 0) return fail(MDVRP_EINVAL, "bad argument");
+  *bytes = dcrex_ws_bytes(n_nodes, ns, np, p_len) + 256;
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_dcrex_counts(int32_t n_depots, int32_t n_nodes, int32_t ns, int32_t s_len,
+                                           const int32_t* s_nodes, const int32_t* s_offs, const int32_t* s_start,
+                                           const int32_t* s_end, const int32_t* s_intro, int32_t np, int32_t p_len,
+                                           const int32_t* p_nodes, const int32_t* p_offs, const int32_t* p_start,
+                                           const int32_t* p_end, int32_t* EI, int32_t* NR, int32_t* NM, int32_t* NC,
+                                           void* ws, size_t ws_bytes, void* stream) {
+  if (n_depots < 1 || n_nodes <= n_depots || n_nodes > 65535) return fail(MDVRP_EINVAL, "bad node counts");
+  if ((int64_t)ns * np > INT32_MAX) return fail(MDVRP_EINVAL, "too many route pairs");
+  if (ns > 0 && !s_intro) return fail(MDVRP_EINVAL, "null intro flags");
+  if ((int64_t)ns * np > 0 && (!EI || !NR || !NM || !NC)) return fail(MDVRP_EINVAL, "null output");
+  hipStream_t s = S(stream);
+  if (mdvrp_status e = check_routes_dev("offspring", n_depots, n_nodes, ns, s_len, s_nodes, s_offs, s_start, s_end,
+                                        s_intro, false, s))
+    return e;
+  if (mdvrp_status e = check_routes_dev("parent", n_depots, n_nodes, np, p_len, p_nodes, p_offs, p_start, p_end,
+                                        nullptr, true, s))
+    return e;
+  const size_t need = dcrex_ws_bytes(n_nodes, ns, np, p_len) + 256;
+  if (!ws || ws_bytes < need) return fail(MDVRP_ENOSPC, "DCREX workspace needs %zu bytes", need);
+  void* w = (void*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  int32_t* err = nullptr;
+  launch_dcrex_counts(s, n_nodes, n_depots, ns, s_len, s_nodes, s_offs, s_start, s_end, s_intro, np, p_len, p_nodes,
+                      p_offs, p_start, p_end, EI, NR, NM, NC, w, &err);
+  HIP_TRY(hipGetLastError());
+  int32_t h_err = 0;
+  HIP_TRY(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h_err) return fail(MDVRP_ENOSPC, "a customer occurs in more than %d offspring routes", kOccMax);
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_dcrex_pick(int32_t ns, int32_t np, const int32_t* EI, const int32_t* NR,
+                                         const int32_t* NM, const int32_t* NC, uint64_t seed, int32_t* out,
+                                         void* stream) {
+  if (ns < 0 || np < 0 || !out || ((int64_t)ns * np > 0 && (!EI || !NR || !NM || !NC)))
+    return fail(MDVRP_EINVAL, "bad argument");
+  if ((int64_t)ns * np > INT32_MAX) return fail(MDVRP_EINVAL, "too many route pairs");
+  launch_dcrex_pick(S(stream), ns, np, EI, NR, NM, NC, seed, out);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_ucb_select(int32_t n_arms, const double* R, const double* N, int32_t* arm,
+                                         void* stream) {
+  if (n_arms < 1 || n_arms > 1024 || !R || !N || !arm) return fail(MDVRP_EINVAL, "bad argument");
+  launch_ucb_select(S(stream), n_arms, R, N, arm);
+  HIP_TRY(hipGetLastError());
+  return MDVRP_OK;
+}
+
+extern "C" mdvrp_status mdvrp_ucb_update(int32_t n_arms, double* R, double* N, const int32_t* arm,
+                                         const double* reward, double gamma, void* stream) {
+  if (n_arms < 1 || n_arms > 1024 || !R || !N || !arm || !reward || !(gamma > 0.0 && gamma <= 1.0))
+    return fail(MDVRP_EINVAL, "bad argument");
+  launch_ucb_update(S(stream), n_arms, R, N, arm, reward, gamma);
   HIP_TRY(hipGetLastError());
   return MDVRP_OK;
 }
@@ -1090,6 +1361,15 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   if (o->filter == MDVRP_FILTER_MLP && !o->mlp) return fail(MDVRP_EINVAL, "the MLP filter needs a network");
   if (o->rescore < 0) return fail(MDVRP_EINVAL, "rescore must be >= 0");
   if (o->graph != 0 && o->graph != 1) return fail(MDVRP_EINVAL, "graph must be 0 or 1");
+  if (o->penalty_adapt != 0 && o->penalty_adapt != 1) return fail(MDVRP_EINVAL, "penalty_adapt must be 0 or 1");
+  if (o->penalty_adapt && o->max_passes == 0)
+    return fail(MDVRP_EINVAL, "penalty_adapt needs a search depth (max_passes > 0): with moving weights a search "
+                              "can revisit solutions forever");
+  if (o->penalty_adapt)
+    for (int k = 0; k < 4; ++k)
+      if (o->w_min[k] < 0 || o->w_min[k] > o->w_max[k] || o->w_max[k] > (1 << 30))
+        return fail(MDVRP_EINVAL, "weight %d: bounds [%d, %d] outside 0 <= w_min <= w_max <= 2^30", k, o->w_min[k],
+                    o->w_max[k]);
   if (mdvrp_status e = need_loaded(B)) return e;
   B->state_changed();
   const int poll = std::max(1, o->poll_every);
@@ -1109,6 +1389,16 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   }
   LaunchCtx L = B->ctx(st);
   L.compact = o->filter != MDVRP_FILTER_NONE;
+  if (o->penalty_adapt) {
+    // every unit starts from its instance's weights; the fused steps adapt them on the device
+    if (weights_to_instance(B))
+      HIP_TRY(hipMemcpyAsync(B->d_units, B->h_units.data(), sizeof(UnitDesc) * B->n_units, hipMemcpyHostToDevice, st));
+    L.adapt_units = B->d_units;
+    for (int k = 0; k < 4; ++k) {
+      L.adapt.lo[k] = o->w_min[k];
+      L.adapt.hi[k] = o->w_max[k];
+    }
+  }
   step_begin(L, o->filter != MDVRP_FILTER_NONE ? 1 : 0, o->filter == MDVRP_FILTER_MLP ? 1 : 0);
   if (!B->h_poll) {
     HIP_TRY(hipHostMalloc((void**)&B->h_poll, 2 * sizeof(int32_t), hipHostMallocDefault));
@@ -1127,7 +1417,12 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     } else {
       const int64_t rank_phase = o->rescore > 0 ? (p % o->rescore == 0) : 0;
       std::vector<int64_t> key = {o->mode, o->leader_only, o->filter, o->rescore, rank_phase, (int64_t)(intptr_t)o->mlp,
-                                  nf};
+                                  o->penalty_adapt, nf};
+      if (o->penalty_adapt)
+        for (int k = 0; k < 4; ++k) {
+          key.push_back(o->w_min[k]);
+          key.push_back(o->w_max[k]);
+        }
       for (int k = 0; k < nf; ++k) key.push_back(fam[k]);
       auto it = B->graphs.find(key);
       if (it == B->graphs.end()) {
@@ -1156,9 +1451,18 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
     }
   }
   HIP_TRY(hipStreamSynchronize(st));
-  launch_cost(L, nullptr, nullptr);
+  launch_cost(L, nullptr, nullptr);  // F under the weights the search ended with
   std::vector<int64_t> stv;
   mdvrp_status s = check_unit_errors(B, stv, st);
+  if (o->penalty_adapt && s != MDVRP_EDEVICE)
+    for (int k = 0; k < B->n_units; ++k) {  // keep the host copy of the descriptors in step
+      const int64_t* x = &stv[(size_t)k * kStateWords];
+      UnitDesc& u = B->h_units[k];
+      u.w_tw = (int32_t)x[12];
+      u.w_load = (int32_t)x[13];
+      u.w_dur = (int32_t)x[14];
+      u.w_depot = x[15];
+    }
   if (use_own) {
     HIP_TRY(hipEventRecord(B->ev_out, st));
     HIP_TRY(hipStreamWaitEvent(S(stream), B->ev_out, 0));
@@ -1175,6 +1479,7 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
       stats[k].device_ms = B->clock_khz > 0 ? (double)(x[11] - x[10]) / B->clock_khz : -1.0;
       stats[k].err = (int32_t)x[5];
       stats[k].converged = x[6] ? 0 : 1;
+      for (int w = 0; w < 4; ++w) stats[k].w_final[w] = x[12 + w];
     }
   }
   return s;

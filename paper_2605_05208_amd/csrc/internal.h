@@ -75,6 +75,8 @@ struct UnitCtl {
   int32_t rebuild_mode;  // latest step: 0 = rebuilt routes appended in place, 1 = full relayout
   int32_t n_build;       // routes to build in place (mode 0)
   int32_t ftiles_eval;   // pair tiles the latest evaluation in filtered mode covered (its lists' tiles)
+  int32_t n_unrouted;    // repair: customers missing from the loaded partial solution
+  int32_t n_inserted;    // repair: customers inserted so far
   int64_t F;             // running objective (sum of applied deltas)
   int64_t evaluated;
   int64_t passes, steps, moves_applied;
@@ -82,7 +84,13 @@ struct UnitCtl {
   int64_t fallbacks;     // full-list fallback passes of a filtered search
   int64_t t_start;       // device clock at the start of the latest search
   int64_t t_end;         // device clock at the end of this unit's latest pass
+  int64_t ins_evaluated; // repair: insertion positions evaluated
   MoveRec leader;
+};
+
+// Bounds of the dynamic penalty weights (time window, load, duration, depot).
+struct AdaptBounds {
+  int32_t lo[4], hi[4];
 };
 
 struct UnitDesc {
@@ -105,7 +113,6 @@ struct UnitDesc {
   int32_t *r_off[2];
   int4* r_meta[2];  // per buffer and slot {offset, length, start depot, end depot}
   int4* r_tot;      // {C, Q, D, TW} of every route
-  int64_t* r_cost;  // penalised route cost
   SegTW* r_core;    // time windows: segment of customers 1..L (routes with L <= kCoreMaxL)
   void* fw[2];
   void* bw[2];
@@ -231,9 +238,8 @@ __device__ __forceinline__ int4 dep_arcs(const UnitDesc& U, int x, int d) {
   return make_int4(ci, U.t_is_c ? ci : arc_t(U, d, x), co, U.t_is_c ? co : arc_t(U, x, d));
 }
 
-// Penalised cost of a complete route from its total segment (fixed-weight Eq. A.1 terms).
+// Terms of Eq. A.1 of a complete route from its total segment.
 struct RouteTerms {
-  int64_t cost;
   int32_t C, TW, LX, DX;
 };
 template <class SEG>
@@ -243,11 +249,10 @@ __device__ __forceinline__ RouteTerms route_terms(const UnitDesc& U, const SEG& 
   r.TW = seg_tw(s);
   r.LX = imax(s.Q - U.Q, 0);
   r.DX = U.Dmax >= 0 ? imax(s.D - U.Dmax, 0) : 0;
-  r.cost = (int64_t)r.C + (int64_t)U.w_tw * r.TW + (int64_t)U.w_load * r.LX + (int64_t)U.w_dur * r.DX;
   return r;
 }
 
-// dF of a move from the int32 deltas of its cost terms. The fixed-weight Eq. A.1 is
+// dF of a move from the int32 deltas of its cost terms. For given weights Eq. A.1 is
 // linear in distance, time warp, load and duration excess and the depot term, so the
 // difference of the route costs equals this combination exactly; the evaluators need
 // no 64-bit per-route costs. (Every route term stays below 2^30, so the deltas fit int32.)
@@ -550,6 +555,15 @@ __device__ __forceinline__ int block_scan_excl(int v, int* sh, int* total) {
   *total = sh[2 * NW];
   __syncthreads();
   return r;
+}
+
+// SplitMix64 (Steele, Lea and Flood, 2014): the pass order of Algorithm 2 and the
+// random insertion draw from it, on the host and on the device.
+__host__ __device__ inline uint64_t splitmix64_next(uint64_t* st) {
+  uint64_t z = (*st += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
 }
 
 // Lexicographic (dF, id) order of move keys.

@@ -54,6 +54,11 @@ struct LaunchCtx {
   int compact;
   int max_nd;                  // largest depot count over the batch's instances
   int32_t* active_count;       // device int
+  // dynamic penalty weights of a local search: the fused step writes each unit's new
+  // weights into this array (the device copy of units) after a step that applied
+  // moves; null = fixed weights
+  UnitDesc* adapt_units;
+  AdaptBounds adapt;
 };
 
 // One item class: 0 pair kinds, 1 depot-insert, 2 depot-replace (no launch when it has no work).
@@ -80,7 +85,7 @@ void launch_load(const LaunchCtx& L, const int32_t* nodes, const int32_t* offs, 
 // Moves evaluated by every unit in the latest evaluation (out[n_units]).
 void launch_evaluated_export(const LaunchCtx& L, int64_t* out);
 void launch_sel_export(const LaunchCtx& L, uint64_t* ids, int64_t* dF, int32_t* counts, int32_t cap_per_unit);
-constexpr int kStateWords = 12;  // per-unit counters exported by launch_state_export
+constexpr int kStateWords = 16;  // per-unit counters and weights exported by launch_state_export
 void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][kStateWords] */);
 
 // ---- learned move filter
@@ -129,6 +134,37 @@ size_t mlp_grad_part_floats(int n);
 void launch_mlp_backward(hipStream_t s, const MlpDev& M, const uint16_t* x, int n, const float* dz, const uint16_t* h1,
                          const uint16_t* h2, float* g, uint16_t* G2, uint16_t* G1, float* part);
 void launch_adam(hipStream_t s, const MlpDev& M, const float* g, float lr, int step);
+
+// population measures (Section 3.4)
+constexpr int kPopMaxMembers = 1024;  // members of one population call
+constexpr int kPopMaxClose = 16;      // largest n_close of the population distance (Eq. 6)
+// Edge keys of the members (units list[0..n)) into keys[n][nc], |E| into n_edges[n], then
+// Eq. 7 for every pair into dist[n][n] (and the common arc counts into common, nullable).
+void launch_pop_distance(const LaunchCtx& L, const int32_t* list, int n, int nc, int2* keys, int64_t* n_edges,
+                         double* dist, int64_t* common);
+void launch_pop_reduce(hipStream_t s, const double* dist, const int64_t* f, int n, int mu, double xi, int n_close,
+                       int32_t* keep, int32_t* order, double* chi, double* dpop);
+
+// repair insertion (Section 3.3): missing-customer lists, then one insertion per unit and
+// round (op: MDVRP_REPAIR_*; order[order_base[u] + i] = the i-th customer inserted in unit u)
+void launch_ins_begin(const LaunchCtx& L);
+void launch_ins_export(const LaunchCtx& L, int64_t* out);  // insertion positions evaluated per unit
+void launch_ins_round(const LaunchCtx& L, int op, uint64_t seed, int max_unrouted, int32_t* order,
+                      const int32_t* order_base);
+
+// DCREX crossover pieces (Algorithm 3) and discounted UCB1 (Eq. 4)
+constexpr int kOccMax = 8;  // occurrences of one customer in an offspring the counts accept
+size_t dcrex_ws_bytes(int n_nodes, int ns, int np, int p_len);
+void launch_dcrex_counts(hipStream_t s, int n_nodes, int n_depots, int ns, int s_len, const int32_t* s_nodes,
+                         const int32_t* s_offs, const int32_t* s_start, const int32_t* s_end, const int32_t* s_intro,
+                         int np, int p_len, const int32_t* p_nodes, const int32_t* p_offs, const int32_t* p_start,
+                         const int32_t* p_end, int32_t* EI, int32_t* NR, int32_t* NM, int32_t* NC, void* ws,
+                         int32_t** err_out);
+void launch_dcrex_pick(hipStream_t s, int ns, int np, const int32_t* EI, const int32_t* NR, const int32_t* NM,
+                       const int32_t* NC, uint64_t seed, int32_t* out);
+void launch_ucb_select(hipStream_t s, int n_arms, const double* R, const double* N, int32_t* arm);
+void launch_ucb_update(hipStream_t s, int n_arms, double* R, double* N, const int32_t* arm, const double* reward,
+                       double gamma);
 
 // instance preprocessing
 void launch_inst_stats(hipStream_t s, const int32_t* c, const int32_t* t, int n, int64_t* partial, int nblocks);

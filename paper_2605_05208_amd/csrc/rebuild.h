@@ -66,11 +66,7 @@ __device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int
         U.pos[x] = p;
         U.apos[x] = (int32_t)(off + p);
       }
-      if (p == P - 1) {
-        const RouteTerms t = route_terms(U, seg);
-        U.r_tot[slot] = make_int4(seg.C, seg.Q, seg.D, seg_tw(seg));
-        U.r_cost[slot] = t.cost;
-      }
+      if (p == P - 1) U.r_tot[slot] = make_int4(seg.C, seg.Q, seg.D, seg_tw(seg));
     }
     const int lv = imin(63, P - 1 - base);
     carry = shfl_seg(seg, lv);

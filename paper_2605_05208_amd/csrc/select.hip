@@ -243,16 +243,60 @@ __device__ __forceinline__ void plan_move(const SelView<APPLY, DEPL>& V, int cur
   atomicAdd(&V.P.F, (unsigned long long)dF);
 }
 
+// Dynamic penalty coefficients (Section 3.2.1; kappa = 1/2, integer form) after a step
+// that applied moves, from the unit's new solution: each weight is doubled when the
+// solution violates its term (time warp; load excess; duration excess; closure or
+// fleet excess) and halved, rounding down, when it does not, then clamped to its
+// bounds. Called by the whole block after the new routes are built; the new weights go
+// to the unit's entry of the device copy of the unit descriptors, which every later
+// launch reads (this kernel reads none of them afterwards).
+template <bool OPEN>
+__device__ __forceinline__ void adapt_weights(const UnitDesc& U, const UnitCtl* ctl, UnitDesc* out,
+                                              const AdaptBounds& b, int* s_viol) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *s_viol = 0;
+  __syncthreads();
+  int v = 0;
+  const int n_alive = ctl->n_slots_alive;
+  for (int i = tid; i < n_alive; i += kSelBlock) {
+    const int s = U.slot_list[i];
+    const int4 t = U.r_tot[s];  // {C, Q, D, TW}
+    if (t.w > 0) v |= 1;
+    if (t.y > U.Q) v |= 2;
+    if (U.Dmax >= 0 && t.z > U.Dmax) v |= 4;
+    if (!OPEN && U.r_end[s] >= 0 && U.r_end[s] != U.r_start[s]) v |= 8;
+  }
+  for (int d = tid; d < U.nd; d += kSelBlock)
+    if (U.ndep[d] > U.NV) v |= 8;
+  if (v) atomicOr(s_viol, v);
+  __syncthreads();
+  if (tid == 0) {
+    const int viol = *s_viol;
+    const int64_t w[4] = {U.w_tw, U.w_load, U.w_dur, U.w_depot};
+    int64_t nw[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t x = (viol >> k & 1) ? 2 * w[k] : w[k] / 2;
+      nw[k] = x < b.lo[k] ? b.lo[k] : (x > b.hi[k] ? b.hi[k] : x);
+    }
+    out->w_tw = (int32_t)nw[0];
+    out->w_load = (int32_t)nw[1];
+    out->w_dur = (int32_t)nw[2];
+    out->w_depot = nw[3];
+  }
+}
+
 template <class SEG, bool TW, bool OPEN, bool APPLY, bool DEPL>
 __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __restrict__ units, uint32_t cls_mask,
-                                                           int leader_only, int scored) {
+                                                           int leader_only, int scored, UnitDesc* adapt_units,
+                                                           AdaptBounds adapt) {
   const UnitDesc& U = units[blockIdx.x];
   UnitCtl* ctl = U.ctl;
   __shared__ int64_t shF[kSelWaves];
   __shared__ uint64_t shI[kSelWaves];
   __shared__ int shT[kSelWaves];
   __shared__ int sh[2 * kSelWaves + 1];
-  __shared__ int s_nsel, s_alive, s_epoch, s_leader_tile, s_ndins, s_nbuild, s_alive_changed;
+  __shared__ int s_nsel, s_alive, s_epoch, s_leader_tile, s_ndins, s_nbuild, s_alive_changed, s_viol;
   __shared__ SelLds S;
   __shared__ PlanLds P;
   if (!ctl->active) return;
@@ -554,17 +598,22 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
       build_recorded_route<SEG, TW, OPEN>(U, rec, src, dst);
     }
     rebuild_items<SEG, TW, OPEN>(U, ctl, wave, kSelWaves);
+    if (adapt_units) {
+      __syncthreads();
+      adapt_weights<OPEN>(U, ctl, adapt_units + blockIdx.x, adapt, &s_viol);
+    }
   }
 }
 
 template <class SEG, bool TW, bool OPEN, bool APPLY>
 static void select_t(const LaunchCtx& L, uint32_t cls, int leader_only, int scored) {
+  UnitDesc* au = APPLY ? L.adapt_units : nullptr;
   if (L.max_nd <= kDepLds)
     hipLaunchKernelGGL((k_select_plan<SEG, TW, OPEN, APPLY, true>), dim3(L.n_units), dim3(kSelBlock), 0, L.stream,
-                       L.units, cls, leader_only, scored);
+                       L.units, cls, leader_only, scored, au, L.adapt);
   else
     hipLaunchKernelGGL((k_select_plan<SEG, TW, OPEN, APPLY, false>), dim3(L.n_units), dim3(kSelBlock), 0, L.stream,
-                       L.units, cls, leader_only, scored);
+                       L.units, cls, leader_only, scored, au, L.adapt);
 }
 
 void launch_select(const LaunchCtx& L, uint32_t fam_mask, int leader_only, int scored, bool apply) {

@@ -163,17 +163,17 @@ __global__ void k_pass_end(const UnitDesc* __restrict__ units, int n_units, int3
 
 // --------------------------------------------------------------------------- cost and export
 
-// F(S) from scratch: route costs + depot weight * (closure + fleet excess) (Eq. A.1).
+// F(S) from scratch (Eq. A.1 under the unit's current weights): the terms summed over
+// the routes and depots, then weighted.
 __global__ __launch_bounds__(kUnitBlock) void k_cost(const UnitDesc* __restrict__ units, int64_t* F, int64_t* terms) {
   const UnitDesc& U = units[blockIdx.x];
   __shared__ unsigned long long acc[7];
   if (threadIdx.x < 7) acc[threadIdx.x] = 0;
   __syncthreads();
-  unsigned long long cost = 0, D = 0, TW = 0, LX = 0, DX = 0, CL = 0, FX = 0;
+  unsigned long long D = 0, TW = 0, LX = 0, DX = 0, CL = 0, FX = 0;
   for (int s = threadIdx.x; s < U.R; s += kUnitBlock) {
     if (U.r_len[s] <= 0) continue;
     const int4 t = U.r_tot[s];
-    cost += (unsigned long long)U.r_cost[s];
     D += (unsigned long long)(int64_t)t.x;
     TW += (unsigned long long)(int64_t)t.w;
     LX += (unsigned long long)(int64_t)imax(t.y - U.Q, 0);
@@ -181,11 +181,12 @@ __global__ __launch_bounds__(kUnitBlock) void k_cost(const UnitDesc* __restrict_
     if (U.r_end[s] >= 0 && U.r_start[s] != U.r_end[s]) CL += 1;
   }
   for (int d = threadIdx.x; d < U.nd; d += kUnitBlock) FX += (unsigned long long)imax(U.ndep[d] - U.NV, 0);
-  atomicAdd(&acc[0], cost); atomicAdd(&acc[1], D); atomicAdd(&acc[2], TW); atomicAdd(&acc[3], LX);
+  atomicAdd(&acc[1], D); atomicAdd(&acc[2], TW); atomicAdd(&acc[3], LX);
   atomicAdd(&acc[4], DX); atomicAdd(&acc[5], CL); atomicAdd(&acc[6], FX);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int64_t f = (int64_t)acc[0] + U.w_depot * ((int64_t)acc[5] + (int64_t)acc[6]);
+    const int64_t f = (int64_t)acc[1] + (int64_t)U.w_tw * (int64_t)acc[2] + (int64_t)U.w_load * (int64_t)acc[3] +
+                      (int64_t)U.w_dur * (int64_t)acc[4] + U.w_depot * ((int64_t)acc[5] + (int64_t)acc[6]);
     U.ctl->F = f;
     if (F) F[blockIdx.x] = f;
     if (terms)
@@ -248,6 +249,7 @@ __global__ void k_state_export(const UnitDesc* __restrict__ units, int n_units, 
   o[0] = c->F; o[1] = c->evaluated; o[2] = c->passes; o[3] = c->steps; o[4] = c->moves_applied;
   o[5] = c->err; o[6] = c->active; o[7] = c->n_sel; o[8] = c->fallbacks; o[9] = c->fmode;
   o[10] = c->t_start; o[11] = c->t_end;
+  o[12] = units[u].w_tw; o[13] = units[u].w_load; o[14] = units[u].w_dur; o[15] = units[u].w_depot;
 }
 
 // --------------------------------------------------------------------------- launchers

@@ -59,13 +59,15 @@ MOVE_DTYPE = np.dtype(MOVE_FIELDS)
 class LsOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("leader_only", C.c_int32), ("max_passes", C.c_int32),
                 ("poll_every", C.c_int32), ("seed", C.c_uint64), ("filter", C.c_int32), ("rescore", C.c_int32),
-                ("mlp", C.c_void_p), ("graph", C.c_int32), ("pad2", C.c_int32)]
+                ("mlp", C.c_void_p), ("graph", C.c_int32), ("penalty_adapt", C.c_int32),
+                ("w_min", C.c_int32 * 4), ("w_max", C.c_int32 * 4)]
 
 
 class LsStats(C.Structure):
     _fields_ = [("passes", C.c_int64), ("steps", C.c_int64), ("moves_applied", C.c_int64),
                 ("evaluated", C.c_int64), ("F", C.c_int64), ("fallback_passes", C.c_int64),
-                ("device_ms", C.c_double), ("converged", C.c_int32), ("err", C.c_int32)]
+                ("device_ms", C.c_double), ("converged", C.c_int32), ("err", C.c_int32),
+                ("w_final", C.c_int64 * 4)]
 
 
 DENSE_DTYPE = np.dtype([("dF", np.int64), ("dD", np.int64), ("dTW", np.int64), ("dLX", np.int64),
@@ -90,9 +92,13 @@ EXPORTED = [
     "mdvrp_filter_anchor_count",
     "mdvrp_filter_features", "mdvrp_filter_labels", "mdvrp_filter_score_topk", "mdvrp_filter_eta_lists",
     "mdvrp_filter_export", "mdvrp_autotune", "mdvrp_set_tile_shapes",
+    "mdvrp_population_workspace_query", "mdvrp_population_distance", "mdvrp_population_reduce",
+    "mdvrp_solutions_load_partial", "mdvrp_repair",
+    "mdvrp_dcrex_workspace_query", "mdvrp_dcrex_counts", "mdvrp_dcrex_pick", "mdvrp_ucb_select", "mdvrp_ucb_update",
 ]
+REPAIR_FBI, REPAIR_IBI, REPAIR_FRI, REPAIR_IRI, REPAIR_RI = range(5)
 PROF_CLASSES = ["eval_pairs", "eval_depot_insert", "eval_depot_replace", "select", "apply", "filter_score"]
-STATE_WORDS = 12
+STATE_WORDS = 16
 
 
 def lib():
@@ -137,6 +143,16 @@ def lib():
             "mdvrp_adam_step": [p, p, C.c_float, i32, p],
             "mdvrp_mlp_train_step": [p, p, p, p, i32, C.c_float, i32, p, p, p, p, sz, p],
             "mdvrp_mlp_train_step_static": [p, p, p, p, i32, C.c_float, i32, p, p, p, p],
+            "mdvrp_population_workspace_query": [p, p, i32, p],
+            "mdvrp_population_distance": [p, p, i32, p, p, p, p, sz, p],
+            "mdvrp_population_reduce": [p, p, i32, i32, C.c_double, i32, p, p, p, p, p],
+            "mdvrp_solutions_load_partial": [p, p, p, p, p, p, i32, i32, p],
+            "mdvrp_repair": [p, i32, u64, p, p, p],
+            "mdvrp_dcrex_workspace_query": [i32, i32, i32, i32, p],
+            "mdvrp_dcrex_counts": [i32, i32, i32, i32, p, p, p, p, p, i32, i32, p, p, p, p, p, p, p, p, p, sz, p],
+            "mdvrp_dcrex_pick": [i32, i32, p, p, p, p, u64, p, p],
+            "mdvrp_ucb_select": [i32, p, p, p, p],
+            "mdvrp_ucb_update": [i32, p, p, p, p, C.c_double, p],
             "mdvrp_filter_workspace_query": [p, i32, p],
             "mdvrp_filter_attach": [p, i32, p, sz, p],
             "mdvrp_filter_anchor_count": [p, p],
@@ -277,6 +293,33 @@ class Batch:
         n, o, s, e, u = self._in
         check(lib().mdvrp_solutions_load(self.handle, _dptr(n), _dptr(o), _dptr(s), _dptr(e), _dptr(u),
                                          len(st), len(nodes), _stream()))
+
+    def load_partial(self, solutions):
+        """Load solutions from which customers may be missing (for repair)."""
+        from .gen import batch_flat
+        nodes, offs, st, en, so = batch_flat(solutions)
+        pad = lambda a: a if len(a) else np.zeros(1, np.int32)  # noqa: E731
+        self._in = [_dev_i32(x) for x in (pad(nodes), offs, pad(st), pad(en), so)]
+        n, o, s, e, u = self._in
+        check(lib().mdvrp_solutions_load_partial(self.handle, _dptr(n), _dptr(o), _dptr(s), _dptr(e), _dptr(u),
+                                                 len(st), len(nodes), _stream()))
+
+    def repair(self, op, seed=0):
+        """Insert the missing customers of every unit with operator op (REPAIR_*): per unit
+        (inserted customers in insertion order, positions evaluated)."""
+        torch = _torch()
+        tot = int(self.nc.sum())
+        order = torch.full((max(tot, 1),), -1, dtype=torch.int32, device="cuda")
+        nev = torch.zeros(self.n_units, dtype=torch.int64, device="cuda")
+        check(lib().mdvrp_repair(self.handle, int(op), int(seed), _dptr(order), _dptr(nev), _stream()))
+        torch.cuda.synchronize()
+        o = order.cpu().numpy()
+        base = np.concatenate([[0], np.cumsum(self.nc)])
+        out = []
+        for k in range(self.n_units):
+            seg = o[base[k]:base[k + 1]]
+            out.append([int(v) for v in seg[seg >= 0]])
+        return out, [int(v) for v in nev.cpu().numpy()]
 
     def export(self):
         from .gen import Solution
@@ -422,14 +465,39 @@ class Batch:
         check(lib().mdvrp_apply_moves(self.handle, _stream()))
 
     def local_search_to_optimum(self, mode=LS_PASSES, seed=0, max_passes=0, leader_only=0, poll_every=1,
-                                filter=FILTER_NONE, mlp=None, rescore=RESCORE_STEP, graph=False):
+                                filter=FILTER_NONE, mlp=None, rescore=RESCORE_STEP, graph=False, adapt=None):
+        """adapt = (w_min, w_max), four weights each (time window, load, duration, depot):
+        dynamic penalty coefficients within those bounds; None = the current fixed weights."""
         opt = LsOptions(mode, leader_only, max_passes, poll_every, seed, filter, rescore,
                         mlp.handle.value if mlp is not None else None, 1 if graph else 0, 0)
+        if adapt is not None:
+            opt.penalty_adapt = 1
+            opt.w_min = (C.c_int32 * 4)(*[int(x) for x in adapt[0]])
+            opt.w_max = (C.c_int32 * 4)(*[int(x) for x in adapt[1]])
         stats = (LsStats * self.n_units)()
         check(lib().mdvrp_local_search_to_optimum(self.handle, C.byref(opt), stats, _stream()))
         return [dict(passes=s.passes, steps=s.steps, moves_applied=s.moves_applied, evaluated=s.evaluated, F=s.F,
-                     fallback_passes=s.fallback_passes, device_ms=s.device_ms, converged=s.converged, err=s.err)
+                     fallback_passes=s.fallback_passes, device_ms=s.device_ms, converged=s.converged, err=s.err,
+                     w_final=[int(x) for x in s.w_final])
                 for s in stats]
+
+    # ------------------------------------------------------------------ population (Section 3.4)
+    def population_distance(self, units):
+        """Eq. 7 between the current solutions of the listed units: device (dist [n][n] fp64,
+        common arcs [n][n] int64, |E| [n] int64)."""
+        torch = _torch()
+        ul = np.ascontiguousarray(units, dtype=np.int32)
+        n = len(ul)
+        nbytes = C.c_size_t(0)
+        check(lib().mdvrp_population_workspace_query(self.handle, ul.ctypes.data_as(C.c_void_p), n,
+                                                     C.byref(nbytes)))
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        dist = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        common = torch.empty((n, n), dtype=torch.int64, device="cuda")
+        ne = torch.empty(n, dtype=torch.int64, device="cuda")
+        check(lib().mdvrp_population_distance(self.handle, ul.ctypes.data_as(C.c_void_p), n, _dptr(dist),
+                                              _dptr(common), _dptr(ne), _dptr(ws), nbytes.value, _stream()))
+        return dist, common, ne
 
     # ------------------------------------------------------------------ autotuner
     def autotune(self, fam_mask=FAM_ALL, reps=3):
@@ -611,6 +679,73 @@ class Mlp:
                                                 n, float(lr), int(step), _dptr(g), _dptr(z), _dptr(loss),
                                                 _stream()))
         return z, loss, g
+
+
+def population_reduce(dist, f, mu, xi=0.7, n_close=5):
+    """Reduce a population to mu members by the score of Eq. 5 (device tensors in, device out):
+    (keep [n] int32, removal order [n - mu] int32, chi [n] fp64, population distance [n] fp64)."""
+    torch = _torch()
+    n = int(f.shape[0])
+    keep = torch.empty(n, dtype=torch.int32, device="cuda")
+    order = torch.empty(max(n - mu, 1), dtype=torch.int32, device="cuda")
+    chi = torch.empty(n, dtype=torch.float64, device="cuda")
+    dpop = torch.empty(n, dtype=torch.float64, device="cuda")
+    check(lib().mdvrp_population_reduce(_dptr(dist), _dptr(f), n, int(mu), float(xi), int(n_close), _dptr(keep),
+                                        _dptr(order), _dptr(chi), _dptr(dpop), _stream()))
+    return keep, order[:max(n - mu, 0)], chi, dpop
+
+
+def _routes_dev(routes):
+    nodes, offs, st, en = [], [0], [], []
+    for a, xs, b in routes:
+        nodes.extend(xs)
+        offs.append(len(nodes))
+        st.append(a)
+        en.append(b)
+    pad = lambda v: v if len(v) else [0]  # noqa: E731
+    return ([_dev_i32(np.asarray(pad(v), np.int32)) for v in (nodes, offs, st, en)], len(routes), len(nodes))
+
+
+def dcrex_counts(n_depots, n_nodes, offspring, intro, parent):
+    """Route-pair counts of the crossover (Algorithm 3) on the device: (EI, NR, NM, NC) as
+    device int32 tensors [ns][np]; offspring / parent are lists of (start, customers, end)."""
+    torch = _torch()
+    (sn, so, ss, se), ns, s_len = _routes_dev(offspring)
+    (pn, po, ps, pe), np_, p_len = _routes_dev(parent)
+    it = _dev_i32(np.asarray(intro if len(intro) else [0], np.int32))
+    out = [torch.zeros(max(ns * np_, 1), dtype=torch.int32, device="cuda") for _ in range(4)]
+    nbytes = C.c_size_t(0)
+    check(lib().mdvrp_dcrex_workspace_query(n_nodes, ns, np_, p_len, C.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+    check(lib().mdvrp_dcrex_counts(n_depots, n_nodes, ns, s_len, _dptr(sn), _dptr(so), _dptr(ss), _dptr(se),
+                                   _dptr(it), np_, p_len, _dptr(pn), _dptr(po), _dptr(ps), _dptr(pe),
+                                   *[_dptr(o) for o in out], _dptr(ws), nbytes.value, _stream()))
+    return [o[:ns * np_].reshape(ns, np_) for o in out]
+
+
+def dcrex_pick(counts, seed):
+    """Algorithm 3's exchange among the five lowest pairs: (i, j, diversity increase, candidates)."""
+    torch = _torch()
+    ei, nr, nm, nc = counts
+    ns, np_ = ei.shape
+    out = torch.empty(4, dtype=torch.int32, device="cuda")
+    check(lib().mdvrp_dcrex_pick(ns, np_, _dptr(ei), _dptr(nr), _dptr(nm), _dptr(nc), int(seed), _dptr(out),
+                                 _stream()))
+    return [int(v) for v in out.cpu().numpy()]
+
+
+def ucb_select(R, N):
+    """Arm chosen by discounted UCB1 (Eq. 4) from device fp64 tensors R, N."""
+    torch = _torch()
+    arm = torch.empty(1, dtype=torch.int32, device="cuda")
+    check(lib().mdvrp_ucb_select(int(R.shape[0]), _dptr(R), _dptr(N), _dptr(arm), _stream()))
+    return arm
+
+
+def ucb_update(R, N, arm, reward, gamma=0.99):
+    """In place on device fp64 tensors R, N; arm a device int32 tensor [1], reward a device fp64 [1]."""
+    check(lib().mdvrp_ucb_update(int(R.shape[0]), _dptr(R), _dptr(N), _dptr(arm), _dptr(reward), float(gamma),
+                                 _stream()))
 
 
 def validate_solutions_host(instances, unit_inst, solutions):
