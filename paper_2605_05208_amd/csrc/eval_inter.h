@@ -118,18 +118,59 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
   const int32_t c_pv2 = fb1.C - fb2.C, t_pv2 = next_t(U, fb2, fb1);
   const Side<SEG> Ypv = block2<SEG>(U, pp_v, p_v, c_pv2, t_pv2);           // (pp(v), p(v))
 
-  // join with a matrix arc (marked for footprint measurements)
-  auto J = [&](const Side<SEG>& a, const Side<SEG>& b) -> Side<SEG> {
-    ar.mark(U, a.last, b.first);
-    return join(U, a, b);
-  };
-  auto AC = [&](int a, int b) -> int32_t {
+  // Every arc the enabled kinds create between the two routes' neighbourhoods, loaded
+  // up front and unconditionally (nodes that do not exist are replaced by u, whose
+  // arcs are then not used), so that the gathers of one anchor overlap instead of
+  // following the kinds' branches one after the other; each distinct arc is read once.
+  auto CT = [&](int a, int b) -> int2 {
     ar.mark(U, a, b);
-    return arc_c(U, a, b);
+    const int32_t c = arc_c(U, a, b);
+    return make_int2(c, U.t_is_c ? c : arc_t(U, a, b));
   };
-  auto AT = [&](int a, int b) -> int32_t {
-    ar.mark(U, a, b);
-    return arc_t(U, a, b);
+  const bool fREL = kinds & ((1u << REL1) | (1u << REL2));
+  const bool fSWP = kinds & ((1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (1u << SWP22));
+  const bool fX2 = kinds & (1u << X2);
+  const int su = s_u >= 0 ? s_u : u, ssu = ss_u >= 0 ? ss_u : u;
+  int2 k_u_v = make_int2(0, 0), k_pv_su = k_u_v, k_pu_su = k_u_v, k_pv_u = k_u_v, k_ppu_su = k_u_v,
+       k_pv_pu = k_u_v, k_pu_ssu = k_u_v, k_pu_pv = k_u_v, k_ppv_u = k_u_v, k_ppu_pv = k_u_v, k_ppv_pu = k_u_v,
+       k_pv_ssu = k_u_v, k_ppv_su = k_u_v, k_pppv_u = k_u_v, k_pu_ppv = k_u_v, k_pppv_pu = k_u_v,
+       k_ppu_ppv = k_u_v, k_pppv_su = k_u_v, k_ppv_ssu = k_u_v;
+  k_u_v = CT(u, v);
+  k_pv_su = CT(p_v, su);
+  if (fREL) {
+    k_pu_su = CT(p_u, su);
+    k_pv_u = CT(p_v, u);
+    k_ppu_su = CT(pp_u, su);
+    k_pv_pu = CT(p_v, p_u);
+    if (sym) k_pu_ssu = CT(p_u, ssu);
+  }
+  if (fSWP) {
+    k_pu_pv = CT(p_u, p_v);
+    k_ppv_u = CT(pp_v, u);
+    k_ppu_pv = CT(pp_u, p_v);
+    k_ppv_pu = CT(pp_v, p_u);
+    k_pppv_u = CT(ppp_v, u);
+    k_pu_ppv = CT(p_u, pp_v);
+    k_pppv_pu = CT(ppp_v, p_u);
+    k_ppu_ppv = CT(pp_u, pp_v);
+    if (sym) {
+      k_pv_ssu = CT(p_v, ssu);
+      k_ppv_su = CT(pp_v, su);
+      k_pppv_su = CT(ppp_v, su);
+      k_ppv_ssu = CT(pp_v, ssu);
+    }
+  }
+  (void)fX2;
+  // join of two sides through a loaded arc
+  auto J = [&](const Side<SEG>& a, const Side<SEG>& b, int2 ct) -> Side<SEG> {
+    return side(cat(a.s, ct.x, ct.y, b.s), a.first, b.last);
+  };
+  // the block (s(u), u) of the reversed 2-node moves (symmetric instances only): its arc
+  // is the route's own arc u -> s(u), read off the suffix segments
+  auto Xsu_block = [&]() -> Side<SEG> {
+    const int32_t c = bau.C - ba1.C;
+    const int32_t t = bau.D - ba1.D - service(U, u);
+    return block2<SEG>(U, s_u, u, c, t);
   };
 
   // move delta: new A' (may be empty), new B' (may be empty), end depots of the new routes
@@ -165,88 +206,85 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
     take(U, o, m, id);
   };
   // A' = prefix + [block] + suffix (suffix may be absent on open routes)
-  auto closeA = [&](const Side<SEG>& left, bool hasS, const Side<SEG>& S) -> SEG {
-    return hasS ? J(left, S).s : left.s;
+  auto closeA = [&](const Side<SEG>& left, bool hasS, const Side<SEG>& S, int2 ct) -> SEG {
+    return hasS ? J(left, S, ct).s : left.s;
   };
 
   // ---------------------------------------------------------------- Relocate
   if (kinds >> REL1 & 1) {
     const bool aEmpty = LA == 1;
     SEG Ap = fa1;
-    if (!aEmpty) Ap = closeA(Pu1, hasSA1, Su1);
-    const SEG Bp = J(J(Pv1, Nu), Sv0).s;
+    if (!aEmpty) Ap = closeA(Pu1, hasSA1, Su1, k_pu_su);
+    const SEG Bp = J(J(Pv1, Nu, k_pv_u), Sv0, k_u_v).s;
     finish(make_id(REL1, 0, u, v), aEmpty, Ap, x.eA, false, Bp, x.eB);
   }
   if (kinds >> REL2 & 1) {
     if (hasPPu) {  // X = (p(u), u)
       const bool aEmpty = LA == 2;
       SEG Ap = fa2;
-      if (!aEmpty) Ap = closeA(Pu2, hasSA1, Su1);
-      const SEG Bp = J(J(Pv1, Xpu), Sv0).s;
+      if (!aEmpty) Ap = closeA(Pu2, hasSA1, Su1, k_ppu_su);
+      const SEG Bp = J(J(Pv1, Xpu, k_pv_pu), Sv0, k_u_v).s;
       finish(make_id(REL2, 0, u, v), aEmpty, Ap, x.eA, false, Bp, x.eB);
     }
     if (sym && hasSu) {  // block (u, s(u)) placed as (s(u), u)
       const bool aEmpty = LA == 2;
       SEG Ap = fa1;
-      if (!aEmpty) Ap = closeA(Pu1, hasSA2, Su2);
-      const Side<SEG> Xsu = block2<SEG>(U, s_u, u, AC(s_u, u), AT(s_u, u));
-      const SEG Bp = J(J(Pv1, Xsu), Sv0).s;
+      if (!aEmpty) Ap = closeA(Pu1, hasSA2, Su2, k_pu_ssu);
+      const SEG Bp = J(J(Pv1, Xsu_block(), k_pv_su), Sv0, k_u_v).s;
       finish(make_id(REL2, 1, u, v), aEmpty, Ap, x.eA, false, Bp, x.eB);
     }
   }
   // ---------------------------------------------------------------- Swap
   if (kinds >> SWP11 & 1) {
     if (hasPv) {
-      const SEG Ap = closeA(J(Pu1, Npv), hasSA1, Su1);
-      const SEG Bp = J(J(Pv2, Nu), Sv0).s;
+      const SEG Ap = closeA(J(Pu1, Npv, k_pu_pv), hasSA1, Su1, k_pv_su);
+      const SEG Bp = J(J(Pv2, Nu, k_ppv_u), Sv0, k_u_v).s;
       finish(make_id(SWP11, 0, u, v), false, Ap, x.eA, false, Bp, x.eB);
     }
   }
   if (kinds >> SWP21 & 1) {
     if (hasPv && hasPPu) {  // X = (p(u), u), Y = (p(v))
-      const SEG Ap = closeA(J(Pu2, Npv), hasSA1, Su1);
-      const SEG Bp = J(J(Pv2, Xpu), Sv0).s;
+      const SEG Ap = closeA(J(Pu2, Npv, k_ppu_pv), hasSA1, Su1, k_pv_su);
+      const SEG Bp = J(J(Pv2, Xpu, k_ppv_pu), Sv0, k_u_v).s;
       finish(make_id(SWP21, 0, u, v), false, Ap, x.eA, false, Bp, x.eB);
     }
     if (sym && hasPv && hasSu) {  // X = (u, s(u)) placed as (s(u), u)
-      const Side<SEG> Xsu = block2<SEG>(U, s_u, u, AC(s_u, u), AT(s_u, u));
-      const SEG Ap = closeA(J(Pu1, Npv), hasSA2, Su2);
-      const SEG Bp = J(J(Pv2, Xsu), Sv0).s;
+      const SEG Ap = closeA(J(Pu1, Npv, k_pu_pv), hasSA2, Su2, k_pv_ssu);
+      const SEG Bp = J(J(Pv2, Xsu_block(), k_ppv_su), Sv0, k_u_v).s;
       finish(make_id(SWP21, 1, u, v), false, Ap, x.eA, false, Bp, x.eB);
     }
   }
   if (kinds >> SWP12 & 1) {
     if (hasPPv) {
-      const SEG Bp = J(J(Pv3, Nu), Sv0).s;
+      const SEG Bp = J(J(Pv3, Nu, k_pppv_u), Sv0, k_u_v).s;
       {  // Y = (pp(v), p(v)) as is
-        const SEG Ap = closeA(J(Pu1, Ypv), hasSA1, Su1);
+        const SEG Ap = closeA(J(Pu1, Ypv, k_pu_ppv), hasSA1, Su1, k_pv_su);
         finish(make_id(SWP12, 0, u, v), false, Ap, x.eA, false, Bp, x.eB);
       }
-      if (sym) {  // Y reversed: (p(v), pp(v))
-        const Side<SEG> Yr = block2<SEG>(U, p_v, pp_v, c_pv2, AT(p_v, pp_v));
-        const SEG Ap = closeA(J(Pu1, Yr), hasSA1, Su1);
+      if (sym) {  // Y reversed: (p(v), pp(v)); its arc is the route's own, symmetric
+        const Side<SEG> Yr = block2<SEG>(U, p_v, pp_v, c_pv2, t_pv2);
+        const SEG Ap = closeA(J(Pu1, Yr, k_pu_pv), hasSA1, Su1, k_ppv_su);
         finish(make_id(SWP12, 1, u, v), false, Ap, x.eA, false, Bp, x.eB);
       }
     }
   }
   if (kinds >> SWP22 & 1) {
     if (hasPPv) {
-      const Side<SEG> Yr = block2<SEG>(U, p_v, pp_v, c_pv2, sym ? AT(p_v, pp_v) : 0);
+      const Side<SEG> Yr = block2<SEG>(U, p_v, pp_v, c_pv2, t_pv2);
       if (hasPPu) {  // X = (p(u), u)
-        const SEG Bp = J(J(Pv3, Xpu), Sv0).s;
-        const SEG Ap = closeA(J(Pu2, Ypv), hasSA1, Su1);
+        const SEG Bp = J(J(Pv3, Xpu, k_pppv_pu), Sv0, k_u_v).s;
+        const SEG Ap = closeA(J(Pu2, Ypv, k_ppu_ppv), hasSA1, Su1, k_pv_su);
         finish(make_id(SWP22, 0, u, v), false, Ap, x.eA, false, Bp, x.eB);
         if (sym) {
-          const SEG Ap2 = closeA(J(Pu2, Yr), hasSA1, Su1);
+          const SEG Ap2 = closeA(J(Pu2, Yr, k_ppu_pv), hasSA1, Su1, k_ppv_su);
           finish(make_id(SWP22, 2, u, v), false, Ap2, x.eA, false, Bp, x.eB);
         }
       }
       if (sym && hasSu) {  // X = (u, s(u)) placed as (s(u), u)
-        const Side<SEG> Xsu = block2<SEG>(U, s_u, u, AC(s_u, u), AT(s_u, u));
-        const SEG Bp = J(J(Pv3, Xsu), Sv0).s;
-        const SEG Ap = closeA(J(Pu1, Ypv), hasSA2, Su2);
+        const SEG Bp = J(J(Pv3, Xsu_block(), k_pppv_su), Sv0, k_u_v).s;
+        const SEG Ap = closeA(J(Pu1, Ypv, k_pu_ppv), hasSA2, Su2, k_pv_ssu);
         finish(make_id(SWP22, 1, u, v), false, Ap, x.eA, false, Bp, x.eB);
-        const SEG Ap2 = closeA(J(Pu1, Yr), hasSA2, Su2);
+        const SEG Ap2 = closeA(J(Pu1, Yr, k_pu_pv), hasSA2, Su2, k_ppv_ssu);
         finish(make_id(SWP22, 3, u, v), false, Ap2, x.eA, false, Bp, x.eB);
       }
     }
@@ -254,15 +292,16 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
   // ---------------------------------------------------------------- 2-opt*
   if (kinds >> X2 & 1) {
     // A' = A[..u] + B[v..] (ends at B's depot), B' = B[..p(v)] + A[s(u)..] (ends at A's depot)
-    const SEG Ap = J(Pu0, Sv0).s;
+    const SEG Ap = J(Pu0, Sv0, k_u_v).s;
     const bool bEmpty = (pv == 1) && (pu == LA);
     SEG Bp = fb1;
     if (!bEmpty) {
       if (pu == LA) {
-        // B' = prefix of B to p(v), then A's end depot (closed) or nothing (open)
-        if (!OPEN) Bp = J(Pv1, single<SEG>(U, x.eA)).s;
+        // B' = prefix of B to p(v), then A's end depot (closed) or nothing (open); the
+        // suffix from s(u) of a closed route is that depot alone, s(u) = its node
+        if (!OPEN) Bp = J(Pv1, single<SEG>(U, x.eA), k_pv_su).s;
       } else {
-        Bp = J(Pv1, Su1).s;
+        Bp = J(Pv1, Su1, k_pv_su).s;
       }
     }
     finish(make_id(X2, 0, u, v), false, Ap, x.eB, bEmpty, Bp, x.eA);
