@@ -291,6 +291,20 @@ def batch_study(n_inst=256, graph=True):
     per = np.array([s["device_ms"] for s in st])
     ev = sum(s["evaluated"] for s in st)
     nc = np.array([I.n_customers for I in insts])
+    # the critical path: the unit that finishes last, searched alone in a batch of its own
+    # (no batch of any design can finish before its own pass chain does)
+    last = int(per.argmax())
+    B1 = mdvrp.Batch([dev[last]], [0])
+    B1.load([sols[last]])
+    B1.set_tile_shapes(shapes)
+    B1.local_search_to_optimum(seed=1, poll_every=4, graph=graph)  # capture
+    B1.load([sols[last]])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st1 = B1.local_search_to_optimum(seed=1, poll_every=4, graph=graph)
+    torch.cuda.synchronize()
+    alone_s = time.perf_counter() - t2
+    assert st1[0]["passes"] == st[last]["passes"]
     return dict(workload=f"{n_inst} uneven MDVRPTW instances (100..5000 customers, 2..20 depots), one solution each, "
                          "one batch, local search to optimum" + (", passes replayed from HIP graphs" if graph else ""),
                 customers=int(nc.sum()), seconds=round(dt, 3), instances_per_s=round(n_inst / dt, 2),
@@ -298,6 +312,8 @@ def batch_study(n_inst=256, graph=True):
                 per_instance_ms_p99=round(float(np.percentile(per, 99)), 2),
                 per_instance_ms_max=round(float(per.max()), 2),
                 passes_max=int(max(s["passes"] for s in st)), first_run_s=round(runs[0][0], 3),
+                last_unit=dict(customers=int(nc[last]), passes=int(st[last]["passes"]),
+                               in_batch_ms=round(float(per[last]), 2), alone_ms=round(alone_s * 1e3, 2)),
                 tile_threads_per_family=shapes,
                 generate_s=round(t_gen, 1))
 

@@ -127,6 +127,13 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
     const int32_t c = arc_c(U, a, b);
     return make_int2(c, U.t_is_c ? c : arc_t(U, a, b));
   };
+  // An arc between the two neighbourhoods, wanted as a -> b with a on v's side: on a
+  // symmetric instance it is read as b -> a, so that every such read of the anchors of
+  // one u (adjacent lanes) comes from the rows of the few nodes around u, whose nearby
+  // columns share cache lines.
+  auto CTv = [&](int a_vside, int b_uside) -> int2 {
+    return sym ? CT(b_uside, a_vside) : CT(a_vside, b_uside);
+  };
   const bool fREL = kinds & ((1u << REL1) | (1u << REL2));
   const bool fSWP = kinds & ((1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (1u << SWP22));
   const bool fX2 = kinds & (1u << X2);
@@ -136,28 +143,28 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
        k_pv_ssu = k_u_v, k_ppv_su = k_u_v, k_pppv_u = k_u_v, k_pu_ppv = k_u_v, k_pppv_pu = k_u_v,
        k_ppu_ppv = k_u_v, k_pppv_su = k_u_v, k_ppv_ssu = k_u_v;
   k_u_v = CT(u, v);
-  k_pv_su = CT(p_v, su);
+  k_pv_su = CTv(p_v, su);
   if (fREL) {
     k_pu_su = CT(p_u, su);
-    k_pv_u = CT(p_v, u);
+    k_pv_u = CTv(p_v, u);
     k_ppu_su = CT(pp_u, su);
-    k_pv_pu = CT(p_v, p_u);
+    k_pv_pu = CTv(p_v, p_u);
     if (sym) k_pu_ssu = CT(p_u, ssu);
   }
   if (fSWP) {
     k_pu_pv = CT(p_u, p_v);
-    k_ppv_u = CT(pp_v, u);
+    k_ppv_u = CTv(pp_v, u);
     k_ppu_pv = CT(pp_u, p_v);
-    k_ppv_pu = CT(pp_v, p_u);
-    k_pppv_u = CT(ppp_v, u);
+    k_ppv_pu = CTv(pp_v, p_u);
+    k_pppv_u = CTv(ppp_v, u);
     k_pu_ppv = CT(p_u, pp_v);
-    k_pppv_pu = CT(ppp_v, p_u);
+    k_pppv_pu = CTv(ppp_v, p_u);
     k_ppu_ppv = CT(pp_u, pp_v);
     if (sym) {
-      k_pv_ssu = CT(p_v, ssu);
-      k_ppv_su = CT(pp_v, su);
-      k_pppv_su = CT(ppp_v, su);
-      k_ppv_ssu = CT(pp_v, ssu);
+      k_pv_ssu = CTv(p_v, ssu);
+      k_ppv_su = CTv(pp_v, su);
+      k_pppv_su = CTv(ppp_v, su);
+      k_ppv_ssu = CTv(pp_v, ssu);
     }
   }
   (void)fX2;
