@@ -113,6 +113,7 @@ struct mdvrp_batch {
   int32_t* d_tile_off[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<int32_t> h_tile_off[4];
   int32_t* d_active = nullptr;
+  int32_t* d_act = nullptr;         // active map of the search's current pass (act_map_words)
   int32_t* d_node_base = nullptr;
   int32_t* d_route_base = nullptr;
   int64_t* d_state = nullptr;
@@ -153,6 +154,16 @@ struct mdvrp_batch {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     graphs.clear();
   }
+  // The passes of a search visit the active units' tiles only (active map written by
+  // each pass's first kernel): the active units' tiles take the first blocks of every
+  // launch, so that they are dispatched first and the blocks of converged units, which
+  // have nothing to do, follow. Grids keep one block per tile of all units (one tile
+  // per block lets the hardware balance the tiles' uneven costs).
+  void search_grids(LaunchCtx& L) const {
+    L.act = d_act;
+    const int T[kActGrids] = {L.tiles[0], L.tiles[1], L.tiles[2], L.tiles_f, L.tiles_r};
+    for (int g = 0; g < kActGrids; ++g) L.act_grid[g] = T[g];
+  }
   LaunchCtx ctx(void* stream) const {
     bool layout_all = true;
     for (const mdvrp_instance* I : inst) layout_all = layout_all && I->pi != nullptr;
@@ -175,6 +186,8 @@ struct mdvrp_batch {
       L.per_unit[k] = per;
     }
     L.active_count = d_active;
+    L.act = nullptr;
+    for (int g = 0; g < kActGrids; ++g) L.act_grid[g] = 0;
     L.adapt_units = nullptr;
     L.adapt = AdaptBounds{};
     auto per = [&](const std::vector<int32_t>& off) {
@@ -531,6 +544,7 @@ void carve_batch(Carve& cv, const mdvrp_instance* const* insts, const int32_t* u
   for (int k = 0; k < 4; ++k) to[k] = cv.take<int32_t>(n_units + 1);
   int32_t* tor = cv.take<int32_t>(n_units + 1);
   int32_t* act = cv.take<int32_t>(1);
+  int32_t* amap = cv.take<int32_t>((size_t)act_map_words(n_units));
   int32_t* nb = cv.take<int32_t>(n_units);
   int32_t* rb = cv.take<int32_t>(n_units);
   int64_t* stt = cv.take<int64_t>((size_t)n_units * kStateWords);
@@ -539,6 +553,7 @@ void carve_batch(Carve& cv, const mdvrp_instance* const* insts, const int32_t* u
     for (int k = 0; k < 4; ++k) B->d_tile_off[k] = to[k];
     B->d_tile_off_r = tor;
     B->d_active = act;
+    B->d_act = amap;
     B->d_node_base = nb;
     B->d_route_base = rb;
     B->d_state = stt;
@@ -1389,6 +1404,7 @@ extern "C" mdvrp_status mdvrp_local_search_to_optimum(mdvrp_batch* B, const mdvr
   }
   LaunchCtx L = B->ctx(st);
   L.compact = o->filter != MDVRP_FILTER_NONE;
+  B->search_grids(L);
   if (o->penalty_adapt) {
     // every unit starts from its instance's weights; the fused steps adapt them on the device
     if (weights_to_instance(B))

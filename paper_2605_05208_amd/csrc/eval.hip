@@ -319,22 +319,36 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
 template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
 __global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__ units,
                                                    const int32_t* __restrict__ tile_off, int n_units, int per_unit,
-                                                   uint32_t kind_arg, DenseOut dense) {
+                                                   uint32_t kind_arg, DenseOut dense,
+                                                   const int32_t* __restrict__ act) {
   const uint32_t kind_mask = KM ? KM : kind_arg;
-  int ui, lt;
-  tile_of_block(tile_off, n_units, per_unit, ui, lt);
-  const UnitDesc& U = units[ui];
-  if (!U.ctl->active) return;
-  // A unit in filtered mode has ftiles tiles: they are spread evenly over its full tile
-  // range (every XCD gets its share); the other blocks have nothing to do.
-  const bool filt = U.ctl->fmode == 1;
-  if (filt) {
-    const int64_t full = U.tile_base[1] - U.tile_base[0];
-    const int f = (int)((int64_t)lt * U.ftiles / full);
-    if (lt > 0 && f == (int)((int64_t)(lt - 1) * U.ftiles / full)) return;
-    lt = f;
+  // In a pass of the search (act) the block visits the active units' tiles of its
+  // stride; otherwise it takes the one tile of its index. (One call site of the tile
+  // body: the kernel's code stays within the instruction cache.)
+  TileStride s{0, 1, 1};
+  int n_act = 0;
+  if (act) {
+    n_act = act[0];
+    s = tile_stride(act[1 + 0]);
   }
-  pairs_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, filt, kind_mask, dense);
+  for (; s.t < s.end; s.t += s.step) {
+    int ui, lt;
+    if (act) act_tile(act, n_units, n_act, 0, per_unit, s.t, ui, lt);
+    else tile_of_block(tile_off, n_units, per_unit, ui, lt);
+    const UnitDesc& U = units[ui];
+    if (!act && !U.ctl->active) return;  // every unit of the map is active
+    // A unit in filtered mode has ftiles tiles: they are spread evenly over its full
+    // tile range (every XCD gets its share); the other tiles have nothing to do.
+    const bool filt = U.ctl->fmode == 1;
+    if (filt) {
+      const int64_t full = U.tile_base[1] - U.tile_base[0];
+      const int f = (int)((int64_t)lt * U.ftiles / full);
+      if (lt > 0 && f == (int)((int64_t)(lt - 1) * U.ftiles / full)) continue;
+      lt = f;
+    }
+    __syncthreads();  // the previous tile's LDS queue is drained
+    pairs_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, filt, kind_mask, dense);
+  }
 }
 
 // The same evaluation on a compact grid of as many blocks per unit as its filtered
@@ -344,18 +358,28 @@ __global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__
 template <class SEG, bool TW, bool OPEN, uint32_t KM, int TPB>
 __global__ __launch_bounds__(TPB) void k_eval_pairs_compact(const UnitDesc* __restrict__ units,
                                                            const int32_t* __restrict__ grid_off, int n_units,
-                                                           int per_unit, uint32_t kind_arg) {
+                                                           int per_unit, uint32_t kind_arg,
+                                                           const int32_t* __restrict__ act) {
   const uint32_t kind_mask = KM ? KM : kind_arg;
-  int ui, g;
-  tile_of_block(grid_off, n_units, per_unit, ui, g);
-  const UnitDesc& U = units[ui];
-  if (!U.ctl->active) return;
-  const bool filt = U.ctl->fmode == 1;
-  const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
-  const int T = filt ? U.ftiles : U.tile_base[1] - U.tile_base[0];
-  for (int lt = g; lt < T; lt += G) {
-    __syncthreads();
-    pairs_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, filt, kind_mask, DenseOut{});
+  TileStride s{0, 1, 1};
+  int n_act = 0;
+  if (act) {
+    n_act = act[0];
+    s = tile_stride(act[1 + 3]);
+  }
+  for (; s.t < s.end; s.t += s.step) {
+    int ui, g;
+    if (act) act_tile(act, n_units, n_act, 3, per_unit, s.t, ui, g);
+    else tile_of_block(grid_off, n_units, per_unit, ui, g);
+    const UnitDesc& U = units[ui];
+    if (!act && !U.ctl->active) return;
+    const bool filt = U.ctl->fmode == 1;
+    const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
+    const int T = filt ? U.ftiles : U.tile_base[1] - U.tile_base[0];
+    for (int lt = g; lt < T; lt += G) {
+      __syncthreads();
+      pairs_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, filt, kind_mask, DenseOut{});
+    }
   }
 }
 
@@ -427,16 +451,26 @@ __device__ __forceinline__ void depot_tile(const UnitDesc& U, int ui, int lt, in
 template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
 __global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__ units,
                                                    const int32_t* __restrict__ tile_off, int n_units, int per_unit,
-                                                   int which, DenseOut dense) {
-  int ui, lt;
-  tile_of_block(tile_off, n_units, per_unit, ui, lt);
-  const UnitDesc& U = units[ui];
-  if (!U.ctl->active) return;
-  // Depot-Replace items cover the alive routes only; the tiles beyond them have
-  // nothing to do (the selection reads as many tiles as the items need).
-  const int n_drep = which == 1 ? U.ctl->n_slots_alive * U.nd : 0;
-  if (which == 1 && lt * kTileSize >= n_drep) return;
-  depot_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, which, n_drep, dense);
+                                                   int which, DenseOut dense, const int32_t* __restrict__ act) {
+  TileStride s{0, 1, 1};
+  int n_act = 0;
+  if (act) {
+    n_act = act[0];
+    s = tile_stride(act[1 + 1 + which]);
+  }
+  for (; s.t < s.end; s.t += s.step) {
+    int ui, lt;
+    if (act) act_tile(act, n_units, n_act, 1 + which, per_unit, s.t, ui, lt);
+    else tile_of_block(tile_off, n_units, per_unit, ui, lt);
+    const UnitDesc& U = units[ui];
+    if (!act && !U.ctl->active) return;
+    // Depot-Replace items cover the alive routes only; the tiles beyond them have
+    // nothing to do (the selection reads as many tiles as the items need).
+    const int n_drep = which == 1 ? U.ctl->n_slots_alive * U.nd : 0;
+    if (which == 1 && lt * kTileSize >= n_drep) continue;
+    __syncthreads();
+    depot_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, which, n_drep, dense);
+  }
 }
 
 // Depot-Replace on a compact grid sized for the routes a solution is expected to hold;
@@ -444,16 +478,25 @@ __global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__
 template <class SEG, bool TW, bool OPEN, int TPB>
 __global__ __launch_bounds__(TPB) void k_eval_drep_compact(const UnitDesc* __restrict__ units,
                                                           const int32_t* __restrict__ grid_off, int n_units,
-                                                          int per_unit) {
-  int ui, g;
-  tile_of_block(grid_off, n_units, per_unit, ui, g);
-  const UnitDesc& U = units[ui];
-  if (!U.ctl->active) return;
-  const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
-  const int n_drep = U.ctl->n_slots_alive * U.nd;
-  for (int lt = g; lt * kTileSize < n_drep; lt += G) {
-    __syncthreads();
-    depot_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, 1, n_drep, DenseOut{});
+                                                          int per_unit, const int32_t* __restrict__ act) {
+  TileStride s{0, 1, 1};
+  int n_act = 0;
+  if (act) {
+    n_act = act[0];
+    s = tile_stride(act[1 + 4]);
+  }
+  for (; s.t < s.end; s.t += s.step) {
+    int ui, g;
+    if (act) act_tile(act, n_units, n_act, 4, per_unit, s.t, ui, g);
+    else tile_of_block(grid_off, n_units, per_unit, ui, g);
+    const UnitDesc& U = units[ui];
+    if (!act && !U.ctl->active) return;
+    const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
+    const int n_drep = U.ctl->n_slots_alive * U.nd;
+    for (int lt = g; lt * kTileSize < n_drep; lt += G) {
+      __syncthreads();
+      depot_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, 1, n_drep, DenseOut{});
+    }
   }
 }
 
@@ -476,6 +519,15 @@ uint32_t eval_classes(const LaunchCtx& L, uint32_t fam_mask) {
   return cls;
 }
 
+// Blocks of a launch over grid g with T tiles in all: one per tile, or in a pass of the
+// search (active map) the grid the batch chose for it, which loops over the active
+// units' tiles.
+static int grid_of(const LaunchCtx& L, int g, int T) {
+  if (!L.act) return T;
+  const int G = L.act_grid[g];
+  return G > 0 && G < T ? G : T;
+}
+
 constexpr uint32_t kRelKinds = (1u << REL1) | (1u << REL2);
 constexpr uint32_t kSwpKinds = (1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (1u << SWP22);
 constexpr uint32_t kX2Kinds = 1u << X2;
@@ -485,13 +537,13 @@ template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
 static void launch_pairs(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) {
   if constexpr (SM == 0 && std::is_same<AR, ArcPlain>::value) {
     if (L.compact && L.tiles_f > 0) {
-      hipLaunchKernelGGL((k_eval_pairs_compact<SEG, TW, OPEN, KM, TPB>), dim3(L.tiles_f), dim3(TPB), 0, L.stream,
-                         L.units, L.tile_off_f, L.n_units, L.per_unit_f, kinds);
+      hipLaunchKernelGGL((k_eval_pairs_compact<SEG, TW, OPEN, KM, TPB>), dim3(grid_of(L, 3, L.tiles_f)), dim3(TPB),
+                         0, L.stream, L.units, L.tile_off_f, L.n_units, L.per_unit_f, kinds, L.act);
       return;
     }
   }
-  hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, SM, AR, KM, TPB>), dim3(L.tiles[0]), dim3(TPB), 0, L.stream, L.units,
-                     L.tile_off[0], L.n_units, L.per_unit[0], kinds, D);
+  hipLaunchKernelGGL((k_eval_pairs<SEG, TW, OPEN, SM, AR, KM, TPB>), dim3(grid_of(L, 0, L.tiles[0])), dim3(TPB), 0,
+                     L.stream, L.units, L.tile_off[0], L.n_units, L.per_unit[0], kinds, D, L.act);
 }
 
 template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
@@ -510,13 +562,13 @@ static void launch_class_t(const LaunchCtx& L, uint32_t fam_mask, int cls, const
   if (!(fam_mask >> (FAM_DINS + w) & 1) || L.tiles[1 + w] <= 0) return;
   if constexpr (SM == 0 && std::is_same<AR, ArcPlain>::value) {
     if (w == 1 && L.tiles_r > 0) {
-      hipLaunchKernelGGL((k_eval_drep_compact<SEG, TW, OPEN, TPB>), dim3(L.tiles_r), dim3(TPB), 0, L.stream, L.units,
-                         L.tile_off_r, L.n_units, L.per_unit_r);
+      hipLaunchKernelGGL((k_eval_drep_compact<SEG, TW, OPEN, TPB>), dim3(grid_of(L, 4, L.tiles_r)), dim3(TPB), 0,
+                         L.stream, L.units, L.tile_off_r, L.n_units, L.per_unit_r, L.act);
       return;
     }
   }
-  hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, SM, AR, TPB>), dim3(L.tiles[1 + w]), dim3(TPB), 0, L.stream, L.units,
-                     L.tile_off[1 + w], L.n_units, L.per_unit[1 + w], w, D);
+  hipLaunchKernelGGL((k_eval_depot<SEG, TW, OPEN, SM, AR, TPB>), dim3(grid_of(L, 1 + w, L.tiles[1 + w])), dim3(TPB), 0,
+                     L.stream, L.units, L.tile_off[1 + w], L.n_units, L.per_unit[1 + w], w, D, L.act);
 }
 
 template <int SM, class AR, int TPB>

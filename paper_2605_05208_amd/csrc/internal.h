@@ -581,6 +581,40 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   return start + k;
 }
 
+// Active map of one pass of the local search, written by k_pass_begin: word 0 holds
+// the number of active units n_act, words 1 .. kActGrids the active tile count of
+// each grid, then n_units words the active units' indices in ascending order, then
+// for each grid n_units + 1 prefix offsets of the active units' tile counts (the
+// first n_act + 1 are valid). Grids: 0 pair tiles, 1 Depot-Insert tiles, 2
+// Depot-Replace tiles, 3 blocks of the filtered pair grid, 4 blocks of the compact
+// Depot-Replace grid.
+constexpr int kActGrids = 5;
+constexpr int kActUnits = 1 + kActGrids;  // first word of the unit list
+__host__ __device__ constexpr int64_t act_map_words(int n_units) {
+  return kActUnits + (int64_t)n_units + (int64_t)kActGrids * (n_units + 1);
+}
+__host__ __device__ constexpr int64_t act_off_word(int n_units, int g) {
+  return kActUnits + (int64_t)n_units + (int64_t)g * (n_units + 1);
+}
+
+// Tiles [0, T) of a launch whose grid is smaller than its tile count: each of the
+// nx = min(8, gridDim.x) block groups b % nx (one per XCD: blocks are dispatched
+// round-robin over the 8 XCDs) takes the contiguous range [T x / nx, T (x + 1) / nx),
+// and its blocks take every group-size-th tile of it.
+struct TileStride {
+  int t, end, step;
+};
+__device__ __forceinline__ TileStride tile_stride(int T) {
+  const int G = (int)gridDim.x, b = (int)blockIdx.x;
+  const int nx = G < 8 ? G : 8;
+  const int x = b % nx, k = b / nx;
+  TileStride s;
+  s.t = (int)((int64_t)T * x / nx) + k;
+  s.end = (int)((int64_t)T * (x + 1) / nx);
+  s.step = (G - x + nx - 1) / nx;
+  return s;
+}
+
 // Find the unit of a tile by binary search over per-unit tile offsets.
 __device__ __forceinline__ int unit_of_tile(const int32_t* off, int n_units, int tile) {
   int lo = 0, hi = n_units;  // off[lo] <= tile < off[hi]
@@ -589,6 +623,24 @@ __device__ __forceinline__ int unit_of_tile(const int32_t* off, int n_units, int
     if (off[mid] <= tile) lo = mid; else hi = mid;
   }
   return lo;
+}
+
+// Unit and local tile of active tile t of grid g (n_act = A[0], read by the caller):
+// with equal tile counts (per_unit > 0) tile t is local tile t / n_act of the
+// (t % n_act)-th active unit, as in the full grid; otherwise the active units' tiles
+// follow one another. While every unit is active the map is the identity.
+__device__ __forceinline__ void act_tile(const int32_t* __restrict__ A, int n_units, int n_act, int g, int per_unit,
+                                         int t, int& ui, int& lt) {
+  int k;
+  if (per_unit > 0) {
+    k = t % n_act;
+    lt = t / n_act;
+  } else {
+    const int32_t* off = A + act_off_word(n_units, g);
+    k = unit_of_tile(off, n_act, t);
+    lt = t - off[k];
+  }
+  ui = n_act == n_units ? k : A[kActUnits + k];
 }
 
 }  // namespace mdvrp

@@ -37,15 +37,37 @@ __device__ __forceinline__ void reset_min(uint64_t* p) {
 
 __device__ __forceinline__ int64_t unpack_dD(uint64_t key) { return (int64_t)(key >> 38) - (1ll << 25); }
 
-// Units whose resources (route slots + depots) fit kLdsRes and whose candidates fit
-// kCandPerThread per thread run the follower rounds out of LDS and registers; the
-// others use the global-memory version (same rounds, same result).
+// Units whose resources (alive route slots + depots) fit kLdsRes and whose candidates
+// fit kCandPerThread per thread run the follower rounds out of LDS and registers; the
+// others use the global-memory version (same rounds, same result). In LDS a route
+// slot is renamed to its rank among the alive slots and depot d to n_alive + d (a
+// bijection: the conflicts, and so the selection, are unchanged).
 constexpr int kLdsRes = 4096;
 constexpr int kCandPerThread = 4;
 
 struct SelLds {
   uint64_t rmin[kLdsRes];  // per resource: minimum key of the live candidates touching it
   uint8_t taken[kLdsRes];  // per resource: taken by a selected move of this step
+};
+
+// LDS name of resource r (a slot of an alive route, R + depot, or -1 = none). A slot
+// that is not alive would be a broken invariant: it is reported (error bit 32) and
+// dropped.
+struct ResRename {
+  const int32_t* rank;       // rank of each alive slot in the alive-slot list
+  const int32_t* slot_list;  // the alive-slot list
+  int R, n_alive;
+  __device__ __forceinline__ int operator()(int r, UnitCtl* ctl) const {
+    if (r < 0) return -1;
+    if (r >= R) return n_alive + (r - R);
+    const int x = rank[r];
+    if (x >= 0 && x < n_alive && slot_list[x] == r) return x;
+    atomicOr(&ctl->err, 32);
+    return -1;
+  }
+  __device__ __forceinline__ int4 operator()(int4 r, UnitCtl* ctl) const {
+    return make_int4((*this)(r.x, ctl), (*this)(r.y, ctl), (*this)(r.z, ctl), r.w);
+  }
 };
 
 __device__ __forceinline__ bool lds_taken(const SelLds& S, const int4& r) {
@@ -100,8 +122,8 @@ struct SelView {
 // Locally dominant rounds with the candidates held in registers (thread t holds
 // candidates t, t + kSelBlock, ...) and the per-resource minima in LDS.
 template <bool APPLY, bool DEPL>
-__device__ __forceinline__ void followers_lds(const SelView<APPLY, DEPL>& V, SelLds& S, int n_cand, uint64_t lead_id, int* s_nsel,
-                              int* s_alive) {
+__device__ __forceinline__ void followers_lds(const SelView<APPLY, DEPL>& V, SelLds& S, const ResRename& rn, int n_cand,
+                                              uint64_t lead_id, int* s_nsel, int* s_alive) {
   const UnitDesc& U = V.U;
   const int tid = threadIdx.x;
   uint64_t ck[kCandPerThread], ci[kCandPerThread];
@@ -114,7 +136,7 @@ __device__ __forceinline__ void followers_lds(const SelView<APPLY, DEPL>& V, Sel
     if (c < n_cand) {
       ck[j] = U.cand_key[c];
       ci[j] = U.cand_id[c];
-      cr[j] = U.cand_res[c];
+      cr[j] = rn(U.cand_res[c], U.ctl);
       st[j] = (ci[j] != lead_id && !lds_taken(S, cr[j])) ? 1 : 0;
     }
   }
@@ -359,13 +381,19 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   if constexpr (DEPL)
     for (int d = tid; d < U.nd; d += kSelBlock) P.ndep[d] = U.ndep[d];
 
-  const int n_res = U.R + U.nd;
+  const int n_alive = ctl->n_slots_alive;
+  const int n_res = n_alive + U.nd;
   const bool lds = !leader_only && n_res <= kLdsRes && n_cand <= kSelBlock * kCandPerThread;
+  // ranks of the alive slots, in the resource minima's storage beyond the room of the
+  // free-slot list the plan keeps there (as int32)
+  int32_t* rank = (int32_t*)U.resmin + (U.R + U.nd);
+  const ResRename rn{rank, U.slot_list, U.R, n_alive};
   if (lds) {
     for (int i = tid; i < n_res; i += kSelBlock) {
       S.rmin[i] = ~0ull;
       S.taken[i] = 0;
     }
+    for (int i = tid; i < n_alive; i += kSelBlock) rank[U.slot_list[i]] = i;
     __syncthreads();
   }
   if (tid == 0) {
@@ -373,15 +401,19 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     s_nsel = 1;
     for (int k = 0; k < 3; ++k)
       if (lead.res[k] >= 0) {
-        if (lds) S.taken[lead.res[k]] = 1;
-        else U.taken[lead.res[k]] = epoch;
+        if (lds) {
+          const int x = rn(lead.res[k], ctl);
+          if (x >= 0) S.taken[x] = 1;
+        } else {
+          U.taken[lead.res[k]] = epoch;
+        }
       }
   }
   __syncthreads();
 
   // ---- followers: locally dominant rounds
   if (lds) {
-    followers_lds(V, S, n_cand, lead.id, &s_nsel, &s_alive);
+    followers_lds(V, S, rn, n_cand, lead.id, &s_nsel, &s_alive);
   } else if (!leader_only) {
     for (int c = tid; c < n_cand; c += kSelBlock) {
       const int4 r = U.cand_res[c];

@@ -123,13 +123,47 @@ __global__ __launch_bounds__(kRebuildBlock) void k_load_routes(const UnitDesc* _
 
 // --------------------------------------------------------------------------- pass bookkeeping
 
-__global__ void k_pass_begin(const UnitDesc* __restrict__ units, int n_units) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_units) return;
-  UnitCtl* c = units[i].ctl;
-  if (c->active) {
-    c->pass_applied = 0;
-    c->passes += 1;
+// Start of a pass: count it for every active unit, and (act != null) write the pass's
+// active map: the active units in ascending order and the prefix offsets of their
+// tiles in each grid (one block; units in chunks of its size).
+struct ActSrc {
+  const int32_t* off[kActGrids];  // per-unit prefix offsets of each grid over all units (null: no such grid)
+};
+__global__ __launch_bounds__(kUnitBlock) void k_pass_begin(const UnitDesc* __restrict__ units, int n_units,
+                                                           ActSrc src, int32_t* __restrict__ act) {
+  __shared__ int sh[2 * (kUnitBlock / 64) + 1];
+  int base_n = 0, base[kActGrids];
+  for (int g = 0; g < kActGrids; ++g) base[g] = 0;
+  for (int i0 = 0; i0 < n_units; i0 += kUnitBlock) {
+    const int i = i0 + (int)threadIdx.x;
+    int a = 0;
+    if (i < n_units) {
+      UnitCtl* c = units[i].ctl;
+      if (c->active) {
+        c->pass_applied = 0;
+        c->passes += 1;
+        a = 1;
+      }
+    }
+    if (!act) continue;  // uniform over the block
+    int tot;
+    const int pos = base_n + block_scan_excl<kUnitBlock>(a, sh, &tot);
+    if (a) act[kActUnits + pos] = i;
+    for (int g = 0; g < kActGrids; ++g) {
+      const int cnt = (a && src.off[g]) ? src.off[g][i + 1] - src.off[g][i] : 0;
+      int tg;
+      const int o = base[g] + block_scan_excl<kUnitBlock>(cnt, sh, &tg);
+      if (a) act[act_off_word(n_units, g) + pos] = o;
+      base[g] += tg;
+    }
+    base_n += tot;
+  }
+  if (act && threadIdx.x == 0) {
+    act[0] = base_n;
+    for (int g = 0; g < kActGrids; ++g) {
+      act[1 + g] = base[g];
+      act[act_off_word(n_units, g) + base_n] = base[g];
+    }
   }
 }
 
@@ -279,7 +313,13 @@ void launch_load(const LaunchCtx& L, const int32_t* nodes, const int32_t* offs, 
 }
 
 void launch_pass_begin(const LaunchCtx& L) {
-  hipLaunchKernelGGL(k_pass_begin, dim3((L.n_units + 255) / 256), dim3(256), 0, L.stream, L.units, L.n_units);
+  ActSrc src;
+  src.off[0] = L.tile_off[0];
+  src.off[1] = L.tile_off[1];
+  src.off[2] = L.tile_off[2];
+  src.off[3] = L.tiles_f > 0 ? L.tile_off_f : nullptr;
+  src.off[4] = L.tiles_r > 0 ? L.tile_off_r : nullptr;
+  hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(kUnitBlock), 0, L.stream, L.units, L.n_units, src, L.act);
 }
 void launch_pass_end(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, L.stream, L.units, L.n_units, L.active_count);
