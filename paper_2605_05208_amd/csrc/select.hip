@@ -37,11 +37,12 @@ __device__ __forceinline__ void reset_min(uint64_t* p) {
 
 __device__ __forceinline__ int64_t unpack_dD(uint64_t key) { return (int64_t)(key >> 38) - (1ll << 25); }
 
-// Units whose resources (alive route slots + depots) fit kLdsRes and whose candidates
-// fit kCandPerThread per thread run the follower rounds out of LDS and registers; the
-// others use the global-memory version (same rounds, same result). In LDS a route
-// slot is renamed to its rank among the alive slots and depot d to n_alive + d (a
-// bijection: the conflicts, and so the selection, are unchanged).
+// Units whose resources (route slots + depots) fit kLdsRes run the follower rounds
+// with the per-resource minima in LDS, the candidates in registers when they fit
+// kCandPerThread per thread; the others use the global-memory version (same rounds,
+// same result). Units with more slots than that rename, in LDS, an alive route slot to
+// its rank among the alive slots and depot d to n_alive + d (a bijection: the
+// conflicts, and so the selection, are unchanged) when those fit.
 constexpr int kLdsRes = 4096;
 constexpr int kCandPerThread = 4;
 
@@ -54,11 +55,11 @@ struct SelLds {
 // that is not alive would be a broken invariant: it is reported (error bit 32) and
 // dropped.
 struct ResRename {
-  const int32_t* rank;       // rank of each alive slot in the alive-slot list
+  const int32_t* rank;       // rank of each alive slot in the alive-slot list (null: no renaming)
   const int32_t* slot_list;  // the alive-slot list
   int R, n_alive;
   __device__ __forceinline__ int operator()(int r, UnitCtl* ctl) const {
-    if (r < 0) return -1;
+    if (!rank || r < 0) return r < 0 ? -1 : r;
     if (r >= R) return n_alive + (r - R);
     const int x = rank[r];
     if (x >= 0 && x < n_alive && slot_list[x] == r) return x;
@@ -179,6 +180,68 @@ __device__ __forceinline__ void followers_lds(const SelView<APPLY, DEPL>& V, Sel
       if (st[j] != 1) continue;
       const int4 r = cr[j];
       if (lds_taken(S, r)) { st[j] = 0; continue; }
+      if (r.x >= 0) S.rmin[r.x] = ~0ull;
+      if (r.y >= 0) S.rmin[r.y] = ~0ull;
+      if (r.z >= 0) S.rmin[r.z] = ~0ull;
+      ++alive;
+    }
+    if (alive) atomicAdd(s_alive, alive);
+    __syncthreads();
+    if (*s_alive == 0) break;
+    if (round > n_cand + 1) {  // every round takes the smallest live move
+      if (tid == 0) atomicOr(&U.ctl->err, 16);
+      break;
+    }
+  }
+}
+
+// The same rounds for more candidates than the registers hold: the per-resource minima
+// and taken flags stay in LDS, the candidates are read from the unit's arrays every
+// round (their resources renamed once, in place) and their state is kept in
+// cand_alive (0 dead, 1 live, 2 selected this round). A move selected in a round
+// takes its resources at once: the other moves of the round only compare minima.
+template <bool APPLY, bool DEPL>
+__device__ __forceinline__ void followers_lds_big(const SelView<APPLY, DEPL>& V, SelLds& S, const ResRename& rn,
+                                                  int n_cand, uint64_t lead_id, int* s_nsel, int* s_alive) {
+  const UnitDesc& U = V.U;
+  const int tid = threadIdx.x;
+  for (int c = tid; c < n_cand; c += kSelBlock) {
+    const int4 r = rn(U.cand_res[c], U.ctl);
+    if (rn.rank) U.cand_res[c] = r;
+    U.cand_alive[c] = (U.cand_id[c] != lead_id && !lds_taken(S, r)) ? 1 : 0;
+  }
+  __syncthreads();
+  for (int round = 0;; ++round) {
+    for (int c = tid; c < n_cand; c += kSelBlock) {
+      if (U.cand_alive[c] != 1) continue;
+      const int4 r = U.cand_res[c];
+      const unsigned long long k = U.cand_key[c];
+      if (r.x >= 0) atomicMin((unsigned long long*)&S.rmin[r.x], k);
+      if (r.y >= 0) atomicMin((unsigned long long*)&S.rmin[r.y], k);
+      if (r.z >= 0) atomicMin((unsigned long long*)&S.rmin[r.z], k);
+    }
+    __syncthreads();
+    for (int c = tid; c < n_cand; c += kSelBlock) {
+      if (U.cand_alive[c] != 1) continue;
+      const int4 r = U.cand_res[c];
+      const uint64_t k = U.cand_key[c];
+      if ((r.x < 0 || S.rmin[r.x] == k) && (r.y < 0 || S.rmin[r.y] == k) && (r.z < 0 || S.rmin[r.z] == k)) {
+        U.cand_alive[c] = 2;
+        V.put(atomicAdd(s_nsel, 1), U.cand_id[c], unpack_dD(k));
+        if (r.x >= 0) S.taken[r.x] = 1;
+        if (r.y >= 0) S.taken[r.y] = 1;
+        if (r.z >= 0) S.taken[r.z] = 1;
+      }
+    }
+    if (tid == 0) *s_alive = 0;
+    __syncthreads();
+    int alive = 0;
+    for (int c = tid; c < n_cand; c += kSelBlock) {
+      const uint8_t st = U.cand_alive[c];
+      if (st == 0) continue;
+      if (st == 2) { U.cand_alive[c] = 0; continue; }
+      const int4 r = U.cand_res[c];
+      if (lds_taken(S, r)) { U.cand_alive[c] = 0; continue; }
       if (r.x >= 0) S.rmin[r.x] = ~0ull;
       if (r.y >= 0) S.rmin[r.y] = ~0ull;
       if (r.z >= 0) S.rmin[r.z] = ~0ull;
@@ -382,18 +445,22 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     for (int d = tid; d < U.nd; d += kSelBlock) P.ndep[d] = U.ndep[d];
 
   const int n_alive = ctl->n_slots_alive;
-  const int n_res = n_alive + U.nd;
-  const bool lds = !leader_only && n_res <= kLdsRes && n_cand <= kSelBlock * kCandPerThread;
+  // resources in LDS: the slots themselves when they fit, else the renamed alive slots
+  const bool rename = U.R + U.nd > kLdsRes;
+  const int n_res = rename ? n_alive + U.nd : U.R + U.nd;
+  const bool lds = !leader_only && n_res <= kLdsRes;
+  const bool lds_regs = lds && n_cand <= kSelBlock * kCandPerThread;
   // ranks of the alive slots, in the resource minima's storage beyond the room of the
   // free-slot list the plan keeps there (as int32)
-  int32_t* rank = (int32_t*)U.resmin + (U.R + U.nd);
+  int32_t* rank = rename ? (int32_t*)U.resmin + (U.R + U.nd) : nullptr;
   const ResRename rn{rank, U.slot_list, U.R, n_alive};
   if (lds) {
     for (int i = tid; i < n_res; i += kSelBlock) {
       S.rmin[i] = ~0ull;
       S.taken[i] = 0;
     }
-    for (int i = tid; i < n_alive; i += kSelBlock) rank[U.slot_list[i]] = i;
+    if (rename)
+      for (int i = tid; i < n_alive; i += kSelBlock) rank[U.slot_list[i]] = i;
     __syncthreads();
   }
   if (tid == 0) {
@@ -412,8 +479,10 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   __syncthreads();
 
   // ---- followers: locally dominant rounds
-  if (lds) {
+  if (lds_regs) {
     followers_lds(V, S, rn, n_cand, lead.id, &s_nsel, &s_alive);
+  } else if (lds) {
+    followers_lds_big(V, S, rn, n_cand, lead.id, &s_nsel, &s_alive);
   } else if (!leader_only) {
     for (int c = tid; c < n_cand; c += kSelBlock) {
       const int4 r = U.cand_res[c];
