@@ -216,22 +216,6 @@ __device__ __forceinline__ void item_flush(const UnitDesc& U, int wg_slot, ItemO
 
 // --------------------------------------------------------------------------- pair kinds
 
-// Unit and local tile of this block. The blocks of one XCD take a contiguous range of
-// tiles. When every unit has the same number of tiles (per_unit > 0), tile t is local
-// tile t / n_units of unit t % n_units: an XCD then serves the same customers of
-// every unit, whose matrix rows stay in its L2.
-__device__ __forceinline__ void tile_of_block(const int32_t* __restrict__ tile_off, int n_units, int per_unit, int& ui,
-                                              int& lt) {
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (per_unit > 0) {
-    ui = tile % n_units;
-    lt = tile / n_units;
-  } else {
-    ui = unit_of_tile(tile_off, n_units, tile);
-    lt = tile - tile_off[ui];
-  }
-}
-
 // One tile of pair anchors of unit ui (local tile lt of its item space: the filtered
 // lists when the unit is in filtered mode, else the granular lists).
 template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
@@ -322,28 +306,23 @@ __global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__
                                                    uint32_t kind_arg, DenseOut dense,
                                                    const int32_t* __restrict__ act) {
   const uint32_t kind_mask = KM ? KM : kind_arg;
-  // In a pass of the search (act) the block visits the active units' tiles of its
-  // stride; otherwise it takes the one tile of its index. (One call site of the tile
-  // body: the kernel's code stays within the instruction cache.)
-  TileStride s{0, 1, 1};
-  int n_act = 0;
-  if (act) {
-    n_act = act[0];
-    s = tile_stride(act[1 + 0]);
-  }
-  for (; s.t < s.end; s.t += s.step) {
+  // In a pass of the search (act) the blocks visit the active units' tiles, the first
+  // blocks first; otherwise every block takes the one tile of its index. (One call site
+  // of the tile body keeps the kernel's code within the instruction cache.)
+  const GridView gv = grid_view(act, n_units, 0, tile_off);
+  for (TileStride s = tile_stride(gv.T); s.t < s.end; s.t += s.step) {
     int ui, lt;
-    if (act) act_tile(act, n_units, n_act, 0, per_unit, s.t, ui, lt);
-    else tile_of_block(tile_off, n_units, per_unit, ui, lt);
+    map_tile(gv.off, gv.n, per_unit, gv.list, s.t, ui, lt);
     const UnitDesc& U = units[ui];
     if (!act && !U.ctl->active) return;  // every unit of the map is active
     // A unit in filtered mode has ftiles tiles: they are spread evenly over its full
-    // tile range (every XCD gets its share); the other tiles have nothing to do.
+    // tile range (every XCD gets its share); the other tiles have nothing to do. (A unit
+    // has at most 65535 * 128 / 256 tiles, so the products fit 32 bits.)
     const bool filt = U.ctl->fmode == 1;
     if (filt) {
-      const int64_t full = U.tile_base[1] - U.tile_base[0];
-      const int f = (int)((int64_t)lt * U.ftiles / full);
-      if (lt > 0 && f == (int)((int64_t)(lt - 1) * U.ftiles / full)) continue;
+      const uint32_t full = (uint32_t)(U.tile_base[1] - U.tile_base[0]), ft = (uint32_t)U.ftiles;
+      const int f = (int)((uint32_t)lt * ft / full);
+      if (lt > 0 && f == (int)((uint32_t)(lt - 1) * ft / full)) continue;
       lt = f;
     }
     __syncthreads();  // the previous tile's LDS queue is drained
@@ -361,16 +340,10 @@ __global__ __launch_bounds__(TPB) void k_eval_pairs_compact(const UnitDesc* __re
                                                            int per_unit, uint32_t kind_arg,
                                                            const int32_t* __restrict__ act) {
   const uint32_t kind_mask = KM ? KM : kind_arg;
-  TileStride s{0, 1, 1};
-  int n_act = 0;
-  if (act) {
-    n_act = act[0];
-    s = tile_stride(act[1 + 3]);
-  }
-  for (; s.t < s.end; s.t += s.step) {
+  const GridView gv = grid_view(act, n_units, 3, grid_off);
+  for (TileStride s = tile_stride(gv.T); s.t < s.end; s.t += s.step) {
     int ui, g;
-    if (act) act_tile(act, n_units, n_act, 3, per_unit, s.t, ui, g);
-    else tile_of_block(grid_off, n_units, per_unit, ui, g);
+    map_tile(gv.off, gv.n, per_unit, gv.list, s.t, ui, g);
     const UnitDesc& U = units[ui];
     if (!act && !U.ctl->active) return;
     const bool filt = U.ctl->fmode == 1;
@@ -452,16 +425,10 @@ template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
 __global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__ units,
                                                    const int32_t* __restrict__ tile_off, int n_units, int per_unit,
                                                    int which, DenseOut dense, const int32_t* __restrict__ act) {
-  TileStride s{0, 1, 1};
-  int n_act = 0;
-  if (act) {
-    n_act = act[0];
-    s = tile_stride(act[1 + 1 + which]);
-  }
-  for (; s.t < s.end; s.t += s.step) {
+  const GridView gv = grid_view(act, n_units, 1 + which, tile_off);
+  for (TileStride s = tile_stride(gv.T); s.t < s.end; s.t += s.step) {
     int ui, lt;
-    if (act) act_tile(act, n_units, n_act, 1 + which, per_unit, s.t, ui, lt);
-    else tile_of_block(tile_off, n_units, per_unit, ui, lt);
+    map_tile(gv.off, gv.n, per_unit, gv.list, s.t, ui, lt);
     const UnitDesc& U = units[ui];
     if (!act && !U.ctl->active) return;
     // Depot-Replace items cover the alive routes only; the tiles beyond them have
@@ -479,16 +446,10 @@ template <class SEG, bool TW, bool OPEN, int TPB>
 __global__ __launch_bounds__(TPB) void k_eval_drep_compact(const UnitDesc* __restrict__ units,
                                                           const int32_t* __restrict__ grid_off, int n_units,
                                                           int per_unit, const int32_t* __restrict__ act) {
-  TileStride s{0, 1, 1};
-  int n_act = 0;
-  if (act) {
-    n_act = act[0];
-    s = tile_stride(act[1 + 4]);
-  }
-  for (; s.t < s.end; s.t += s.step) {
+  const GridView gv = grid_view(act, n_units, 4, grid_off);
+  for (TileStride s = tile_stride(gv.T); s.t < s.end; s.t += s.step) {
     int ui, g;
-    if (act) act_tile(act, n_units, n_act, 4, per_unit, s.t, ui, g);
-    else tile_of_block(grid_off, n_units, per_unit, ui, g);
+    map_tile(gv.off, gv.n, per_unit, gv.list, s.t, ui, g);
     const UnitDesc& U = units[ui];
     if (!act && !U.ctl->active) return;
     const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];

@@ -571,16 +571,6 @@ __device__ __forceinline__ bool key_less(int64_t f1, uint64_t i1, int64_t f2, ui
   return f1 < f2 || (f1 == f2 && i1 < i2);
 }
 
-// Map a block index to a tile so that the tiles served by one XCD are contiguous
-// (blocks are dispatched round-robin over the 8 XCDs).
-__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
-  const int nx = 8;
-  int per = nblocks / nx, rem = nblocks % nx;
-  int x = bid % nx, k = bid / nx;
-  int start = x * per + (x < rem ? x : rem);
-  return start + k;
-}
-
 // Active map of one pass of the local search, written by k_pass_begin: word 0 holds
 // the number of active units n_act, words 1 .. kActGrids the active tile count of
 // each grid, then n_units words the active units' indices in ascending order, then
@@ -597,21 +587,27 @@ __host__ __device__ constexpr int64_t act_off_word(int n_units, int g) {
   return kActUnits + (int64_t)n_units + (int64_t)g * (n_units + 1);
 }
 
-// Tiles [0, T) of a launch whose grid is smaller than its tile count: each of the
-// nx = min(8, gridDim.x) block groups b % nx (one per XCD: blocks are dispatched
-// round-robin over the 8 XCDs) takes the contiguous range [T x / nx, T (x + 1) / nx),
-// and its blocks take every group-size-th tile of it.
+// Tiles [0, T) of a launch of gridDim.x blocks, split into 8 contiguous ranges, one per
+// XCD (blocks are dispatched round-robin over the 8 XCDs: block b runs on XCD b % 8):
+// range x holds T / 8 tiles plus one for x < T % 8, and the blocks of XCD x take every
+// (blocks of XCD x)-th tile of it, starting at b / 8. With gridDim.x == T every block
+// takes exactly one tile. Grids of fewer than 8 blocks stride over all tiles.
 struct TileStride {
   int t, end, step;
 };
 __device__ __forceinline__ TileStride tile_stride(int T) {
   const int G = (int)gridDim.x, b = (int)blockIdx.x;
-  const int nx = G < 8 ? G : 8;
-  const int x = b % nx, k = b / nx;
   TileStride s;
-  s.t = (int)((int64_t)T * x / nx) + k;
-  s.end = (int)((int64_t)T * (x + 1) / nx);
-  s.step = (G - x + nx - 1) / nx;
+  if (G < 8) {
+    s.t = b;
+    s.end = T;
+    s.step = G;
+    return s;
+  }
+  const int x = b & 7, per = T >> 3, rem = T & 7;
+  s.t = x * per + (x < rem ? x : rem) + (b >> 3);
+  s.end = (x + 1) * per + (x + 1 < rem ? x + 1 : rem);
+  s.step = (G - x + 7) >> 3;
   return s;
 }
 
@@ -625,22 +621,46 @@ __device__ __forceinline__ int unit_of_tile(const int32_t* off, int n_units, int
   return lo;
 }
 
-// Unit and local tile of active tile t of grid g (n_act = A[0], read by the caller):
-// with equal tile counts (per_unit > 0) tile t is local tile t / n_act of the
-// (t % n_act)-th active unit, as in the full grid; otherwise the active units' tiles
-// follow one another. While every unit is active the map is the identity.
-__device__ __forceinline__ void act_tile(const int32_t* __restrict__ A, int n_units, int n_act, int g, int per_unit,
-                                         int t, int& ui, int& lt) {
+// Unit and local tile of tile t of a grid whose n units have the tile offsets off
+// (n + 1 prefix sums): with equal tile counts (per_unit > 0) tile t is local tile
+// t / n of the (t % n)-th unit (an XCD then serves the same customers of every unit,
+// whose matrix rows stay in its L2); otherwise the units' tiles follow one another.
+// The k-th unit is list[k], or k itself without a list.
+__device__ __forceinline__ void map_tile(const int32_t* __restrict__ off, int n, int per_unit,
+                                         const int32_t* __restrict__ list, int t, int& ui, int& lt) {
   int k;
   if (per_unit > 0) {
-    k = t % n_act;
-    lt = t / n_act;
+    k = t % n;
+    lt = t / n;
   } else {
-    const int32_t* off = A + act_off_word(n_units, g);
-    k = unit_of_tile(off, n_act, t);
+    k = unit_of_tile(off, n, t);
     lt = t - off[k];
   }
-  ui = n_act == n_units ? k : A[kActUnits + k];
+  ui = list ? list[k] : k;
+}
+
+// The units, tile offsets and tile count of grid g of a launch: the active units of
+// the pass when the launch has an active map, else every unit of the batch.
+struct GridView {
+  const int32_t* off;
+  const int32_t* list;
+  int n, T;
+};
+__device__ __forceinline__ GridView grid_view(const int32_t* __restrict__ act, int n_units, int g,
+                                              const int32_t* __restrict__ all_off) {
+  GridView v;
+  if (act) {
+    v.n = act[0];
+    v.T = act[1 + g];
+    v.off = act + act_off_word(n_units, g);
+    v.list = v.n < n_units ? act + kActUnits : nullptr;
+  } else {
+    v.n = n_units;
+    v.T = (int)gridDim.x;
+    v.off = all_off;
+    v.list = nullptr;
+  }
+  return v;
 }
 
 }  // namespace mdvrp
