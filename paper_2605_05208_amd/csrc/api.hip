@@ -159,11 +159,7 @@ struct mdvrp_batch {
   // launch, so that they are dispatched first and the blocks of converged units, which
   // have nothing to do, follow. Grids keep one block per tile of all units (one tile
   // per block lets the hardware balance the tiles' uneven costs).
-  void search_grids(LaunchCtx& L) const {
-    L.act = d_act;
-    const int T[kActGrids] = {L.tiles[0], L.tiles[1], L.tiles[2], L.tiles_f, L.tiles_r};
-    for (int g = 0; g < kActGrids; ++g) L.act_grid[g] = T[g];
-  }
+  void search_grids(LaunchCtx& L) const { L.act = d_act; }
   LaunchCtx ctx(void* stream) const {
     bool layout_all = true;
     for (const mdvrp_instance* I : inst) layout_all = layout_all && I->pi != nullptr;
@@ -187,7 +183,6 @@ struct mdvrp_batch {
     }
     L.active_count = d_active;
     L.act = nullptr;
-    for (int g = 0; g < kActGrids; ++g) L.act_grid[g] = 0;
     L.adapt_units = nullptr;
     L.adapt = AdaptBounds{};
     auto per = [&](const std::vector<int32_t>& off) {

@@ -306,28 +306,26 @@ __global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__
                                                    uint32_t kind_arg, DenseOut dense,
                                                    const int32_t* __restrict__ act) {
   const uint32_t kind_mask = KM ? KM : kind_arg;
-  // In a pass of the search (act) the blocks visit the active units' tiles, the first
-  // blocks first; otherwise every block takes the one tile of its index. (One call site
-  // of the tile body keeps the kernel's code within the instruction cache.)
+  // In a pass of the search (act) the first blocks take the active units' tiles, one
+  // each, and the others have none; otherwise every block takes the tile of its index.
   const GridView gv = grid_view(act, n_units, 0, tile_off);
-  for (TileStride s = tile_stride(gv.T); s.t < s.end; s.t += s.step) {
-    int ui, lt;
-    map_tile(gv.off, gv.n, per_unit, gv.list, s.t, ui, lt);
-    const UnitDesc& U = units[ui];
-    if (!act && !U.ctl->active) return;  // every unit of the map is active
-    // A unit in filtered mode has ftiles tiles: they are spread evenly over its full
-    // tile range (every XCD gets its share); the other tiles have nothing to do. (A unit
-    // has at most 65535 * 128 / 256 tiles, so the products fit 32 bits.)
-    const bool filt = U.ctl->fmode == 1;
-    if (filt) {
-      const uint32_t full = (uint32_t)(U.tile_base[1] - U.tile_base[0]), ft = (uint32_t)U.ftiles;
-      const int f = (int)((uint32_t)lt * ft / full);
-      if (lt > 0 && f == (int)((uint32_t)(lt - 1) * ft / full)) continue;
-      lt = f;
-    }
-    __syncthreads();  // the previous tile's LDS queue is drained
-    pairs_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, filt, kind_mask, dense);
+  const int t = block_tile(gv.T);
+  if (t < 0) return;
+  int ui, lt;
+  map_tile(gv.off, gv.n, per_unit, gv.list, t, ui, lt);
+  const UnitDesc& U = units[ui];
+  if (!act && !U.ctl->active) return;  // every unit of the map is active
+  // A unit in filtered mode has ftiles tiles: they are spread evenly over its full tile
+  // range (every XCD gets its share); the other tiles have nothing to do. (A unit has at
+  // most 65535 * 128 / 256 tiles, so the products fit 32 bits.)
+  const bool filt = U.ctl->fmode == 1;
+  if (filt) {
+    const uint32_t full = (uint32_t)(U.tile_base[1] - U.tile_base[0]), ft = (uint32_t)U.ftiles;
+    const int f = (int)((uint32_t)lt * ft / full);
+    if (lt > 0 && f == (int)((uint32_t)(lt - 1) * ft / full)) return;
+    lt = f;
   }
+  pairs_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, filt, kind_mask, dense);
 }
 
 // The same evaluation on a compact grid of as many blocks per unit as its filtered
@@ -341,18 +339,18 @@ __global__ __launch_bounds__(TPB) void k_eval_pairs_compact(const UnitDesc* __re
                                                            const int32_t* __restrict__ act) {
   const uint32_t kind_mask = KM ? KM : kind_arg;
   const GridView gv = grid_view(act, n_units, 3, grid_off);
-  for (TileStride s = tile_stride(gv.T); s.t < s.end; s.t += s.step) {
-    int ui, g;
-    map_tile(gv.off, gv.n, per_unit, gv.list, s.t, ui, g);
-    const UnitDesc& U = units[ui];
-    if (!act && !U.ctl->active) return;
-    const bool filt = U.ctl->fmode == 1;
-    const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
-    const int T = filt ? U.ftiles : U.tile_base[1] - U.tile_base[0];
-    for (int lt = g; lt < T; lt += G) {
-      __syncthreads();
-      pairs_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, filt, kind_mask, DenseOut{});
-    }
+  const int t = block_tile(gv.T);
+  if (t < 0) return;
+  int ui, g;
+  map_tile(gv.off, gv.n, per_unit, gv.list, t, ui, g);
+  const UnitDesc& U = units[ui];
+  if (!act && !U.ctl->active) return;
+  const bool filt = U.ctl->fmode == 1;
+  const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
+  const int T = filt ? U.ftiles : U.tile_base[1] - U.tile_base[0];
+  for (int lt = g; lt < T; lt += G) {
+    __syncthreads();
+    pairs_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, filt, kind_mask, DenseOut{});
   }
 }
 
@@ -426,18 +424,17 @@ __global__ __launch_bounds__(TPB) void k_eval_depot(const UnitDesc* __restrict__
                                                    const int32_t* __restrict__ tile_off, int n_units, int per_unit,
                                                    int which, DenseOut dense, const int32_t* __restrict__ act) {
   const GridView gv = grid_view(act, n_units, 1 + which, tile_off);
-  for (TileStride s = tile_stride(gv.T); s.t < s.end; s.t += s.step) {
-    int ui, lt;
-    map_tile(gv.off, gv.n, per_unit, gv.list, s.t, ui, lt);
-    const UnitDesc& U = units[ui];
-    if (!act && !U.ctl->active) return;
-    // Depot-Replace items cover the alive routes only; the tiles beyond them have
-    // nothing to do (the selection reads as many tiles as the items need).
-    const int n_drep = which == 1 ? U.ctl->n_slots_alive * U.nd : 0;
-    if (which == 1 && lt * kTileSize >= n_drep) continue;
-    __syncthreads();
-    depot_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, which, n_drep, dense);
-  }
+  const int t = block_tile(gv.T);
+  if (t < 0) return;
+  int ui, lt;
+  map_tile(gv.off, gv.n, per_unit, gv.list, t, ui, lt);
+  const UnitDesc& U = units[ui];
+  if (!act && !U.ctl->active) return;
+  // Depot-Replace items cover the alive routes only; the tiles beyond them have
+  // nothing to do (the selection reads as many tiles as the items need).
+  const int n_drep = which == 1 ? U.ctl->n_slots_alive * U.nd : 0;
+  if (which == 1 && lt * kTileSize >= n_drep) return;
+  depot_tile<SEG, TW, OPEN, SM, AR, TPB>(U, ui, lt, which, n_drep, dense);
 }
 
 // Depot-Replace on a compact grid sized for the routes a solution is expected to hold;
@@ -447,17 +444,17 @@ __global__ __launch_bounds__(TPB) void k_eval_drep_compact(const UnitDesc* __res
                                                           const int32_t* __restrict__ grid_off, int n_units,
                                                           int per_unit, const int32_t* __restrict__ act) {
   const GridView gv = grid_view(act, n_units, 4, grid_off);
-  for (TileStride s = tile_stride(gv.T); s.t < s.end; s.t += s.step) {
-    int ui, g;
-    map_tile(gv.off, gv.n, per_unit, gv.list, s.t, ui, g);
-    const UnitDesc& U = units[ui];
-    if (!act && !U.ctl->active) return;
-    const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
-    const int n_drep = U.ctl->n_slots_alive * U.nd;
-    for (int lt = g; lt * kTileSize < n_drep; lt += G) {
-      __syncthreads();
-      depot_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, 1, n_drep, DenseOut{});
-    }
+  const int t = block_tile(gv.T);
+  if (t < 0) return;
+  int ui, g;
+  map_tile(gv.off, gv.n, per_unit, gv.list, t, ui, g);
+  const UnitDesc& U = units[ui];
+  if (!act && !U.ctl->active) return;
+  const int G = per_unit > 0 ? per_unit : grid_off[ui + 1] - grid_off[ui];
+  const int n_drep = U.ctl->n_slots_alive * U.nd;
+  for (int lt = g; lt * kTileSize < n_drep; lt += G) {
+    __syncthreads();
+    depot_tile<SEG, TW, OPEN, 0, ArcPlain, TPB>(U, ui, lt, 1, n_drep, DenseOut{});
   }
 }
 
@@ -480,14 +477,9 @@ uint32_t eval_classes(const LaunchCtx& L, uint32_t fam_mask) {
   return cls;
 }
 
-// Blocks of a launch over grid g with T tiles in all: one per tile, or in a pass of the
-// search (active map) the grid the batch chose for it, which loops over the active
-// units' tiles.
-static int grid_of(const LaunchCtx& L, int g, int T) {
-  if (!L.act) return T;
-  const int G = L.act_grid[g];
-  return G > 0 && G < T ? G : T;
-}
+// Blocks of a launch over grid g with T tiles in all: one per tile of every unit (in a
+// pass of the search the active units' tiles, fewer, take the first blocks).
+static int grid_of(const LaunchCtx&, int, int T) { return T; }
 
 constexpr uint32_t kRelKinds = (1u << REL1) | (1u << REL2);
 constexpr uint32_t kSwpKinds = (1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (1u << SWP22);

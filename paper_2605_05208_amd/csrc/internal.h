@@ -587,28 +587,15 @@ __host__ __device__ constexpr int64_t act_off_word(int n_units, int g) {
   return kActUnits + (int64_t)n_units + (int64_t)g * (n_units + 1);
 }
 
-// Tiles [0, T) of a launch of gridDim.x blocks, split into 8 contiguous ranges, one per
-// XCD (blocks are dispatched round-robin over the 8 XCDs: block b runs on XCD b % 8):
-// range x holds T / 8 tiles plus one for x < T % 8, and the blocks of XCD x take every
-// (blocks of XCD x)-th tile of it, starting at b / 8. With gridDim.x == T every block
-// takes exactly one tile. Grids of fewer than 8 blocks stride over all tiles.
-struct TileStride {
-  int t, end, step;
-};
-__device__ __forceinline__ TileStride tile_stride(int T) {
-  const int G = (int)gridDim.x, b = (int)blockIdx.x;
-  TileStride s;
-  if (G < 8) {
-    s.t = b;
-    s.end = T;
-    s.step = G;
-    return s;
-  }
-  const int x = b & 7, per = T >> 3, rem = T & 7;
-  s.t = x * per + (x < rem ? x : rem) + (b >> 3);
-  s.end = (x + 1) * per + (x + 1 < rem ? x + 1 : rem);
-  s.step = (G - x + 7) >> 3;
-  return s;
+// The tile of this block among T tiles, for a grid of at least T blocks: the tiles are
+// split into 8 contiguous ranges, one per XCD (blocks are dispatched round-robin over
+// the 8 XCDs: block b runs on XCD b % 8); range x holds T / 8 tiles plus one for
+// x < T % 8 and its tiles go to the blocks of XCD x in order. -1: the block has none
+// (with exactly T blocks every block has one).
+__device__ __forceinline__ int block_tile(int T) {
+  const int b = (int)blockIdx.x, x = b & 7, k = b >> 3, per = T >> 3, rem = T & 7;
+  const int len = per + (x < rem ? 1 : 0);
+  return k < len ? x * per + (x < rem ? x : rem) + k : -1;
 }
 
 // Find the unit of a tile by binary search over per-unit tile offsets.

@@ -55,10 +55,9 @@ struct LaunchCtx {
   int max_nd;                  // largest depot count over the batch's instances
   int32_t* active_count;       // device int
   // active map of the local search's current pass (written by launch_pass_begin; null
-  // outside the search): the evaluation kernels then visit the active units' tiles
-  // only, each on a grid of act_grid[g] blocks (grids as in act_off)
+  // outside the search): the evaluation kernels then map their first blocks onto the
+  // active units' tiles
   int32_t* act;
-  int act_grid[kActGrids];
   // dynamic penalty weights of a local search: the fused step writes each unit's new
   // weights into this array (the device copy of units) after a step that applied
   // moves; null = fixed weights
