@@ -169,7 +169,11 @@ struct mdvrp_batch {
     L.n_units = n_units;
     L.has_tw = has_tw;
     L.max_nd = 0;
-    for (const mdvrp_instance* I : inst) L.max_nd = std::max(L.max_nd, I->d.n_depots);
+    L.t_is_c_all = 1;
+    for (const mdvrp_instance* I : inst) {
+      L.max_nd = std::max(L.max_nd, I->d.n_depots);
+      L.t_is_c_all = L.t_is_c_all && I->t_is_c;
+    }
     L.open = open;
     for (int k = 0; k < 4; ++k) {
       L.tile_off[k] = d_tile_off[k];

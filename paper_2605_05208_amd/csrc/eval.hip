@@ -28,7 +28,7 @@ struct ItemOut {
   int32_t b_res0, b_res1, b_res2;
   uint64_t k0, k1, k2;
   uint64_t i0, i1, i2;
-  int4 r0, r1, r2;
+  uint64_t r0, r1, r2;  // resource sets, packed by pack_res
   int32_t evaluated;  // moves evaluated by this thread in this launch
   int32_t err;        // error bits, posted once by the block epilogue (no store inside the
                       // evaluation, so repeated matrix and segment loads can be merged)
@@ -43,8 +43,15 @@ __device__ __forceinline__ void item_init(ItemOut& o) {
   o.err = 0;
 }
 
-__device__ __forceinline__ bool same_res(const int4& r, const MoveEval& m) {
-  return r.x == m.res[0] && r.y == m.res[1] && r.z == m.res[2];
+// The (up to) three resources of a move in one word: 21 bits each, holding id + 1
+// (0 = none); resource ids are below R + nd = N <= 65535. (Two registers per slot of
+// the thread's follower bookkeeping instead of four.)
+__device__ __forceinline__ uint64_t pack_res(const MoveEval& m) {
+  return (uint64_t)(uint32_t)(m.res[0] + 1) | (uint64_t)(uint32_t)(m.res[1] + 1) << 21 |
+         (uint64_t)(uint32_t)(m.res[2] + 1) << 42;
+}
+__device__ __forceinline__ int4 unpack_res(uint64_t p) {
+  return make_int4((int)(p & 0x1fffff) - 1, (int)((p >> 21) & 0x1fffff) - 1, (int)((p >> 42) & 0x1fffff) - 1, 0);
 }
 
 __device__ __forceinline__ void item_take(const UnitDesc& U, ItemOut& o, const MoveEval& m, uint64_t id) {
@@ -58,12 +65,12 @@ __device__ __forceinline__ void item_take(const UnitDesc& U, ItemOut& o, const M
   }
   if (follower(m)) {
     const uint64_t key = pack_key(U, m.dD, id);
-    const int4 r = make_int4(m.res[0], m.res[1], m.res[2], 0);
-    if (o.k0 == ~0ull || same_res(o.r0, m)) {
+    const uint64_t r = pack_res(m);
+    if (o.k0 == ~0ull || o.r0 == r) {
       if (key < o.k0) { o.k0 = key; o.i0 = id; o.r0 = r; }
-    } else if (o.k1 == ~0ull || same_res(o.r1, m)) {
+    } else if (o.k1 == ~0ull || o.r1 == r) {
       if (key < o.k1) { o.k1 = key; o.i1 = id; o.r1 = r; }
-    } else if (o.k2 == ~0ull || same_res(o.r2, m)) {
+    } else if (o.k2 == ~0ull || o.r2 == r) {
       if (key < o.k2) { o.k2 = key; o.i2 = id; o.r2 = r; }
     } else {
       o.err |= 8;
@@ -131,11 +138,11 @@ __device__ __forceinline__ void take(const UnitDesc& U, Sink<SM>& s, const MoveE
 
 namespace mdvrp {
 
-__device__ __forceinline__ void cand_put(const UnitDesc& U, int at, uint64_t k, uint64_t id, const int4& r) {
+__device__ __forceinline__ void cand_put(const UnitDesc& U, int at, uint64_t k, uint64_t id, uint64_t r) {
   if (at < U.cand_cap) {
     U.cand_key[at] = k;
     U.cand_id[at] = id;
-    U.cand_res[at] = r;
+    U.cand_res[at] = unpack_res(r);
   } else {
     atomicOr(&U.ctl->err, 1);
   }
@@ -215,6 +222,18 @@ __device__ __forceinline__ void item_flush(const UnitDesc& U, int wg_slot, ItemO
 }
 
 // --------------------------------------------------------------------------- pair kinds
+
+constexpr uint32_t kRelKinds = (1u << REL1) | (1u << REL2);
+constexpr uint32_t kSwpKinds = (1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (1u << SWP22);
+constexpr uint32_t kX2Kinds = 1u << X2;
+constexpr uint32_t k2optKinds = 1u << TWOOPT;
+
+// Waves per SIMD the compiler must fit a pair kernel into (1: as many as its registers
+// allow).
+template <bool TW, uint32_t KM, int TPB, class AR>
+constexpr int pair_min_waves() {
+  return (KM == kSwpKinds && !TW && TPB == 64 && AR::kTisC) ? 4 : 1;
+}
 
 // One tile of pair anchors of unit ui (local tile lt of its item space: the filtered
 // lists when the unit is in filtered mode, else the granular lists).
@@ -301,7 +320,7 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
 // autotuner picks; results do not depend on it). One block per tile of the
 // granular lists.
 template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
-__global__ __launch_bounds__(TPB) void k_eval_pairs(const UnitDesc* __restrict__ units,
+__global__ __launch_bounds__(TPB, (pair_min_waves<TW, KM, TPB, AR>())) void k_eval_pairs(const UnitDesc* __restrict__ units,
                                                    const int32_t* __restrict__ tile_off, int n_units, int per_unit,
                                                    uint32_t kind_arg, DenseOut dense,
                                                    const int32_t* __restrict__ act) {
@@ -481,10 +500,6 @@ uint32_t eval_classes(const LaunchCtx& L, uint32_t fam_mask) {
 // pass of the search the active units' tiles, fewer, take the first blocks).
 static int grid_of(const LaunchCtx&, int, int T) { return T; }
 
-constexpr uint32_t kRelKinds = (1u << REL1) | (1u << REL2);
-constexpr uint32_t kSwpKinds = (1u << SWP11) | (1u << SWP21) | (1u << SWP12) | (1u << SWP22);
-constexpr uint32_t kX2Kinds = 1u << X2;
-constexpr uint32_t k2optKinds = 1u << TWOOPT;
 
 template <class SEG, bool TW, bool OPEN, int SM, class AR, uint32_t KM, int TPB>
 static void launch_pairs(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) {
@@ -500,15 +515,28 @@ static void launch_pairs(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) 
 }
 
 template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
+static void launch_pair_kinds(const LaunchCtx& L, uint32_t kinds, const DenseOut& D) {
+  if (kinds == kRelKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kRelKinds, TPB>(L, kinds, D);
+  else if (kinds == kSwpKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kSwpKinds, TPB>(L, kinds, D);
+  else if (kinds == kX2Kinds) launch_pairs<SEG, TW, OPEN, SM, AR, kX2Kinds, TPB>(L, kinds, D);
+  else if (!TW && kinds == k2optKinds) launch_pairs<SEG, TW, OPEN, SM, AR, k2optKinds, TPB>(L, kinds, D);
+  else launch_pairs<SEG, TW, OPEN, SM, AR, 0u, kTileSize>(L, kinds, D);
+}
+
+template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
 static void launch_class_t(const LaunchCtx& L, uint32_t fam_mask, int cls, const DenseOut& D) {
   if (cls == 0) {
     const uint32_t kinds = pair_kinds(fam_mask, TW);
     if (!kinds || L.tiles[0] <= 0) return;
-    if (kinds == kRelKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kRelKinds, TPB>(L, kinds, D);
-    else if (kinds == kSwpKinds) launch_pairs<SEG, TW, OPEN, SM, AR, kSwpKinds, TPB>(L, kinds, D);
-    else if (kinds == kX2Kinds) launch_pairs<SEG, TW, OPEN, SM, AR, kX2Kinds, TPB>(L, kinds, D);
-    else if (!TW && kinds == k2optKinds) launch_pairs<SEG, TW, OPEN, SM, AR, k2optKinds, TPB>(L, kinds, D);
-    else launch_pairs<SEG, TW, OPEN, SM, AR, 0u, kTileSize>(L, kinds, D);
+    // without time windows, batches whose travel times are their costs take the kernels
+    // that read no t entries (fewer registers: a Swap tile fits 4 waves per SIMD)
+    if constexpr (!TW && SM == 0 && std::is_same<AR, ArcPlain>::value) {
+      if (L.t_is_c_all && !(L.compact && L.tiles_f > 0)) {
+        launch_pair_kinds<SEG, TW, OPEN, SM, ArcPlainTC, TPB>(L, kinds, D);
+        return;
+      }
+    }
+    launch_pair_kinds<SEG, TW, OPEN, SM, AR, TPB>(L, kinds, D);
     return;
   }
   const int w = cls - 1;

@@ -56,10 +56,18 @@ __device__ __forceinline__ SegTW mid_range<SegTW, true>(const UnitDesc& U, const
 // Matrix access policies: the plain one reads c and t; the footprint one also
 // marks every entry it reads in a bitmap (measurement of the distinct matrix
 // bytes a launch needs).
+// kTisC: the kernel is launched only for units whose travel times are the costs, so
+// a t entry is never read (and never held beside its c entry).
 struct ArcPlain {
+  static constexpr bool kTisC = false;
+  __device__ __forceinline__ void mark(const UnitDesc&, int, int) const {}
+};
+struct ArcPlainTC {
+  static constexpr bool kTisC = true;
   __device__ __forceinline__ void mark(const UnitDesc&, int, int) const {}
 };
 struct ArcFoot {
+  static constexpr bool kTisC = false;
   uint32_t* bits;
   __device__ __forceinline__ void mark(const UnitDesc& U, int a, int b) const {
     const uint64_t i = (uint64_t)a * U.n + b;
@@ -95,7 +103,7 @@ __device__ SEG eval_route(const UnitDesc& U, const SEG* fw, const SEG* bw, const
     const int first = p.rev ? node_at(fw, cx.off + p.to) : node_at(fw, cx.off + p.from);
     ar.mark(U, last, first);
     const int32_t cab = arc_c(U, last, first);
-    const int32_t tab = TW ? arc_t(U, last, first) : (U.t_is_c ? cab : arc_t(U, last, first));
+    const int32_t tab = TW ? arc_t(U, last, first) : ((AR::kTisC || U.t_is_c) ? cab : arc_t(U, last, first));
     if (k == np - 1 && !p.rev && p.to == cx.L && end == cx.end) {
       return cat(acc, cab, tab, ld(bw, cx.off + p.from));
     }
@@ -111,7 +119,7 @@ __device__ SEG eval_route(const UnitDesc& U, const SEG* fw, const SEG* bw, const
   if (end >= 0) {
     ar.mark(U, last, end);
     const int32_t cab = arc_c(U, last, end);
-    const int32_t tab = U.t_is_c ? cab : arc_t(U, last, end);
+    const int32_t tab = (AR::kTisC || U.t_is_c) ? cab : arc_t(U, last, end);
     acc = cat(acc, cab, tab, node_seg<SEG>(U, end));
   }
   return acc;

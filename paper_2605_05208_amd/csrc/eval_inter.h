@@ -27,13 +27,6 @@ __device__ __forceinline__ Side<SEG> side(const SEG& s, int first, int last) {
   return r;
 }
 
-template <class SEG>
-__device__ __forceinline__ Side<SEG> join(const UnitDesc& U, const Side<SEG>& a, const Side<SEG>& b) {
-  const int32_t c = arc_c(U, a.last, b.first);
-  const int32_t t = U.t_is_c ? c : arc_t(U, a.last, b.first);
-  return side(cat(a.s, c, t, b.s), a.first, b.last);
-}
-
 // Two-node block x -> y whose internal arc costs c_xy / t_xy are known.
 template <class SEG>
 __device__ __forceinline__ Side<SEG> block2(const UnitDesc& U, int x, int y, int32_t cxy, int32_t txy) {
@@ -125,7 +118,7 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
   auto CT = [&](int a, int b) -> int2 {
     ar.mark(U, a, b);
     const int32_t c = arc_c(U, a, b);
-    return make_int2(c, U.t_is_c ? c : arc_t(U, a, b));
+    return make_int2(c, (AR::kTisC || U.t_is_c) ? c : arc_t(U, a, b));
   };
   // An arc between the two neighbourhoods, wanted as a -> b with a on v's side: on a
   // symmetric instance it is read as b -> a, so that every such read of the anchors of

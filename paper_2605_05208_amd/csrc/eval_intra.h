@@ -63,7 +63,7 @@ __device__ __forceinline__ SEG eval_shape(const UnitDesc& U, const SEG* fw, cons
     const int first = node_at(fw, A.off + (m.rev ? m.to : m.from));
     ar.mark(U, last, first);
     const int32_t c = arc_c(U, last, first);
-    const int32_t t = U.t_is_c ? c : arc_t(U, last, first);
+    const int32_t t = (AR::kTisC || U.t_is_c) ? c : arc_t(U, last, first);
     if (m.from == m.to) {
       acc = cat(acc, c, t, node_seg<SEG>(U, first));
     } else {
@@ -76,7 +76,7 @@ __device__ __forceinline__ SEG eval_shape(const UnitDesc& U, const SEG* fw, cons
     const SEG suf = ld(bw, A.off + s.y);
     ar.mark(U, last, suf.node);
     const int32_t c = arc_c(U, last, suf.node);
-    const int32_t t = U.t_is_c ? c : arc_t(U, last, suf.node);
+    const int32_t t = (AR::kTisC || U.t_is_c) ? c : arc_t(U, last, suf.node);
     acc = cat(acc, c, t, suf);
   }
   return acc;

@@ -40,6 +40,7 @@ struct LaunchCtx {
   const UnitDesc* units;    // device array [n_units]
   int n_units;
   int has_tw, open;
+  int t_is_c_all;           // every instance's travel times are its costs (one matrix)
   // item classes: 0 pairs, 1 depot-insert, 2 depot-replace, 3 route slots, 4 one block per unit
   const int32_t* tile_off[4];  // device arrays [n_units + 1]
   int tiles[4];
