@@ -305,6 +305,7 @@ def batch_study(n_inst=256, graph=True):
     torch.cuda.synchronize()
     alone_s = time.perf_counter() - t2
     assert st1[0]["passes"] == st[last]["passes"]
+    lanes = batch_lanes(dev, sols, shapes, nc, [s["F"] for s in st], graph)
     return dict(workload=f"{n_inst} uneven MDVRPTW instances (100..5000 customers, 2..20 depots), one solution each, "
                          "one batch, local search to optimum" + (", passes replayed from HIP graphs" if graph else ""),
                 customers=int(nc.sum()), seconds=round(dt, 3), instances_per_s=round(n_inst / dt, 2),
@@ -314,8 +315,62 @@ def batch_study(n_inst=256, graph=True):
                 passes_max=int(max(s["passes"] for s in st)), first_run_s=round(runs[0][0], 3),
                 last_unit=dict(customers=int(nc[last]), passes=int(st[last]["passes"]),
                                in_batch_ms=round(float(per[last]), 2), alone_ms=round(alone_s * 1e3, 2)),
-                tile_threads_per_family=shapes,
+                tile_threads_per_family=shapes, lanes=lanes,
                 generate_s=round(t_gen, 1))
+
+
+def batch_lanes(dev, sols, shapes, nc, ref_F, graph, k_big=16):
+    """The same instances as two batches searched at once on two streams: the k_big
+    largest in one, the rest in the other (each host thread drives one batch). The
+    large instances' long pass chains then no longer wait for the small instances'
+    passes, which is what a persistent work queue would buy."""
+    import threading
+
+    import torch
+
+    from paper_2605_05208_amd import mdvrp
+    order = np.argsort(-np.asarray(nc), kind="stable")
+    groups = [sorted(order[:k_big].tolist()), sorted(order[k_big:].tolist())]
+    batches = []
+    for g in groups:
+        Bg = mdvrp.Batch(dev, g)
+        Bg.set_tile_shapes(shapes)
+        batches.append(Bg)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    res = {}
+
+    def run(k):
+        with torch.cuda.stream(streams[k]):
+            res[k] = batches[k].local_search_to_optimum(seed=1, poll_every=4, graph=graph)
+            torch.cuda.current_stream().synchronize()
+
+    dt = None
+    for _ in range(2):  # the first run captures the graphs
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                batches[k].load([sols[i] for i in groups[k]])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        threads = [threading.Thread(target=run, args=(k,)) for k in range(2)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    per = np.zeros(len(nc))
+    F = [0] * len(nc)
+    for k in range(2):
+        for i, s in zip(groups[k], res[k]):
+            assert s["converged"] and s["err"] == 0
+            per[i] = s["device_ms"]
+            F[i] = s["F"]
+    assert F == list(ref_F), "two concurrent batches must reach the single batch's optima"
+    n = len(nc)
+    return dict(design=f"two concurrent batches on two streams: the {k_big} largest instances and the other {n - k_big}",
+                seconds=round(dt, 3), instances_per_s=round(n / dt, 2),
+                per_instance_ms_p50=round(float(np.percentile(per, 50)), 2),
+                per_instance_ms_p99=round(float(np.percentile(per, 99)), 2))
 
 
 def _event_ms(fn, reps=1):

@@ -229,7 +229,11 @@ constexpr uint32_t kX2Kinds = 1u << X2;
 constexpr uint32_t k2optKinds = 1u << TWOOPT;
 
 // Waves per SIMD the compiler must fit a pair kernel into (1: as many as its registers
-// allow).
+// allow). The kernels wait on gathers most of their time, so a wave more per SIMD hides
+// more of that wait: the t-free Swap kernel in 64-thread tiles needs 140 VGPRs (3
+// waves); held to 128 (4 waves) it keeps a few values in scratch and the search without
+// time windows is 1.7 % faster. (The time-window Swap kernel held to 4 waves spills far
+// more and is 2.6 % slower.)
 template <bool TW, uint32_t KM, int TPB, class AR>
 constexpr int pair_min_waves() {
   return (KM == kSwpKinds && !TW && TPB == 64 && AR::kTisC) ? 4 : 1;
