@@ -230,13 +230,17 @@ constexpr uint32_t k2optKinds = 1u << TWOOPT;
 
 // Waves per SIMD the compiler must fit a pair kernel into (1: as many as its registers
 // allow). The kernels wait on gathers most of their time, so a wave more per SIMD hides
-// more of that wait: the t-free Swap kernel in 64-thread tiles needs 140 VGPRs (3
-// waves); held to 128 (4 waves) it keeps a few values in scratch and the search without
-// time windows is 1.7 % faster. (The time-window Swap kernel held to 4 waves spills far
-// more and is 2.6 % slower.)
+// more of that wait. In 64-thread tiles the t-free Swap kernel needs 140 VGPRs and the
+// time-window Relocate kernel 132 (3 waves each); held to 128 (4 waves) they keep a few
+// values in scratch, and the searches are 1.7 % (without time windows) and 1.7-2.5 %
+// (with) faster. (The time-window Swap kernel held to 4 waves spills far more and is
+// 2.6 % slower; a fifth wave for Relocate or 2-opt* without time windows gained nothing.)
 template <bool TW, uint32_t KM, int TPB, class AR>
 constexpr int pair_min_waves() {
-  return (KM == kSwpKinds && !TW && TPB == 64 && AR::kTisC) ? 4 : 1;
+  if (TPB != 64) return 1;
+  if (KM == kSwpKinds && !TW && AR::kTisC) return 4;
+  if (KM == kRelKinds && TW) return 4;
+  return 1;
 }
 
 // One tile of pair anchors of unit ui (local tile lt of its item space: the filtered
