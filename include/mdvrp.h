@@ -114,9 +114,11 @@ mdvrp_status mdvrp_instance_workspace_query(const mdvrp_instance_desc* desc, siz
 
 /* Preprocess an instance (once): matrix statistics, the Theta normaliser and
  * Gamma of Eq. A.1 / Eq. 3, time-window arc pruning and the theta-nearest
- * granular lists by eta (Section 3.2.3); with at most 64 depots also a table of
- * the arcs between every customer and every depot (16 bytes per pair, read by
- * Depot-Insert and Depot-Replace). Synchronises the stream.
+ * granular lists by eta (Section 3.2.3), with c(u, v) and t(u, v) of every list
+ * slot kept beside the lists (8 bytes per slot, read by the pair evaluation in
+ * place of the matrix gather of the arc u -> v); with at most 64 depots also a
+ * table of the arcs between every customer and every depot (16 bytes per pair,
+ * read by Depot-Insert and Depot-Replace). Synchronises the stream.
  * Errors: EINVAL (bad desc or data, asymmetric c/t without time windows,
  * negative entries), ERANGE (distances too large for the fixed-point keys:
  * 8*max c >= 2^25), ENOSPC (ws_bytes too small), EDEVICE. */

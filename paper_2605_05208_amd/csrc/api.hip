@@ -65,6 +65,7 @@ struct mdvrp_instance {
   int N = 0;
   int32_t* nbr = nullptr;
   int32_t* nbr_len = nullptr;
+  int2* nbr_ct = nullptr;  // {c, t} of every list slot
   int4* attr = nullptr;
   int4* dep_arc = nullptr;  // depot-arc table (null beyond kDepArcMaxDepots depots)
   int64_t* partial = nullptr;
@@ -297,6 +298,7 @@ static void carve_instance(Carve& cv, const mdvrp_instance_desc* d, mdvrp_instan
   const int nb = inst_stats_blocks(n);
   int32_t* nbr = cv.take<int32_t>((size_t)d->n_customers * d->theta);
   int32_t* nbl = cv.take<int32_t>(d->n_customers);
+  int2* nct = cv.take<int2>((size_t)d->n_customers * d->theta);
   int4* attr = cv.take<int4>(n);
   int4* dep_arc = d->n_depots <= kDepArcMaxDepots ? cv.take<int4>((size_t)d->n_customers * d->n_depots) : nullptr;
   int64_t* part = cv.take<int64_t>((size_t)nb * 8);
@@ -304,6 +306,7 @@ static void carve_instance(Carve& cv, const mdvrp_instance_desc* d, mdvrp_instan
   if (I) {
     I->nbr = nbr;
     I->nbr_len = nbl;
+    I->nbr_ct = nct;
     I->attr = attr;
     I->dep_arc = dep_arc;
     I->partial = part;
@@ -411,6 +414,7 @@ extern "C" mdvrp_status mdvrp_instance_create(const mdvrp_instance_desc* d, void
   launch_nbr_lists(S(stream), d->c, d->t, d->s, d->e, d->l, d->n_depots, d->n_customers, d->theta, d->has_tw,
                    I->gnum, I->gden, I->nbr, I->nbr_len);
   launch_nn_sum(S(stream), d->c, I->nbr, I->nbr_len, d->n_depots, d->n_customers, d->theta, I->stats);
+  launch_nbr_arcs(S(stream), d->c, d->t, I->nbr, I->nbr_len, d->n_depots, d->n_customers, d->theta, I->nbr_ct);
   if (I->pi)
     launch_layout(S(stream), d->c, d->t, n, d->n_depots, I->lm, I->keys, I->pi, I->inv, I->corder, I->cl, I->tl);
   int64_t nn[2] = {0, 0};
@@ -600,7 +604,7 @@ extern "C" mdvrp_status mdvrp_batch_create(const mdvrp_instance* const* insts, i
     const UnitSizes z = unit_sizes(I);
     UnitDesc& u = B->h_units[k];
     u.c = I->d.c; u.t = I->d.t; u.q = I->d.q; u.s = I->d.s; u.e = I->d.e; u.l = I->d.l;
-    u.nbr = I->nbr; u.nbr_len = I->nbr_len; u.attr = I->attr; u.dep_arc = I->dep_arc;
+    u.nbr = I->nbr; u.nbr_len = I->nbr_len; u.nbr_ct = I->nbr_ct; u.attr = I->attr; u.dep_arc = I->dep_arc;
     u.cl = I->cl; u.tl = I->tl ? I->tl : I->cl; u.pi = I->pi; u.corder = I->corder;
     u.nd = z.nd; u.nc = z.nc; u.n = z.n; u.theta = z.theta;
     u.Q = I->d.Q; u.NV = I->d.NV; u.Dmax = I->d.Dmax;

@@ -243,6 +243,16 @@ constexpr int pair_min_waves() {
   return 1;
 }
 
+// The same for the compact kernel of filtered searches, whose per-unit tile loop costs
+// registers: its Swap kernel would need 169-170 VGPRs (2 waves per SIMD) and is held to
+// 168 (3 waves; 2 values in scratch). Together with the changes of the same build the
+// network-filtered search at k = 8 went from 1.96 to 1.84 s; holding the time-window
+// Relocate kernel to 4 waves as well (23 values in scratch) gained nothing more.
+template <bool TW, uint32_t KM, int TPB>
+constexpr int compact_min_waves() {
+  return (TPB <= 128 && KM == kSwpKinds) ? 3 : 1;
+}
+
 // One tile of pair anchors of unit ui (local tile lt of its item space: the filtered
 // lists when the unit is in filtered mode, else the granular lists).
 template <class SEG, bool TW, bool OPEN, int SM, class AR, int TPB>
@@ -280,6 +290,8 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
       const int i = U.corder ? ld(U.corder, ri) : ri;
       const int item = i * th + k;
       const int v = ld(lists, item);
+      const bool uv_cached = !filt && U.pi;
+      const int2 uvc = uv_cached ? ld(U.nbr_ct, item) : make_int2(0, 0);
       if ((filt || k < ld(U.nbr_len, i)) && v >= 0) {
         const int u = U.nd + i;
         const int sa = ld(U.rt, u), sb = ld(U.rt, v);
@@ -294,6 +306,13 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
             x.eA = ma.w; x.eB = mb.w;
             x.au = ld(U.apos, u); x.av = ld(U.apos, v);
             x.pu = x.au - ma.x; x.pv = x.av - mb.x;
+            // the arc u -> v every pair move creates: from the slot's cache on the granular
+            // lists of instances in the locality layout (read beside the list entry instead
+            // of a gather through the layout's permutation); from the matrix on the filtered
+            // lists and on cache-resident matrices, where the gather is cheaper than the
+            // extra load (1.4 % on 8 x 1000)
+            x.uv_ok = uv_cached;
+            x.uv = uvc;
             eval_inter<SEG, TW, OPEN>(U, fw, bw, ma.x, mb.x, x, inter_kinds, ar, sk);
           }
         } else if (intra_kinds) {
@@ -360,7 +379,7 @@ __global__ __launch_bounds__(TPB, (pair_min_waves<TW, KM, TPB, AR>())) void k_ev
 // takes one tile, a block of a unit evaluating its full lists loops over every
 // blocks-per-unit-th tile.
 template <class SEG, bool TW, bool OPEN, uint32_t KM, int TPB>
-__global__ __launch_bounds__(TPB) void k_eval_pairs_compact(const UnitDesc* __restrict__ units,
+__global__ __launch_bounds__(TPB, (compact_min_waves<TW, KM, TPB>())) void k_eval_pairs_compact(const UnitDesc* __restrict__ units,
                                                            const int32_t* __restrict__ grid_off, int n_units,
                                                            int per_unit, uint32_t kind_arg,
                                                            const int32_t* __restrict__ act) {

@@ -97,6 +97,7 @@ struct UnitDesc {
   // instance
   const int32_t *c, *t, *q, *s, *e, *l;
   const int32_t *nbr, *nbr_len;
+  const int2* nbr_ct;  // {c(u, v), t(u, v)} of every granular-list slot, beside the list (0 past a list's end)
   // locality layout (null when off): c and t reordered so that nearby nodes have nearby
   // indices (cl[pi[a] * n + pi[b]] = c(a, b)), and the customers in that order
   const int32_t *cl, *tl, *pi, *corder;

@@ -190,5 +190,8 @@ void launch_nn_sum(hipStream_t s, const int32_t* c, const int32_t* nbr, const in
 void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* sv, const int32_t* ev,
                       const int32_t* lv, int nd, int nc, int theta, int has_tw, int64_t gnum, int64_t gden,
                       int32_t* nbr, int32_t* nbr_len);
+// {c(u, v), t(u, v)} of every granular-list slot (0 past the end of a list).
+void launch_nbr_arcs(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* nbr, const int32_t* nbr_len,
+                     int nd, int nc, int theta, int2* out);
 
 }  // namespace mdvrp

@@ -213,6 +213,31 @@ void launch_depot_arcs(hipStream_t s, const int32_t* c, const int32_t* t, int nd
   hipLaunchKernelGGL(k_depot_arcs, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, c, t, nd, nc, out);
 }
 
+// {c(u, v), t(u, v)} of every list slot, kept beside the lists so that the evaluation
+// reads the arc u -> v with the list entry instead of gathering it from the matrices
+// (0 past the end of a list).
+__global__ void k_nbr_arcs(const int32_t* __restrict__ c, const int32_t* __restrict__ t,
+                           const int32_t* __restrict__ nbr, const int32_t* __restrict__ nbr_len, int nd, int nc,
+                           int theta, int2* __restrict__ out) {
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= (int64_t)nc * theta) return;
+  const int i = (int)(item / theta), k = (int)(item - (int64_t)i * theta);
+  const int64_t n = (int64_t)nd + nc;
+  int2 r = make_int2(0, 0);
+  if (k < nbr_len[i]) {
+    const int64_t a = (int64_t)(nd + i) * n + nbr[item];
+    r = make_int2(c[a], t[a]);
+  }
+  out[item] = r;
+}
+
+void launch_nbr_arcs(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* nbr, const int32_t* nbr_len,
+                     int nd, int nc, int theta, int2* out) {
+  const int64_t items = (int64_t)nc * theta;
+  hipLaunchKernelGGL(k_nbr_arcs, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, c, t, nbr, nbr_len, nd, nc,
+                     theta, out);
+}
+
 void launch_nbr_lists(hipStream_t s, const int32_t* c, const int32_t* t, const int32_t* sv, const int32_t* ev,
                       const int32_t* lv, int nd, int nc, int theta, int has_tw, int64_t gnum, int64_t gden,
                       int32_t* nbr, int32_t* nbr_len) {

@@ -152,12 +152,12 @@ __device__ __forceinline__ int piece_node(const SEG* fws, const int4 (&pc)[kMaxP
 // mode 0: the step's new routes were given fresh space at the end of the current
 // buffer; only they are built. mode 1: full relayout into the other buffer (the
 // current one after the flip): untouched routes are copied, new ones built.
+// in_place: mode 0; dst: the buffer current after the step; n_items: routes to build
+// (mode 0) or alive routes (mode 1).
 template <class SEG, bool TW, bool OPEN>
-__device__ __forceinline__ void rebuild_items(const UnitDesc& U, const UnitCtl* ctl, int w0, int stride) {
-  const bool in_place = ctl->rebuild_mode == 0;
-  const int dst = ctl->cur, src = in_place ? dst : dst ^ 1;
-  const int epoch = ctl->epoch;
-  const int n_items = in_place ? ctl->n_build : ctl->n_slots_alive;
+__device__ __forceinline__ void rebuild_items(const UnitDesc& U, bool in_place, int dst, int epoch, int n_items,
+                                              int w0, int stride) {
+  const int src = in_place ? dst : dst ^ 1;
   const SEG* fws = (const SEG*)U.fw[src];
   const SEG* bws = (const SEG*)U.bw[src];
   SEG* fwd = (SEG*)U.fw[dst];
@@ -187,6 +187,14 @@ __device__ __forceinline__ void rebuild_items(const UnitDesc& U, const UnitCtl* 
     build_route_wave<SEG, TW, OPEN>(U, dst, slot, U.r_off[dst][slot], L, U.r_start[slot], OPEN ? -1 : U.r_end[slot],
                                     nodeAt);
   }
+}
+
+// The same, with the step's mode and counts read from the unit's control block.
+template <class SEG, bool TW, bool OPEN>
+__device__ __forceinline__ void rebuild_items(const UnitDesc& U, const UnitCtl* ctl, int w0, int stride) {
+  const bool in_place = ctl->rebuild_mode == 0;
+  rebuild_items<SEG, TW, OPEN>(U, in_place, ctl->cur, ctl->epoch, in_place ? ctl->n_build : ctl->n_slots_alive, w0,
+                               stride);
 }
 
 // A new route of the step whose recipe is held in LDS (the fused select-and-apply

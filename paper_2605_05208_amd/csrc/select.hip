@@ -381,13 +381,19 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   __shared__ uint64_t shI[kSelWaves];
   __shared__ int shT[kSelWaves];
   __shared__ int sh[2 * kSelWaves + 1];
-  __shared__ int s_nsel, s_alive, s_epoch, s_leader_tile, s_ndins, s_nbuild, s_alive_changed, s_viol;
+  __shared__ MoveRec shRec[kSelWaves];
+  __shared__ int s_nsel, s_alive, s_epoch, s_leader_wave, s_ndins, s_nbuild, s_alive_changed, s_viol;
   __shared__ SelLds S;
   __shared__ PlanLds P;
   if (!ctl->active) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-  const int cur = ctl->cur;
+  // every control field the step reads, loaded at once (the step is a chain of memory
+  // round trips; these need not add to it)
+  const int cur = ctl->cur, fmode = ctl->fmode, ftiles_ev = ctl->ftiles_eval, n_alive = ctl->n_slots_alive;
+  const int epoch0 = ctl->epoch, n_cand0 = ctl->n_cand, top = ctl->arena_top;
   const SelView<APPLY, DEPL> V{U, P};
+  if constexpr (DEPL)
+    for (int d = tid; d < U.nd; d += kSelBlock) P.ndep[d] = U.ndep[d];
 
   // ---- leader: minimum (dF, id) over the block bests of the evaluated item classes
   int64_t bf = kNoMove;
@@ -398,8 +404,8 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     // a filtered unit's pair tiles cover its candidate lists only; Depot-Replace tiles
     // cover the alive routes only
     int t_end = U.tile_base[c + 1];
-    if (c == 0 && ctl->fmode == 1) t_end = U.tile_base[0] + ctl->ftiles_eval;
-    if (c == 2) t_end = imin(t_end, U.tile_base[2] + (ctl->n_slots_alive * U.nd + kTileSize - 1) / kTileSize);
+    if (c == 0 && fmode == 1) t_end = U.tile_base[0] + ftiles_ev;
+    if (c == 2) t_end = imin(t_end, U.tile_base[2] + (n_alive * U.nd + kTileSize - 1) / kTileSize);
     for (int t = U.tile_base[c] + tid; t < t_end; t += kSelBlock) {
       const int64_t f = U.wg_best[t].dF;
       const uint64_t i = U.wg_best[t].id;
@@ -412,12 +418,18 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     const int t2 = __shfl_xor(bt, off);
     if (key_less(f2, i2, bf, bi)) { bf = f2; bi = i2; bt = t2; }
   }
-  if (lane == 0) { shF[wave] = bf; shI[wave] = bi; shT[wave] = bt; }
+  // each wavefront's best record goes to LDS with its key, so that the leader's record
+  // needs no further load once the wavefronts are compared
+  if (lane == 0) {
+    shF[wave] = bf; shI[wave] = bi; shT[wave] = bt;
+    if (bt >= 0) shRec[wave] = U.wg_best[bt];
+  }
   __syncthreads();
   if (tid == 0) {
+    int bw = 0;
     for (int w = 1; w < kSelWaves; ++w)
-      if (key_less(shF[w], shI[w], shF[0], shI[0])) { shF[0] = shF[w]; shI[0] = shI[w]; shT[0] = shT[w]; }
-    s_leader_tile = shT[0];
+      if (key_less(shF[w], shI[w], shF[bw], shI[bw])) bw = w;
+    s_leader_wave = bw;
     s_nsel = 0;
     s_ndins = 0;
     s_nbuild = 0;
@@ -425,11 +437,11 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     P.F = 0;
     ctl->steps += 1;
     // the lists scored before this step's evaluation reflect every route up to this epoch
-    if (scored && ctl->fmode == 1) ctl->scored_epoch = ctl->epoch;
-    if (shF[0] < 0) {
-      s_epoch = ctl->epoch + 1;
+    if (scored && fmode == 1) ctl->scored_epoch = epoch0;
+    if (shF[bw] < 0) {
+      s_epoch = epoch0 + 1;
       ctl->epoch = s_epoch;
-      ctl->leader = U.wg_best[shT[0]];
+      ctl->leader = shRec[bw];
     } else {
       s_epoch = 0;
       ctl->n_sel = 0;
@@ -439,12 +451,9 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
   __syncthreads();
   if (s_epoch == 0) return;  // no improving move: this step applies nothing
   const int epoch = s_epoch;
-  const MoveRec lead = U.wg_best[s_leader_tile];
-  const int n_cand = imin(ctl->n_cand, U.cand_cap);
-  if constexpr (DEPL)
-    for (int d = tid; d < U.nd; d += kSelBlock) P.ndep[d] = U.ndep[d];
+  const MoveRec lead = shRec[s_leader_wave];
+  const int n_cand = imin(n_cand0, U.cand_cap);
 
-  const int n_alive = ctl->n_slots_alive;
   // resources in LDS: the slots themselves when they fit, else the renamed alive slots
   const bool rename = U.R + U.nd > kLdsRes;
   const int n_res = rename ? n_alive + U.nd : U.R + U.nd;
@@ -604,8 +613,8 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     total += tot;
   }
   __syncthreads();
-  const int top = ctl->arena_top;
   const bool in_place = (int64_t)top + total <= U.cap;
+  int rb_alive = 0;  // alive routes after a relayout (the routes the rebuild visits)
   if (in_place) {
     for (int k = tid; k < n_sel; k += kSelBlock) {
       int at = top + V.size(k);
@@ -653,7 +662,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     }
   } else {
     const int dst = cur ^ 1;
-    int carry = 0, alive_carry = 0;
+    int carry = 0, alive_carry = 0;  // (alive_carry ends equal in every thread)
     for (int base = 0; base < U.R; base += kSelBlock) {
       const int s = base + tid;
       const int len = s < U.R ? U.r_len[s] : 0;
@@ -669,6 +678,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
       carry += tot;
       alive_carry += tot2;
     }
+    rb_alive = alive_carry;
     if (tid == 0) {
       if (carry > U.cap) atomicOr(&ctl->err, 2);
       ctl->n_slots_alive = alive_carry;
@@ -698,7 +708,9 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
       if (!in_place) rec.off = U.r_off[dst][rec.slot];
       build_recorded_route<SEG, TW, OPEN>(U, rec, src, dst);
     }
-    rebuild_items<SEG, TW, OPEN>(U, ctl, wave, kSelWaves);
+    // (mode, buffer, epoch and counts from this step's own values: no reload of the
+    // control block)
+    rebuild_items<SEG, TW, OPEN>(U, in_place, dst, epoch, in_place ? s_nbuild : rb_alive, wave, kSelWaves);
     if (adapt_units) {
       __syncthreads();
       adapt_weights<OPEN>(U, ctl, adapt_units + blockIdx.x, adapt, &s_viol);
