@@ -486,45 +486,86 @@ __device__ __forceinline__ uint64_t make_id(int kind, int var, int a, int b) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-template <class T> __device__ __forceinline__ T shfl_up_seg(const T& v, int off);
-template <> __device__ __forceinline__ SegNT shfl_up_seg<SegNT>(const SegNT& v, int off) {
+// Segment shuffles within groups of W lanes (W = 64: the whole wavefront; W = 32: each
+// half builds a route of its own).
+template <class T, int W = 64> __device__ __forceinline__ T shfl_up_seg(const T& v, int off);
+template <> __device__ __forceinline__ SegNT shfl_up_seg<SegNT, 64>(const SegNT& v, int off) {
   SegNT r;
   r.C = __shfl_up(v.C, off); r.Q = __shfl_up(v.Q, off); r.D = __shfl_up(v.D, off);
   r.node = __shfl_up(v.node, off);
   return r;
 }
-template <> __device__ __forceinline__ SegTW shfl_up_seg<SegTW>(const SegTW& v, int off) {
+template <> __device__ __forceinline__ SegNT shfl_up_seg<SegNT, 32>(const SegNT& v, int off) {
+  SegNT r;
+  r.C = __shfl_up(v.C, off, 32); r.Q = __shfl_up(v.Q, off, 32); r.D = __shfl_up(v.D, off, 32);
+  r.node = __shfl_up(v.node, off, 32);
+  return r;
+}
+template <> __device__ __forceinline__ SegTW shfl_up_seg<SegTW, 64>(const SegTW& v, int off) {
   SegTW r;
   r.C = __shfl_up(v.C, off); r.Q = __shfl_up(v.Q, off); r.D = __shfl_up(v.D, off);
   r.TW = __shfl_up(v.TW, off); r.E = __shfl_up(v.E, off); r.L = __shfl_up(v.L, off);
   r.node = __shfl_up(v.node, off); r.aux = __shfl_up(v.aux, off);
   return r;
 }
-template <class T> __device__ __forceinline__ T shfl_down_seg(const T& v, int off);
-template <> __device__ __forceinline__ SegNT shfl_down_seg<SegNT>(const SegNT& v, int off) {
+template <> __device__ __forceinline__ SegTW shfl_up_seg<SegTW, 32>(const SegTW& v, int off) {
+  SegTW r;
+  r.C = __shfl_up(v.C, off, 32); r.Q = __shfl_up(v.Q, off, 32); r.D = __shfl_up(v.D, off, 32);
+  r.TW = __shfl_up(v.TW, off, 32); r.E = __shfl_up(v.E, off, 32); r.L = __shfl_up(v.L, off, 32);
+  r.node = __shfl_up(v.node, off, 32); r.aux = __shfl_up(v.aux, off, 32);
+  return r;
+}
+template <class T, int W = 64> __device__ __forceinline__ T shfl_down_seg(const T& v, int off);
+template <> __device__ __forceinline__ SegNT shfl_down_seg<SegNT, 64>(const SegNT& v, int off) {
   SegNT r;
   r.C = __shfl_down(v.C, off); r.Q = __shfl_down(v.Q, off); r.D = __shfl_down(v.D, off);
   r.node = __shfl_down(v.node, off);
   return r;
 }
-template <> __device__ __forceinline__ SegTW shfl_down_seg<SegTW>(const SegTW& v, int off) {
+template <> __device__ __forceinline__ SegNT shfl_down_seg<SegNT, 32>(const SegNT& v, int off) {
+  SegNT r;
+  r.C = __shfl_down(v.C, off, 32); r.Q = __shfl_down(v.Q, off, 32); r.D = __shfl_down(v.D, off, 32);
+  r.node = __shfl_down(v.node, off, 32);
+  return r;
+}
+template <> __device__ __forceinline__ SegTW shfl_down_seg<SegTW, 64>(const SegTW& v, int off) {
   SegTW r;
   r.C = __shfl_down(v.C, off); r.Q = __shfl_down(v.Q, off); r.D = __shfl_down(v.D, off);
   r.TW = __shfl_down(v.TW, off); r.E = __shfl_down(v.E, off); r.L = __shfl_down(v.L, off);
   r.node = __shfl_down(v.node, off); r.aux = __shfl_down(v.aux, off);
   return r;
 }
-template <class T> __device__ __forceinline__ T shfl_seg(const T& v, int src);
-template <> __device__ __forceinline__ SegNT shfl_seg<SegNT>(const SegNT& v, int src) {
+template <> __device__ __forceinline__ SegTW shfl_down_seg<SegTW, 32>(const SegTW& v, int off) {
+  SegTW r;
+  r.C = __shfl_down(v.C, off, 32); r.Q = __shfl_down(v.Q, off, 32); r.D = __shfl_down(v.D, off, 32);
+  r.TW = __shfl_down(v.TW, off, 32); r.E = __shfl_down(v.E, off, 32); r.L = __shfl_down(v.L, off, 32);
+  r.node = __shfl_down(v.node, off, 32); r.aux = __shfl_down(v.aux, off, 32);
+  return r;
+}
+template <class T, int W = 64> __device__ __forceinline__ T shfl_seg(const T& v, int src);
+template <> __device__ __forceinline__ SegNT shfl_seg<SegNT, 64>(const SegNT& v, int src) {
   SegNT r;
   r.C = __shfl(v.C, src); r.Q = __shfl(v.Q, src); r.D = __shfl(v.D, src); r.node = __shfl(v.node, src);
   return r;
 }
-template <> __device__ __forceinline__ SegTW shfl_seg<SegTW>(const SegTW& v, int src) {
+template <> __device__ __forceinline__ SegNT shfl_seg<SegNT, 32>(const SegNT& v, int src) {
+  SegNT r;
+  r.C = __shfl(v.C, src, 32); r.Q = __shfl(v.Q, src, 32); r.D = __shfl(v.D, src, 32);
+  r.node = __shfl(v.node, src, 32);
+  return r;
+}
+template <> __device__ __forceinline__ SegTW shfl_seg<SegTW, 64>(const SegTW& v, int src) {
   SegTW r;
   r.C = __shfl(v.C, src); r.Q = __shfl(v.Q, src); r.D = __shfl(v.D, src);
   r.TW = __shfl(v.TW, src); r.E = __shfl(v.E, src); r.L = __shfl(v.L, src);
   r.node = __shfl(v.node, src); r.aux = __shfl(v.aux, src);
+  return r;
+}
+template <> __device__ __forceinline__ SegTW shfl_seg<SegTW, 32>(const SegTW& v, int src) {
+  SegTW r;
+  r.C = __shfl(v.C, src, 32); r.Q = __shfl(v.Q, src, 32); r.D = __shfl(v.D, src, 32);
+  r.TW = __shfl(v.TW, src, 32); r.E = __shfl(v.E, src, 32); r.L = __shfl(v.L, src, 32);
+  r.node = __shfl(v.node, src, 32); r.aux = __shfl(v.aux, src, 32);
   return r;
 }
 

@@ -17,13 +17,15 @@ template <> __device__ __forceinline__ void set_aux<SegTW>(SegTW& s, int32_t v) 
 
 // Build positions 0..P-1 of one route at flat offset `off` of buffer `dst`.
 // nodeAt(p) returns the customer at position p (1..L). Each lane reads its own node
-// once per chunk and gets its neighbours' by shuffles; a route of at most 64
+// once per chunk and gets its neighbours' by shuffles; a route of at most W
 // positions (one chunk) reuses the forward pass's nodes, arcs and node segments in
 // the backward pass.
-template <class SEG, bool TW, bool OPEN, class NodeFn>
+// W = 64: the whole wavefront builds the route; W = 32: each half of the wavefront
+// builds a route of its own (every shuffle stays within the half).
+template <class SEG, bool TW, bool OPEN, int W = 64, class NodeFn>
 __device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int slot, int64_t off, int L, int start, int end,
                                  NodeFn nodeAt) {
-  const int lane = lane_id();
+  const int lane = lane_id() & (W - 1);
   const int P = OPEN ? L + 1 : L + 2;
   SEG* fw = (SEG*)U.fw[dst];
   SEG* bw = (SEG*)U.bw[dst];
@@ -32,19 +34,19 @@ __device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int
     if (p == L + 1) return end;
     return nodeAt(p);
   };
-  const bool one_chunk = P <= 64;
+  const bool one_chunk = P <= W;
   int x1 = start;       // one chunk: this lane's node,
   int32_t c1 = 0, t1 = 0;  // the arc to the next position,
   SEG n1;               // and its node segment
   // forward scan
   SEG carry;
   int32_t carry_c = 0, carry_t = 0;
-  for (int base = 0; base < P; base += 64) {
+  for (int base = 0; base < P; base += W) {
     const int p = base + lane;
     const bool valid = p < P;
     const int x = valid ? node(p) : start;
-    int xn = __shfl_down(x, 1);
-    if (lane == 63) xn = p + 1 < P ? node(p + 1) : -1;
+    int xn = __shfl_down(x, 1, W);
+    if (lane == W - 1) xn = p + 1 < P ? node(p + 1) : -1;
     if (p + 1 >= P) xn = -1;
     const int32_t oc = xn >= 0 ? arc_c(U, x, xn) : 0;
     const int32_t ot = xn >= 0 ? arc_t(U, x, xn) : 0;
@@ -52,10 +54,10 @@ __device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int
     if (one_chunk) { x1 = x; c1 = oc; t1 = ot; n1 = nseg; }
     SEG seg = nseg;
     set_aux(seg, ot);
-    for (int o = 1; o < 64; o <<= 1) {
-      const SEG l = shfl_up_seg(seg, o);
-      const int32_t lc = __shfl_up(oc, o);
-      const int32_t lt = __shfl_up(ot, o);
+    for (int o = 1; o < W; o <<= 1) {
+      const SEG l = shfl_up_seg<SEG, W>(seg, o);
+      const int32_t lc = __shfl_up(oc, o, W);
+      const int32_t lt = __shfl_up(ot, o, W);
       if (lane >= o) seg = cat(l, lc, lt, seg);
     }
     if (base > 0) seg = cat(carry, carry_c, carry_t, seg);
@@ -68,28 +70,28 @@ __device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int
       }
       if (p == P - 1) U.r_tot[slot] = make_int4(seg.C, seg.Q, seg.D, seg_tw(seg));
     }
-    const int lv = imin(63, P - 1 - base);
-    carry = shfl_seg(seg, lv);
-    carry_c = __shfl(oc, lv);
-    carry_t = __shfl(ot, lv);
+    const int lv = imin(W - 1, P - 1 - base);
+    carry = shfl_seg<SEG, W>(seg, lv);
+    carry_c = __shfl(oc, lv, W);
+    carry_t = __shfl(ot, lv, W);
   }
   // time windows, one chunk: the segment of the customers alone (an inclusive scan that
   // starts at position 1), kept for Depot-Replace
   if constexpr (TW) {
     if (one_chunk && L >= 1 && L <= kCoreMaxL) {
       SEG seg = n1;
-      for (int o = 1; o < 64; o <<= 1) {
-        const SEG l = shfl_up_seg(seg, o);
-        const int32_t lc = __shfl_up(c1, o);
-        const int32_t lt = __shfl_up(t1, o);
+      for (int o = 1; o < W; o <<= 1) {
+        const SEG l = shfl_up_seg<SEG, W>(seg, o);
+        const int32_t lc = __shfl_up(c1, o, W);
+        const int32_t lt = __shfl_up(t1, o, W);
         if (lane - o >= 1) seg = cat(l, lc, lt, seg);
       }
       if (lane == L) U.r_core[slot] = seg;
     }
   }
   // backward scan
-  const int last_base = ((P - 1) / 64) * 64;
-  for (int base = last_base; base >= 0; base -= 64) {
+  const int last_base = ((P - 1) / W) * W;
+  for (int base = last_base; base >= 0; base -= W) {
     const int p = base + lane;
     const bool valid = p < P;
     int x;
@@ -98,32 +100,32 @@ __device__ __forceinline__ void build_route_wave(const UnitDesc& U, int dst, int
     if (one_chunk) {
       // the arc into position p is the forward arc out of position p - 1
       x = x1;
-      ic = __shfl_up(c1, 1);
-      it = __shfl_up(t1, 1);
+      ic = __shfl_up(c1, 1, W);
+      it = __shfl_up(t1, 1, W);
       if (lane == 0) { ic = 0; it = 0; }
       seg = n1;
     } else {
       x = valid ? node(p) : start;
-      int xp = __shfl_up(x, 1);
+      int xp = __shfl_up(x, 1, W);
       if (lane == 0) xp = p >= 1 ? node(p - 1) : -1;
       if (!valid) xp = -1;
       ic = xp >= 0 ? arc_c(U, xp, x) : 0;
       it = xp >= 0 ? arc_t(U, xp, x) : 0;
       seg = node_seg<SEG>(U, x);
     }
-    for (int o = 1; o < 64; o <<= 1) {
-      const SEG r = shfl_down_seg(seg, o);
-      const int32_t rc = __shfl_down(ic, o);
-      const int32_t rt = __shfl_down(it, o);
-      if (lane + o < 64 && p + o < P) seg = cat(seg, rc, rt, r);
+    for (int o = 1; o < W; o <<= 1) {
+      const SEG r = shfl_down_seg<SEG, W>(seg, o);
+      const int32_t rc = __shfl_down(ic, o, W);
+      const int32_t rt = __shfl_down(it, o, W);
+      if (lane + o < W && p + o < P) seg = cat(seg, rc, rt, r);
     }
     if (base != last_base) seg = cat(seg, carry_c, carry_t, carry);
     seg.node = x;
     set_aux(seg, 0);
     if (valid) bw[off + p] = seg;
-    carry = shfl_seg(seg, 0);
-    carry_c = __shfl(ic, 0);
-    carry_t = __shfl(it, 0);
+    carry = shfl_seg<SEG, W>(seg, 0);
+    carry_c = __shfl(ic, 0, W);
+    carry_t = __shfl(it, 0, W);
   }
 }
 
@@ -207,7 +209,7 @@ struct RouteRec {
 
 // Build one recorded route (len > 0) at rec.off of buffer dst, reading its customers
 // from the pieces of the old routes in buffer src.
-template <class SEG, bool TW, bool OPEN>
+template <class SEG, bool TW, bool OPEN, int W = 64>
 __device__ __forceinline__ void build_recorded_route(const UnitDesc& U, const RouteRec& rec, int src, int dst) {
   const SEG* fws = (const SEG*)U.fw[src];
   const int np = rec.np;
@@ -215,7 +217,7 @@ __device__ __forceinline__ void build_recorded_route(const UnitDesc& U, const Ro
 #pragma unroll
   for (int j = 0; j < kMaxPieces; ++j) pc[j] = j < np ? rec.pc[j] : make_int4(0, 0, -1, 0);
   auto nodeAt = [&](int p) -> int { return piece_node(fws, pc, np, p); };
-  build_route_wave<SEG, TW, OPEN>(U, dst, rec.slot, rec.off, rec.len, rec.start, OPEN ? -1 : rec.end, nodeAt);
+  build_route_wave<SEG, TW, OPEN, W>(U, dst, rec.slot, rec.off, rec.len, rec.start, OPEN ? -1 : rec.end, nodeAt);
 }
 
 }  // namespace mdvrp

@@ -702,9 +702,18 @@ __global__ __launch_bounds__(kSelBlock) void k_select_plan(const UnitDesc* __res
     const int n_rec = 2 * imin(n_sel, kPlanLds);
     const int src = cur;  // the old routes live in the buffer that was current before this step
     const int dst = in_place ? cur : cur ^ 1;
+    // routes of at most 32 positions (most of them): one per half-wavefront, two at a
+    // time per wavefront; the longer ones: one per wavefront
+    const int half = lane >> 5;
+    for (int r = 2 * wave + half; r < n_rec; r += 2 * kSelWaves) {
+      RouteRec rec = P.rr[r];
+      if (rec.len <= 0 || (OPEN ? rec.len + 1 : rec.len + 2) > 32) continue;
+      if (!in_place) rec.off = U.r_off[dst][rec.slot];
+      build_recorded_route<SEG, TW, OPEN, 32>(U, rec, src, dst);
+    }
     for (int r = wave; r < n_rec; r += kSelWaves) {
       RouteRec rec = P.rr[r];
-      if (rec.len <= 0) continue;
+      if (rec.len <= 0 || (OPEN ? rec.len + 1 : rec.len + 2) <= 32) continue;
       if (!in_place) rec.off = U.r_off[dst][rec.slot];
       build_recorded_route<SEG, TW, OPEN>(U, rec, src, dst);
     }

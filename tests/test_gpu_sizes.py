@@ -7,7 +7,8 @@ that earlier tests did not reach (exact integers throughout):
 * searches of up to ten passes on instances above 4 096 nodes, where the
   selection keeps its per-resource minima in global memory instead of LDS;
 * separate, asymmetric c and t (Gamma != 1) with 64 and 65 depots and with the
-  locality layout of the matrices;
+  locality layout of the matrices; separate symmetric t without time windows (the
+  kernels that read t, beside the t-free ones);
 * routes beyond the int32-safe length are refused at load time.
 """
 import numpy as np
@@ -130,6 +131,57 @@ def test_separate_asymmetric_times(layout, open_r):
             for key in ("F", "passes", "steps", "moves_applied", "evaluated"):
                 assert st[u][key] == rst[j][key], (k, j, key)
             u += 1
+
+
+def _with_symmetric_times(inst, seed, dmax_frac):
+    """A copy of an instance without time windows whose travel times are a separate,
+    symmetric matrix t = c + a symmetric per-arc offset, with a duration limit that
+    binds (so that t enters F through the duration excess)."""
+    rng = np.random.default_rng(seed)
+    n = inst.N
+    off = rng.integers(0, 40, (n, n))
+    off = np.triu(off, 1)
+    off = off + off.T
+    out = gen.Instance(**{**inst.__dict__})
+    out.t = np.ascontiguousarray(inst.c.astype(np.int64) + off, np.int32)
+    out.Dmax = int(dmax_frac * np.sort(out.t[:inst.n_depots].ravel())[-1])
+    out.w_dur = 5
+    out.name = inst.name + "-t"
+    return out
+
+
+@pytest.mark.parametrize("layout", [mdvrp.LAYOUT_GIVEN, mdvrp.LAYOUT_ORDERED])
+def test_separate_symmetric_times_without_windows(layout):
+    """Without time windows the batches whose travel times are their costs take kernels
+    that never read t; an instance with a separate t matrix (symmetric, as required, and
+    a binding duration limit) takes the kernels that do, alone and in a batch beside an
+    instance with t = c: dense move tables and whole searches against the oracle."""
+    a = _with_symmetric_times(gen.config1(), 7, 3.0)
+    b = _with_symmetric_times(gen.tiny(97_000, has_tw=0, nd=3, nc=12), 8, 2.0)
+    c = gen.config1(111)
+    for insts in ([a], [a, b, c]):
+        sols = [[gen.random_solution(i, 3), gen.start_solution(i, 4)] for i in insts]
+        log("separate symmetric times", layout, len(insts))
+        dev, B, flat = _make_batch_layout(insts, sols, layout)
+        for fam in [ALL_FAMILIES] + ALL_PLAIN:
+            got = B.eval_neighbourhood(fam, dense_cap=dense_cap_for([insts[k] for k in B.unit_inst]))
+            u = 0
+            for k, inst in enumerate(insts):
+                ref = Ref(inst)
+                for sol in sols[k]:
+                    compare_dense(got[got["unit"] == u], ref.eval(sol, fam), inst.n_customers, f"inst {k} unit {u}")
+                    u += 1
+        dev, B, flat = _make_batch_layout(insts, sols, layout)
+        st = B.local_search_to_optimum(seed=29)
+        got = B.export()
+        u = 0
+        for k, inst in enumerate(insts):
+            out, rst = Ref(inst).local_search(sols[k], seed=29)
+            for j in range(len(sols[k])):
+                assert canonical(got[u].routes) == canonical(out[j].routes), (k, j)
+                for key in ("F", "passes", "steps", "moves_applied", "evaluated"):
+                    assert st[u][key] == rst[j][key], (k, j, key)
+                u += 1
 
 
 def test_route_beyond_the_int32_safe_length_is_refused():
