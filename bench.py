@@ -84,14 +84,15 @@ def measured_traffic(workload):
 
 def instance_bytes(inst):
     """Compulsory bytes of one pair-evaluation launch that the units of one instance
-    share, read once per launch: granular lists (entries, lengths, and, for instances in
-    the locality layout, the {c, t} of the arc u -> v kept beside every slot) and node
-    attributes. The matrix entries are
+    share, read once per launch: granular lists (entries, lengths, and, for time-window
+    instances in the locality layout, the {c, t} of the arc u -> v kept beside every
+    slot) and node attributes. The matrix entries are
     counted the same way, once per instance: 4 bytes per distinct entry the launch
     reads (mdvrp_eval_footprint)."""
     nc, n, th = inst.n_customers, inst.N, inst.theta
     attrs = 16 if inst.has_tw else 8
-    slot_arcs = nc * th * 8 if inst.N * inst.N * 4 > (64 << 20) else 0  # read with the locality layout only
+    # read with time windows and the locality layout only
+    slot_arcs = nc * th * 8 if inst.has_tw and inst.N * inst.N * 4 > (64 << 20) else 0
     return (nc * th * 4 + nc * 4 + slot_arcs) + attrs * n
 
 

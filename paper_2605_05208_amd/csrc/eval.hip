@@ -290,8 +290,6 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
       const int i = U.corder ? ld(U.corder, ri) : ri;
       const int item = i * th + k;
       const int v = ld(lists, item);
-      const bool uv_cached = !filt && U.pi;
-      const int2 uvc = uv_cached ? ld(U.nbr_ct, item) : make_int2(0, 0);
       if ((filt || k < ld(U.nbr_len, i)) && v >= 0) {
         const int u = U.nd + i;
         const int sa = ld(U.rt, u), sb = ld(U.rt, v);
@@ -306,13 +304,14 @@ __device__ __forceinline__ void pairs_tile(const UnitDesc& U, int ui, int lt, bo
             x.eA = ma.w; x.eB = mb.w;
             x.au = ld(U.apos, u); x.av = ld(U.apos, v);
             x.pu = x.au - ma.x; x.pv = x.av - mb.x;
-            // the arc u -> v every pair move creates: from the slot's cache on the granular
-            // lists of instances in the locality layout (read beside the list entry instead
-            // of a gather through the layout's permutation); from the matrix on the filtered
-            // lists and on cache-resident matrices, where the gather is cheaper than the
-            // extra load (1.4 % on 8 x 1000)
-            x.uv_ok = uv_cached;
-            x.uv = uvc;
+            // the arc u -> v every pair move creates: with time windows, from the slot's
+            // cache on the granular lists of instances in the locality layout (instead of a
+            // gather through the layout's permutation; loaded with the other arcs, so that
+            // it holds no register longer than they do); otherwise from the matrix: on the
+            // filtered lists, on cache-resident matrices (where the gather is cheaper than
+            // the extra load: 1.4 % on 8 x 1000), and without time windows (where the Swap
+            // kernel, held to 128 VGPRs, would keep more values in scratch)
+            x.uv_item = (TW && !filt && U.pi) ? item : -1;
             eval_inter<SEG, TW, OPEN>(U, fw, bw, ma.x, mb.x, x, inter_kinds, ar, sk);
           }
         } else if (intra_kinds) {

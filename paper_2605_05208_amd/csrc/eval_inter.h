@@ -52,8 +52,7 @@ struct InterCtx {
   int u, v;
   int slotA, slotB, LA, LB, sA, sB, eA, eB, pu, pv;
   int au, av;  // absolute positions of u and v in the current buffer
-  int2 uv;     // {c(u, v), t(u, v)} from the list slot's cache when uv_ok (granular lists)
-  bool uv_ok;
+  int uv_item;  // list slot whose cache holds {c(u, v), t(u, v)}, or -1: read the matrix
 };
 
 template <class SEG, bool TW, bool OPEN, class AR, class OUT>
@@ -137,7 +136,7 @@ __device__ __forceinline__ void eval_inter(const UnitDesc& U, const SEG* fw, con
        k_pv_pu = k_u_v, k_pu_ssu = k_u_v, k_pu_pv = k_u_v, k_ppv_u = k_u_v, k_ppu_pv = k_u_v, k_ppv_pu = k_u_v,
        k_pv_ssu = k_u_v, k_ppv_su = k_u_v, k_pppv_u = k_u_v, k_pu_ppv = k_u_v, k_pppv_pu = k_u_v,
        k_ppu_ppv = k_u_v, k_pppv_su = k_u_v, k_ppv_ssu = k_u_v;
-  k_u_v = x.uv_ok ? x.uv : CT(u, v);
+  k_u_v = x.uv_item >= 0 ? ld(U.nbr_ct, (uint32_t)x.uv_item) : CT(u, v);
   k_pv_su = CTv(p_v, su);
   if (fREL) {
     k_pu_su = CT(p_u, su);
