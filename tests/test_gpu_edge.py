@@ -5,7 +5,10 @@
 * the largest granular lists the library accepts (theta = 128) on medium
   instances, with and without time windows;
 * a search that starts at a local optimum (one pass, nothing applied);
-* one batch that mixes all of these with ordinary units.
+* one batch that mixes all of these with ordinary units;
+* long routes (up to about 80 customers), whose rebuild in the fused step takes a
+  whole wavefront and, beyond 62 customers, more than one 64-position chunk, beside
+  short routes built two per wavefront.
 """
 import numpy as np
 import pytest
@@ -110,3 +113,30 @@ def test_many_depots(tw, open_r):
     for fam in [ALL_FAMILIES, 16, 32]:
         _dense_compare(insts, sols, fam, f"many depots tw={tw} open={open_r} fam {fam}")
     _ls_compare(insts, sols, 0, 17, tag=f"many depots tw={tw} open={open_r}")
+
+
+def _long_routes(tw, open_r):
+    """Two depots, capacity so large that the start solution has one route per depot."""
+    rng = np.random.default_rng(61 + 2 * tw + open_r)
+    if tw:
+        inst = gen._tw_instance(rng, 2, 130, 1000, 60.0, 3, 30, 10**6, 10, 200_000, 16,
+                                "mdvrptw-2x130-long", 61, NV=3)
+    else:
+        nd, nc = 2, 160
+        xy = rng.integers(0, 1001, size=(nd + nc, 2))
+        q = np.concatenate([np.zeros(nd, np.int64), rng.integers(1, 26, nc)])
+        n = nd + nc
+        inst = gen._make(nd, nc, xy, 10, q, np.zeros(n), np.zeros(n), np.full(n, gen.BIG_HORIZON), Q=10**6,
+                         NV=3, Dmax=-1, open_routes=0, has_tw=0, theta=16, w_tw=0, w_load=10, w_dur=0,
+                         w_depot=-1, name="mdvrp-2x160-long", seed=62)
+    inst.open_routes = open_r
+    return inst
+
+
+@pytest.mark.parametrize("tw,open_r", [(0, 0), (0, 1), (1, 0)])
+def test_long_routes_in_the_fused_step(tw, open_r):
+    inst = _long_routes(tw, open_r)
+    sols = [gen.start_solution(inst, 5), gen.start_solution(inst, 6)]
+    assert max(len(r[1]) for s in sols for r in s.routes) > 62
+    log("long routes", tw, open_r)
+    _ls_compare([inst], [sols], 0, 77, max_passes=6, tag=f"long tw={tw} open={open_r}")
