@@ -640,44 +640,96 @@ __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ G, 
   part[(int64_t)blockIdx.x * kH + o] = acc;
 }
 
-constexpr int kSplitK = 1024;  // samples per wave in the weight-gradient products
+constexpr int kSplitK = 1024;  // samples per chunk of the weight-gradient products
+constexpr int kWgM = 64;       // output rows of one weight-gradient block (4 waves x 16)
+constexpr int kWgLd = 40;      // LDS row length (bf16) of the transposed 32-sample slabs
 
 // Weight gradient of one chunk of kSplitK samples: part[ch][M][N] = sum_p L[p][m] R[p][n]
-// over the chunk's samples (both bf16, row-major with row lengths M and N); one wave per
-// (16 x 16 tile, chunk).
+// over the chunk's samples (both bf16, row-major with row lengths M and N; M a multiple
+// of 64, N of 16). One block per (64 x 64 output tile, chunk): per step of 32 samples the
+// block loads the 32 x 64 slabs of L and R with 16-byte row loads and stores them
+// transposed in LDS (sample index contiguous), so that every MFMA operand fragment is one
+// 16-byte LDS read; wave w computes rows 16 w .. 16 w + 15 of the tile against its (up
+// to 64) columns. The operands of every MFMA (the 32 samples of one step, in order) are
+// those of a one-tile-per-wave loop over the same steps, so the sums are too.
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ Lm, int M, const uint16_t* __restrict__ Rm,
                                                int N, int n, float* __restrict__ part) {
-  const int wave = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4;
-  const int tm = M / 16, tn = N / 16, chunks = (n + kSplitK - 1) / kSplitK;
-  for (int t = blockIdx.x * 4 + wave; t < tm * tn * chunks; t += gridDim.x * 4) {
-    const int tile = t % (tm * tn), ch = t / (tm * tn);
-    const int m = (tile / tn) * 16 + (lane & 15), nn = (tile % tn) * 16 + (lane & 15);
-    const int p0 = ch * kSplitK, p1 = min(n, p0 + kSplitK);
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = p0; k0 < p1; k0 += 32) {
-      bf16x8 a, b;
+  __shared__ __attribute__((aligned(16))) uint16_t LT[kWgM * kWgLd];
+  __shared__ __attribute__((aligned(16))) uint16_t RT[kWgM * kWgLd];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id(), g = lane >> 4;
+  const int mb = M / kWgM, nb = (N + kWgM - 1) / kWgM;
+  const int tile = blockIdx.x % (mb * nb), ch = blockIdx.x / (mb * nb);
+  const int m0 = (tile / nb) * kWgM, n0 = (tile % nb) * kWgM;
+  const int nw = min(kWgM, N - n0), tn = nw / 16;  // columns of this tile, in 16-column MFMA tiles
+  const int p0 = ch * kSplitK, p1 = min(n, p0 + kSplitK);
+  f32x4 acc[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int p = k0 + 8 * g + e;
-        a[e] = as_bf(p < p1 ? Lm[(int64_t)p * M + m] : (uint16_t)0);
-        b[e] = as_bf(p < p1 ? Rm[(int64_t)p * N + nn] : (uint16_t)0);
-      }
-      acc = mfma(a, b, acc);
+  for (int j = 0; j < 4; ++j) acc[j] = {0.f, 0.f, 0.f, 0.f};
+  // slab loaders: thread t takes sample row t / 8 of the step and 8 consecutive columns;
+  // the next step's rows are loaded while this step's MFMAs run
+  const int row = tid >> 3, c8 = (tid & 7) * 8;
+  auto load = [&](int k0, uint4& lv, uint4& rv) {
+    const int p = k0 + row;
+    lv = make_uint4(0, 0, 0, 0);
+    rv = make_uint4(0, 0, 0, 0);
+    if (p < p1) {
+      lv = *(const uint4*)&Lm[(int64_t)p * M + m0 + c8];
+      if (c8 < nw) rv = *(const uint4*)&Rm[(int64_t)p * N + n0 + c8];
     }
-    float* C = part + (int64_t)ch * M * N;
+  };
+  uint4 lv, rv;
+  load(p0, lv, rv);
+  for (int k0 = p0; k0 < p1; k0 += 32) {
+    __syncthreads();  // the previous step's MFMAs have read the slabs
+    const uint32_t lw[4] = {lv.x, lv.y, lv.z, lv.w}, rw[4] = {rv.x, rv.y, rv.z, rv.w};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) C[((tile / tn) * 16 + 4 * g + r) * N + nn] = acc[r];
+    for (int i = 0; i < 8; ++i) {
+      LT[(c8 + i) * kWgLd + row] = (uint16_t)(lw[i >> 1] >> (16 * (i & 1)));
+      RT[(c8 + i) * kWgLd + row] = (uint16_t)(rw[i >> 1] >> (16 * (i & 1)));
+    }
+    load(k0 + 32, lv, rv);
+    __syncthreads();
+    const bf16x8 a = *(const bf16x8*)&LT[(16 * wave + (lane & 15)) * kWgLd + 8 * g];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j >= tn) break;
+      const bf16x8 bj = *(const bf16x8*)&RT[(16 * j + (lane & 15)) * kWgLd + 8 * g];
+      acc[j] = mfma(a, bj, acc[j]);
+    }
+  }
+  float* C = part + (int64_t)ch * M * N;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j >= tn) break;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[(m0 + 16 * wave + 4 * g + r) * N + n0 + 16 * j + (lane & 15)] = acc[j][r];
   }
 }
 
-// out[j] = sum over r = 0, 1, .., rows - 1 of part[r][j] (the same order every run).
-__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ part, int rows, int width,
-                                                     float* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= width) return;
-  float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += part[(int64_t)r * width + j];
-  out[j] = s;
+// out[j] = sum over r of part[r][j], in the same order every run: 8 groups of rows
+// (group k takes rows k, k + 8, ..., in order), then the 8 group sums in order. A block
+// takes 32 columns (coalesced 128-byte row segments) with 8 threads per column.
+constexpr int kRedCols = 32, kRedGroups = 8;
+__global__ __launch_bounds__(kRedCols * kRedGroups) void k_reduce_rows(const float* __restrict__ part, int rows,
+                                                                       int width, float* __restrict__ out) {
+  __shared__ float sh[kRedGroups][kRedCols + 1];
+  const int c = threadIdx.x % kRedCols, grp = threadIdx.x / kRedCols;
+  const int j = blockIdx.x * kRedCols + c;
+  float acc = 0.f;
+  if (j < width)
+    for (int r = grp; r < rows; r += kRedGroups) acc += part[(int64_t)r * width + j];
+  sh[grp][c] = acc;
+  __syncthreads();
+  if (grp == 0 && j < width) {
+    float t = sh[0][c];
+    for (int k = 1; k < kRedGroups; ++k) t += sh[k][c];
+    out[j] = t;
+  }
+}
+
+static void launch_reduce_rows(hipStream_t s, const float* part, int rows, int width, float* out) {
+  hipLaunchKernelGGL(k_reduce_rows, dim3((width + kRedCols - 1) / kRedCols), dim3(kRedCols * kRedGroups), 0, s, part,
+                     rows, width, out);
 }
 
 // Adam on the fp32 master parameters (bias-corrected moments).
@@ -791,22 +843,23 @@ void launch_mlp_backward(hipStream_t s, const MlpDev& M, const uint16_t* x, int 
   float* p_w2 = p_b1 + (int64_t)rows * kH;
   float* p_w1 = p_w2 + (int64_t)chunks * kH * kH;
   hipLaunchKernelGGL(k_back_out, dim3(rows), dim3(kH), 0, s, dz, h2, (const float*)M.w3b, n, p_out, G2);
-  hipLaunchKernelGGL(k_reduce_rows, dim3((kOutPart + 255) / 256), dim3(256), 0, s, (const float*)p_out, rows,
+  launch_reduce_rows(s, (const float*)p_out, rows,
                      kOutPart, g + P_B2);
   // dW2[o2][o1] = sum_p G2[p][o2] h1[p][o1]
-  hipLaunchKernelGGL(k_wgrad, dim3(grid_for((int64_t)(kH / 16) * (kH / 16) * chunks, 4, 4096)), dim3(256), 0, s,
+  static_assert(kH % kWgM == 0 && kH % 16 == 0 && kF % 16 == 0, "weight-gradient tiling");
+  hipLaunchKernelGGL(k_wgrad, dim3((kH / kWgM) * ((kH + kWgM - 1) / kWgM) * chunks), dim3(256), 0, s,
                      (const uint16_t*)G2, kH, h1, kH, n, p_w2);
-  hipLaunchKernelGGL(k_reduce_rows, dim3(kH * kH / 256), dim3(256), 0, s, (const float*)p_w2, chunks, kH * kH,
+  launch_reduce_rows(s, (const float*)p_w2, chunks, kH * kH,
                      g + P_W2);
   const int64_t tiles = (int64_t)(n + 15) / 16 * (kH / 16);
   hipLaunchKernelGGL(k_back_hidden, dim3(grid_for(tiles, 4, 4096)), dim3(256), 0, s, (const uint16_t*)G2,
                      (const uint16_t*)M.w2h, h1, n, G1);
   hipLaunchKernelGGL(k_colsum, dim3(rows), dim3(kH), 0, s, (const uint16_t*)G1, n, p_b1);
-  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(256), 0, s, (const float*)p_b1, rows, kH, g + P_B1);
+  launch_reduce_rows(s, (const float*)p_b1, rows, kH, g + P_B1);
   // dW1[o1][i] = sum_p G1[p][o1] x[p][i]
-  hipLaunchKernelGGL(k_wgrad, dim3(grid_for((int64_t)(kH / 16) * (kF / 16) * chunks, 4, 4096)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_wgrad, dim3((kH / kWgM) * ((kF + kWgM - 1) / kWgM) * chunks), dim3(256), 0, s,
                      (const uint16_t*)G1, kH, x, kF, n, p_w1);
-  hipLaunchKernelGGL(k_reduce_rows, dim3(kH * kF / 256), dim3(256), 0, s, (const float*)p_w1, chunks, kH * kF,
+  launch_reduce_rows(s, (const float*)p_w1, chunks, kH * kF,
                      g + P_W1);
 }
 
