@@ -305,7 +305,8 @@ __global__ __launch_bounds__(256) void k_features(const UnitDesc* __restrict__ u
 // the top-k of the customers that own such an anchor from the cached logits.
 
 constexpr int kScoreWaves = 8;
-constexpr int kScoreT = 2;  // sample tiles per pass through W2
+constexpr int kScoreT = 4;      // sample tiles per pass through W2 (one anchor per lane)
+constexpr int kScoreStage = 2;  // tiles staged in LDS at a time
 
 __global__ void k_queue_reset(int32_t* __restrict__ count) { *count = 0; }
 
@@ -359,17 +360,20 @@ __global__ __launch_bounds__(256) void k_anchor_mark(const UnitDesc* __restrict_
   }
 }
 
-// Logits of the queued anchors: each wavefront takes 16 T anchors at a time, builds
-// their features (one anchor per lane of the first 16 T lanes), stages them in LDS
-// as B fragments, and runs the network on the matrix cores.
+// Logits of the queued anchors: each wavefront takes 64 anchors at a time (one per
+// lane), builds their features, stages them in LDS as B fragments (32 anchors at a
+// time), and runs the network on the matrix cores, 4 sample tiles per pass through
+// the LDS copy of W2.
 template <class SEG, bool TW>
 __global__ __launch_bounds__(64 * kScoreWaves) void k_score_anchors(
     const UnitDesc* __restrict__ units, const int64_t* __restrict__ anchor_off, int n_units,
     const bf16x8* __restrict__ w1f, const bf16x8* __restrict__ w2f, const float* __restrict__ P,
     const float* __restrict__ w3b, const int32_t* __restrict__ queue, const int32_t* __restrict__ qcount,
     float* __restrict__ lcache) {
+  static_assert(16 * kScoreT == 64 && kScoreT % kScoreStage == 0, "one anchor per lane");
+  constexpr int SR = 16 * kScoreStage;  // staged rows
   __shared__ MlpSmem S;
-  __shared__ __attribute__((aligned(16))) uint16_t xs[kScoreWaves][16 * kScoreT * kF];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[kScoreWaves][SR * kF];
   // without a queue every anchor of the batch is scored (missing list entries get zero
   // features; nothing reads their logits)
   const int n = queue ? *qcount : (int)anchor_off[n_units];
@@ -379,8 +383,8 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score_anchors(
   const int wave = threadIdx.x >> 6, lane = lane_id();
   constexpr int G = 16 * kScoreT;
   for (int g0 = (blockIdx.x * kScoreWaves + wave) * G; g0 < n; g0 += gridDim.x * kScoreWaves * G) {
-    if (lane < G) {
-      uint16_t f[kF];
+    uint16_t f[kF];
+    {
       const int q = g0 + lane;
       bool have = false;
       if (q < n) {
@@ -398,15 +402,21 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score_anchors(
 #pragma unroll
         for (int z = 0; z < kF; ++z) f[z] = 0;
       }
-      uint4* row = (uint4*)&xs[wave][lane * kF];
-#pragma unroll
-      for (int z = 0; z < 4; ++z) row[z] = pack8(f + 8 * z);
     }
-    wave_lds_sync();
     bf16x8 xb[kScoreT];
 #pragma unroll
-    for (int t = 0; t < kScoreT; ++t) xb[t] = *(const bf16x8*)&xs[wave][(16 * t + (lane & 15)) * kF + 8 * (lane >> 4)];
-    wave_lds_sync();
+    for (int h = 0; h < kScoreT / kScoreStage; ++h) {
+      if (lane / SR == h) {
+        uint4* row = (uint4*)&xs[wave][(lane % SR) * kF];
+#pragma unroll
+        for (int z = 0; z < 4; ++z) row[z] = pack8(f + 8 * z);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int t = 0; t < kScoreStage; ++t)
+        xb[h * kScoreStage + t] = *(const bf16x8*)&xs[wave][(16 * t + (lane & 15)) * kF + 8 * (lane >> 4)];
+      wave_lds_sync();
+    }
     float z[kScoreT];
     mlp_tiles<kScoreT>(S, w1f, xb, b3, z, nullptr, nullptr);
 #pragma unroll
