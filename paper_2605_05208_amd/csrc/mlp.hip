@@ -654,6 +654,12 @@ constexpr int kSplitK = 1024;  // samples per chunk of the weight-gradient produ
 constexpr int kWgM = 64;       // output rows of one weight-gradient block (4 waves x 16)
 constexpr int kWgLd = 40;      // LDS row length (bf16) of the transposed 32-sample slabs
 
+// Position of sample s (0..31) in the LDS row of column c: the four 8-sample groups are
+// permuted by bits 3-4 of c (XOR), so that the transposing 16-bit stores of the columns
+// c8 .. c8 + 7 of different 8-column groups fall into different banks; a group stays
+// contiguous and 16-byte aligned for the fragment reads.
+__device__ __forceinline__ int wg_swz(int c, int s) { return s ^ (((c >> 3) & 3) << 3); }
+
 // Weight gradient of one chunk of kSplitK samples: part[ch][M][N] = sum_p L[p][m] R[p][n]
 // over the chunk's samples (both bf16, row-major with row lengths M and N; M a multiple
 // of 64, N of 16). One block per (64 x 64 output tile, chunk): per step of 32 samples the
@@ -692,18 +698,21 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ Lm, 
   for (int k0 = p0; k0 < p1; k0 += 32) {
     __syncthreads();  // the previous step's MFMAs have read the slabs
     const uint32_t lw[4] = {lv.x, lv.y, lv.z, lv.w}, rw[4] = {rv.x, rv.y, rv.z, rv.w};
+    const int srow = wg_swz(c8, row);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      LT[(c8 + i) * kWgLd + row] = (uint16_t)(lw[i >> 1] >> (16 * (i & 1)));
-      RT[(c8 + i) * kWgLd + row] = (uint16_t)(rw[i >> 1] >> (16 * (i & 1)));
+      LT[(c8 + i) * kWgLd + srow] = (uint16_t)(lw[i >> 1] >> (16 * (i & 1)));
+      RT[(c8 + i) * kWgLd + srow] = (uint16_t)(rw[i >> 1] >> (16 * (i & 1)));
     }
     load(k0 + 32, lv, rv);
     __syncthreads();
-    const bf16x8 a = *(const bf16x8*)&LT[(16 * wave + (lane & 15)) * kWgLd + 8 * g];
+    const int ca = 16 * wave + (lane & 15);
+    const bf16x8 a = *(const bf16x8*)&LT[ca * kWgLd + wg_swz(ca, 8 * g)];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (j >= tn) break;
-      const bf16x8 bj = *(const bf16x8*)&RT[(16 * j + (lane & 15)) * kWgLd + 8 * g];
+      const int cb = 16 * j + (lane & 15);
+      const bf16x8 bj = *(const bf16x8*)&RT[cb * kWgLd + wg_swz(cb, 8 * g)];
       acc[j] = mfma(a, bj, acc[j]);
     }
   }
