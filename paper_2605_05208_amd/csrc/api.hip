@@ -1591,7 +1591,7 @@ void carve_mlp(Carve& cv, MlpDev* M) {
   m.v = cv.take<float>(np);
   m.w1f = cv.take<char>(16 * 64 * 16);
   m.w2f = cv.take<char>(16 * 8 * 64 * 16);
-  m.w2h = cv.take<uint16_t>(256 * 256);
+  m.w2b = cv.take<char>(16 * 8 * 64 * 16);
   m.w3b = cv.take<float>(256);
   m.scratch = cv.take<float>(2 + kBceBlocks);
   if (M) *M = m;

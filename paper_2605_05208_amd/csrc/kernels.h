@@ -95,13 +95,12 @@ void launch_state_export(const LaunchCtx& L, int64_t* out /* [n_units][kStateWor
 
 // ---- learned move filter
 // Device buffers of one network: fp32 master parameters, Adam moments, and the
-// bf16 operand copies the kernels read (W1 / W2 in MFMA fragment order, W2
-// row-major, w3 rounded and widened back to fp32); scratch holds the loss kernel's weight
+// bf16 operand copies the kernels read (W1 / W2 in MFMA fragment order, W2 in the
+// fragment order of the hidden-layer backward, w3 rounded and widened back to fp32); scratch holds the loss kernel's weight
 // sum and per-block partials (2 + kBceBlocks floats).
 struct MlpDev {
   float *P, *m, *v;
-  void *w1f, *w2f;
-  uint16_t* w2h;
+  void *w1f, *w2f, *w2b;
   float* w3b;
   float* scratch;
 };

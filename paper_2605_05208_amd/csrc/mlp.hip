@@ -71,8 +71,10 @@ __device__ __forceinline__ uint4 pack8(const uint16_t* f) {
 // W2 fragment (ob, j, lane): row 16 ob + lane % 16; columns 32 j + 4 (lane / 16) + e for
 // e < 4 and 32 j + 16 + 4 (lane / 16) + e - 4 for e >= 4 -- the order in which layer 1's
 // output fragments of blocks 2j and 2j+1 land in a lane.
+// W2 backward fragment (nb, kb, lane): W2[32 kb + 8 (lane / 16) + e][16 nb + lane % 16], the
+// B operand of the hidden-layer gradient (columns 16 nb .., inputs 32 kb ..).
 __global__ void k_mlp_pack(const float* __restrict__ P, bf16x8* __restrict__ w1f, bf16x8* __restrict__ w2f,
-                           uint16_t* __restrict__ w2h, float* __restrict__ w3b) {
+                           bf16x8* __restrict__ w2b, float* __restrict__ w3b) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < 16 * 64) {
     const int ob = t / 64, lane = t % 64;
@@ -90,7 +92,12 @@ __global__ void k_mlp_pack(const float* __restrict__ P, bf16x8* __restrict__ w1f
     }
     w2f[t] = v;
   }
-  if (t < kH * kH) w2h[t] = f2bf(P[P_W2 + t]);
+  if (t < 16 * 8 * 64) {
+    const int nb = t / 512, kb = (t / 64) % 8, lane = t % 64;
+    bf16x8 v;
+    for (int e = 0; e < 8; ++e) v[e] = as_bf(f2bf(P[P_W2 + (32 * kb + 8 * (lane / 16) + e) * kH + 16 * nb + lane % 16]));
+    w2b[t] = v;
+  }
   if (t < kH) w3b[t] = bf2f(f2bf(P[P_W3 + t]));
 }
 
@@ -610,7 +617,7 @@ __global__ __launch_bounds__(256) void k_back_out(const float* __restrict__ dz, 
 
 // G1 = (G2 W2) masked by [h1 > 0], rounded to bf16; one wave per 16 x 16 output tile.
 // A(m, k) = G2[m][k] (row-major, 16-byte loads), B(k, n) = W2[k][n].
-__global__ __launch_bounds__(256) void k_back_hidden(const uint16_t* __restrict__ G2, const uint16_t* __restrict__ w2h,
+__global__ __launch_bounds__(256) void k_back_hidden(const uint16_t* __restrict__ G2, const bf16x8* __restrict__ w2b,
                                                      const uint16_t* __restrict__ h1, int n, uint16_t* __restrict__ G1) {
   const int wave = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4;
   const int tm = (n + 15) / 16, tn = kH / 16;
@@ -627,8 +634,7 @@ __global__ __launch_bounds__(256) void k_back_hidden(const uint16_t* __restrict_
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[e] = as_bf(0);
       }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) b[e] = as_bf(w2h[(k0 + 8 * g + e) * kH + nn]);
+      b = w2b[((n0 / 16) * 8 + k0 / 32) * 64 + lane];  // W2[k0 + 8 g + e][nn], e = 0..7
       acc = mfma(a, b, acc);
     }
 #pragma unroll
@@ -773,7 +779,7 @@ static int grid_for(int64_t work, int per_block, int cap) {
 
 void launch_mlp_pack(hipStream_t s, const MlpDev& M) {
   hipLaunchKernelGGL(k_mlp_pack, dim3((kH * kH + 255) / 256), dim3(256), 0, s, (const float*)M.P, (bf16x8*)M.w1f,
-                     (bf16x8*)M.w2f, M.w2h, M.w3b);
+                     (bf16x8*)M.w2f, (bf16x8*)M.w2b, M.w3b);
 }
 
 void launch_mlp_zero(hipStream_t s, float* p, int n) {
@@ -872,7 +878,7 @@ void launch_mlp_backward(hipStream_t s, const MlpDev& M, const uint16_t* x, int 
                      g + P_W2);
   const int64_t tiles = (int64_t)(n + 15) / 16 * (kH / 16);
   hipLaunchKernelGGL(k_back_hidden, dim3(grid_for(tiles, 4, 4096)), dim3(256), 0, s, (const uint16_t*)G2,
-                     (const uint16_t*)M.w2h, h1, n, G1);
+                     (const bf16x8*)M.w2b, h1, n, G1);
   hipLaunchKernelGGL(k_colsum, dim3(rows), dim3(kH), 0, s, (const uint16_t*)G1, n, p_b1);
   launch_reduce_rows(s, (const float*)p_b1, rows, kH, g + P_B1);
   // dW1[o1][i] = sum_p G1[p][o1] x[p][i]
