@@ -615,34 +615,43 @@ __global__ __launch_bounds__(256) void k_back_out(const float* __restrict__ dz, 
   if (o == 0) row[2 * kH] = ab3;
 }
 
-// G1 = (G2 W2) masked by [h1 > 0], rounded to bf16; one wave per 16 x 16 output tile.
-// A(m, k) = G2[m][k] (row-major, 16-byte loads), B(k, n) = W2[k][n].
+// G1 = (G2 W2) masked by [h1 > 0], rounded to bf16; one wave per 16 samples x 64 outputs
+// (four 16 x 16 tiles sharing each A fragment). A(m, k) = G2[m][k] (row-major, 16-byte
+// loads), B(k, n) = W2[k][n] (packed 16-byte fragments).
+constexpr int kBhTiles = 4;
 __global__ __launch_bounds__(256) void k_back_hidden(const uint16_t* __restrict__ G2, const bf16x8* __restrict__ w2b,
                                                      const uint16_t* __restrict__ h1, int n, uint16_t* __restrict__ G1) {
   const int wave = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4;
-  const int tm = (n + 15) / 16, tn = kH / 16;
-  for (int t = blockIdx.x * 4 + wave; t < tm * tn; t += gridDim.x * 4) {
-    const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
-    const int m = m0 + (lane & 15), nn = n0 + (lane & 15);
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int tm = (n + 15) / 16, tq = kH / (16 * kBhTiles);
+  for (int t = blockIdx.x * 4 + wave; t < tm * tq; t += gridDim.x * 4) {
+    const int m0 = (t / tq) * 16, nb0 = (t % tq) * kBhTiles;
+    const int m = m0 + (lane & 15);
+    f32x4 acc[kBhTiles];
+#pragma unroll
+    for (int q = 0; q < kBhTiles; ++q) acc[q] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
     for (int k0 = 0; k0 < kH; k0 += 32) {
-      bf16x8 a, b;
+      bf16x8 a;
       if (m < n) {
         a = *(const bf16x8*)&G2[(int64_t)m * kH + k0 + 8 * g];
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[e] = as_bf(0);
       }
-      b = w2b[((n0 / 16) * 8 + k0 / 32) * 64 + lane];  // W2[k0 + 8 g + e][nn], e = 0..7
-      acc = mfma(a, b, acc);
+#pragma unroll
+      for (int q = 0; q < kBhTiles; ++q)  // W2[k0 + 8 g + e][16 (nb0 + q) + lane % 16], e = 0..7
+        acc[q] = mfma(a, w2b[((nb0 + q) * 8 + k0 / 32) * 64 + lane], acc[q]);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int mr = m0 + 4 * g + r;
-      if (mr < n) {
-        const int64_t at = (int64_t)mr * kH + nn;
-        G1[at] = f2bf(bf2f(h1[at]) > 0.f ? acc[r] : 0.f);
+    for (int q = 0; q < kBhTiles; ++q) {
+      const int nn = 16 * (nb0 + q) + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mr = m0 + 4 * g + r;
+        if (mr < n) {
+          const int64_t at = (int64_t)mr * kH + nn;
+          G1[at] = f2bf(bf2f(h1[at]) > 0.f ? acc[q][r] : 0.f);
+        }
       }
     }
   }
@@ -876,7 +885,7 @@ void launch_mlp_backward(hipStream_t s, const MlpDev& M, const uint16_t* x, int 
                      (const uint16_t*)G2, kH, h1, kH, n, p_w2);
   launch_reduce_rows(s, (const float*)p_w2, chunks, kH * kH,
                      g + P_W2);
-  const int64_t tiles = (int64_t)(n + 15) / 16 * (kH / 16);
+  const int64_t tiles = (int64_t)(n + 15) / 16 * (kH / (16 * kBhTiles));
   hipLaunchKernelGGL(k_back_hidden, dim3(grid_for(tiles, 4, 4096)), dim3(256), 0, s, (const uint16_t*)G2,
                      (const bf16x8*)M.w2b, h1, n, G1);
   hipLaunchKernelGGL(k_colsum, dim3(rows), dim3(kH), 0, s, (const uint16_t*)G1, n, p_b1);
