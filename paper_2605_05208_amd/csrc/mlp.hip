@@ -681,8 +681,8 @@ __device__ __forceinline__ int wg_swz(int c, int s) { return s ^ (((c >> 3) & 3)
 // block loads the 32 x 64 slabs of L and R with 16-byte row loads and stores them
 // transposed in LDS (sample index contiguous), so that every MFMA operand fragment is one
 // 16-byte LDS read; wave w computes rows 16 w .. 16 w + 15 of the tile against its (up
-// to 64) columns. The operands of every MFMA (the 32 samples of one step, in order) are
-// those of a one-tile-per-wave loop over the same steps, so the sums are too.
+// to 64) columns. Every output element accumulates the chunk's samples 32 at a time in
+// sample order, whatever the block shape, so the partial sums are deterministic.
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ Lm, int M, const uint16_t* __restrict__ Rm,
                                                int N, int n, float* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) uint16_t LT[kWgM * kWgLd];
