@@ -743,15 +743,28 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ Lm, 
 // out[j] = sum over r of part[r][j], in the same order every run: 8 groups of rows
 // (group k takes rows k, k + 8, ..., in order), then the 8 group sums in order. A block
 // takes 32 columns (coalesced 128-byte row segments) with 8 threads per column.
-constexpr int kRedCols = 32, kRedGroups = 8;
+constexpr int kRedCols = 32, kRedGroups = 8, kRedBatch = 16;
 __global__ __launch_bounds__(kRedCols * kRedGroups) void k_reduce_rows(const float* __restrict__ part, int rows,
                                                                        int width, float* __restrict__ out) {
   __shared__ float sh[kRedGroups][kRedCols + 1];
   const int c = threadIdx.x % kRedCols, grp = threadIdx.x / kRedCols;
   const int j = blockIdx.x * kRedCols + c;
   float acc = 0.f;
-  if (j < width)
-    for (int r = grp; r < rows; r += kRedGroups) acc += part[(int64_t)r * width + j];
+  if (j < width) {
+    // rows grp, grp + 8, ... added in order; loaded kRedBatch at a time so that the loads
+    // overlap
+    for (int r0 = grp; r0 < rows; r0 += kRedGroups * kRedBatch) {
+      float v[kRedBatch];
+#pragma unroll
+      for (int u = 0; u < kRedBatch; ++u) {
+        const int r = r0 + kRedGroups * u;
+        v[u] = r < rows ? part[(int64_t)r * width + j] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kRedBatch; ++u)
+        if (r0 + kRedGroups * u < rows) acc += v[u];
+    }
+  }
   sh[grp][c] = acc;
   __syncthreads();
   if (grp == 0 && j < width) {
