@@ -547,7 +547,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the local search of a population is data parallel over "
-              "solutions, and this build runs on a single MI355X (see the design notes for how it shards).",
+              "solutions, and this implementation runs on a single MI355X; a population would shard by solutions, one process per GPU.",
               file=sys.stderr)
         return 2
 
