@@ -2,7 +2,7 @@
 
 This module only synthesises inputs. It holds none of the method's arithmetic
 (no route cost, no time warp, no move evaluation): both the HIP path and the
-CPU checker consume what it produces.
+CPU oracle consume what it produces.
 
 Instances follow the problem statement of the paper (Section 1): depots take
 ids [0, n_depots), customers take [n_depots, N); c and t are symmetric integer
